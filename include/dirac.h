@@ -1,0 +1,198 @@
+/*
+ * dirac.h - C ABI of the MI355X (gfx950) library for the QCD+QED O(a)-improved
+ * Wilson-Dirac operator and its even-odd preconditioned Krylov solves.
+ *
+ * Paper: R. Gruber et al., "O(a)-improved QCD+QED Wilson Dirac operator on GPUs",
+ * arXiv:2502.02490 (LATTICE2024).
+ *
+ * ---------------------------------------------------------------------------
+ * Operator (the paper names D_w in Sec. 2 but does not write it out; the
+ * readings below are the library's definition and are fixed here):
+ *
+ *   D psi(x) = (4 + m0) psi(x) + C(x) psi(x)
+ *              - 1/2 sum_mu [ V_mu(x) b+_mu(x) (1 - gamma_mu) psi(x + mu)
+ *                           + V_mu(x - mu)^dag b-_mu(x) (1 + gamma_mu) psi(x - mu) ]
+ *   m0 = 1/(2 kappa) - 4             (D itself, not 2 kappa D)
+ *   V_mu(x) = exp(i qhat theta_mu(x)) U_mu(x)       (U(3) link, Sec. 4.3)
+ *   b+_mu(x) = exp(i phi_mu) if x_mu = L_mu - 1, b-_mu(x) = exp(-i phi_mu) if x_mu = 0
+ *   C(x) = c_sw (i/4) sum_{mu != nu} sigma_{mu nu} F_{mu nu}(x)
+ *        + c_sw^QED qhat (i/4) sum_{mu != nu} sigma_{mu nu} F^U(1)_{mu nu}(x)   (Sec. 4.3)
+ *   F = (Q - Q^dag)/8, Q = sum of the four plaquette leaves at x in the (mu, nu)
+ *   plane, from U alone (SU(3) part) or from exp(i theta) alone (U(1) part);
+ *   no traceless projection; boundary phases do not enter C.
+ *   gamma matrices: chiral basis, gamma_0 = [[0,-1],[-1,0]],
+ *   gamma_k = [[0,-i sigma_k],[i sigma_k,0]], gamma_5 = diag(1,1,-1,-1),
+ *   sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu].  A = (4 + m0) + C is Hermitian and
+ *   block-diagonal in chirality: an upper block (spins 0,1) and a lower block
+ *   (spins 2,3), each 6x6 (Sec. 2).
+ *
+ * Even-odd (Schur) form: D = [[A_ee, D_eo], [D_oe, A_oo]] with D_eo = -H_eo / 2,
+ *   D-hat = A_ee - D_eo A_oo^-1 D_oe  on the even sites,
+ *   D-hat^dag = gamma_5 D-hat gamma_5.
+ *
+ * ---------------------------------------------------------------------------
+ * Sites and layouts (Sec. 4.1.1).  Coordinates x = (x0, x1, x2, x3), x0 = time.
+ * All four extents must be even (the checkerboard must survive the periodic wrap).
+ *   Lambda(x) = L3 L2 L1 x0 + L3 L2 x1 + L3 x2 + x3                  eq. (lexi)
+ *   parity P(x) = (x0 + x1 + x2 + x3) mod 2
+ *   xhat(x) = floor(Lambda / 2) + P(x) V / 2      eq. (ipt) with one block (B = L)
+ *
+ * DIRAC_LAYOUT_LEX     spinor: [V][4 spin][3 colour] complex (re, im), colour
+ *                      fastest (Sec. 2, Sec. 4.1.2), sites in Lambda order.
+ * DIRAC_LAYOUT_EO      the same per-site layout, sites in xhat order (even
+ *                      sites first).  A half (even-site) vector is the first
+ *                      V/2 sites of an EO vector.
+ * DIRAC_LAYOUT_NATIVE  the library's device layout: per parity, 16-byte planes
+ *                      [24/W][V/2][W] reals (W = 2 for F64, 4 for F32, 8 for F16
+ *                      and BF16); a full vector is the even half then the odd
+ *                      half.  Within a plane, site k is floor(Lambda / 2) of the
+ *                      k-th site of that parity.  Use this layout when timing.
+ * User-layout (LEX/EO) buffers are complex128 for DIRAC_F64 and complex64 for
+ * DIRAC_F32; F16 and BF16 exist in the NATIVE layout only.
+ *
+ * Gauge input (Sec. 4.1.4): su3_links [V][mu = 0..3][a][b] complex128, row-major
+ * 3x3 SU(3) matrices, four forward links per site, LEX order; u1_angles
+ * [V][4] float64 (theta_mu(x)) or NULL for theta = 0.
+ * Clover input/output (Sec. 4.1.3): [site][2][36] float64 per site, block + then
+ * block -, each 6 diagonal reals followed by (re, im) of the 15 strictly-upper
+ * entries in row-major order, block row index 3 * spin + colour.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions of every call.
+ *   All pointers to fields are device pointers; the caller owns them and keeps
+ *   them alive until the work queued on `stream` has finished.  `stream` is a
+ *   hipStream_t (NULL = the default stream).  Apply calls are asynchronous on
+ *   `stream`; calls that return a value computed on the device (clover_invert,
+ *   dirac_solve) synchronise `stream` before returning.
+ *   No call aborts, throws or prints.  On failure it returns a status other than
+ *   DIRAC_OK and dirac_last_error() returns a message (thread-local, valid until
+ *   the next call on the same thread).  Output buffers must not alias inputs.
+ *   A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef DIRAC_H
+#define DIRAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dirac_ctx dirac_ctx;
+
+typedef enum {
+    DIRAC_OK = 0,
+    DIRAC_EINVAL = 1,      /* bad argument: NULL pointer, odd extent, aliasing, bad enum */
+    DIRAC_ENOMEM = 2,      /* device allocation failed */
+    DIRAC_EHIP = 3,        /* a HIP runtime call failed */
+    DIRAC_ESINGULAR = 4,   /* a 6x6 clover block is singular (first site in the message) */
+    DIRAC_ENOCONV = 5,     /* solver stopped at max_iter; x holds the best iterate */
+    DIRAC_ENONFINITE = 6,  /* NaN or Inf met in a reduction */
+    DIRAC_EUNSUPPORTED = 7 /* precision / layout combination not offered */
+} dirac_status;
+
+typedef enum { DIRAC_F64 = 0, DIRAC_F32 = 1, DIRAC_F16 = 2, DIRAC_BF16 = 3 } dirac_prec;
+typedef enum { DIRAC_LAYOUT_LEX = 0, DIRAC_LAYOUT_EO = 1, DIRAC_LAYOUT_NATIVE = 2 } dirac_layout;
+
+typedef struct {
+    int dims[4];        /* L0 (time), L1, L2, L3; each even and >= 2 */
+    double kappa;       /* hopping parameter: 4 + m0 = 1 / (2 kappa) */
+    double csw;         /* SU(3) Sheikholeslami-Wohlert coefficient */
+    double csw_qed;     /* U(1) SW coefficient c_sw^U(1) (Sec. 4.3) */
+    int qhat;           /* integer charge multiplying theta in the link and the U(1) SW term */
+    double bc_phase[4]; /* phi_mu in radians: {pi, 0, 0, 0} = antiperiodic time, periodic space */
+} dirac_params;
+
+/* Create a context: copies the gauge field, compresses the links (two rows of
+ * SU(3) plus one phase per link), builds the clover field on the device and
+ * inverts its odd-site blocks.  Returns DIRAC_ESINGULAR if an odd-site block is
+ * singular (the context is still created and must be destroyed).  Blocking. */
+dirac_status dirac_create(const dirac_params *params, const void *su3_links, const double *u1_angles,
+                          void *stream, dirac_ctx **out);
+dirac_status dirac_destroy(dirac_ctx *ctx);
+
+/* Replace the clover field A = (4 + m0) + C by a user field (Sec. 4.1.3: the
+ * application may compute the QCD+QED clover term itself and upload it).
+ * `clover` is [V][2][36] float64 in LEX or EO site order.  Inverses and
+ * lower-precision copies are invalidated; call clover_invert next. */
+dirac_status dirac_load_clover(dirac_ctx *ctx, const double *clover, dirac_layout layout, void *stream);
+
+/* Copy the clover field (inverse = 0) or its inverse (inverse = 1) out, [V][2][36]
+ * float64 in LEX or EO order.  Sites whose inverse was not computed read 0. */
+dirac_status dirac_get_clover(dirac_ctx *ctx, double *out, int inverse, dirac_layout layout, void *stream);
+
+/* Invert the 6x6 chirality blocks of A in FP64: parity_mask bit 0 = even sites,
+ * bit 1 = odd sites.  A block is singular when a pivot of Gauss-Jordan
+ * elimination with partial pivoting has modulus below 1e-14 * max|A_block|; the
+ * call then returns DIRAC_ESINGULAR and names the first such site (Lambda).
+ * Blocking. */
+dirac_status clover_invert(dirac_ctx *ctx, int parity_mask, void *stream);
+
+/* Size in bytes of a NATIVE vector: sites = 0 full lattice, 1 one parity. */
+size_t dirac_native_bytes(const dirac_ctx *ctx, dirac_prec prec, int sites);
+
+/* Layout conversion of a spinor field.  sites = 0: full vector (LEX or EO user
+ * layout); sites = 1: even half (EO user layout only); sites = 2: odd half (EO
+ * user layout only, the second V/2 sites of an EO vector).  `user` is complex128
+ * for F64 and F16/BF16 targets, complex64 for F32. */
+dirac_status dirac_import(dirac_ctx *ctx, void *native, const void *user, int sites, dirac_prec prec,
+                          dirac_layout user_layout, void *stream);
+dirac_status dirac_export(dirac_ctx *ctx, void *user, const void *native, int sites, dirac_prec prec,
+                          dirac_layout user_layout, void *stream);
+
+/* out = D in (dagger = 0) or D^dag in (dagger = 1), full lattice. */
+dirac_status dirac_apply(dirac_ctx *ctx, void *out, const void *in, dirac_prec prec, dirac_layout layout,
+                         int dagger, void *stream);
+
+/* out_e = D-hat in_e (dagger = 0) or D-hat^dag in_e, even half-vectors (EO or NATIVE layout). */
+dirac_status dirac_apply_eo(dirac_ctx *ctx, void *out_e, const void *in_e, dirac_prec prec, dirac_layout layout,
+                            int dagger, void *stream);
+
+/* out_p = D_{p,1-p} in_{1-p} = -1/2 H in (the hopping term between parities), NATIVE
+ * half-vectors; out_parity selects p.  dagger = 1 gives gamma_5 D_{p,1-p} gamma_5. */
+dirac_status dirac_apply_hop(dirac_ctx *ctx, void *out, const void *in, int out_parity, dirac_prec prec,
+                             int dagger, void *stream);
+
+/* out_p = A_pp in_p (inverse = 0) or A_pp^-1 in_p (inverse = 1), NATIVE half-vectors. */
+dirac_status dirac_apply_clover(dirac_ctx *ctx, void *out, const void *in, int parity, int inverse,
+                                dirac_prec prec, void *stream);
+
+/* ---------------------------------------------------------------- solvers */
+typedef enum { DIRAC_SOLVER_CGLS = 0, DIRAC_SOLVER_GCR = 1, DIRAC_SOLVER_MIXED_GCR = 2 } dirac_solver;
+
+typedef struct {
+    int method;          /* dirac_solver */
+    int restart;         /* GCR cycle length (Krylov vectors kept), 1..64 */
+    int max_iter;        /* operator applications allowed (inner ones for MIXED_GCR) */
+    double tol;          /* stop when ||eta - D psi|| / ||eta|| < tol (FP64, recomputed) */
+    int inner_prec;      /* MIXED_GCR: dirac_prec of the inner solve (F32, F16, BF16) */
+    double inner_tol;    /* MIXED_GCR: relative reduction asked of each inner solve */
+    int x0_given;        /* 1: x holds the initial guess */
+    int precision;       /* GCR / CGLS: dirac_prec of the whole solve (F64 or F32) */
+} dirac_solver_params;
+
+typedef struct {
+    int iters;            /* operator applications (D-hat or D / D^dag) in the working precision */
+    int restarts;         /* GCR cycles after the first (or CGLS residual recomputations) */
+    int outer;            /* defect-correction steps (MIXED_GCR) */
+    int fell_back;        /* 1 if MIXED_GCR finished in plain FP64 GCR */
+    double true_rel_res;  /* ||eta - D psi|| / ||eta|| recomputed in FP64 at the end */
+    double seconds;       /* wall time of the call */
+} dirac_solve_info;
+
+/* Solve D psi = eta.  x (solution) and b (right-hand side) are full-lattice
+ * vectors in `layout` (F64 for LEX/EO; NATIVE in the solve precision, or F64
+ * for MIXED_GCR).  GCR and MIXED_GCR run on the even-odd Schur system and
+ * reconstruct the odd half; CGLS runs on the full D.  Blocking.  Returns
+ * DIRAC_ENOCONV (x = last iterate) when max_iter is reached first. */
+dirac_status dirac_solve(dirac_ctx *ctx, void *x, const void *b, dirac_layout layout,
+                         const dirac_solver_params *params, dirac_solve_info *info, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *dirac_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIRAC_H */

@@ -1,0 +1,85 @@
+"""ctypes declarations of the C ABI in include/dirac.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdirac.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESINGULAR, ENOCONV, ENONFINITE, EUNSUPPORTED = range(8)
+STATUS_NAMES = ["DIRAC_OK", "DIRAC_EINVAL", "DIRAC_ENOMEM", "DIRAC_EHIP", "DIRAC_ESINGULAR", "DIRAC_ENOCONV",
+                "DIRAC_ENONFINITE", "DIRAC_EUNSUPPORTED"]
+F64, F32, F16, BF16 = 0, 1, 2, 3
+LEX, EO, NATIVE = 0, 1, 2
+CGLS, GCR, MIXED_GCR = 0, 1, 2
+
+# every symbol declared in include/dirac.h
+EXPORTS = ["dirac_create", "dirac_destroy", "dirac_load_clover", "dirac_get_clover", "clover_invert",
+           "dirac_native_bytes", "dirac_import", "dirac_export", "dirac_apply", "dirac_apply_eo",
+           "dirac_apply_hop", "dirac_apply_clover", "dirac_solve", "dirac_last_error"]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("kappa", ctypes.c_double), ("csw", ctypes.c_double),
+                ("csw_qed", ctypes.c_double), ("qhat", ctypes.c_int), ("bc_phase", ctypes.c_double * 4)]
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("tol", ctypes.c_double), ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("x0_given", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("outer", ctypes.c_int),
+                ("fell_back", ctypes.c_int), ("true_rel_res", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class DiracError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdirac.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_2502_02490_amd.build` "
+                           "(the library has no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i, st = ctypes.c_void_p, ctypes.c_int, ctypes.c_int
+    lib.dirac_create.argtypes = [ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(vp)]
+    lib.dirac_destroy.argtypes = [vp]
+    lib.dirac_load_clover.argtypes = [vp, vp, i, vp]
+    lib.dirac_get_clover.argtypes = [vp, vp, i, i, vp]
+    lib.clover_invert.argtypes = [vp, i, vp]
+    lib.dirac_native_bytes.argtypes = [vp, i, i]
+    lib.dirac_native_bytes.restype = ctypes.c_size_t
+    lib.dirac_import.argtypes = [vp, vp, vp, i, i, i, vp]
+    lib.dirac_export.argtypes = [vp, vp, vp, i, i, i, vp]
+    lib.dirac_apply.argtypes = [vp, vp, vp, i, i, i, vp]
+    lib.dirac_apply_eo.argtypes = [vp, vp, vp, i, i, i, vp]
+    lib.dirac_apply_hop.argtypes = [vp, vp, vp, i, i, i, vp]
+    lib.dirac_apply_clover.argtypes = [vp, vp, vp, i, i, i, vp]
+    lib.dirac_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(SolverParams), ctypes.POINTER(SolveInfo), vp]
+    lib.dirac_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("dirac_native_bytes", "dirac_last_error"):
+            getattr(lib, name).restype = st
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> int:
+    if status != OK:
+        msg = _lib.dirac_last_error().decode() if _lib is not None else ""
+        raise DiracError(status, msg)
+    return status

@@ -1,0 +1,310 @@
+// C ABI entry points (include/dirac.h): argument validation, context lifetime,
+// staging between the user layouts and the NATIVE layout, status codes.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+dirac_status fail(dirac_status s, const std::string &m) {
+    g_err = m;
+    return s;
+}
+
+#define API_BEGIN \
+    g_err.clear(); \
+    try {
+#define API_END                                                        \
+    }                                                                  \
+    catch (const dl::Error &e) {                                       \
+        return fail(e.status, e.what());                               \
+    }                                                                  \
+    catch (const std::bad_alloc &) {                                   \
+        return fail(DIRAC_ENOMEM, "host allocation failed");           \
+    }                                                                  \
+    catch (const std::exception &e) {                                  \
+        return fail(DIRAC_EHIP, std::string("internal error: ") + e.what()); \
+    }                                                                  \
+    catch (...) {                                                      \
+        return fail(DIRAC_EHIP, "internal error");                     \
+    }                                                                  \
+    return DIRAC_OK;
+
+using dl::require;
+
+// The pointer must be device memory with at least `bytes` bytes from `ptr` to the end
+// of its allocation (a kernel reading past it would fault the GPU).
+void check_dev(const void *ptr, size_t bytes, const char *name) {
+    require(ptr != nullptr, std::string(name) + " is NULL");
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, ptr);
+    if (e != hipSuccess) (void)hipGetLastError();
+    require(e == hipSuccess && (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged),
+            std::string(name) + " is not device memory");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return;  // range unknown (e.g. imported memory): the type check above still holds
+    }
+    const size_t off = (size_t)((const char *)ptr - (const char *)base);
+    require(off <= size && size - off >= bytes,
+            std::string(name) + " is smaller than the " + std::to_string(bytes) + " bytes this call reads or writes");
+}
+
+void check_no_alias(const void *a, size_t na, const void *b, size_t nb) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    require(x + na <= y || y + nb <= x, "output buffer overlaps an input buffer");
+}
+
+void check_ctx(const dirac_ctx *c) { require(c != nullptr, "context is NULL"); }
+
+void check_prec(int pr) { require(pr >= DIRAC_F64 && pr <= DIRAC_BF16, "unknown precision"); }
+
+size_t user_bytes(const dirac_ctx *c, dirac_prec pr, int sites) {
+    const size_t n = sites == 0 ? (size_t)c->V : (size_t)c->vh;
+    return n * 24 * (pr == DIRAC_F32 ? 4 : 8);
+}
+size_t native_bytes(const dirac_ctx *c, dirac_prec pr, int sites) {
+    const size_t n = sites == 0 ? (size_t)c->V : (size_t)c->vh;
+    return n * 24 * dl::real_size(pr);
+}
+
+void check_user_layout(dirac_prec pr, dirac_layout lay) {
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_NATIVE, "unknown layout");
+    if (lay != DIRAC_LAYOUT_NATIVE && (pr == DIRAC_F16 || pr == DIRAC_BF16))
+        throw dl::Error(DIRAC_EUNSUPPORTED, "F16 and BF16 fields exist in the NATIVE layout only");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dirac_last_error(void) { return g_err.c_str(); }
+
+dirac_status dirac_create(const dirac_params *prm, const void *su3_links, const double *u1_angles, void *stream,
+                          dirac_ctx **out) {
+    dirac_ctx *c = nullptr;
+    g_err.clear();
+    try {
+        require(prm != nullptr && out != nullptr, "params and out must not be NULL");
+        *out = nullptr;
+        int64_t V = 1;
+        for (int m = 0; m < 4; ++m) {
+            require(prm->dims[m] >= 2 && prm->dims[m] % 2 == 0,
+                    "every lattice extent must be even and >= 2 (dims[" + std::to_string(m) + "] = " +
+                        std::to_string(prm->dims[m]) + ")");
+            V *= prm->dims[m];
+        }
+        require(V < (int64_t)1 << 30, "lattice too large for 32-bit site indices");
+        require(std::isfinite(prm->kappa) && prm->kappa != 0.0, "kappa must be finite and non-zero");
+        require(std::isfinite(prm->csw) && std::isfinite(prm->csw_qed), "c_sw and c_sw^QED must be finite");
+        for (int m = 0; m < 4; ++m) require(std::isfinite(prm->bc_phase[m]), "boundary phases must be finite");
+        check_dev(su3_links, (size_t)V * 4 * 9 * 16, "su3_links");
+        if (u1_angles) check_dev(u1_angles, (size_t)V * 4 * 8, "u1_angles");
+        hipStream_t s = (hipStream_t)stream;
+        c = new dirac_ctx();
+        c->p = *prm;
+        c->V = V;
+        c->vh = V / 2;
+        for (int m = 0; m < 4; ++m) c->g.L[m] = prm->dims[m];
+        c->g.h3 = prm->dims[3] / 2;
+        c->g.vh = (int)c->vh;
+        c->U_lex.alloc((size_t)V * 4 * 9 * 16);
+        HIP_CHECK(hipMemcpyAsync(c->U_lex.p, su3_links, (size_t)V * 4 * 9 * 16, hipMemcpyDeviceToDevice, s));
+        if (u1_angles) {
+            c->theta_lex.alloc((size_t)V * 4 * 8);
+            HIP_CHECK(hipMemcpyAsync(c->theta_lex.p, u1_angles, (size_t)V * 4 * 8, hipMemcpyDeviceToDevice, s));
+        }
+        dl::import_links(c, s);
+        dl::clover_build(c, s);
+        const int64_t bad = dl::clover_invert_parity(c, 1, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        // the gauge input is no longer needed: links are compressed, the clover field is built
+        c->U_lex.release();
+        c->theta_lex.release();
+        *out = c;
+        if (bad >= 0) return fail(DIRAC_ESINGULAR, "singular odd-site clover block at Lambda = " + std::to_string(bad));
+    } catch (const dl::Error &e) {
+        if (c) { dirac_destroy(c); }
+        return fail(e.status, e.what());
+    } catch (const std::bad_alloc &) {
+        if (c) dirac_destroy(c);
+        return fail(DIRAC_ENOMEM, "host allocation failed");
+    } catch (...) {
+        if (c) dirac_destroy(c);
+        return fail(DIRAC_EHIP, "internal error");
+    }
+    return DIRAC_OK;
+}
+
+
+
+dirac_status dirac_destroy(dirac_ctx *c) {
+    API_BEGIN
+    if (!c) return DIRAC_OK;
+    (void)hipDeviceSynchronize();
+    dl::free_solver_work(c);
+    c->U_lex.release();
+    c->theta_lex.release();
+    for (auto &f : c->f) {
+        for (int p = 0; p < 2; ++p) {
+            f.links[p].release(); f.omega[p].release(); f.clov[p].release(); f.clinv[p].release();
+        }
+        f.tmp_half.release(); f.user_in.release(); f.user_out.release();
+    }
+    c->flags.release();
+    c->red.release();
+    delete c;
+    API_END
+}
+
+size_t dirac_native_bytes(const dirac_ctx *c, dirac_prec pr, int sites) {
+    if (!c || pr < DIRAC_F64 || pr > DIRAC_BF16) return 0;
+    return native_bytes(c, pr, sites);
+}
+
+dirac_status dirac_load_clover(dirac_ctx *c, const double *clover, dirac_layout lay, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_dev(clover, (size_t)c->V * 72 * 8, "clover");
+    dl::clover_import(c, clover, lay, (hipStream_t)stream);
+    API_END
+}
+
+dirac_status dirac_get_clover(dirac_ctx *c, double *out, int inverse, dirac_layout lay, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_dev(out, (size_t)c->V * 72 * 8, "out");
+    dl::clover_export(c, out, inverse, lay, (hipStream_t)stream);
+    API_END
+}
+
+dirac_status clover_invert(dirac_ctx *c, int mask, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    require(mask >= 1 && mask <= 3, "parity_mask must be 1 (even), 2 (odd) or 3 (both)");
+    std::string msg;
+    for (int p = 0; p < 2; ++p) {
+        if (!(mask & (1 << p))) continue;
+        const int64_t bad = dl::clover_invert_parity(c, p, (hipStream_t)stream);
+        if (bad >= 0 && msg.empty())
+            msg = std::string("singular ") + (p ? "odd" : "even") + "-site clover block at Lambda = " +
+                  std::to_string(bad);
+    }
+    if (!msg.empty()) return fail(DIRAC_ESINGULAR, msg);
+    API_END
+}
+
+dirac_status dirac_import(dirac_ctx *c, void *native, const void *user, int sites, dirac_prec pr,
+                          dirac_layout lay, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_prec(pr);
+    require(sites >= 0 && sites <= 2, "sites must be 0, 1 or 2");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO, "user layout must be LEX or EO");
+    const size_t ub = sites == 0 ? (size_t)c->V * 24 * (pr == DIRAC_F32 ? 4 : 8) : (size_t)c->vh * 24 * (pr == DIRAC_F32 ? 4 : 8);
+    check_dev(user, ub, "user");
+    check_dev(native, native_bytes(c, pr, sites), "native");
+    check_no_alias(native, native_bytes(c, pr, sites), user, ub);
+    dl::spinor_import(c, native, user, sites, pr, lay, (hipStream_t)stream);
+    API_END
+}
+
+dirac_status dirac_export(dirac_ctx *c, void *user, const void *native, int sites, dirac_prec pr,
+                          dirac_layout lay, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_prec(pr);
+    require(sites >= 0 && sites <= 2, "sites must be 0, 1 or 2");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO, "user layout must be LEX or EO");
+    const size_t ub = sites == 0 ? (size_t)c->V * 24 * (pr == DIRAC_F32 ? 4 : 8) : (size_t)c->vh * 24 * (pr == DIRAC_F32 ? 4 : 8);
+    check_dev(user, ub, "user");
+    check_dev(native, native_bytes(c, pr, sites), "native");
+    check_no_alias(native, native_bytes(c, pr, sites), user, ub);
+    dl::spinor_export(c, user, native, sites, pr, lay, (hipStream_t)stream);
+    API_END
+}
+
+dirac_status dirac_apply(dirac_ctx *c, void *out, const void *in, dirac_prec pr, dirac_layout lay, int dagger,
+                         void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_prec(pr);
+    check_user_layout(pr, lay);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = lay == DIRAC_LAYOUT_NATIVE ? native_bytes(c, pr, 0) : user_bytes(c, pr, 0);
+    check_dev(in, nb, "in");
+    check_dev(out, nb, "out");
+    check_no_alias(out, nb, in, nb);
+    if (lay == DIRAC_LAYOUT_NATIVE) {
+        dl::full_apply(c, out, in, dagger != 0, pr, s);
+    } else {
+        dl::PrecFields &f = c->f[pr];
+        f.user_in.alloc(native_bytes(c, pr, 0));
+        f.user_out.alloc(native_bytes(c, pr, 0));
+        dl::spinor_import(c, f.user_in.p, in, 0, pr, lay, s);
+        dl::full_apply(c, f.user_out.p, f.user_in.p, dagger != 0, pr, s);
+        dl::spinor_export(c, out, f.user_out.p, 0, pr, lay, s);
+    }
+    API_END
+}
+
+dirac_status dirac_apply_eo(dirac_ctx *c, void *out, const void *in, dirac_prec pr, dirac_layout lay, int dagger,
+                            void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_prec(pr);
+    check_user_layout(pr, lay);
+    require(lay != DIRAC_LAYOUT_LEX, "an even half-vector is defined in the EO or NATIVE layout, not LEX");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = lay == DIRAC_LAYOUT_NATIVE ? native_bytes(c, pr, 1) : user_bytes(c, pr, 1);
+    check_dev(in, nb, "in_e");
+    check_dev(out, nb, "out_e");
+    check_no_alias(out, nb, in, nb);
+    if (lay == DIRAC_LAYOUT_NATIVE) {
+        dl::schur_apply(c, out, in, dagger != 0, pr, s);
+    } else {
+        dl::PrecFields &f = c->f[pr];
+        f.user_in.alloc(native_bytes(c, pr, 0));
+        f.user_out.alloc(native_bytes(c, pr, 0));
+        dl::spinor_import(c, f.user_in.p, in, 1, pr, lay, s);
+        dl::schur_apply(c, f.user_out.p, f.user_in.p, dagger != 0, pr, s);
+        dl::spinor_export(c, out, f.user_out.p, 1, pr, lay, s);
+    }
+    API_END
+}
+
+dirac_status dirac_apply_hop(dirac_ctx *c, void *out, const void *in, int out_parity, dirac_prec pr, int dagger,
+                             void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_prec(pr);
+    const size_t nb = native_bytes(c, pr, 1);
+    check_dev(in, nb, "in");
+    check_dev(out, nb, "out");
+    check_no_alias(out, nb, in, nb);
+    dl::hop_apply(c, out, in, nullptr, out_parity, dl::HOP_PLAIN, -0.5, dagger != 0, pr, (hipStream_t)stream);
+    API_END
+}
+
+dirac_status dirac_apply_clover(dirac_ctx *c, void *out, const void *in, int parity, int inverse, dirac_prec pr,
+                                void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_prec(pr);
+    const size_t nb = native_bytes(c, pr, 1);
+    check_dev(in, nb, "in");
+    check_dev(out, nb, "out");
+    check_no_alias(out, nb, in, nb);
+    dl::clover_apply(c, out, in, parity, inverse != 0, pr, (hipStream_t)stream);
+    API_END
+}
+
+}  // extern "C"

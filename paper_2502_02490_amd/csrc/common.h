@@ -1,0 +1,203 @@
+// Device-side building blocks shared by the HIP kernels: complex arithmetic,
+// storage-precision traits for the 16-byte plane layout, and site geometry.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DEV __device__ __forceinline__
+#define HD __host__ __device__ __forceinline__
+
+// ------------------------------------------------------------------ complex
+template <typename T>
+struct cx {
+    T r, i;
+};
+template <typename T> DEV cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T> DEV cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T> DEV cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T> DEV cx<T> operator-(cx<T> a) { return {-a.r, -a.i}; }
+template <typename T> DEV cx<T> operator*(cx<T> a, cx<T> b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+template <typename T> DEV cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+template <typename T> DEV cx<T> conj(cx<T> a) { return {a.r, -a.i}; }
+template <typename T> DEV cx<T> times_i(cx<T> a) { return {-a.i, a.r}; }      // i a
+template <typename T> DEV cx<T> times_mi(cx<T> a) { return {a.i, -a.r}; }     // -i a
+template <typename T> DEV cx<T> conj_mul(cx<T> a, cx<T> b) { return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r}; }  // conj(a) b
+template <typename T> DEV void madd(cx<T> &acc, cx<T> a, cx<T> b) {  // acc += a b
+    acc.r = fma(a.r, b.r, acc.r); acc.r = fma(-a.i, b.i, acc.r);
+    acc.i = fma(a.r, b.i, acc.i); acc.i = fma(a.i, b.r, acc.i);
+}
+template <typename T> DEV void cmadd(cx<T> &acc, cx<T> a, cx<T> b) {  // acc += conj(a) b
+    acc.r = fma(a.r, b.r, acc.r); acc.r = fma(a.i, b.i, acc.r);
+    acc.i = fma(a.r, b.i, acc.i); acc.i = fma(-a.i, b.r, acc.i);
+}
+
+// ------------------------------------------------------------------ storage precision
+// A field of n reals per site is stored, per parity, as n / W planes of 16-byte
+// vectors: plane k holds reals [k W, (k + 1) W) of every site, site-fastest.
+// Accumulation is FP64 for FP64 storage and FP32 otherwise.
+template <typename S> struct St;
+template <> struct St<double> {
+    using acc = double; using vec = double2; static constexpr int W = 2;
+    static DEV void unpack(const vec &v, acc *o) { o[0] = v.x; o[1] = v.y; }
+    static DEV vec pack(const acc *o) { return make_double2(o[0], o[1]); }
+};
+template <> struct St<float> {
+    using acc = float; using vec = float4; static constexpr int W = 4;
+    static DEV void unpack(const vec &v, acc *o) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
+    static DEV vec pack(const acc *o) { return make_float4(o[0], o[1], o[2], o[3]); }
+};
+template <> struct St<__half> {
+    using acc = float; using vec = uint4; static constexpr int W = 8;
+    static DEV void unpack(const vec &v, acc *o) {
+        const __half2 *h = reinterpret_cast<const __half2 *>(&v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { float2 f = __half22float2(h[k]); o[2 * k] = f.x; o[2 * k + 1] = f.y; }
+    }
+    static DEV vec pack(const acc *o) {
+        vec v;
+        __half2 *h = reinterpret_cast<__half2 *>(&v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) h[k] = __floats2half2_rn(o[2 * k], o[2 * k + 1]);
+        return v;
+    }
+};
+template <> struct St<__hip_bfloat16> {
+    using acc = float; using vec = uint4; static constexpr int W = 8;
+    static DEV void unpack(const vec &v, acc *o) {
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(&v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            o[2 * k] = __uint_as_float(w[k] << 16);
+            o[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+        }
+    }
+    static DEV uint32_t rne(float f) {  // round to nearest even (inputs are finite)
+        uint32_t u = __float_as_uint(f);
+        return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    }
+    static DEV vec pack(const acc *o) {
+        vec v;
+        uint32_t *w = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = rne(o[2 * k]) | (rne(o[2 * k + 1]) << 16);
+        return v;
+    }
+};
+
+// Load / store n reals (n a multiple of W) of site s from planes with stride `vh` vectors.
+// The plane address is uniform across the wavefront and the per-lane part is a 32-bit byte
+// offset, so every access is one scalar-base + vector-offset instruction: no 64-bit address
+// per plane and lane has to be kept in registers.
+template <typename V>
+DEV const V &at_off(const V *__restrict__ plane, uint32_t byte_off) {
+    return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(plane) + byte_off);
+}
+template <typename V>
+DEV V &at_off(V *__restrict__ plane, uint32_t byte_off) {
+    return *reinterpret_cast<V *>(reinterpret_cast<char *>(plane) + byte_off);
+}
+template <typename S, int N>
+DEV void load_planes(const typename St<S>::vec *__restrict__ base, size_t vh, uint32_t s, typename St<S>::acc *o) {
+    using V = typename St<S>::vec;
+    constexpr int W = St<S>::W;
+    const uint32_t off = s * (uint32_t)sizeof(V);
+#pragma unroll
+    for (int k = 0; k < N / W; ++k) St<S>::unpack(at_off(base + k * vh, off), o + k * W);
+}
+template <typename S, int N>
+DEV void store_planes(typename St<S>::vec *__restrict__ base, size_t vh, uint32_t s, const typename St<S>::acc *o) {
+    using V = typename St<S>::vec;
+    constexpr int W = St<S>::W;
+    const uint32_t off = s * (uint32_t)sizeof(V);
+#pragma unroll
+    for (int k = 0; k < N / W; ++k) at_off(base + k * vh, off) = St<S>::pack(o + k * W);
+}
+
+// ------------------------------------------------------------------ geometry
+// Site of parity p with half index i: i = ((x0 L1 + x1) L2 + x2) (L3/2) + floor(x3/2),
+// which is floor(Lambda / 2) (eq. (lexi) with x3 fastest).
+struct Geom {
+    int L[4];
+    int h3;   // L3 / 2
+    int vh;   // V / 2
+};
+
+DEV void site_coords(const Geom &g, int i, int p, int x[4]) {
+    int h = i % g.h3;
+    int r = i / g.h3;
+    x[2] = r % g.L[2];
+    r /= g.L[2];
+    x[1] = r % g.L[1];
+    x[0] = r / g.L[1];
+    x[3] = 2 * h + ((x[0] + x[1] + x[2] + p) & 1);
+}
+DEV int half_index(const Geom &g, const int x[4]) {
+    return ((x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.h3 + (x[3] >> 1);
+}
+DEV int lex_index(const Geom &g, const int x[4]) {
+    return ((x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
+}
+DEV void lex_coords(const Geom &g, int lam, int x[4]) {
+    x[3] = lam % g.L[3];
+    int r = lam / g.L[3];
+    x[2] = r % g.L[2];
+    r /= g.L[2];
+    x[1] = r % g.L[1];
+    x[0] = r / g.L[1];
+}
+DEV int wrap_up(int v, int L) { return v + 1 == L ? 0 : v + 1; }
+DEV int wrap_dn(int v, int L) { return v == 0 ? L - 1 : v - 1; }
+
+// Work-group order that gives each XCD a contiguous range of sites: dispatch sends
+// work-group b to XCD b mod 8, so logical block (b mod 8) * (nb8 / 8) + b / 8 keeps
+// neighbouring tiles (and their shared neighbour reads) in one XCD's L2.
+DEV int xcd_block(int nb8) {
+    int b = blockIdx.x;
+    return (b & 7) * (nb8 >> 3) + (b >> 3);
+}
+
+// ------------------------------------------------------------------ link storage
+// A link is 12 reals (rows 0 and 1 of the SU(3) matrix, row-major, (re, im)) in
+// 12 / W planes of `vec`, plus one angle omega of type `om`.
+template <typename S> struct Lk;
+template <> struct Lk<double> {
+    using vec = double2; using om = double; using acc = double; static constexpr int W = 2;
+    static DEV void unpack(const vec &v, acc *o) { o[0] = v.x; o[1] = v.y; }
+    static DEV vec pack(const double *o) { return make_double2(o[0], o[1]); }
+};
+template <> struct Lk<float> {
+    using vec = float4; using om = float; using acc = float; static constexpr int W = 4;
+    static DEV void unpack(const vec &v, acc *o) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
+    static DEV vec pack(const double *o) { return make_float4((float)o[0], (float)o[1], (float)o[2], (float)o[3]); }
+};
+template <> struct Lk<__half> {
+    using vec = uint2; using om = float; using acc = float; static constexpr int W = 4;
+    static DEV void unpack(const vec &v, acc *o) {
+        const __half2 *h = reinterpret_cast<const __half2 *>(&v);
+        float2 a = __half22float2(h[0]), b = __half22float2(h[1]);
+        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+    }
+    static DEV vec pack(const double *o) {
+        vec v;
+        __half2 *h = reinterpret_cast<__half2 *>(&v);
+        h[0] = __floats2half2_rn((float)o[0], (float)o[1]);
+        h[1] = __floats2half2_rn((float)o[2], (float)o[3]);
+        return v;
+    }
+};
+template <> struct Lk<__hip_bfloat16> {
+    using vec = uint2; using om = float; using acc = float; static constexpr int W = 4;
+    static DEV void unpack(const vec &v, acc *o) {
+        o[0] = __uint_as_float(v.x << 16); o[1] = __uint_as_float(v.x & 0xffff0000u);
+        o[2] = __uint_as_float(v.y << 16); o[3] = __uint_as_float(v.y & 0xffff0000u);
+    }
+    static DEV vec pack(const double *o) {
+        vec v;
+        v.x = St<__hip_bfloat16>::rne((float)o[0]) | (St<__hip_bfloat16>::rne((float)o[1]) << 16);
+        v.y = St<__hip_bfloat16>::rne((float)o[2]) | (St<__hip_bfloat16>::rne((float)o[3]) << 16);
+        return v;
+    }
+};

@@ -1,0 +1,246 @@
+// Hopping term between parities, fused with the clover field, and the even-odd
+// Schur and full operators built from it (one thread per output site).
+//
+//   H psi(x) = sum_mu [ V_mu(x) b+ (1 - gamma_mu) psi(x + mu) + V_mu(x - mu)^dag b- (1 + gamma_mu) psi(x - mu) ]
+//
+// For each of the 8 neighbours the kernel loads the neighbour's spinor, projects it to a
+// half-spinor, multiplies by the link (two stored rows, third rebuilt, phase exp(+-i omega)),
+// and accumulates the reconstructed spinor.  The dagger, gamma_5 H gamma_5, flips the
+// projector signs.  Epilogues: HOP_INV applies A_pp^-1 to the result, HOP_CLOV adds A_pp chi.
+#include "dirac_ops.h"
+#include "internal.h"
+
+namespace dl {
+namespace {
+
+template <typename S>
+struct HopArgs {
+    Geom g;
+    int p;           // output parity
+    int nb8;         // work-groups launched (multiple of 8), for the XCD-contiguous order
+    const typename St<S>::vec *in;     // parity 1 - p, 24 reals per site
+    const typename Lk<S>::vec *links;  // parity p, [8 dir][12 / W][vh]
+    const typename Lk<S>::om *omega;   // parity p, [8 dir][vh]
+    const typename St<S>::vec *clov;   // parity p, 72 reals: A (HOP_CLOV) or A^-1 (HOP_INV)
+    const typename St<S>::vec *chi;    // parity p (HOP_CLOV)
+    typename St<S>::vec *out;          // parity p
+    typename St<S>::acc coef;
+};
+
+template <typename S>
+DEV void load_spinor(const typename St<S>::vec *__restrict__ base, size_t vh, uint32_t s, C<typename St<S>::acc> psi[12]) {
+    using T = typename St<S>::acc;
+    T r[24];
+    load_planes<S, 24>(base, vh, s, r);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = mk(r[2 * k], r[2 * k + 1]);
+}
+
+template <typename S>
+DEV void load_link(const HopArgs<S> &a, int dir, uint32_t i, C<typename St<S>::acc> u[6], typename St<S>::acc &co,
+                   typename St<S>::acc &si) {
+    using T = typename St<S>::acc;
+    using LV = typename Lk<S>::vec;
+    using OM = typename Lk<S>::om;
+    constexpr int W = Lk<S>::W;
+    const size_t vh = (size_t)a.g.vh;
+    const LV *b = a.links + (size_t)dir * (12 / W) * vh;
+    T r[12];
+#pragma unroll
+    for (int k = 0; k < 12 / W; ++k) Lk<S>::unpack(at_off(b + k * vh, i * (uint32_t)sizeof(LV)), r + k * W);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) u[k] = mk(r[2 * k], r[2 * k + 1]);
+    const T w = (T)at_off(a.omega + (size_t)dir * vh, i * (uint32_t)sizeof(OM));
+    sc(w, si, co);
+}
+
+// Spin structure of gamma_mu = [[0, e_mu], [e_mu^dag, 0]]: e_mu is monomial, row k has its
+// one entry c_k in column p_k, with p_1 = 1 - p_0.  Per mu: (p_0, c_0, c_1), c in {+-1, +-i}:
+//   e_0 = -1: (0, -1, -1)   e_1 = -i sigma_1: (1, -i, -i)
+//   e_2 = -i sigma_2: (1, -1, +1)   e_3 = -i sigma_3: (0, -i, +i)
+// so (e l)_k = c_k l_{p_k} and (e^dag w)_{p_k} = conj(c_k) w_k.
+template <typename T>
+DEV C<T> cmul_unit(T cr, T ci, C<T> z) { return mk(cr * z.r - ci * z.i, cr * z.i + ci * z.r); }
+
+// The 8 neighbours (n = 2 mu + back) run as iterations of a loop that is not unrolled, with
+// the direction a uniform run-time value: straight-line code lets the compiler issue the
+// loads of all eight neighbours up front, which needs more registers than a lane has
+// (spills, one wave per SIMD).  The loop keeps one neighbour's data live at a time.
+template <typename S, int DAG>
+DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<S>::acc> acc[12]) {
+    using T = typename St<S>::acc;
+    const size_t vh = (size_t)a.g.vh;
+    const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
+#pragma nounroll
+    for (int n = 0; n < 8; ++n) {
+        const int mu = n >> 1, back = n & 1;
+        const int xm = mu == 0 ? x[0] : mu == 1 ? x[1] : mu == 2 ? x[2] : x[3];
+        const int Lm = mu == 0 ? a.g.L[0] : mu == 1 ? a.g.L[1] : mu == 2 ? a.g.L[2] : a.g.L[3];
+        const int xn = back ? (xm == 0 ? Lm - 1 : xm - 1) : (xm + 1 == Lm ? 0 : xm + 1);
+        const int rs = mu == 0 ? a.g.L[1] * a.g.L[2] : mu == 1 ? a.g.L[2] : 1;
+        const uint32_t j = mu == 3 ? (uint32_t)(row * a.g.h3 + (xn >> 1))
+                                   : (uint32_t)((row + (xn - xm) * rs) * a.g.h3 + (x[3] >> 1));
+        // projector sign: forward (1 + SF gamma), backward (1 - SF gamma); SF = -1 for D, +1 for D^dag
+        const T sg = (DAG ? T(1) : T(-1)) * (back ? T(-1) : T(1));
+        const int sw = (mu == 1 || mu == 2);
+        const T c0r = (mu == 0 || mu == 2) ? T(-1) : T(0), c0i = (mu == 1 || mu == 3) ? T(-1) : T(0);
+        const T c1r = mu == 0 ? T(-1) : mu == 2 ? T(1) : T(0), c1i = mu == 1 ? T(-1) : mu == 3 ? T(1) : T(0);
+        C<T> psi[12], h[6], u[6], w[6];
+        T co, si;
+        load_spinor<S>(a.in, vh, j, psi);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const C<T> l0 = psi[6 + c], l1 = psi[9 + c];
+            const C<T> e0 = cmul_unit(c0r, c0i, sw ? l1 : l0);
+            const C<T> e1 = cmul_unit(c1r, c1i, sw ? l0 : l1);
+            h[c] = mk(fma(sg, e0.r, psi[c].r), fma(sg, e0.i, psi[c].i));
+            h[3 + c] = mk(fma(sg, e1.r, psi[3 + c].r), fma(sg, e1.i, psi[3 + c].i));
+        }
+        load_link(a, n, i, u, co, si);
+        if (back) link_adj_mul(u, co, si, h, w);
+        else link_mul(u, co, si, h, w);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[c] = acc[c] + w[c];
+            acc[3 + c] = acc[3 + c] + w[3 + c];
+            const C<T> t0 = cmul_unit(c0r, -c0i, w[c]);      // conj(c_0) w_0 -> lower spin p_0
+            const C<T> t1 = cmul_unit(c1r, -c1i, w[3 + c]);  // conj(c_1) w_1 -> lower spin p_1
+            const C<T> l0 = sw ? t1 : t0, l1 = sw ? t0 : t1;
+            acc[6 + c] = mk(fma(sg, l0.r, acc[6 + c].r), fma(sg, l0.i, acc[6 + c].i));
+            acc[9 + c] = mk(fma(sg, l1.r, acc[9 + c].r), fma(sg, l1.i, acc[9 + c].i));
+        }
+    }
+}
+
+template <typename S, int DAG, int MODE, int XCD>
+__global__ __launch_bounds__(kBlock) void k_hop(HopArgs<S> a) {
+    using T = typename St<S>::acc;
+    const int blk = XCD ? xcd_block(a.nb8) : (int)blockIdx.x;
+    const int ii = blk * kBlock + threadIdx.x;
+    if (ii >= a.g.vh) return;
+    const uint32_t i = (uint32_t)ii;
+    const size_t vh = (size_t)a.g.vh;
+    int x[4];
+    site_coords(a.g, ii, a.p, x);
+    C<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = mk(T(0), T(0));
+    hop_all<S, DAG>(a, x, i, acc);
+    C<T> y[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) y[k] = a.coef * acc[k];
+    if constexpr (MODE == HOP_INV) {
+        T pk[36];
+        C<T> t[6];
+        load_planes<S, 36>(a.clov, vh, i, pk);
+        block_mul(pk, y, t);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) y[k] = t[k];
+        load_planes<S, 36>(a.clov + 36 / St<S>::W * vh, vh, i, pk);
+        block_mul(pk, y + 6, t);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) y[6 + k] = t[k];
+    } else if constexpr (MODE == HOP_CLOV) {
+        C<T> chi[12], t[6];
+        T pk[36];
+        load_spinor<S>(a.chi, vh, i, chi);
+        load_planes<S, 36>(a.clov, vh, i, pk);
+        block_mul(pk, chi, t);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) y[k] = y[k] + t[k];
+        load_planes<S, 36>(a.clov + 36 / St<S>::W * vh, vh, i, pk);
+        block_mul(pk, chi + 6, t);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) y[6 + k] = y[6 + k] + t[k];
+    }
+    T r[24];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) { r[2 * k] = y[k].r; r[2 * k + 1] = y[k].i; }
+    store_planes<S, 24>(a.out, vh, i, r);
+}
+
+bool use_xcd_order() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("DIRAC_XCD_ORDER");
+        v = e ? atoi(e) != 0 : 1;
+    }
+    return v != 0;
+}
+
+template <typename S, int DAG, int MODE>
+void launch_hop(HopArgs<S> a, hipStream_t s) {
+    if (use_xcd_order()) {
+        a.nb8 = grid_xcd(a.g.vh);
+        k_hop<S, DAG, MODE, 1><<<a.nb8, kBlock, 0, s>>>(a);
+    } else {
+        a.nb8 = grid_for(a.g.vh);
+        k_hop<S, DAG, MODE, 0><<<a.nb8, kBlock, 0, s>>>(a);
+    }
+}
+
+template <typename S>
+void hop_t(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopMode mode, double coef, int dagger,
+           dirac_prec pr, hipStream_t s) {
+    PrecFields &f = c->f[pr];
+    HopArgs<S> a;
+    a.g = c->g;
+    a.p = p;
+    a.nb8 = 0;
+    a.in = (const typename St<S>::vec *)in;
+    a.links = (const typename Lk<S>::vec *)f.links[p].p;
+    a.omega = (const typename Lk<S>::om *)f.omega[p].p;
+    a.clov = (const typename St<S>::vec *)(mode == HOP_INV ? f.clinv[p].p : mode == HOP_CLOV ? f.clov[p].p : nullptr);
+    a.chi = (const typename St<S>::vec *)chi;
+    a.out = (typename St<S>::vec *)out;
+    a.coef = (typename St<S>::acc)coef;
+    if (dagger) {
+        if (mode == HOP_PLAIN) launch_hop<S, 1, HOP_PLAIN>(a, s);
+        else if (mode == HOP_INV) launch_hop<S, 1, HOP_INV>(a, s);
+        else launch_hop<S, 1, HOP_CLOV>(a, s);
+    } else {
+        if (mode == HOP_PLAIN) launch_hop<S, 0, HOP_PLAIN>(a, s);
+        else if (mode == HOP_INV) launch_hop<S, 0, HOP_INV>(a, s);
+        else launch_hop<S, 0, HOP_CLOV>(a, s);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace
+
+void hop_apply(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopMode mode, double coef, int dagger,
+               dirac_prec pr, hipStream_t s) {
+    require(p == 0 || p == 1, "parity must be 0 (even) or 1 (odd)");
+    ensure_prec(c, pr, s);
+    PrecFields &f = c->f[pr];
+    require(mode != HOP_INV || f.inv_ready[p], "clover inverse of this parity not computed; call clover_invert");
+    switch (pr) {
+        case DIRAC_F64: hop_t<double>(c, out, in, chi, p, mode, coef, dagger, pr, s); break;
+        case DIRAC_F32: hop_t<float>(c, out, in, chi, p, mode, coef, dagger, pr, s); break;
+        case DIRAC_F16: hop_t<__half>(c, out, in, chi, p, mode, coef, dagger, pr, s); break;
+        case DIRAC_BF16: hop_t<__hip_bfloat16>(c, out, in, chi, p, mode, coef, dagger, pr, s); break;
+        default: throw Error(DIRAC_EINVAL, "unknown precision");
+    }
+}
+
+// D-hat in_e = A_ee in_e - D_eo A_oo^-1 D_oe in_e, D_eo = -H_eo / 2:
+//   t_o = A_oo^-1 (-1/2 H_oe in_e);   out_e = A_ee in_e + 1/2 H_eo t_o
+void schur_apply(dirac_ctx *c, void *out_e, const void *in_e, int dagger, dirac_prec pr, hipStream_t s) {
+    ensure_prec(c, pr, s);
+    PrecFields &f = c->f[pr];
+    require(f.inv_ready[1], "odd-site clover inverse not available (clover_invert failed or was not run)");
+    f.tmp_half.alloc((size_t)24 * real_size(pr) * c->vh);
+    hop_apply(c, f.tmp_half.p, in_e, nullptr, 1, HOP_INV, -0.5, dagger, pr, s);
+    hop_apply(c, out_e, f.tmp_half.p, in_e, 0, HOP_CLOV, 0.5, dagger, pr, s);
+}
+
+// D in: out_p = A_pp in_p - 1/2 H in_{1-p} for both parities (NATIVE full vectors).
+void full_apply(dirac_ctx *c, void *out, const void *in, int dagger, dirac_prec pr, hipStream_t s) {
+    const size_t hb = (size_t)24 * real_size(pr) * c->vh;
+    const char *ie = (const char *)in, *io = ie + hb;
+    char *oe = (char *)out, *oo = oe + hb;
+    hop_apply(c, oe, io, ie, 0, HOP_CLOV, -0.5, dagger, pr, s);
+    hop_apply(c, oo, ie, io, 1, HOP_CLOV, -0.5, dagger, pr, s);
+}
+
+}  // namespace dl

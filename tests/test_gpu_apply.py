@@ -1,0 +1,168 @@
+"""GPU parity of the operator kernels against the FP64 oracle, through the C ABI.
+
+Bars: FP64 apply relative error <= 1e-13, FP32 <= 1e-6 (element-wise comparisons on the same
+seeded inputs).  Lattices span one tile (2^4), several tiles with a ragged tail (6x6x6x10:
+V/2 = 1080 sites, 4 full work-groups of 256 and a partial one), mixed extents, and the
+32^3 x 64 production shape on sampled output sites."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import Case, flush, need_gpu, rel, to_dev
+from oracle import dirac as odirac
+from oracle import geometry as geo
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(2, 2, 2, 2), (4, 4, 4, 4), (2, 4, 6, 8), (6, 6, 6, 10), (8, 4, 4, 12)]
+
+
+@pytest.fixture(scope="module", params=SHAPES, ids=lambda d: "x".join(map(str, d)))
+def case(request):
+    need_gpu()
+    flush(f"[gpu] case dims={request.param}")
+    phase = (math.pi, 0.3, -0.8, 1.3) if request.param == (2, 4, 6, 8) else (math.pi, 0.0, 0.0, 0.0)
+    qhat = 2 if request.param == (6, 6, 6, 10) else -1
+    c = Case(request.param, qhat=qhat, bc_phase=phase, seed=301 + sum(request.param))
+    yield c
+    c.D.close()
+
+
+def test_clover_field_matches_oracle(case):
+    got = case.D.clover().cpu().numpy()
+    exp = odirac.pack_clover(case.f.clover())
+    assert np.abs(got - exp).max() <= 1e-13 * np.abs(exp).max()
+
+
+def test_clover_inverse_matches_oracle(case):
+    case.D.clover_invert(3)
+    got = case.D.clover(inverse=True).cpu().numpy()
+    exp = odirac.pack_clover(case.f.clover_inv())
+    assert np.abs(got - exp).max() <= 1e-13 * np.abs(exp).max()
+
+
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_full_apply_f64_lex(case, dagger):
+    psi = case.spinor(11)
+    out = torch.empty_like(to_dev(psi))
+    case.D.apply(out, to_dev(psi), "f64", "lex", dagger=bool(dagger))
+    exp = odirac.apply_Ddag(case.f, psi) if dagger else odirac.apply_D(case.f, psi)
+    assert rel(out.cpu().numpy(), exp) <= 1e-13
+
+
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_schur_apply_f64_eo(case, dagger):
+    psi_e = case.spinor(12)[case.even]  # EO order = even sites by ascending Lambda
+    out = torch.empty_like(to_dev(psi_e))
+    case.D.apply_eo(out, to_dev(psi_e), "f64", "eo", dagger=bool(dagger))
+    exp = odirac.apply_schur_dag(case.f, psi_e) if dagger else odirac.apply_schur(case.f, psi_e)
+    assert rel(out.cpu().numpy(), exp) <= 1e-13
+
+
+def test_hop_and_clover_native(case):
+    D = case.D
+    psi = case.spinor(13)
+    nat = D.to_native(to_dev(psi), "f64", "lex")
+    half = nat.numel() // 2
+    ev, od = nat[:half], nat[half:]
+    out = D.native_empty("f64", 1)
+    # D_oe psi_e, exported as the odd half of an EO vector
+    D.apply_hop(out, ev, 1, "f64")
+    got = D.from_native(out, "f64", "eo", sites=2).cpu().numpy()
+    assert rel(got, odirac.apply_Doe(case.f, psi[case.even])) <= 1e-13
+    D.apply_hop(out, od, 0, "f64", dagger=True)
+    got = D.from_native(out, "f64", "eo", sites=1).cpu().numpy()
+    g5 = np.array([1, 1, -1, -1])[None, :, None]
+    assert rel(got, g5 * odirac.apply_Deo(case.f, g5 * psi[case.odd])) <= 1e-13
+    D.clover_invert(3)
+    for par, sites in ((0, case.even), (1, case.odd)):
+        src = ev if par == 0 else od
+        for inv in (False, True):
+            D.apply_clover(out, src, par, inverse=inv, prec="f64")
+            got = D.from_native(out, "f64", "eo", sites=1 + par).cpu().numpy()
+            assert rel(got, odirac.apply_clover(case.f, psi[sites], par, inverse=inv)) <= 1e-13
+
+
+def test_layout_round_trip_is_exact(case):
+    D = case.D
+    psi = to_dev(case.spinor(14))
+    for lay in ("lex", "eo"):
+        back = D.from_native(D.to_native(psi, "f64", lay), "f64", lay)
+        assert torch.equal(back, psi)
+    # EO export of a LEX import reorders by eq. (ipt) with one block
+    eo = D.from_native(D.to_native(psi, "f64", "lex"), "f64", "eo").cpu().numpy()
+    perm = geo.lex_to_eo_perm(case.dims)
+    assert np.array_equal(eo, psi.cpu().numpy()[perm])
+
+
+def test_full_apply_f32(case):
+    psi = case.spinor(15)
+    inp = to_dev(psi.astype(np.complex64))
+    out = torch.empty_like(inp)
+    case.D.apply(out, inp, "f32", "lex")
+    exp = odirac.apply_D(case.f, psi.astype(np.complex64).astype(np.complex128))
+    assert rel(out.cpu().numpy(), exp) <= 1e-6
+
+
+def test_schur_apply_f32_native(case):
+    D = case.D
+    psi_e = case.spinor(16)[case.even]
+    nat = D.to_native(to_dev(psi_e.astype(np.complex64)), "f32", "eo", sites=1)
+    out = D.native_empty("f32", 1)
+    D.apply_eo(out, nat, "f32", "native")
+    got = D.from_native(out, "f32", "eo", sites=1).cpu().numpy()
+    exp = odirac.apply_schur(case.f, psi_e.astype(np.complex64).astype(np.complex128))
+    assert rel(got, exp) <= 1e-6
+
+
+@pytest.mark.parametrize("prec,bound", [("f16", 5e-3), ("bf16", 4e-2)])
+def test_schur_apply_half_precision_storage(case, prec, bound):
+    """16-bit storage with FP32 arithmetic: the error is set by the storage rounding
+    (unit roundoff 2^-11 for FP16, 2^-8 for BF16) of links, clover and spinors."""
+    D = case.D
+    psi_e = case.spinor(17)[case.even]
+    nat = D.to_native(to_dev(psi_e), prec, "eo", sites=1)
+    out = D.native_empty(prec, 1)
+    D.apply_eo(out, nat, prec, "native")
+    got = D.from_native(out, prec, "eo", sites=1).cpu().numpy()
+    err = rel(got, odirac.apply_schur(case.f, psi_e))
+    flush(f"[gpu] {prec} Schur relative error {err:.2e} dims={case.dims}")
+    assert err <= bound
+
+
+def test_repeat_is_bitwise_identical(case):
+    psi_e = to_dev(case.spinor(18)[case.even])
+    a, b = torch.empty_like(psi_e), torch.empty_like(psi_e)
+    case.D.apply_eo(a, psi_e)
+    case.D.apply_eo(b, psi_e)
+    assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------- production shape, sampled
+@pytest.mark.parametrize("qhat", [-1, 2])
+def test_schur_32c64_sampled_sites(qhat):
+    """32^3 x 64 (config shape of the plain-method solve): the whole Schur apply on the GPU,
+    checked at 64 sampled even sites, each recomputed by the oracle from the definition."""
+    need_gpu()
+    flush(f"[gpu] 32^3x64 Schur sampled qhat={qhat}")
+    c = Case((64, 32, 32, 32), qhat=qhat, seed=201)
+    try:
+        psi_e = c.spinor(21)[c.even]
+        out = torch.empty_like(to_dev(psi_e))
+        c.D.apply_eo(out, to_dev(psi_e), "f64", "eo")
+        got = out.cpu().numpy()
+        rng = np.random.default_rng(qhat + 5)
+        pick = np.concatenate([[0, len(c.even) - 1], rng.choice(len(c.even), 62, replace=False)])
+        exp = odirac.schur_at(c.f, psi_e, c.even[pick])
+        assert rel(got[pick], exp) <= 1e-13
+        # FP32 at the same sites
+        nat = c.D.to_native(to_dev(psi_e.astype(np.complex64)), "f32", "eo", sites=1)
+        o32 = c.D.native_empty("f32", 1)
+        c.D.apply_eo(o32, nat, "f32", "native")
+        g32 = c.D.from_native(o32, "f32", "eo", sites=1).cpu().numpy()
+        exp32 = odirac.schur_at(c.f, psi_e.astype(np.complex64).astype(np.complex128), c.even[pick])
+        assert rel(g32[pick], exp32) <= 1e-6
+    finally:
+        c.D.close()
