@@ -1,0 +1,196 @@
+"""Benchmark of the even-odd Schur Dirac apply (and the solves built on it) on one MI355X.
+
+Workload: 32^3 x 64 lattice, synthetic SU(3) x U(1) fields (eps = 0.5, theta in (-0.3, 0.3)),
+kappa = 0.1245, c_sw = 1.6, c_sw^QED = 1.0, qhat = -1, antiperiodic time.  One step is one
+application of the even-odd Schur operator D-hat in FP64 on the NATIVE layout, inputs resident
+in HBM.  Prints one JSON line on stdout; diagnostics go to stderr.
+
+Algorithmic bytes (each field read once, output written once, links as 12 reals + 1 angle):
+  Schur D-hat   472 reals per even site  (3776 B in FP64, 1888 B in FP32)
+  hop + A_ee chi (second Schur kernel)  248 reals per site (1984 B FP64)
+  hop + A_oo^-1  (first Schur kernel)   224 reals per site (1792 B FP64)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DIMS = (64, 32, 32, 32)  # (L0 = time, L1, L2, L3)
+KAPPA, CSW, CSW_QED, QHAT, EPS, SEED = 0.1245, 1.6, 1.0, -1, 0.5, 201
+SCHUR_REALS, CLOV_HOP_REALS, INV_HOP_REALS = 472, 248, 224
+FLOP_SCHUR, FLOP_HOP, FLOP_CLOVER = 3672, 1320, 504
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(fn, n, stream):
+    import torch
+
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(n):
+        fn()
+    stop.record(stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) / 1e3  # seconds
+
+
+def cpu_baseline(reps: int = 3):
+    """The oracle's D-hat (FP64, numpy, one thread) on a 16^4 lattice with the same parameters and
+    field recipe: the same per-site work as the 32^3 x 64 workload on 1/32 of its volume.  As for
+    the GPU, the clover field and its inverse are set-up work outside the timed applies."""
+    import numpy as np
+
+    import gen
+    from oracle import dirac as odirac
+
+    dims = (16, 16, 16, 16)
+    f = odirac.Fields(gen.su3_field(dims, EPS, SEED), gen.u1_field(dims, 0.3, SEED),
+                      odirac.Params(dims, KAPPA, CSW, CSW_QED, QHAT))
+    ev, _ = odirac.even_odd(f)
+    f.clover()
+    f.clover_inv()
+    psi_e = gen.gaussian_spinor(dims, SEED)[ev]
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        odirac.apply_schur(f, psi_e)
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": round(len(ev) * SCHUR_REALS * 8 / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle D-hat (FP64) on a 16^4 lattice with the 32^3x64 parameters (same per-site work, "
+                      f"1/32 of the volume), mean of {reps} applies, {dt:.2f} s each, clover set-up excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the operator runs on a single MI355X (multi-GPU halo exchange is "
+              "designed, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2502_02490_amd as P
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    U = gen.su3_field(DIMS, EPS, SEED)
+    th = gen.u1_field(DIMS, 0.3, SEED)
+    psi = gen.gaussian_spinor(DIMS, SEED)
+    log(f"[bench] fields generated in {time.perf_counter() - t0:.1f} s")
+    V = math.prod(DIMS)
+    vh = V // 2
+    D = P.Dirac(torch.from_numpy(U).cuda(), torch.from_numpy(th).cuda(), DIMS, KAPPA, CSW, CSW_QED, QHAT)
+    x = D.to_native(torch.from_numpy(psi).cuda(), "f64", "lex")
+    xe = x[: x.numel() // 2].clone()
+    ye = torch.empty_like(xe)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K Schur applies (FP64, NATIVE)
+    schur = lambda: D.apply_eo(ye, xe, "f64", "native")  # noqa: E731
+    for _ in range(args.warmup):
+        schur()
+    torch.cuda.synchronize()
+    t_schur = timed(schur, args.steps, stream)
+    torch.cuda.synchronize()
+    ms = t_schur / args.steps * 1e3
+    gbs = SCHUR_REALS * 8 * vh * args.steps / t_schur / 1e9
+    log(f"[bench] Schur FP64: {ms * 1e3:.1f} us/apply, {gbs:.0f} GB/s")
+
+    # ---- dominant kernel alone: the hop + A chi kernel, two launches per full-D apply
+    full = lambda: D.apply(y, x, "f64", "native")  # noqa: E731
+    for _ in range(5):
+        full()
+    t_full = timed(full, args.steps, stream)
+    k_dur = t_full / (2 * args.steps)
+    k_gbs = CLOV_HOP_REALS * 8 * vh / k_dur / 1e9
+    log(f"[bench] hop+clover kernel FP64: {k_dur * 1e6:.1f} us/launch, {k_gbs:.0f} GB/s")
+
+    extra = {}
+    # FP32 Schur
+    x32 = D.to_native(torch.from_numpy(psi.astype(np.complex64)).cuda(), "f32", "lex")
+    xe32 = x32[: x32.numel() // 2].clone()
+    ye32 = torch.empty_like(xe32)
+    s32 = lambda: D.apply_eo(ye32, xe32, "f32", "native")  # noqa: E731
+    for _ in range(5):
+        s32()
+    t32 = timed(s32, args.steps, stream)
+    extra["schur_f32_GBps"] = round(SCHUR_REALS * 4 * vh * args.steps / t32 / 1e9, 1)
+    extra["schur_f32_us"] = round(t32 / args.steps * 1e6, 1)
+    for pr in ("f16", "bf16"):
+        xh = D.to_native(torch.from_numpy(psi).cuda(), pr, "lex")
+        xeh = xh[: xh.numel() // 2].clone()
+        yeh = torch.empty_like(xeh)
+        sh = lambda: D.apply_eo(yeh, xeh, pr, "native")  # noqa: E731
+        for _ in range(5):
+            sh()
+        th_ = timed(sh, args.steps, stream)
+        extra[f"schur_{pr}_GBps"] = round(SCHUR_REALS * 2 * vh * args.steps / th_ / 1e9, 1)
+        extra[f"schur_{pr}_us"] = round(th_ / args.steps * 1e6, 1)
+    # standalone hop and clover (FP64)
+    ho = torch.empty_like(xe)
+    hop = lambda: D.apply_hop(ho, xe, 1, "f64")  # noqa: E731
+    for _ in range(5):
+        hop()
+    th_ = timed(hop, args.steps, stream)
+    extra["hop_f64_GBps"] = round(152 * 8 * vh * args.steps / th_ / 1e9, 1)
+    cl = lambda: D.apply_clover(ho, xe, 0, False, "f64")  # noqa: E731
+    for _ in range(5):
+        cl()
+    tc = timed(cl, args.steps, stream)
+    extra["clover_f64_GBps"] = round(120 * 8 * vh * args.steps / tc / 1e9, 1)
+    log(f"[bench] extra {extra}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline()
+        log(f"[bench] cpu baseline {cpu}")
+
+    out = {
+        "metric": "Dirac apply GB/s & %HBM roofline (even-odd Schur D-hat, FP64)",
+        "value": round(gbs, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "32^3x64 even-odd Schur apply, FP64, NATIVE layout", "lattice": "64x32x32x32",
+                   "kappa": KAPPA, "csw": CSW, "csw_qed": CSW_QED, "qhat": QHAT, "eps": EPS},
+        "roofline": {"bound": "hbm", "achieved": round(k_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_hop<double, dagger 0, HOP_CLOV> (A_pp chi - H/2 psi)",
+                     "bytes_per_launch": CLOV_HOP_REALS * 8 * vh, "us_per_launch": round(k_dur * 1e6, 2)},
+        "schur_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+        "gflops_schur": round(FLOP_SCHUR * vh * args.steps / t_schur / 1e9, 1),
+        **extra,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    D.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -129,29 +129,34 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs<S> a) {
     C<T> y[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) y[k] = a.coef * acc[k];
-    if constexpr (MODE == HOP_INV) {
-        T pk[36];
-        C<T> t[6];
-        load_planes<S, 36>(a.clov, vh, i, pk);
-        block_mul(pk, y, t);
+    if constexpr (MODE != HOP_PLAIN) {
+        // 72 packed reals per site: block + (spins 0, 1) then block - (spins 2, 3).  With 8 reals
+        // per plane (16-bit storage) the two blocks share a plane, so all 72 are loaded at once;
+        // otherwise one block at a time.
+        constexpr int W = St<S>::W;
+        constexpr bool split = (36 % W) == 0;
+        T pk[split ? 36 : 72];
+        C<T> t[6], chi[12];
+        if constexpr (MODE == HOP_CLOV) load_spinor<S>(a.chi, vh, i, chi);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) y[k] = t[k];
-        load_planes<S, 36>(a.clov + 36 / St<S>::W * vh, vh, i, pk);
-        block_mul(pk, y + 6, t);
+        for (int blk = 0; blk < 2; ++blk) {
+            const T *q = pk;
+            if constexpr (split) {
+                load_planes<S, 36>(a.clov + blk * (36 / W) * vh, vh, i, pk);
+            } else {
+                if (blk == 0) load_planes<S, 72>(a.clov, vh, i, pk);
+                q = pk + 36 * blk;
+            }
+            if constexpr (MODE == HOP_INV) {
+                block_mul(q, y + 6 * blk, t);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) y[6 + k] = t[k];
-    } else if constexpr (MODE == HOP_CLOV) {
-        C<T> chi[12], t[6];
-        T pk[36];
-        load_spinor<S>(a.chi, vh, i, chi);
-        load_planes<S, 36>(a.clov, vh, i, pk);
-        block_mul(pk, chi, t);
+                for (int k = 0; k < 6; ++k) y[6 * blk + k] = t[k];
+            } else {
+                block_mul(q, chi + 6 * blk, t);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) y[k] = y[k] + t[k];
-        load_planes<S, 36>(a.clov + 36 / St<S>::W * vh, vh, i, pk);
-        block_mul(pk, chi + 6, t);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) y[6 + k] = y[6 + k] + t[k];
+                for (int k = 0; k < 6; ++k) y[6 * blk + k] = y[6 * blk + k] + t[k];
+            }
+        }
     }
     T r[24];
 #pragma unroll
