@@ -1,6 +1,8 @@
 // C ABI entry points (include/dirac.h): argument validation, context lifetime,
 // staging between the user layouts and the NATIVE layout, status codes.
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -304,6 +306,47 @@ dirac_status dirac_apply_clover(dirac_ctx *c, void *out, const void *in, int par
     check_dev(out, nb, "out");
     check_no_alias(out, nb, in, nb);
     dl::clover_apply(c, out, in, parity, inverse != 0, pr, (hipStream_t)stream);
+    API_END
+}
+
+dirac_status dirac_solve(dirac_ctx *c, void *x, const void *b, dirac_layout lay, const dirac_solver_params *p,
+                         dirac_solve_info *info, void *stream) {
+    const auto t0 = std::chrono::steady_clock::now();
+    API_BEGIN
+    check_ctx(c);
+    require(info != nullptr, "info is NULL");
+    *info = dirac_solve_info{};
+    dl::check_solver_params(p);
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_NATIVE, "unknown layout");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = lay == DIRAC_LAYOUT_NATIVE ? native_bytes(c, DIRAC_F64, 0) : user_bytes(c, DIRAC_F64, 0);
+    check_dev(b, nb, "b");
+    check_dev(x, nb, "x");
+    check_no_alias(x, nb, b, nb);
+    const dirac_prec inner = p->method == DIRAC_SOLVER_MIXED_GCR ? (dirac_prec)p->inner_prec : DIRAC_F64;
+    dl::ensure_work(c, p->method == DIRAC_SOLVER_CGLS ? 1 : p->restart, inner);
+    void *bn = dl::solver_full64(c, 0), *xn = dl::solver_full64(c, 1);
+    if (lay == DIRAC_LAYOUT_NATIVE) {
+        HIP_CHECK(hipMemcpyAsync(bn, b, nb, hipMemcpyDeviceToDevice, s));
+        if (p->x0_given) HIP_CHECK(hipMemcpyAsync(xn, x, nb, hipMemcpyDeviceToDevice, s));
+    } else {
+        dl::spinor_import(c, bn, b, 0, DIRAC_F64, lay, s);
+        if (p->x0_given) dl::spinor_import(c, xn, x, 0, DIRAC_F64, lay, s);
+    }
+    const dirac_status st = p->method == DIRAC_SOLVER_CGLS ? dl::solve_cgls(c, p, p->x0_given != 0, info, s)
+                                                            : dl::solve_native(c, p, p->x0_given != 0, info, s);
+    if (lay == DIRAC_LAYOUT_NATIVE)
+        HIP_CHECK(hipMemcpyAsync(x, xn, nb, hipMemcpyDeviceToDevice, s));
+    else
+        dl::spinor_export(c, x, xn, 0, DIRAC_F64, lay, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st != DIRAC_OK) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "solver stopped after %d iterations, true relative residual %.3e", info->iters,
+                 info->true_rel_res);
+        return fail(st, st == DIRAC_ENONFINITE ? std::string("non-finite value in the solve; ") + msg : msg);
+    }
     API_END
 }
 

@@ -1,0 +1,44 @@
+// Host interface of the solver vector kernels (blas.hip).  Reductions write their results
+// (FP64, already summed over the lattice and multiplied by `scale`) to device memory, so a
+// solver iteration needs no host round trip except where it reads a norm to decide.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "internal.h"
+
+namespace dl {
+
+struct Blas {
+    dirac_ctx *c = nullptr;
+    DevBuf part, scal;
+
+    void reserve(int64_t nsites_max, int kmax);
+    // out[j] = scale <Q_j, q>, j < k (complex, 2 doubles each)
+    void mdot(dirac_prec pr, int nh, const void *Q, size_t qstride_bytes, int k, const void *q, double *out_dev,
+              double scale, hipStream_t s);
+    // q -= sum_j coef_j Q_j; out = scale {|q|^2, <q, r>}
+    void maxpy_dot(dirac_prec pr, int nh, const void *Q, size_t qstride_bytes, int k, const double *coef_dev, void *q,
+                   const void *r, double *out_dev, double scale, hipStream_t s);
+    void gcr_scalars(const double *red, double *sc, double *gam, double *alp, int k, hipStream_t s);
+    // q /= gamma; r -= alpha q; pnext = r; out = scale |r|^2
+    void gcr_update(dirac_prec pr, int nh, const double *sc, void *q, void *r, void *pnext, double *out_dev,
+                    double scale, hipStream_t s);
+    // x += xscale sum_j coef_j P_j
+    void axpy_multi(dirac_prec px, dirac_prec pp, int nh, void *x, const void *P, size_t pstride_bytes, int k,
+                    const double *coef_dev, double xscale, hipStream_t s);
+    // out = alpha a + beta b; copy2 = out; out_dev = scale {|out|^2, nonfinite flag}
+    void lincomb(dirac_prec po, dirac_prec pa, dirac_prec pb, int nh, void *out, void *copy2, double alpha,
+                 const void *a, double beta, const void *b, double *out_dev, double scale, hipStream_t s);
+    void cgls_xs(int nh, const double *rho, const double *wn, void *x, const void *p, void *sv, const void *w,
+                 double *out_dev, hipStream_t s);
+    void cgls_p(int nh, const double *rho_new, const double *rho_old, void *p, const void *r, hipStream_t s);
+    void set(double *p, double v, hipStream_t s);
+    void copy_scalar(const double *src, double *dst, hipStream_t s);
+};
+
+int blas_grid(int64_t nsites);
+
+}  // namespace dl

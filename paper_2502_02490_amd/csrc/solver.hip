@@ -1,11 +1,351 @@
-// Krylov solvers (placeholder until the BLAS kernels land).
-#include "internal.h"
+// Krylov solvers on the device (host-driven loops; all vector work in blas.hip kernels):
+//   CGLS  - conjugate gradients on D^dag D for the full operator (least-squares CG, the
+//           residual s = b - D x of the original system is tracked and re-checked);
+//   GCR(m) on the even-odd Schur system, FP64 (Eisenstat, Elman and Schultz 1983), classical
+//           Gram-Schmidt against the stored q_j, x updated by back-substitution at the end of
+//           each cycle and the true residual recomputed at every restart;
+//   MIXED - defect correction (iterative refinement): the FP64 residual of the Schur system is
+//           scaled to unit RMS, rounded to FP32 / FP16 / BF16, solved there by GCR(m) to a
+//           relative tolerance, and the correction added to the FP64 iterate; the residual is
+//           recomputed with the FP64 operator after each step.  A step that reduces the residual
+//           by less than 2x raises the inner precision (16-bit -> FP32 -> plain FP64 GCR).
+// Inner products inside GCR are normalised by the vector length (mean instead of sum), so that
+// unit-norm Krylov vectors have O(1) components in every storage precision.
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "blas.h"
 
 namespace dl {
-void free_solver_work(dirac_ctx *) {}
+
+struct SolverWork {
+    Blas blas;
+    DevBuf P, Q, r, e, b;   // inner solver, inner precision
+    DevBuf h64[4];          // FP64 half vectors: eta-hat, x_e, r, tmp
+    DevBuf f64[3];          // FP64 full vectors: b, x, r
+    int m = 0;
+    dirac_prec pr = DIRAC_F64;
+};
+
+namespace {
+
+// device scalar slots (doubles) inside Blas::scal
+constexpr int S_RED = 0, S_SC = 8, S_MISC = 16, S_GAM = 64, S_ALP = 192, S_C = 320, S_BETA = 512;
+constexpr int kMaxRestart = 64;
+
+struct GcrOut {
+    int iters = 0, restarts = 0;
+    bool converged = false, nonfinite = false;
+    double rnorm = 0.0;  // normalised norm of the last true residual
+};
+
+double *sc_ptr(SolverWork &w, int slot) { return (double *)w.blas.scal.p + slot; }
+
+double read_scalar(SolverWork &w, int slot, hipStream_t s) {
+    double h = 0.0;
+    HIP_CHECK(hipMemcpyAsync(&h, sc_ptr(w, slot), sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return h;
+}
+
+}  // namespace
+
+// Solver buffers; they only grow, so a later call with a wider precision or a longer
+// restart reallocates (contents are not kept across calls).
+void ensure_work(dirac_ctx *c, int m, dirac_prec inner) {
+    if (!c->work) {
+        c->work = new SolverWork();
+        c->work->blas.c = c;
+    }
+    SolverWork &w = *c->work;
+    w.blas.reserve(c->V, kMaxRestart);
+    const size_t half64 = (size_t)24 * 8 * c->vh;
+    for (auto &b : w.h64) b.alloc(half64);
+    for (auto &b : w.f64) b.alloc(2 * half64);
+    const size_t hb = (size_t)24 * real_size(inner) * c->vh;
+    w.P.alloc(hb * (m + 1));
+    w.Q.alloc(hb * m);
+    w.r.alloc(hb);
+    w.e.alloc(hb);
+    w.b.alloc(hb);
+    w.m = m;
+    w.pr = inner;
+}
+
+namespace {
+
+// GCR(m) on D-hat in precision pr: x (half, pr) solves D-hat x = b (half, pr) to
+// |b - D-hat x| <= target (normalised norm).  x holds the initial guess when x0.
+GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, bool x0, double target, int m,
+           int max_iter, hipStream_t s) {
+    Blas &B = w.blas;
+    const double scale = 1.0 / (24.0 * (double)c->vh);
+    const size_t hb = (size_t)24 * real_size(pr) * c->vh;
+    char *P = (char *)w.P.p, *Q = (char *)w.Q.p;
+    void *r = w.r.p;
+    GcrOut out;
+    if (x0) {
+        schur_apply(c, Q, x, 0, pr, s);
+        B.lincomb(pr, pr, pr, 1, r, nullptr, 1.0, b, -1.0, Q, sc_ptr(w, S_RED + 4), scale, s);
+    } else {
+        B.lincomb(pr, pr, pr, 1, x, nullptr, 0.0, b, 0.0, nullptr, nullptr, 1.0, s);
+        B.lincomb(pr, pr, pr, 1, r, nullptr, 1.0, b, 0.0, nullptr, sc_ptr(w, S_RED + 4), scale, s);
+    }
+    double rn2 = read_scalar(w, S_RED + 4, s);
+    if (read_scalar(w, S_RED + 5, s) != 0.0 || !std::isfinite(rn2)) {
+        out.nonfinite = true;
+        return out;
+    }
+    out.rnorm = std::sqrt(rn2);
+    if (out.rnorm <= target) {
+        out.converged = true;
+        return out;
+    }
+    std::vector<double> gam(m), alp(2 * m), beta(2 * m * m), cc(2 * m);
+    while (out.iters < max_iter) {
+        B.lincomb(pr, pr, pr, 1, P, nullptr, 1.0, r, 0.0, nullptr, nullptr, 1.0, s);
+        int n = 0;
+        for (int k = 0; k < m; ++k) {
+            char *qk = Q + k * hb;
+            schur_apply(c, qk, P + k * hb, 0, pr, s);
+            double *bcol = sc_ptr(w, S_BETA + 2 * kMaxRestart * k);
+            if (k > 0) B.mdot(pr, 1, Q, hb, k, qk, bcol, scale, s);
+            B.maxpy_dot(pr, 1, Q, hb, k, bcol, qk, r, sc_ptr(w, S_RED), scale, s);
+            B.gcr_scalars(sc_ptr(w, S_RED), sc_ptr(w, S_SC), sc_ptr(w, S_GAM), sc_ptr(w, S_ALP), k, s);
+            B.gcr_update(pr, 1, sc_ptr(w, S_SC), qk, r, P + (k + 1) * hb, sc_ptr(w, S_RED + 4), scale, s);
+            rn2 = read_scalar(w, S_RED + 4, s);
+            ++out.iters;
+            n = k + 1;
+            if (!std::isfinite(rn2)) {
+                out.nonfinite = true;
+                return out;
+            }
+            if (std::sqrt(rn2) <= target || out.iters >= max_iter) break;
+        }
+        // back-substitution: alpha_j = c_j gamma_j + sum_{k > j} c_k beta_jk
+        HIP_CHECK(hipMemcpyAsync(gam.data(), sc_ptr(w, S_GAM), n * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(alp.data(), sc_ptr(w, S_ALP), 2 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+        for (int k = 1; k < n; ++k)
+            HIP_CHECK(hipMemcpyAsync(beta.data() + 2 * m * k, sc_ptr(w, S_BETA + 2 * kMaxRestart * k),
+                                     2 * k * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        for (int j = n - 1; j >= 0; --j) {
+            std::complex<double> acc(alp[2 * j], alp[2 * j + 1]);
+            for (int k = j + 1; k < n; ++k)
+                acc -= std::complex<double>(beta[2 * m * k + 2 * j], beta[2 * m * k + 2 * j + 1]) *
+                       std::complex<double>(cc[2 * k], cc[2 * k + 1]);
+            acc /= gam[j];
+            cc[2 * j] = acc.real();
+            cc[2 * j + 1] = acc.imag();
+        }
+        HIP_CHECK(hipMemcpyAsync(sc_ptr(w, S_C), cc.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice, s));
+        B.axpy_multi(pr, pr, 1, x, P, hb, n, sc_ptr(w, S_C), 1.0, s);
+        // true residual of the updated iterate
+        schur_apply(c, Q, x, 0, pr, s);
+        B.lincomb(pr, pr, pr, 1, r, nullptr, 1.0, b, -1.0, Q, sc_ptr(w, S_RED + 4), scale, s);
+        rn2 = read_scalar(w, S_RED + 4, s);
+        if (!std::isfinite(rn2) || read_scalar(w, S_RED + 5, s) != 0.0) {
+            out.nonfinite = true;
+            return out;
+        }
+        out.rnorm = std::sqrt(rn2);
+        if (out.rnorm <= target) {
+            out.converged = true;
+            break;
+        }
+        if (out.iters < max_iter) ++out.restarts;
+    }
+    return out;
+}
+
+}  // namespace
+
+void check_solver_params(const dirac_solver_params *p) {
+    require(p != nullptr, "solver params are NULL");
+    require(p->method >= DIRAC_SOLVER_CGLS && p->method <= DIRAC_SOLVER_MIXED_GCR, "unknown solver method");
+    require(std::isfinite(p->tol) && p->tol > 0.0 && p->tol < 1.0, "tol must be in (0, 1)");
+    require(p->max_iter > 0, "max_iter must be positive");
+    if (p->method != DIRAC_SOLVER_CGLS) require(p->restart >= 1 && p->restart <= kMaxRestart, "restart must be 1..64");
+    if (p->method == DIRAC_SOLVER_MIXED_GCR)
+        require(p->inner_prec == DIRAC_F32 || p->inner_prec == DIRAC_F16 || p->inner_prec == DIRAC_BF16,
+                "inner_prec must be F32, F16 or BF16");
+    else if (p->precision != DIRAC_F64)
+        throw Error(DIRAC_EUNSUPPORTED, "CGLS and GCR run in F64; use MIXED_GCR for lower-precision inner solves");
+}
+
+namespace {
+
+double default_inner_tol(dirac_prec pr) { return pr == DIRAC_F32 ? 1e-5 : pr == DIRAC_F16 ? 1e-3 : 1e-2; }
+
+}  // namespace
+
+void *solver_full64(dirac_ctx *c, int k) { return c->work->f64[k].p; }
+
+void free_solver_work(dirac_ctx *c) {
+    if (!c->work) return;
+    SolverWork &w = *c->work;
+    w.blas.part.release();
+    w.blas.scal.release();
+    w.P.release(); w.Q.release(); w.r.release(); w.e.release(); w.b.release();
+    for (auto &b : w.h64) b.release();
+    for (auto &b : w.f64) b.release();
+    delete c->work;
+    c->work = nullptr;
+}
+
+// Even-odd solve of D x = b on NATIVE FP64 full vectors (b, x in w.f64[0], w.f64[1]).
+dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, dirac_solve_info *info,
+                          hipStream_t s) {
+    ensure_prec(c, DIRAC_F64, s);
+    const dirac_prec inner = p->method == DIRAC_SOLVER_MIXED_GCR ? (dirac_prec)p->inner_prec : DIRAC_F64;
+    if (inner != DIRAC_F64) ensure_prec(c, inner, s);
+    SolverWork &w = *c->work;
+    Blas &B = w.blas;
+    const double scale = 1.0 / (24.0 * (double)c->vh);
+    const size_t half64 = (size_t)24 * 8 * c->vh;
+    char *bf = (char *)w.f64[0].p, *xf = (char *)w.f64[1].p, *rf = (char *)w.f64[2].p;
+    char *be = bf, *bo = bf + half64, *xe = xf, *xo = xf + half64;
+    void *eta = w.h64[0].p, *r64 = w.h64[2].p, *t64 = w.h64[3].p;
+    require(c->f[DIRAC_F64].inv_ready[1], "odd-site clover inverse not available (singular block?)");
+
+    // |b|^2 (normalised by the half-vector length, like every norm below)
+    B.mdot(DIRAC_F64, 2, bf, 0, 1, bf, sc_ptr(w, S_MISC), scale, s);
+    const double bn = std::sqrt(read_scalar(w, S_MISC, s));
+    require(std::isfinite(bn), "right-hand side holds NaN or Inf", DIRAC_ENONFINITE);
+    if (bn == 0.0) {
+        B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 2, xf, nullptr, 0.0, bf, 0.0, nullptr, nullptr, 1.0, s);
+        info->true_rel_res = 0.0;
+        return DIRAC_OK;
+    }
+    const double target = p->tol * bn;
+    // eta-hat_e = b_e - D_eo A_oo^-1 b_o
+    clover_apply(c, t64, bo, 1, 1, DIRAC_F64, s);
+    hop_apply(c, r64, t64, nullptr, 0, HOP_PLAIN, -0.5, 0, DIRAC_F64, s);
+    B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, eta, nullptr, 1.0, be, -1.0, r64, nullptr, 1.0, s);
+
+    dirac_status st = DIRAC_OK;
+    if (p->method == DIRAC_SOLVER_GCR) {
+        // the iterate lives directly in the even half of x
+        GcrOut g = gcr(c, w, DIRAC_F64, xe, eta, x0, target, p->restart, p->max_iter, s);
+        info->iters = g.iters;
+        info->restarts = g.restarts;
+        if (g.nonfinite) st = DIRAC_ENONFINITE;
+        else if (!g.converged) st = DIRAC_ENOCONV;
+    } else {
+        // defect correction around an inner GCR in precision `cur`
+        dirac_prec cur = inner;
+        double dtol = p->inner_tol > 0.0 ? p->inner_tol : default_inner_tol(cur);
+        if (!x0) B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, xe, nullptr, 0.0, eta, 0.0, nullptr, nullptr, 1.0, s);
+        schur_apply(c, t64, xe, 0, DIRAC_F64, s);
+        B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, r64, nullptr, 1.0, eta, -1.0, t64, sc_ptr(w, S_MISC + 2),
+                  scale, s);
+        double rn = std::sqrt(read_scalar(w, S_MISC + 2, s));
+        int iters = 0;
+        while (rn > target) {
+            if (iters >= p->max_iter) { st = DIRAC_ENOCONV; break; }
+            if (!std::isfinite(rn)) { st = DIRAC_ENONFINITE; break; }
+            if (cur == DIRAC_F64) {  // fallback: plain FP64 GCR from the current iterate
+                info->fell_back = 1;
+                ensure_work(c, p->restart, DIRAC_F64);
+                GcrOut g = gcr(c, w, DIRAC_F64, xe, eta, true, target, p->restart, p->max_iter - iters, s);
+                iters += g.iters;
+                info->restarts += g.restarts;
+                if (g.nonfinite) st = DIRAC_ENONFINITE;
+                else if (!g.converged) st = DIRAC_ENOCONV;
+                break;
+            }
+            ensure_prec(c, cur, s);
+            ensure_work(c, p->restart, cur);
+            // r_lo = r64 / rn (unit normalised RMS), inner solve, x_e += rn e_lo
+            B.lincomb(cur, DIRAC_F64, DIRAC_F64, 1, w.b.p, nullptr, 1.0 / rn, r64, 0.0, nullptr, nullptr, 1.0, s);
+            GcrOut g = gcr(c, w, cur, w.e.p, w.b.p, false, dtol, p->restart, p->max_iter - iters, s);
+            iters += g.iters;
+            info->restarts += g.restarts;
+            ++info->outer;
+            if (!g.nonfinite) {
+                B.set(sc_ptr(w, S_C), 1.0, s);
+                B.set(sc_ptr(w, S_C + 1), 0.0, s);
+                B.axpy_multi(DIRAC_F64, cur, 1, xe, w.e.p, 0, 1, sc_ptr(w, S_C), rn, s);
+            }
+            schur_apply(c, t64, xe, 0, DIRAC_F64, s);
+            B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, r64, nullptr, 1.0, eta, -1.0, t64, sc_ptr(w, S_MISC + 2),
+                      scale, s);
+            const double rn_new = std::sqrt(read_scalar(w, S_MISC + 2, s));
+            if (g.nonfinite || !(rn_new < 0.5 * rn)) {
+                cur = cur == DIRAC_F32 ? DIRAC_F64 : DIRAC_F32;  // raise the inner precision
+                dtol = p->inner_tol > 0.0 && cur == DIRAC_F32 ? std::max(p->inner_tol, 1e-5) : default_inner_tol(cur);
+            }
+            rn = rn_new;
+        }
+        info->iters = iters;
+    }
+    // x_o = A_oo^-1 (b_o - D_oe x_e)
+    hop_apply(c, t64, xe, nullptr, 1, HOP_PLAIN, -0.5, 0, DIRAC_F64, s);
+    B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, r64, nullptr, 1.0, bo, -1.0, t64, nullptr, 1.0, s);
+    clover_apply(c, xo, r64, 1, 1, DIRAC_F64, s);
+    // a-posteriori check: |b - D x| / |b| in FP64
+    full_apply(c, rf, xf, 0, DIRAC_F64, s);
+    B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 2, rf, nullptr, 1.0, bf, -1.0, rf, sc_ptr(w, S_MISC + 4), scale, s);
+    info->true_rel_res = std::sqrt(read_scalar(w, S_MISC + 4, s)) / bn;
+    if (st == DIRAC_OK && !(info->true_rel_res < p->tol)) st = DIRAC_ENOCONV;
+    return st;
+}
+
+// CGLS on the full operator, FP64 NATIVE full vectors (b = w.f64[0], x = w.f64[1]).
+dirac_status solve_cgls(dirac_ctx *c, const dirac_solver_params *p, bool x0, dirac_solve_info *info,
+                        hipStream_t s) {
+    SolverWork &w = *c->work;
+    Blas &B = w.blas;
+    const double scale = 1.0 / (24.0 * (double)c->vh);
+    char *bf = (char *)w.f64[0].p, *xf = (char *)w.f64[1].p, *sv = (char *)w.f64[2].p;
+    // CGLS needs three more full vectors: r, p, w (inside the inner-solver buffers, FP64)
+    const size_t full64 = (size_t)48 * 8 * c->vh;
+    w.P.alloc(3 * full64);
+    char *rv = (char *)w.P.p, *pv = rv + full64, *wv = pv + full64;
+    double *rho = sc_ptr(w, S_MISC + 8), *rho_new = sc_ptr(w, S_MISC + 10), *wn = sc_ptr(w, S_MISC + 12);
+    B.mdot(DIRAC_F64, 2, bf, 0, 1, bf, sc_ptr(w, S_MISC), scale, s);
+    const double bn = std::sqrt(read_scalar(w, S_MISC, s));
+    require(std::isfinite(bn), "right-hand side holds NaN or Inf", DIRAC_ENONFINITE);
+    if (!x0) B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 2, xf, nullptr, 0.0, bf, 0.0, nullptr, nullptr, 1.0, s);
+    const double target = p->tol * bn;
+    dirac_status st = DIRAC_ENOCONV;
+    int it = 0;
+    while (it < p->max_iter) {
+        // s = b - D x; r = D^dag s; p = r; rho = |r|^2
+        full_apply(c, wv, xf, 0, DIRAC_F64, s);
+        B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 2, sv, nullptr, 1.0, bf, -1.0, wv, sc_ptr(w, S_MISC + 6), scale, s);
+        double sn = std::sqrt(read_scalar(w, S_MISC + 6, s));
+        if (!std::isfinite(sn)) { st = DIRAC_ENONFINITE; break; }
+        if (sn <= target) { st = DIRAC_OK; break; }
+        if (it > 0) ++info->restarts;
+        full_apply(c, rv, sv, 1, DIRAC_F64, s);
+        B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 2, pv, nullptr, 1.0, rv, 0.0, nullptr, nullptr, 1.0, s);
+        B.mdot(DIRAC_F64, 2, rv, 0, 1, rv, rho, scale, s);
+        while (it < p->max_iter) {
+            full_apply(c, wv, pv, 0, DIRAC_F64, s);
+            B.mdot(DIRAC_F64, 2, wv, 0, 1, wv, wn, scale, s);
+            B.cgls_xs(2, rho, wn, xf, pv, sv, wv, sc_ptr(w, S_MISC + 6), s);
+            full_apply(c, rv, sv, 1, DIRAC_F64, s);
+            B.mdot(DIRAC_F64, 2, rv, 0, 1, rv, rho_new, scale, s);
+            B.cgls_p(2, rho_new, rho, pv, rv, s);
+            B.copy_scalar(rho_new, rho, s);
+            ++it;
+            sn = std::sqrt(read_scalar(w, S_MISC + 6, s));
+            if (!std::isfinite(sn)) break;
+            if (sn <= target) break;
+        }
+    }
+    info->iters = it;
+    // a-posteriori check
+    full_apply(c, wv, xf, 0, DIRAC_F64, s);
+    B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 2, sv, nullptr, 1.0, bf, -1.0, wv, sc_ptr(w, S_MISC + 6), scale, s);
+    info->true_rel_res = std::sqrt(read_scalar(w, S_MISC + 6, s)) / bn;
+    if (st == DIRAC_OK && !(info->true_rel_res < p->tol)) st = DIRAC_ENOCONV;
+    if (!std::isfinite(info->true_rel_res)) st = DIRAC_ENONFINITE;
+    return st;
+}
+
 }  // namespace dl
 
-extern "C" dirac_status dirac_solve(dirac_ctx *, void *, const void *, dirac_layout, const dirac_solver_params *,
-                                    dirac_solve_info *, void *) {
-    return DIRAC_EUNSUPPORTED;
-}
