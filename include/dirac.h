@@ -42,11 +42,13 @@
  * DIRAC_LAYOUT_EO      the same per-site layout, sites in xhat order (even
  *                      sites first).  A half (even-site) vector is the first
  *                      V/2 sites of an EO vector.
- * DIRAC_LAYOUT_NATIVE  the library's device layout: per parity, 16-byte planes
- *                      [24/W][V/2][W] reals (W = 2 for F64, 4 for F32, 8 for F16
- *                      and BF16); a full vector is the even half then the odd
- *                      half.  Within a plane, site k is floor(Lambda / 2) of the
- *                      k-th site of that parity.  Use this layout when timing.
+ * DIRAC_LAYOUT_NATIVE  the library's device layout.  Per parity, the V/2 sites (in
+ *                      floor(Lambda / 2) order) are padded to Vp = a multiple of 64 and
+ *                      grouped in blocks of 64: [Vp / 64][24 / W][64][W] reals with W = 2
+ *                      for F64, 4 for F32, 8 for F16 and BF16 (16-byte vectors).  A full
+ *                      vector is the even half then the odd half; dirac_native_bytes gives
+ *                      the size.  Padding sites are never read or written.  Use this layout
+ *                      when timing.
  * User-layout (LEX/EO) buffers are complex128 for DIRAC_F64 and complex64 for
  * DIRAC_F32; F16 and BF16 exist in the NATIVE layout only.
  *

@@ -74,7 +74,7 @@ size_t user_bytes(const dirac_ctx *c, dirac_prec pr, int sites) {
     return n * 24 * (pr == DIRAC_F32 ? 4 : 8);
 }
 size_t native_bytes(const dirac_ctx *c, dirac_prec pr, int sites) {
-    const size_t n = sites == 0 ? (size_t)c->V : (size_t)c->vh;
+    const size_t n = (sites == 0 ? 2 : 1) * (size_t)c->g.vhp;
     return n * 24 * dl::real_size(pr);
 }
 
@@ -118,6 +118,7 @@ dirac_status dirac_create(const dirac_params *prm, const void *su3_links, const 
         for (int m = 0; m < 4; ++m) c->g.L[m] = prm->dims[m];
         c->g.h3 = prm->dims[3] / 2;
         c->g.vh = (int)c->vh;
+        c->g.vhp = (int)padded_sites(c->vh);
         c->U_lex.alloc((size_t)V * 4 * 9 * 16);
         HIP_CHECK(hipMemcpyAsync(c->U_lex.p, su3_links, (size_t)V * 4 * 9 * 16, hipMemcpyDeviceToDevice, s));
         if (u1_angles) {

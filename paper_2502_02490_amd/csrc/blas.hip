@@ -15,23 +15,18 @@ namespace {
 
 constexpr int kRed = 256;  // work-group size of the reducing kernels
 
-template <typename S>
-struct VecRef {
-    typename St<S>::vec *p;
-};
-
-// (block h, plane base) of site t of an nh-block vector
+// (half h, base) of site t of an nh-half vector; halves are 24 / W planes of vhp sites apart
 template <typename S>
 DEV const typename St<S>::vec *blk_base(const typename St<S>::vec *p, int t, int vh, uint32_t &i) {
     const int h = t >= vh;
     i = (uint32_t)(t - h * vh);
-    return p + (size_t)h * (24 / St<S>::W) * vh;
+    return p + (size_t)h * (24 / St<S>::W) * (size_t)padded_sites(vh);
 }
 template <typename S>
 DEV typename St<S>::vec *blk_base(typename St<S>::vec *p, int t, int vh, uint32_t &i) {
     const int h = t >= vh;
     i = (uint32_t)(t - h * vh);
-    return p + (size_t)h * (24 / St<S>::W) * vh;
+    return p + (size_t)h * (24 / St<S>::W) * (size_t)padded_sites(vh);
 }
 
 template <typename S>
@@ -39,7 +34,7 @@ DEV void ld(const typename St<S>::vec *p, int t, int vh, double *o) {
     uint32_t i;
     const typename St<S>::vec *b = blk_base<S>(p, t, vh, i);
     typename St<S>::acc r[24];
-    load_planes<S, 24>(b, vh, i, r);
+    load_field<S, 24>(b, i, r);
 #pragma unroll
     for (int k = 0; k < 24; ++k) o[k] = (double)r[k];
 }
@@ -50,7 +45,7 @@ DEV void st(typename St<S>::vec *p, int t, int vh, const double *o) {
     typename St<S>::acc r[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) r[k] = (typename St<S>::acc)o[k];
-    store_planes<S, 24>(b, vh, i, r);
+    store_field<S, 24>(b, i, r);
 }
 
 // Sum of v over the work-group (fixed tree: wave shuffles, then the waves in order).
@@ -387,9 +382,9 @@ void Blas::axpy_multi(dirac_prec px, dirac_prec pp, int nh, void *x, const void 
     k_axpy_multi<SX, SP><<<nb, kRed, 0, s>>>(n, vh, (typename St<SX>::vec *)x, (const typename St<SP>::vec *)P, \
                                              pstride_bytes / sizeof(typename St<SP>::vec), k,                \
                                              (const double2 *)coef_dev, xscale);
-#define FN(SP)                                                               \
-    if (px == DIRAC_F64) { FN2(double, SP) } else if (px == DIRAC_F32) { FN2(float, SP) }  \
-    else throw Error(DIRAC_EINVAL, "solution vectors are F64 or F32");
+#define FN(SP)                                                                                     \
+    if (px == DIRAC_F64) { FN2(double, SP) } else if (px == DIRAC_F32) { FN2(float, SP) }          \
+    else if (px == DIRAC_F16) { FN2(__half, SP) } else { FN2(__hip_bfloat16, SP) }
     DISPATCH_PREC(pp, FN)
 #undef FN
 #undef FN2

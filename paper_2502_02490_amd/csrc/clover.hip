@@ -125,7 +125,6 @@ __global__ __launch_bounds__(kBlock) void k_clover_build(Geom g, int p, const do
     double pk[72];
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
-        const double sg = blk == 0 ? 1.0 : -1.0;
         C<double> G1[9], G2[9], G3[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -137,7 +136,6 @@ __global__ __launch_bounds__(kBlock) void k_clover_build(Geom g, int p, const do
             G2[k] = 0.5 * times_i(f2);
             G3[k] = 0.5 * times_i(f3);
         }
-        (void)sg;
         auto B = [&](int r, int c) -> C<double> {
             const int s = r / 3, a = r % 3, t = c / 3, b = c % 3;
             const int k = 3 * a + b;
@@ -163,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_clover_build(Geom g, int p, const do
                 k += 2;
             }
     }
-    store_planes<double, 72>(out, g.vh, i, pk);
+    store_field<double, 72>(out, (uint32_t)i, pk);
 }
 
 // Gauss-Jordan inversion of a 6x6 complex block with partial pivoting (pivot row chosen by
@@ -229,9 +227,10 @@ __global__ __launch_bounds__(kBlock) void k_clover_invert(Geom g, int p, const d
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
         double pk[36];
+        const double2 *Ai = site_ptr(A, (uint32_t)i, 36);
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
-            double2 v = A[(size_t)(18 * blk + k) * g.vh + i];
+            double2 v = Ai[(18 * blk + k) * kSB];
             pk[2 * k] = v.x;
             pk[2 * k + 1] = v.y;
         }
@@ -266,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_clover_invert(Geom g, int p, const d
                 k += 2;
             }
     }
-    store_planes<double, 72>(Ainv, g.vh, i, out);
+    store_field<double, 72>(Ainv, (uint32_t)i, out);
     if (!ok) {
         int x[4];
         site_coords(g, i, p, x);
@@ -282,8 +281,8 @@ __global__ __launch_bounds__(kBlock) void k_clover_apply(int vh, const typename 
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= vh) return;
     T r[24], pk[72];
-    load_planes<S, 24>(in, vh, i, r);
-    load_planes<S, 72>(A, vh, i, pk);
+    load_field<S, 24>(in, (uint32_t)i, r);
+    load_field<S, 72>(A, (uint32_t)i, pk);
     C<T> psi[12], y[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) psi[k] = mk(r[2 * k], r[2 * k + 1]);
@@ -291,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_clover_apply(int vh, const typename 
     block_mul(pk + 36, psi + 6, y + 6);
 #pragma unroll
     for (int k = 0; k < 12; ++k) { r[2 * k] = y[k].r; r[2 * k + 1] = y[k].i; }
-    store_planes<S, 24>(out, vh, i, r);
+    store_field<S, 24>(out, (uint32_t)i, r);
 }
 
 template <typename S>
@@ -312,7 +311,7 @@ void clover_build(dirac_ctx *c, hipStream_t s) {
     PrecFields &f = c->f[DIRAC_F64];
     const double diag = 1.0 / (2.0 * c->p.kappa);
     for (int p = 0; p < 2; ++p) {
-        f.clov[p].alloc((size_t)72 * sizeof(double) * c->vh);
+        f.clov[p].alloc((size_t)72 * sizeof(double) * c->g.vhp);
         k_clover_build<<<grid_for(c->vh), kBlock, 0, s>>>(c->g, p, (const double *)c->U_lex.p,
                                                           (const double *)c->theta_lex.p, c->p.csw,
                                                           c->p.csw_qed * c->p.qhat, diag, (double2 *)f.clov[p].p);
@@ -327,7 +326,7 @@ void clover_build(dirac_ctx *c, hipStream_t s) {
 int64_t clover_invert_parity(dirac_ctx *c, int p, hipStream_t s) {
     PrecFields &f = c->f[DIRAC_F64];
     require(f.clover_ready, "no clover field");
-    f.clinv[p].alloc((size_t)72 * sizeof(double) * c->vh);
+    f.clinv[p].alloc((size_t)72 * sizeof(double) * c->g.vhp);
     c->flags.alloc(256);
     int *bad = (int *)c->flags.p + 8;
     const int big = 0x7fffffff;

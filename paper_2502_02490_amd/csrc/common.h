@@ -87,33 +87,49 @@ template <> struct St<__hip_bfloat16> {
     }
 };
 
-// Load / store n reals (n a multiple of W) of site s from planes with stride `vh` vectors.
-// The plane address is uniform across the wavefront and the per-lane part is a 32-bit byte
-// offset, so every access is one scalar-base + vector-offset instruction: no 64-bit address
-// per plane and lane has to be kept in registers.
+// Site-blocked layout ("NATIVE"): the sites of one parity are grouped in blocks of kSB = 64
+// (one wavefront); a field with np planes per site is stored as [block][plane][64 sites] of
+// 16-byte vectors (8-byte for 16-bit links).  A wavefront's load of one plane is one contiguous
+// 1 KB run, and all planes of a block sit next to each other, so the DRAM pages a wavefront
+// touches are few and contiguous.  Plane k of a site is 64 vectors after plane k - 1, which the
+// compiler folds into the load's immediate offset.  The site count is padded to a multiple of 64.
+constexpr int kSB = 64;
+HD int64_t padded_sites(int64_t vh) { return (vh + kSB - 1) & ~(int64_t)(kSB - 1); }
+
 template <typename V>
-DEV const V &at_off(const V *__restrict__ plane, uint32_t byte_off) {
-    return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(plane) + byte_off);
+DEV const V *site_ptr(const V *base, uint32_t s, int np) {
+    return base + ((size_t)(s >> 6) * (size_t)np * kSB + (s & (kSB - 1)));
 }
 template <typename V>
-DEV V &at_off(V *__restrict__ plane, uint32_t byte_off) {
-    return *reinterpret_cast<V *>(reinterpret_cast<char *>(plane) + byte_off);
+DEV V *site_ptr(V *base, uint32_t s, int np) {
+    return base + ((size_t)(s >> 6) * (size_t)np * kSB + (s & (kSB - 1)));
+}
+
+// Load / store N reals (a multiple of W) of site s, planes [p0, p0 + N / W) of a field with np planes.
+template <typename S, int N>
+DEV void load_planes(const typename St<S>::vec *__restrict__ base, int np, int p0, uint32_t s,
+                     typename St<S>::acc *o) {
+    constexpr int W = St<S>::W;
+    const typename St<S>::vec *q = site_ptr(base, s, np) + p0 * kSB;
+#pragma unroll
+    for (int k = 0; k < N / W; ++k) St<S>::unpack(q[k * kSB], o + k * W);
 }
 template <typename S, int N>
-DEV void load_planes(const typename St<S>::vec *__restrict__ base, size_t vh, uint32_t s, typename St<S>::acc *o) {
-    using V = typename St<S>::vec;
+DEV void store_planes(typename St<S>::vec *__restrict__ base, int np, int p0, uint32_t s,
+                      const typename St<S>::acc *o) {
     constexpr int W = St<S>::W;
-    const uint32_t off = s * (uint32_t)sizeof(V);
+    typename St<S>::vec *q = site_ptr(base, s, np) + p0 * kSB;
 #pragma unroll
-    for (int k = 0; k < N / W; ++k) St<S>::unpack(at_off(base + k * vh, off), o + k * W);
+    for (int k = 0; k < N / W; ++k) q[k * kSB] = St<S>::pack(o + k * W);
+}
+// whole-field shorthands: N reals per site in N / W planes
+template <typename S, int N>
+DEV void load_field(const typename St<S>::vec *__restrict__ base, uint32_t s, typename St<S>::acc *o) {
+    load_planes<S, N>(base, N / St<S>::W, 0, s, o);
 }
 template <typename S, int N>
-DEV void store_planes(typename St<S>::vec *__restrict__ base, size_t vh, uint32_t s, const typename St<S>::acc *o) {
-    using V = typename St<S>::vec;
-    constexpr int W = St<S>::W;
-    const uint32_t off = s * (uint32_t)sizeof(V);
-#pragma unroll
-    for (int k = 0; k < N / W; ++k) at_off(base + k * vh, off) = St<S>::pack(o + k * W);
+DEV void store_field(typename St<S>::vec *__restrict__ base, uint32_t s, const typename St<S>::acc *o) {
+    store_planes<S, N>(base, N / St<S>::W, 0, s, o);
 }
 
 // ------------------------------------------------------------------ geometry
@@ -123,6 +139,7 @@ struct Geom {
     int L[4];
     int h3;   // L3 / 2
     int vh;   // V / 2
+    int vhp;  // V / 2 padded to a multiple of 64 (site blocks)
 };
 
 DEV void site_coords(const Geom &g, int i, int p, int x[4]) {

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kBlock) void k_import_links(Geom g, int p, const do
     int x[4];
     site_coords(g, i, p, x);
     const double ph[4] = {phase.x, phase.y, phase.z, phase.w};
-    const size_t vh = (size_t)g.vh;
+    const size_t vhp = (size_t)g.vhp;
     double dev = 0.0;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
@@ -34,11 +34,11 @@ __global__ __launch_bounds__(kBlock) void k_import_links(Geom g, int p, const do
             const int lam = lex_index(g, y);
             const double *u = U + ((size_t)lam * 4 + mu) * 18;
             const int dir = 2 * mu + back;
-            double2 *dst = planes + (size_t)dir * 6 * vh;
+            double2 *dst = site_ptr(planes + (size_t)dir * 6 * vhp, (uint32_t)i, 6);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) dst[k * vh + i] = make_double2(u[2 * k], u[2 * k + 1]);
+            for (int k = 0; k < 6; ++k) dst[k * kSB] = make_double2(u[2 * k], u[2 * k + 1]);
             double w = (theta ? qhat * theta[(size_t)lam * 4 + mu] : 0.0) + (y[mu] == g.L[mu] - 1 ? ph[mu] : 0.0);
-            omega[(size_t)dir * vh + i] = w;
+            omega[(size_t)dir * vhp + i] = w;
             if (!back) {
                 // deviation from SU(3): max |U U^dag - 1| and |det U - 1|; the row-2 rebuild needs det U = 1
                 cx<double> m[9];
@@ -65,24 +65,26 @@ __global__ __launch_bounds__(kBlock) void k_import_links(Geom g, int p, const do
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_convert_links(int vh, const double2 *__restrict__ src,
+__global__ __launch_bounds__(kBlock) void k_convert_links(int vh, int vhp, const double2 *__restrict__ src,
                                                            const double *__restrict__ om_src,
                                                            typename Lk<S>::vec *__restrict__ dst,
                                                            typename Lk<S>::om *__restrict__ om_dst) {
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= vh) return;
     constexpr int W = Lk<S>::W;
-    const size_t n = (size_t)vh;
+    const size_t n = (size_t)vhp;
     for (int dir = 0; dir < 8; ++dir) {
         double r[12];
+        const double2 *s0 = site_ptr(src + (size_t)dir * 6 * n, (uint32_t)i, 6);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            double2 v = src[((size_t)dir * 6 + k) * n + i];
+            double2 v = s0[k * kSB];
             r[2 * k] = v.x;
             r[2 * k + 1] = v.y;
         }
+        typename Lk<S>::vec *d0 = site_ptr(dst + (size_t)dir * (12 / W) * n, (uint32_t)i, 12 / W);
 #pragma unroll
-        for (int k = 0; k < 12 / W; ++k) dst[((size_t)dir * (12 / W) + k) * n + i] = Lk<S>::pack(r + k * W);
+        for (int k = 0; k < 12 / W; ++k) d0[k * kSB] = Lk<S>::pack(r + k * W);
         om_dst[(size_t)dir * n + i] = (typename Lk<S>::om)om_src[(size_t)dir * n + i];
     }
 }
@@ -94,11 +96,11 @@ __global__ __launch_bounds__(kBlock) void k_convert_clover(int vh, const double2
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= vh) return;
     double r[72];
-    load_planes<double, 72>(src, vh, i, r);
+    load_field<double, 72>(src, i, r);
     typename St<S>::acc a[72];
 #pragma unroll
     for (int k = 0; k < 72; ++k) a[k] = (typename St<S>::acc)r[k];
-    store_planes<S, 72>(dst, vh, i, a);
+    store_field<S, 72>(dst, i, a);
 }
 
 // user index of the site (p, i): LEX -> Lambda, EO -> xhat (relative to `base_parity` for half vectors)
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_clover_in(Geom g, int p, int lay, co
     double r[72];
 #pragma unroll
     for (int k = 0; k < 72; ++k) r[k] = u[k];
-    store_planes<double, 72>(dst, g.vh, i, r);
+    store_field<double, 72>(dst, i, r);
 }
 
 __global__ __launch_bounds__(kBlock) void k_clover_out(Geom g, int p, int lay, const double2 *__restrict__ src,
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_clover_out(Geom g, int p, int lay, c
     double *u = user + user_site(g, p, i, lay, 0) * 72;
     double r[72];
     if (src) {
-        load_planes<double, 72>(src, g.vh, i, r);
+        load_field<double, 72>(src, i, r);
     } else {
 #pragma unroll
         for (int k = 0; k < 72; ++k) r[k] = 0.0;
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_spinor_in(Geom g, int p, int lay, in
     typename St<S>::acc r[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) r[k] = (typename St<S>::acc)u[k];
-    store_planes<S, 24>(dst, g.vh, i, r);
+    store_field<S, 24>(dst, i, r);
 }
 
 template <typename U, typename S>
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_spinor_out(Geom g, int p, int lay, i
     if (i >= g.vh) return;
     U *u = user + user_site(g, p, i, lay, half) * 24;
     typename St<S>::acc r[24];
-    load_planes<S, 24>(src, g.vh, i, r);
+    load_field<S, 24>(src, i, r);
 #pragma unroll
     for (int k = 0; k < 24; ++k) u[k] = (U)r[k];
 }
@@ -169,12 +171,13 @@ void convert_fields(dirac_ctx *c, dirac_prec pr, hipStream_t s) {
     PrecFields &lo = c->f[pr];
     PrecFields &hi = c->f[DIRAC_F64];
     const int vh = (int)c->vh;
+    const size_t vhp = (size_t)c->g.vhp;
     if (!lo.links_ready) {
         for (int p = 0; p < 2; ++p) {
-            lo.links[p].alloc((size_t)8 * 12 * sizeof(typename Lk<S>::vec) / Lk<S>::W * c->vh);
-            lo.omega[p].alloc((size_t)8 * sizeof(typename Lk<S>::om) * c->vh);
+            lo.links[p].alloc((size_t)8 * 12 * sizeof(typename Lk<S>::vec) / Lk<S>::W * vhp);
+            lo.omega[p].alloc((size_t)8 * sizeof(typename Lk<S>::om) * vhp);
             k_convert_links<S><<<grid_for(vh), kBlock, 0, s>>>(
-                vh, (const double2 *)hi.links[p].p, (const double *)hi.omega[p].p,
+                vh, (int)vhp, (const double2 *)hi.links[p].p, (const double *)hi.omega[p].p,
                 (typename Lk<S>::vec *)lo.links[p].p, (typename Lk<S>::om *)lo.omega[p].p);
         }
         HIP_CHECK(hipGetLastError());
@@ -182,7 +185,7 @@ void convert_fields(dirac_ctx *c, dirac_prec pr, hipStream_t s) {
     }
     if (!lo.clover_ready) {
         for (int p = 0; p < 2; ++p) {
-            lo.clov[p].alloc((size_t)72 * sizeof(S) * c->vh);
+            lo.clov[p].alloc((size_t)72 * sizeof(S) * vhp);
             k_convert_clover<S><<<grid_for(vh), kBlock, 0, s>>>(vh, (const double2 *)hi.clov[p].p,
                                                                   (typename St<S>::vec *)lo.clov[p].p);
         }
@@ -191,7 +194,7 @@ void convert_fields(dirac_ctx *c, dirac_prec pr, hipStream_t s) {
     }
     for (int p = 0; p < 2; ++p) {
         if (hi.inv_ready[p] && !lo.inv_ready[p]) {
-            lo.clinv[p].alloc((size_t)72 * sizeof(S) * c->vh);
+            lo.clinv[p].alloc((size_t)72 * sizeof(S) * vhp);
             k_convert_clover<S><<<grid_for(vh), kBlock, 0, s>>>(vh, (const double2 *)hi.clinv[p].p,
                                                                   (typename St<S>::vec *)lo.clinv[p].p);
             HIP_CHECK(hipGetLastError());
@@ -203,7 +206,7 @@ void convert_fields(dirac_ctx *c, dirac_prec pr, hipStream_t s) {
 template <typename U, typename S>
 void spinor_io(dirac_ctx *c, void *native, const void *user, bool in, int sites, dirac_layout lay, hipStream_t s) {
     const int vh = (int)c->vh;
-    const size_t half_bytes = (size_t)24 * sizeof(S) * c->vh;
+    const size_t half_bytes = (size_t)24 * sizeof(S) * c->g.vhp;
     for (int p = 0; p < 2; ++p) {
         if (sites == 1 && p == 1) continue;
         if (sites == 2 && p == 0) continue;
@@ -253,8 +256,8 @@ void import_links(dirac_ctx *c, hipStream_t s) {
     HIP_CHECK(hipMemsetAsync(maxdev, 0, sizeof(unsigned long long), s));
     const double4 ph = make_double4(c->p.bc_phase[0], c->p.bc_phase[1], c->p.bc_phase[2], c->p.bc_phase[3]);
     for (int p = 0; p < 2; ++p) {
-        f.links[p].alloc((size_t)8 * 6 * sizeof(double2) * c->vh);
-        f.omega[p].alloc((size_t)8 * sizeof(double) * c->vh);
+        f.links[p].alloc((size_t)8 * 6 * sizeof(double2) * c->g.vhp);
+        f.omega[p].alloc((size_t)8 * sizeof(double) * c->g.vhp);
         k_import_links<<<grid_for(c->vh), kBlock, 0, s>>>(c->g, p, (const double *)c->U_lex.p,
                                                           (const double *)c->theta_lex.p, c->p.qhat, ph,
                                                           (double2 *)f.links[p].p, (double *)f.omega[p].p, maxdev);
@@ -294,7 +297,7 @@ void clover_import(dirac_ctx *c, const double *user, dirac_layout lay, hipStream
     require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO, "clover layout must be LEX or EO");
     PrecFields &f = c->f[DIRAC_F64];
     for (int p = 0; p < 2; ++p) {
-        f.clov[p].alloc((size_t)72 * sizeof(double) * c->vh);
+        f.clov[p].alloc((size_t)72 * sizeof(double) * c->g.vhp);
         k_clover_in<<<grid_for(c->vh), kBlock, 0, s>>>(c->g, p, lay, user, (double2 *)f.clov[p].p);
     }
     HIP_CHECK(hipGetLastError());

@@ -28,10 +28,10 @@ struct HopArgs {
 };
 
 template <typename S>
-DEV void load_spinor(const typename St<S>::vec *__restrict__ base, size_t vh, uint32_t s, C<typename St<S>::acc> psi[12]) {
+DEV void load_spinor(const typename St<S>::vec *__restrict__ base, uint32_t s, C<typename St<S>::acc> psi[12]) {
     using T = typename St<S>::acc;
     T r[24];
-    load_planes<S, 24>(base, vh, s, r);
+    load_field<S, 24>(base, s, r);
 #pragma unroll
     for (int k = 0; k < 12; ++k) psi[k] = mk(r[2 * k], r[2 * k + 1]);
 }
@@ -43,14 +43,14 @@ DEV void load_link(const HopArgs<S> &a, int dir, uint32_t i, C<typename St<S>::a
     using LV = typename Lk<S>::vec;
     using OM = typename Lk<S>::om;
     constexpr int W = Lk<S>::W;
-    const size_t vh = (size_t)a.g.vh;
-    const LV *b = a.links + (size_t)dir * (12 / W) * vh;
+    const size_t vhp = (size_t)a.g.vhp;
+    const LV *b = site_ptr(a.links + (size_t)dir * (12 / W) * vhp, i, 12 / W);
     T r[12];
 #pragma unroll
-    for (int k = 0; k < 12 / W; ++k) Lk<S>::unpack(at_off(b + k * vh, i * (uint32_t)sizeof(LV)), r + k * W);
+    for (int k = 0; k < 12 / W; ++k) Lk<S>::unpack(b[k * kSB], r + k * W);
 #pragma unroll
     for (int k = 0; k < 6; ++k) u[k] = mk(r[2 * k], r[2 * k + 1]);
-    const T w = (T)at_off(a.omega + (size_t)dir * vh, i * (uint32_t)sizeof(OM));
+    const T w = (T)a.omega[(size_t)dir * vhp + i];
     sc(w, si, co);
 }
 
@@ -69,7 +69,6 @@ DEV C<T> cmul_unit(T cr, T ci, C<T> z) { return mk(cr * z.r - ci * z.i, cr * z.i
 template <typename S, int DAG>
 DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<S>::acc> acc[12]) {
     using T = typename St<S>::acc;
-    const size_t vh = (size_t)a.g.vh;
     const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
 #pragma nounroll
     for (int n = 0; n < 8; ++n) {
@@ -87,7 +86,7 @@ DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<
         const T c1r = mu == 0 ? T(-1) : mu == 2 ? T(1) : T(0), c1i = mu == 1 ? T(-1) : mu == 3 ? T(1) : T(0);
         C<T> psi[12], h[6], u[6], w[6];
         T co, si;
-        load_spinor<S>(a.in, vh, j, psi);
+        load_spinor<S>(a.in, j, psi);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const C<T> l0 = psi[6 + c], l1 = psi[9 + c];
@@ -119,7 +118,6 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs<S> a) {
     const int ii = blk * kBlock + threadIdx.x;
     if (ii >= a.g.vh) return;
     const uint32_t i = (uint32_t)ii;
-    const size_t vh = (size_t)a.g.vh;
     int x[4];
     site_coords(a.g, ii, a.p, x);
     C<T> acc[12];
@@ -137,14 +135,14 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs<S> a) {
         constexpr bool split = (36 % W) == 0;
         T pk[split ? 36 : 72];
         C<T> t[6], chi[12];
-        if constexpr (MODE == HOP_CLOV) load_spinor<S>(a.chi, vh, i, chi);
+        if constexpr (MODE == HOP_CLOV) load_spinor<S>(a.chi, i, chi);
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) {
             const T *q = pk;
             if constexpr (split) {
-                load_planes<S, 36>(a.clov + blk * (36 / W) * vh, vh, i, pk);
+                load_planes<S, 36>(a.clov, 72 / W, blk * (36 / W), i, pk);
             } else {
-                if (blk == 0) load_planes<S, 72>(a.clov, vh, i, pk);
+                if (blk == 0) load_field<S, 72>(a.clov, i, pk);
                 q = pk + 36 * blk;
             }
             if constexpr (MODE == HOP_INV) {
@@ -161,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs<S> a) {
     T r[24];
 #pragma unroll
     for (int k = 0; k < 12; ++k) { r[2 * k] = y[k].r; r[2 * k + 1] = y[k].i; }
-    store_planes<S, 24>(a.out, vh, i, r);
+    store_field<S, 24>(a.out, i, r);
 }
 
 bool use_xcd_order() {
@@ -234,14 +232,14 @@ void schur_apply(dirac_ctx *c, void *out_e, const void *in_e, int dagger, dirac_
     ensure_prec(c, pr, s);
     PrecFields &f = c->f[pr];
     require(f.inv_ready[1], "odd-site clover inverse not available (clover_invert failed or was not run)");
-    f.tmp_half.alloc((size_t)24 * real_size(pr) * c->vh);
+    f.tmp_half.alloc((size_t)24 * real_size(pr) * c->g.vhp);
     hop_apply(c, f.tmp_half.p, in_e, nullptr, 1, HOP_INV, -0.5, dagger, pr, s);
     hop_apply(c, out_e, f.tmp_half.p, in_e, 0, HOP_CLOV, 0.5, dagger, pr, s);
 }
 
 // D in: out_p = A_pp in_p - 1/2 H in_{1-p} for both parities (NATIVE full vectors).
 void full_apply(dirac_ctx *c, void *out, const void *in, int dagger, dirac_prec pr, hipStream_t s) {
-    const size_t hb = (size_t)24 * real_size(pr) * c->vh;
+    const size_t hb = (size_t)24 * real_size(pr) * c->g.vhp;
     const char *ie = (const char *)in, *io = ie + hb;
     char *oe = (char *)out, *oo = oe + hb;
     hop_apply(c, oe, io, ie, 0, HOP_CLOV, -0.5, dagger, pr, s);

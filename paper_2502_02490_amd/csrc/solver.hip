@@ -61,10 +61,10 @@ void ensure_work(dirac_ctx *c, int m, dirac_prec inner) {
     }
     SolverWork &w = *c->work;
     w.blas.reserve(c->V, kMaxRestart);
-    const size_t half64 = (size_t)24 * 8 * c->vh;
+    const size_t half64 = (size_t)24 * 8 * c->g.vhp;
     for (auto &b : w.h64) b.alloc(half64);
     for (auto &b : w.f64) b.alloc(2 * half64);
-    const size_t hb = (size_t)24 * real_size(inner) * c->vh;
+    const size_t hb = (size_t)24 * real_size(inner) * c->g.vhp;
     w.P.alloc(hb * (m + 1));
     w.Q.alloc(hb * m);
     w.r.alloc(hb);
@@ -82,7 +82,7 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
            int max_iter, hipStream_t s) {
     Blas &B = w.blas;
     const double scale = 1.0 / (24.0 * (double)c->vh);
-    const size_t hb = (size_t)24 * real_size(pr) * c->vh;
+    const size_t hb = (size_t)24 * real_size(pr) * c->g.vhp;
     char *P = (char *)w.P.p, *Q = (char *)w.Q.p;
     void *r = w.r.p;
     GcrOut out;
@@ -204,7 +204,7 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
     SolverWork &w = *c->work;
     Blas &B = w.blas;
     const double scale = 1.0 / (24.0 * (double)c->vh);
-    const size_t half64 = (size_t)24 * 8 * c->vh;
+    const size_t half64 = (size_t)24 * 8 * c->g.vhp;
     char *bf = (char *)w.f64[0].p, *xf = (char *)w.f64[1].p, *rf = (char *)w.f64[2].p;
     char *be = bf, *bo = bf + half64, *xe = xf, *xo = xf + half64;
     void *eta = w.h64[0].p, *r64 = w.h64[2].p, *t64 = w.h64[3].p;
@@ -301,7 +301,7 @@ dirac_status solve_cgls(dirac_ctx *c, const dirac_solver_params *p, bool x0, dir
     const double scale = 1.0 / (24.0 * (double)c->vh);
     char *bf = (char *)w.f64[0].p, *xf = (char *)w.f64[1].p, *sv = (char *)w.f64[2].p;
     // CGLS needs three more full vectors: r, p, w (inside the inner-solver buffers, FP64)
-    const size_t full64 = (size_t)48 * 8 * c->vh;
+    const size_t full64 = (size_t)48 * 8 * c->g.vhp;
     w.P.alloc(3 * full64);
     char *rv = (char *)w.P.p, *pv = rv + full64, *wv = pv + full64;
     double *rho = sc_ptr(w, S_MISC + 8), *rho_new = sc_ptr(w, S_MISC + 10), *wn = sc_ptr(w, S_MISC + 12);
