@@ -70,12 +70,37 @@ def cpu_baseline(reps: int = 3):
                       f"1/32 of the volume), mean of {reps} applies, {dt:.2f} s each, clover set-up excluded"}
 
 
+def solve_suite(D, b, inner_precs):
+    """Time to |b - D x| / |b| < 1e-10: plain FP64 even-odd GCR(32), then FP64 defect correction
+    around FP32 / FP16 / BF16 inner GCR(32); each mixed solution is compared with the FP64 one."""
+    import torch
+
+    import paper_2502_02490_amd as P
+
+    res = {}
+    x64 = torch.zeros_like(b)
+    info = D.solve(x64, b, method=P.GCR, tol=1e-10, restart=32, max_iter=100000)
+    res["fp64_gcr"] = {"seconds": round(info.seconds, 4), "iters": info.iters, "restarts": info.restarts,
+                       "true_rel_res": info.true_rel_res}
+    nx = torch.linalg.vector_norm(x64).item()
+    for pr in inner_precs:
+        x = torch.zeros_like(b)
+        info = D.solve(x, b, method=P.MIXED_GCR, inner_prec=pr, tol=1e-10, restart=32, max_iter=100000)
+        res[f"mixed_{pr}"] = {"seconds": round(info.seconds, 4), "inner_iters": info.iters, "outer": info.outer,
+                              "fell_back": info.fell_back, "true_rel_res": info.true_rel_res,
+                              "rel_err_vs_fp64": torch.linalg.vector_norm(x - x64).item() / nx,
+                              "speedup_vs_fp64": round(res["fp64_gcr"]["seconds"] / info.seconds, 3)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the solve timings")
+    ap.add_argument("--no-48", action="store_true", help="skip the 48^3x96 mixed-precision solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the operator runs on a single MI355X (multi-GPU halo exchange is "
@@ -159,6 +184,26 @@ def main():
     extra["clover_f64_GBps"] = round(120 * 8 * vh * args.steps / tc / 1e9, 1)
     log(f"[bench] extra {extra}")
 
+    solves = {}
+    if not args.no_solve:
+        solves["32^3x64"] = solve_suite(D, torch.from_numpy(psi).cuda(), ("f32", "f16", "bf16"))
+        log(f"[bench] solves 32^3x64 {solves['32^3x64']}")
+    D.close()
+    del x, xe, ye, y, x32, xe32, ye32
+    torch.cuda.empty_cache()
+    if not args.no_solve and not args.no_48:
+        d3 = (96, 48, 48, 48)
+        t0 = time.perf_counter()
+        U3 = gen.su3_field(d3, EPS, 301)
+        th3 = gen.u1_field(d3, 0.3, 301)
+        b3 = gen.gaussian_spinor(d3, 301)
+        D3 = P.Dirac(torch.from_numpy(U3).cuda(), torch.from_numpy(th3).cuda(), d3, 0.1250, CSW, CSW_QED, 2)
+        del U3, th3
+        log(f"[bench] 48^3x96 set-up {time.perf_counter() - t0:.1f} s")
+        solves["48^3x96"] = solve_suite(D3, torch.from_numpy(b3).cuda(), ("f32", "f16", "bf16"))
+        log(f"[bench] solves 48^3x96 {solves['48^3x96']}")
+        D3.close()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline()
@@ -186,10 +231,10 @@ def main():
         "schur_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
         "gflops_schur": round(FLOP_SCHUR * vh * args.steps / t_schur / 1e9, 1),
         **extra,
+        "solve": solves,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    D.close()
 
 
 if __name__ == "__main__":

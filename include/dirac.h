@@ -161,7 +161,14 @@ dirac_status dirac_apply_clover(dirac_ctx *ctx, void *out, const void *in, int p
                                 dirac_prec prec, void *stream);
 
 /* ---------------------------------------------------------------- solvers */
-typedef enum { DIRAC_SOLVER_CGLS = 0, DIRAC_SOLVER_GCR = 1, DIRAC_SOLVER_MIXED_GCR = 2 } dirac_solver;
+typedef enum {
+    DIRAC_SOLVER_CGLS = 0,      /* CG on D^dag D, full lattice, FP64 */
+    DIRAC_SOLVER_GCR = 1,       /* even-odd GCR(restart), FP64 */
+    DIRAC_SOLVER_MIXED_GCR = 2, /* FP64 defect correction around an inner_prec even-odd GCR */
+    DIRAC_SOLVER_FGCR_PTC = 3   /* flexible GCR on the full D with a PTC network as preconditioner */
+} dirac_solver;
+
+typedef struct dirac_ptc dirac_ptc;  /* parallel-transport convolution network (see below) */
 
 typedef struct {
     int method;          /* dirac_solver */
@@ -171,7 +178,8 @@ typedef struct {
     int inner_prec;      /* MIXED_GCR: dirac_prec of the inner solve (F32, F16, BF16) */
     double inner_tol;    /* MIXED_GCR: relative reduction asked of each inner solve */
     int x0_given;        /* 1: x holds the initial guess */
-    int precision;       /* GCR / CGLS: dirac_prec of the whole solve (F64 or F32) */
+    int precision;       /* GCR / CGLS: dirac_prec of the whole solve (F64 only) */
+    const dirac_ptc *ptc; /* FGCR_PTC: the preconditioner network (trained weights) */
 } dirac_solver_params;
 
 typedef struct {
@@ -183,13 +191,45 @@ typedef struct {
     double seconds;       /* wall time of the call */
 } dirac_solve_info;
 
-/* Solve D psi = eta.  x (solution) and b (right-hand side) are full-lattice
- * vectors in `layout` (F64 for LEX/EO; NATIVE in the solve precision, or F64
- * for MIXED_GCR).  GCR and MIXED_GCR run on the even-odd Schur system and
- * reconstruct the odd half; CGLS runs on the full D.  Blocking.  Returns
- * DIRAC_ENOCONV (x = last iterate) when max_iter is reached first. */
+/* Solve D psi = eta.  x (solution) and b (right-hand side) are full-lattice FP64
+ * vectors in `layout`.  GCR and MIXED_GCR run on the even-odd Schur system and
+ * reconstruct the odd half; CGLS runs on the full D; FGCR_PTC runs flexible GCR
+ * on the full D with p_k = N(r_k) and falls back to even-odd GCR from the current
+ * iterate (info.fell_back = 1) when a cycle reduces the residual by less than 2x
+ * or meets a non-finite value.  Blocking.  Returns DIRAC_ENOCONV (x = last
+ * iterate) when max_iter is reached first. */
 dirac_status dirac_solve(dirac_ctx *ctx, void *x, const void *b, dirac_layout layout,
                          const dirac_solver_params *params, dirac_solve_info *info, void *stream);
+
+/* ---------------------------------------------------------------- learned preconditioner
+ * A gauge-covariant parallel-transport convolution (PTC) network N (a reading of the
+ * learned part; the paper has none):
+ *   y_c(x) = sum_{c'} sum_p W[p][c][c'] (T_p x_{c'})(x),  p = 0, +0, -0, +1, -1, +2, -2, +3, -3,
+ *   T_{+mu} psi(x) = V_mu(x) b+_mu(x) psi(x + mu),  T_{-mu} psi(x) = V_mu(x - mu)^dag b-_mu(x) psi(x - mu),
+ * W[p][c][c'] a complex 4x4 spin matrix; no nonlinearity, no bias.  Weights of layer l
+ * are [9][c_{l+1}][c_l][4][4] complex, stored as interleaved (re, im) float, layer after
+ * layer.  FP32 master weights, BF16 working weights, FP32 activations and accumulation.
+ * Activations and gradients are NATIVE F32 full-lattice vectors (one channel in and out).
+ * Training: loss L = mean_i |N(r_i) - e_i|^2 / |e_i|^2, gradients dL/dW* (Wirtinger),
+ * Adam (lr given, beta = 0.9, 0.999, eps = 1e-8) on (Re W, Im W). */
+dirac_status ptc_create(const int *channels, int nlayers, dirac_ptc **out);  /* channels[0] = channels[nlayers] = 1 */
+dirac_status ptc_destroy(dirac_ptc *net);
+size_t ptc_num_weights(const dirac_ptc *net);                                /* floats (2 per complex weight) */
+dirac_status ptc_set_weights(dirac_ptc *net, const float *host_w, size_t n); /* resets Adam state */
+dirac_status ptc_get_weights(const dirac_ptc *net, float *host_w, size_t n);
+dirac_status ptc_get_grad(const dirac_ptc *net, float *host_g, size_t n);   /* accumulated dL/dW* */
+dirac_status ptc_zero_grad(dirac_ptc *net, void *stream);
+/* out = N(in) */
+dirac_status ptc_forward(dirac_ctx *ctx, dirac_ptc *net, void *out, const void *in, void *stream);
+/* Given grad_out = dL/dN(in)*, accumulate dL/dW* into the network and, if grad_in is not
+ * NULL, write dL/d(in)*.  Recomputes the forward activations of `in`. */
+dirac_status ptc_backward(dirac_ctx *ctx, dirac_ptc *net, void *grad_in, const void *in, const void *grad_out,
+                          void *stream);
+dirac_status ptc_adam_step(dirac_ptc *net, double lr, void *stream);
+/* One minibatch step: zero the gradient, accumulate over the nbatch pairs (r[i], e[i])
+ * (NATIVE F32 full vectors), take one Adam step; *loss = L before the step.  Blocking. */
+dirac_status ptc_train_step(dirac_ctx *ctx, dirac_ptc *net, const void *const *r, const void *const *e, int nbatch,
+                            double lr, double *loss, void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *dirac_last_error(void);

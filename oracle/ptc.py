@@ -1,0 +1,161 @@
+"""Gauge-covariant parallel-transport convolution (PTC) network, FP64 reference.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The learned preconditioner is not in the paper; this is the reading of it that the library
+builds (after Lehner and Wettig, gauge-equivariant neural networks as preconditioners, 2023):
+
+  layer:   y_c(x) = sum_{c'} sum_{p in P} W[p, c, c'] (T_p x_{c'})(x)
+  paths:   P = (0, +0, -0, +1, -1, +2, -2, +3, -3)
+           T_0 = 1
+           T_{+mu} psi(x) = V_mu(x) b+_mu(x) psi(x + mu)
+           T_{-mu} psi(x) = V_mu(x - mu)^dag b-_mu(x) psi(x - mu)
+  W[p, c, c'] is a complex 4x4 matrix acting on spin (colour untouched, hence gauge
+  equivariant); channels 1 -> 8 -> 8 -> 1, no nonlinearity, no bias.
+  loss:    L = mean_i |N(r_i) - e_i|^2 / |e_i|^2
+  gradients (Wirtinger, L real):  with g = dL/dy*,
+           dL/dx*_{c'} = sum_{p, c} T_p^dag W[p, c, c']^dag g_c
+           dL/dW*[p, c, c'] = sum_{x, colour} g_c(x) (T_p x_{c'})(x)^dag
+  The adjoint transport is T_{+mu}^dag = T_{-mu}.
+  A real parameter w = Re W or Im W has dL/dw = 2 Re(dL/dW*) or 2 Im(dL/dW*).
+  Adam (Kingma and Ba 2015) on the real and imaginary parts.
+Fields are full LEX spinor fields [V, 4, 3]; weights of a layer are [9, n_out, n_in, 4, 4].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import dirac
+from . import geometry as geo
+
+PATHS = [(None, 0), (0, 1), (0, -1), (1, 1), (1, -1), (2, 1), (2, -1), (3, 1), (3, -1)]
+NPATH = len(PATHS)
+ADJ = [0, 2, 1, 4, 3, 6, 5, 8, 7]  # T_p^dag = T_{ADJ[p]}
+
+
+def transport(f: dirac.Fields, psi: np.ndarray, p: int) -> np.ndarray:
+    """T_p psi for a full LEX field psi [V, 4, 3]."""
+    mu, d = PATHS[p]
+    if mu is None:
+        return psi.copy()
+    L = f.p.dims
+    sites = np.arange(f.V)
+    x = geo.coords(sites, L)
+    phi = f.p.bc_phase[mu]
+    if d > 0:
+        nb = geo.shift(sites, L, mu, 1)
+        b = np.where(x[:, mu] == L[mu] - 1, np.exp(1j * phi), 1.0)
+        return b[:, None, None] * np.einsum("nab,nsb->nsa", f.Vlink[:, mu], psi[nb])
+    nb = geo.shift(sites, L, mu, -1)
+    b = np.where(x[:, mu] == 0, np.exp(-1j * phi), 1.0)
+    Vd = np.conj(np.swapaxes(f.Vlink[nb, mu], -1, -2))
+    return b[:, None, None] * np.einsum("nab,nsb->nsa", Vd, psi[nb])
+
+
+def layer(f: dirac.Fields, W: np.ndarray, xs) -> list:
+    """y_c = sum_{c', p} W[p, c, c'] T_p x_{c'}; xs a list of n_in fields, W [9, n_out, n_in, 4, 4]."""
+    n_out, n_in = W.shape[1], W.shape[2]
+    assert len(xs) == n_in
+    ys = [np.zeros_like(xs[0]) for _ in range(n_out)]
+    for cp in range(n_in):
+        for p in range(NPATH):
+            t = transport(f, xs[cp], p)
+            for c in range(n_out):
+                ys[c] += np.einsum("st,ntc->nsc", W[p, c, cp], t)
+    return ys
+
+
+def forward(f: dirac.Fields, weights, r: np.ndarray):
+    """N(r) and the activations of every layer (inputs of layer l are acts[l])."""
+    acts = [[r]]
+    for W in weights:
+        acts.append(layer(f, W, acts[-1]))
+    return acts[-1][0], acts
+
+
+def backward(f: dirac.Fields, weights, acts, g_out: np.ndarray):
+    """Given g = dL/dN(r)*, return (dL/dr*, [dL/dW*] per layer)."""
+    grads = [None] * len(weights)
+    g = [g_out]
+    for l in range(len(weights) - 1, -1, -1):
+        W = weights[l]
+        xs = acts[l]
+        n_out, n_in = W.shape[1], W.shape[2]
+        gW = np.zeros_like(W)
+        gx = [np.zeros_like(xs[0]) for _ in range(n_in)]
+        for cp in range(n_in):
+            for p in range(NPATH):
+                t = transport(f, xs[cp], p)
+                for c in range(n_out):
+                    # dL/dW*[p, c, c'] = sum_{x, colour} g_c (T_p x_{c'})^dag
+                    gW[p, c, cp] += np.einsum("nsa,nta->st", g[c], np.conj(t))
+        for cp in range(n_in):
+            for p in range(NPATH):
+                acc = np.zeros_like(xs[0])
+                for c in range(n_out):
+                    acc += np.einsum("ts,nta->nsa", np.conj(W[p, c, cp]), g[c])  # W^dag g
+                gx[cp] += transport(f, acc, ADJ[p])  # T_p^dag = T_{ADJ[p]}
+        grads[l] = gW
+        g = gx
+    return g[0], grads
+
+
+def loss_and_grads(f: dirac.Fields, weights, pairs):
+    """L = mean_i |N(r_i) - e_i|^2 / |e_i|^2 and dL/dW* per layer."""
+    total = 0.0
+    gsum = [np.zeros_like(W) for W in weights]
+    n = len(pairs)
+    for r, e in pairs:
+        y, acts = forward(f, weights, r)
+        ne2 = np.vdot(e, e).real
+        d = y - e
+        total += np.vdot(d, d).real / ne2 / n
+        _, gw = backward(f, weights, acts, d / ne2 / n)
+        for k in range(len(weights)):
+            gsum[k] += gw[k]
+    return total, gsum
+
+
+def dirac_as_layer(f: dirac.Fields) -> np.ndarray:
+    """The single 1 -> 1 layer that equals D when the clover term vanishes:
+    W_0 = (4 + m0) 1, W_{+mu} = -1/2 (1 - gamma_mu), W_{-mu} = -1/2 (1 + gamma_mu)."""
+    W = np.zeros((NPATH, 1, 1, 4, 4), dtype=np.complex128)
+    W[0, 0, 0] = (4.0 + f.p.m0) * np.eye(4)
+    for p in range(1, NPATH):
+        mu, d = PATHS[p]
+        W[p, 0, 0] = -0.5 * (dirac.ONE4 - d * dirac.GAMMA[mu])
+    return W
+
+
+def init_weights(channels, seed: int, scale: float = 0.1):
+    """Random complex weights [9, c_out, c_in, 4, 4] per layer, N(0, scale^2 / fan_in) per real part."""
+    rng = np.random.default_rng(seed)
+    ws = []
+    for cin, cout in zip(channels[:-1], channels[1:]):
+        s = scale / np.sqrt(NPATH * cin)
+        ws.append(s * (rng.normal(size=(NPATH, cout, cin, 4, 4)) + 1j * rng.normal(size=(NPATH, cout, cin, 4, 4))))
+    return ws
+
+
+class Adam:
+    """Adam on the real and imaginary parts of complex weights (Kingma and Ba 2015)."""
+
+    def __init__(self, weights, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
+        self.m = [np.zeros(W.shape + (2,)) for W in weights]
+        self.v = [np.zeros(W.shape + (2,)) for W in weights]
+        self.t = 0
+
+    def step(self, weights, grads_conj):
+        """grads_conj: dL/dW*; the real gradient of (Re W, Im W) is 2 (Re, Im) of it."""
+        self.t += 1
+        out = []
+        for k, (W, G) in enumerate(zip(weights, grads_conj)):
+            g = 2.0 * np.stack([G.real, G.imag], axis=-1)
+            self.m[k] = self.b1 * self.m[k] + (1 - self.b1) * g
+            self.v[k] = self.b2 * self.v[k] + (1 - self.b2) * g * g
+            mh = self.m[k] / (1 - self.b1 ** self.t)
+            vh = self.v[k] / (1 - self.b2 ** self.t)
+            w = np.stack([W.real, W.imag], axis=-1) - self.lr * mh / (np.sqrt(vh) + self.eps)
+            out.append(w[..., 0] + 1j * w[..., 1])
+        return out

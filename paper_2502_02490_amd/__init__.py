@@ -12,8 +12,8 @@ import math
 import torch
 
 from . import _lib
-from ._lib import (BF16, CGLS, EO, F16, F32, F64, GCR, LEX, MIXED_GCR, NATIVE, DiracError,  # noqa: F401
-                   SolveInfo, SolverParams)
+from ._lib import (BF16, CGLS, EO, F16, F32, F64, FGCR_PTC, GCR, LEX, MIXED_GCR, NATIVE,  # noqa: F401
+                   DiracError, SolveInfo, SolverParams)
 
 _TORCH_REAL = {F64: torch.float64, F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
 _TORCH_USER = {F64: torch.complex128, F32: torch.complex64, F16: torch.complex128, BF16: torch.complex128}
@@ -29,11 +29,15 @@ def _layout(l):
     return _LAYOUT[l] if isinstance(l, str) else int(l)
 
 
-def _ptr(t: torch.Tensor):
+def _ptr(t: torch.Tensor, nbytes: int = 0):
+    """Device address of a contiguous GPU tensor holding at least nbytes (the library can only
+    check the size of the underlying allocation, not of a tensor carved out of it)."""
     if not t.is_cuda:
         raise ValueError("tensors passed to the library must live on the GPU")
     if not t.is_contiguous():
         raise ValueError("tensors passed to the library must be contiguous")
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"tensor of {t.numel() * t.element_size()} bytes where {nbytes} are needed")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -62,7 +66,8 @@ class Dirac:
         p.kappa, p.csw, p.csw_qed, p.qhat = float(kappa), float(csw), float(csw_qed), int(qhat)
         self.params = p
         self._ctx = ctypes.c_void_p()
-        st = self.lib.dirac_create(ctypes.byref(p), _ptr(U), _ptr(theta) if theta is not None else None,
+        st = self.lib.dirac_create(ctypes.byref(p), _ptr(U, self.V * 576),
+                                   _ptr(theta, self.V * 32) if theta is not None else None,
                                    _stream(stream), ctypes.byref(self._ctx))
         self.singular = st == _lib.ESINGULAR
         if st != _lib.OK and not (self.singular and allow_singular and self._ctx.value):
@@ -91,6 +96,16 @@ class Dirac:
         self.close()
 
     # -------------------------------------------------------------- buffers
+    def native_bytes(self, prec="f64", sites: int = 0) -> int:
+        return int(self.lib.dirac_native_bytes(self._ctx, _prec(prec), sites))
+
+    def user_bytes(self, prec="f64", sites: int = 0) -> int:
+        n = self.V if sites == 0 else self.vh
+        return n * 24 * (4 if _prec(prec) == F32 else 8)
+
+    def _vec_bytes(self, prec, layout, sites):
+        return self.native_bytes(prec, sites) if _layout(layout) == NATIVE else self.user_bytes(prec, sites)
+
     def native_empty(self, prec="f64", sites: int = 0) -> torch.Tensor:
         """A NATIVE vector: sites = 0 full lattice, 1 one parity."""
         pr = _prec(prec)
@@ -100,7 +115,9 @@ class Dirac:
     def to_native(self, user: torch.Tensor, prec="f64", layout="lex", sites: int = 0, out=None, stream=None):
         pr = _prec(prec)
         out = self.native_empty(pr, 0 if sites == 0 else 1) if out is None else out
-        _lib.check(self.lib.dirac_import(self._ctx, _ptr(out), _ptr(user), sites, pr, _layout(layout), _stream(stream)))
+        _lib.check(self.lib.dirac_import(self._ctx, _ptr(out, self.native_bytes(pr, min(sites, 1))),
+                                         _ptr(user, self.user_bytes(pr, sites)), sites, pr, _layout(layout),
+                                         _stream(stream)))
         return out
 
     def from_native(self, native: torch.Tensor, prec="f64", layout="lex", sites: int = 0, out=None, stream=None):
@@ -108,31 +125,37 @@ class Dirac:
         n = self.V if sites == 0 else self.vh
         out = torch.empty((n, 4, 3), dtype=_TORCH_USER[pr] if pr == F32 else torch.complex128,
                           device="cuda") if out is None else out
-        _lib.check(self.lib.dirac_export(self._ctx, _ptr(out), _ptr(native), sites, pr, _layout(layout), _stream(stream)))
+        _lib.check(self.lib.dirac_export(self._ctx, _ptr(out, self.user_bytes(pr, sites)),
+                                         _ptr(native, self.native_bytes(pr, min(sites, 1))), sites, pr,
+                                         _layout(layout), _stream(stream)))
         return out
 
     # -------------------------------------------------------------- operators
     def apply(self, out, inp, prec="f64", layout="lex", dagger=False, stream=None):
         """out = D inp (full lattice)."""
-        _lib.check(self.lib.dirac_apply(self._ctx, _ptr(out), _ptr(inp), _prec(prec), _layout(layout), int(dagger),
-                                        _stream(stream)))
+        nb = self._vec_bytes(prec, layout, 0)
+        _lib.check(self.lib.dirac_apply(self._ctx, _ptr(out, nb), _ptr(inp, nb), _prec(prec), _layout(layout),
+                                        int(dagger), _stream(stream)))
         return out
 
     def apply_eo(self, out, inp, prec="f64", layout="eo", dagger=False, stream=None):
         """out_e = D-hat inp_e (even-odd Schur operator on even half-vectors)."""
-        _lib.check(self.lib.dirac_apply_eo(self._ctx, _ptr(out), _ptr(inp), _prec(prec), _layout(layout), int(dagger),
-                                           _stream(stream)))
+        nb = self._vec_bytes(prec, layout, 1)
+        _lib.check(self.lib.dirac_apply_eo(self._ctx, _ptr(out, nb), _ptr(inp, nb), _prec(prec), _layout(layout),
+                                           int(dagger), _stream(stream)))
         return out
 
     def apply_hop(self, out, inp, out_parity: int, prec="f64", dagger=False, stream=None):
         """out_p = D_{p,1-p} inp = -1/2 H inp (NATIVE half-vectors)."""
-        _lib.check(self.lib.dirac_apply_hop(self._ctx, _ptr(out), _ptr(inp), int(out_parity), _prec(prec),
+        nb = self.native_bytes(prec, 1)
+        _lib.check(self.lib.dirac_apply_hop(self._ctx, _ptr(out, nb), _ptr(inp, nb), int(out_parity), _prec(prec),
                                             int(dagger), _stream(stream)))
         return out
 
     def apply_clover(self, out, inp, parity: int, inverse=False, prec="f64", stream=None):
         """out_p = A_pp inp or A_pp^-1 inp (NATIVE half-vectors)."""
-        _lib.check(self.lib.dirac_apply_clover(self._ctx, _ptr(out), _ptr(inp), int(parity), int(inverse),
+        nb = self.native_bytes(prec, 1)
+        _lib.check(self.lib.dirac_apply_clover(self._ctx, _ptr(out, nb), _ptr(inp, nb), int(parity), int(inverse),
                                                _prec(prec), _stream(stream)))
         return out
 
@@ -140,27 +163,123 @@ class Dirac:
     def clover(self, inverse=False, layout="lex", stream=None) -> torch.Tensor:
         """Packed clover field (or inverse) [V, 2, 36] float64 (Sec. 4.1.3 packing)."""
         out = torch.empty((self.V, 2, 36), dtype=torch.float64, device="cuda")
-        _lib.check(self.lib.dirac_get_clover(self._ctx, _ptr(out), int(inverse), _layout(layout), _stream(stream)))
+        _lib.check(self.lib.dirac_get_clover(self._ctx, _ptr(out, self.V * 576), int(inverse), _layout(layout),
+                                             _stream(stream)))
         return out
 
     def load_clover(self, packed: torch.Tensor, layout="lex", stream=None):
-        _lib.check(self.lib.dirac_load_clover(self._ctx, _ptr(packed), _layout(layout), _stream(stream)))
+        _lib.check(self.lib.dirac_load_clover(self._ctx, _ptr(packed, self.V * 576), _layout(layout), _stream(stream)))
 
     def clover_invert(self, parity_mask: int = 2, stream=None):
         _lib.check(self.lib.clover_invert(self._ctx, int(parity_mask), _stream(stream)))
 
     # -------------------------------------------------------------- solvers
     def solve(self, x, b, method=GCR, tol=1e-10, restart=32, max_iter=10000, layout="lex", precision="f64",
-              inner_prec="f32", inner_tol=None, x0_given=False, stream=None, raise_on_noconv=True):
+              inner_prec="f32", inner_tol=None, x0_given=False, ptc=None, stream=None, raise_on_noconv=True):
+        """Solve D x = b (full-lattice FP64 vectors in `layout`); returns the SolveInfo."""
         sp = SolverParams()
         sp.method, sp.restart, sp.max_iter, sp.tol = int(method), int(restart), int(max_iter), float(tol)
         sp.inner_prec = _prec(inner_prec)
         sp.inner_tol = float(inner_tol) if inner_tol is not None else 0.0
         sp.x0_given, sp.precision = int(x0_given), _prec(precision)
+        sp.ptc = ptc._net if ptc is not None else None
         info = SolveInfo()
-        st = self.lib.dirac_solve(self._ctx, _ptr(x), _ptr(b), _layout(layout), ctypes.byref(sp), ctypes.byref(info),
-                                  _stream(stream))
+        nb = self._vec_bytes("f64", layout, 0)
+        st = self.lib.dirac_solve(self._ctx, _ptr(x, nb), _ptr(b, nb), _layout(layout), ctypes.byref(sp),
+                                  ctypes.byref(info), _stream(stream))
         if st == _lib.ENOCONV and not raise_on_noconv:
             return info
         _lib.check(st)
         return info
+
+
+class PTC:
+    """Parallel-transport convolution network (the learned preconditioner), e.g. channels (1, 8, 8, 1).
+
+    Weights: complex [9][c_out][c_in][4][4] per layer; get/set as numpy complex64 arrays."""
+
+    def __init__(self, channels=(1, 8, 8, 1)):
+        self.lib = _lib.load()
+        self.channels = tuple(int(c) for c in channels)
+        arr = (ctypes.c_int * len(self.channels))(*self.channels)
+        self._net = ctypes.c_void_p()
+        _lib.check(self.lib.ptc_create(arr, len(self.channels) - 1, ctypes.byref(self._net)))
+        self.n = int(self.lib.ptc_num_weights(self._net))
+
+    def shapes(self):
+        return [(9, co, ci, 4, 4) for ci, co in zip(self.channels[:-1], self.channels[1:])]
+
+    def _flat(self, layers):
+        import numpy as np
+
+        flat = np.concatenate([np.asarray(w, dtype=np.complex64).reshape(-1) for w in layers])
+        if flat.size * 2 != self.n:
+            raise ValueError("weight shapes do not match the network")
+        return np.ascontiguousarray(flat.view(np.float32))
+
+    def _unflat(self, flat):
+        import numpy as np
+
+        c = flat.view(np.complex64)
+        out, o = [], 0
+        for sh in self.shapes():
+            k = int(np.prod(sh))
+            out.append(c[o:o + k].reshape(sh).copy())
+            o += k
+        return out
+
+    def set_weights(self, layers):
+        flat = self._flat(layers)
+        _lib.check(self.lib.ptc_set_weights(self._net, flat.ctypes.data_as(ctypes.c_void_p), flat.size))
+
+    def get_weights(self):
+        import numpy as np
+
+        flat = np.empty(self.n, dtype=np.float32)
+        _lib.check(self.lib.ptc_get_weights(self._net, flat.ctypes.data_as(ctypes.c_void_p), self.n))
+        return self._unflat(flat)
+
+    def get_grad(self):
+        import numpy as np
+
+        flat = np.empty(self.n, dtype=np.float32)
+        _lib.check(self.lib.ptc_get_grad(self._net, flat.ctypes.data_as(ctypes.c_void_p), self.n))
+        return self._unflat(flat)
+
+    def zero_grad(self, stream=None):
+        _lib.check(self.lib.ptc_zero_grad(self._net, _stream(stream)))
+
+    def forward(self, D: Dirac, out, inp, stream=None):
+        nb = D.native_bytes("f32", 0)
+        _lib.check(self.lib.ptc_forward(D._ctx, self._net, _ptr(out, nb), _ptr(inp, nb), _stream(stream)))
+        return out
+
+    def backward(self, D: Dirac, grad_in, inp, grad_out, stream=None):
+        nb = D.native_bytes("f32", 0)
+        _lib.check(self.lib.ptc_backward(D._ctx, self._net, _ptr(grad_in, nb) if grad_in is not None else None,
+                                         _ptr(inp, nb), _ptr(grad_out, nb), _stream(stream)))
+
+    def adam_step(self, lr, stream=None):
+        _lib.check(self.lib.ptc_adam_step(self._net, float(lr), _stream(stream)))
+
+    def train_step(self, D: Dirac, rs, es, lr, stream=None) -> float:
+        nb = D.native_bytes("f32", 0)
+        n = len(rs)
+        ra = (ctypes.c_void_p * n)(*[_ptr(r, nb).value for r in rs])
+        ea = (ctypes.c_void_p * n)(*[_ptr(e, nb).value for e in es])
+        loss = ctypes.c_double()
+        _lib.check(self.lib.ptc_train_step(D._ctx, self._net, ra, ea, n, float(lr), ctypes.byref(loss),
+                                           _stream(stream)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_net", None) is not None and self._net.value:
+            torch.cuda.synchronize()
+            _lib.check(self.lib.ptc_destroy(self._net))
+            self._net = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

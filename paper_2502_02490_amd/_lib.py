@@ -12,12 +12,14 @@ STATUS_NAMES = ["DIRAC_OK", "DIRAC_EINVAL", "DIRAC_ENOMEM", "DIRAC_EHIP", "DIRAC
                 "DIRAC_ENONFINITE", "DIRAC_EUNSUPPORTED"]
 F64, F32, F16, BF16 = 0, 1, 2, 3
 LEX, EO, NATIVE = 0, 1, 2
-CGLS, GCR, MIXED_GCR = 0, 1, 2
+CGLS, GCR, MIXED_GCR, FGCR_PTC = 0, 1, 2, 3
 
 # every symbol declared in include/dirac.h
 EXPORTS = ["dirac_create", "dirac_destroy", "dirac_load_clover", "dirac_get_clover", "clover_invert",
            "dirac_native_bytes", "dirac_import", "dirac_export", "dirac_apply", "dirac_apply_eo",
-           "dirac_apply_hop", "dirac_apply_clover", "dirac_solve", "dirac_last_error"]
+           "dirac_apply_hop", "dirac_apply_clover", "dirac_solve", "dirac_last_error",
+           "ptc_create", "ptc_destroy", "ptc_num_weights", "ptc_set_weights", "ptc_get_weights", "ptc_get_grad",
+           "ptc_zero_grad", "ptc_forward", "ptc_backward", "ptc_adam_step", "ptc_train_step"]
 
 
 class Params(ctypes.Structure):
@@ -28,7 +30,7 @@ class Params(ctypes.Structure):
 class SolverParams(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("x0_given", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("x0_given", ctypes.c_int), ("precision", ctypes.c_int), ("ptc", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -71,8 +73,20 @@ def load(path: str = LIB_PATH):
     lib.dirac_apply_clover.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(SolverParams), ctypes.POINTER(SolveInfo), vp]
     lib.dirac_last_error.restype = ctypes.c_char_p
+    lib.ptc_create.argtypes = [vp, i, ctypes.POINTER(vp)]
+    lib.ptc_destroy.argtypes = [vp]
+    lib.ptc_num_weights.argtypes = [vp]
+    lib.ptc_num_weights.restype = ctypes.c_size_t
+    lib.ptc_set_weights.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.ptc_get_weights.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.ptc_get_grad.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.ptc_zero_grad.argtypes = [vp, vp]
+    lib.ptc_forward.argtypes = [vp, vp, vp, vp, vp]
+    lib.ptc_backward.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.ptc_adam_step.argtypes = [vp, ctypes.c_double, vp]
+    lib.ptc_train_step.argtypes = [vp, vp, vp, vp, i, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
     for name in EXPORTS:
-        if name not in ("dirac_native_bytes", "dirac_last_error"):
+        if name not in ("dirac_native_bytes", "dirac_last_error", "ptc_num_weights"):
             getattr(lib, name).restype = st
     _lib = lib
     return lib

@@ -7,7 +7,9 @@
 #include <new>
 #include <string>
 
+#include "blas.h"
 #include "internal.h"
+#include "ptc.h"
 
 namespace {
 
@@ -325,7 +327,7 @@ dirac_status dirac_solve(dirac_ctx *c, void *x, const void *b, dirac_layout lay,
     check_dev(x, nb, "x");
     check_no_alias(x, nb, b, nb);
     const dirac_prec inner = p->method == DIRAC_SOLVER_MIXED_GCR ? (dirac_prec)p->inner_prec : DIRAC_F64;
-    dl::ensure_work(c, p->method == DIRAC_SOLVER_CGLS ? 1 : p->restart, inner);
+    dl::ensure_work(c, p->method == DIRAC_SOLVER_CGLS ? 1 : p->restart, inner, 1);
     void *bn = dl::solver_full64(c, 0), *xn = dl::solver_full64(c, 1);
     if (lay == DIRAC_LAYOUT_NATIVE) {
         HIP_CHECK(hipMemcpyAsync(bn, b, nb, hipMemcpyDeviceToDevice, s));
@@ -348,6 +350,168 @@ dirac_status dirac_solve(dirac_ctx *c, void *x, const void *b, dirac_layout lay,
                  info->true_rel_res);
         return fail(st, st == DIRAC_ENONFINITE ? std::string("non-finite value in the solve; ") + msg : msg);
     }
+    API_END
+}
+
+// ---------------------------------------------------------------- learned preconditioner
+dirac_status ptc_create(const int *channels, int nlayers, dirac_ptc **out) {
+    API_BEGIN
+    require(channels != nullptr && out != nullptr, "channels and out must not be NULL");
+    require(nlayers >= 1 && nlayers <= 8, "nlayers must be 1..8");
+    require(channels[0] == 1 && channels[nlayers] == 1, "the network maps one channel to one channel");
+    for (int l = 0; l <= nlayers; ++l)
+        require(channels[l] == 1 || channels[l] == 2 || channels[l] == 4 || channels[l] == 8,
+                "channel counts must be 1, 2, 4 or 8");
+    dirac_ptc *n = new dirac_ptc();
+    n->nlayers = nlayers;
+    for (int l = 0; l <= nlayers; ++l) n->ch[l] = channels[l];
+    try {
+        dl::ptc_alloc(n);
+    } catch (...) {
+        delete n;
+        throw;
+    }
+    *out = n;
+    API_END
+}
+
+dirac_status ptc_destroy(dirac_ptc *n) {
+    API_BEGIN
+    if (!n) return DIRAC_OK;
+    (void)hipDeviceSynchronize();
+    for (dl::DevBuf *b : {&n->w, &n->wbf, &n->wt, &n->grad, &n->m, &n->v, &n->acts, &n->gbuf, &n->part}) b->release();
+    delete n;
+    API_END
+}
+
+size_t ptc_num_weights(const dirac_ptc *n) { return n ? 2 * n->total : 0; }
+
+dirac_status ptc_set_weights(dirac_ptc *n, const float *host_w, size_t cnt) {
+    API_BEGIN
+    require(n != nullptr && host_w != nullptr, "network and weights must not be NULL");
+    require(cnt == 2 * n->total, "weight count must equal ptc_num_weights");
+    HIP_CHECK(hipMemcpy(n->w.p, host_w, cnt * sizeof(float), hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemset(n->m.p, 0, cnt * sizeof(float)));
+    HIP_CHECK(hipMemset(n->v.p, 0, cnt * sizeof(float)));
+    n->step = 0;
+    dl::ptc_refresh_bf16(n, nullptr);
+    HIP_CHECK(hipDeviceSynchronize());
+    API_END
+}
+
+dirac_status ptc_get_weights(const dirac_ptc *n, float *host_w, size_t cnt) {
+    API_BEGIN
+    require(n != nullptr && host_w != nullptr, "network and buffer must not be NULL");
+    require(cnt == 2 * n->total, "weight count must equal ptc_num_weights");
+    HIP_CHECK(hipDeviceSynchronize());
+    HIP_CHECK(hipMemcpy(host_w, n->w.p, cnt * sizeof(float), hipMemcpyDeviceToHost));
+    API_END
+}
+
+dirac_status ptc_get_grad(const dirac_ptc *n, float *host_g, size_t cnt) {
+    API_BEGIN
+    require(n != nullptr && host_g != nullptr, "network and buffer must not be NULL");
+    require(cnt == 2 * n->total, "gradient count must equal ptc_num_weights");
+    HIP_CHECK(hipDeviceSynchronize());
+    HIP_CHECK(hipMemcpy(host_g, n->grad.p, cnt * sizeof(float), hipMemcpyDeviceToHost));
+    API_END
+}
+
+dirac_status ptc_zero_grad(dirac_ptc *n, void *stream) {
+    API_BEGIN
+    require(n != nullptr, "network is NULL");
+    n->grad_zero((hipStream_t)stream);
+    API_END
+}
+
+dirac_status ptc_forward(dirac_ctx *c, dirac_ptc *n, void *out, const void *in, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    require(n != nullptr, "network is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = native_bytes(c, DIRAC_F32, 0);
+    check_dev(in, nb, "in");
+    check_dev(out, nb, "out");
+    check_no_alias(out, nb, in, nb);
+    dl::ptc_ensure_acts(c, n);
+    HIP_CHECK(hipMemcpyAsync(dl::ptc_act(c, n, 0), in, nb, hipMemcpyDeviceToDevice, s));
+    dl::ptc_forward_acts(c, n, s);
+    HIP_CHECK(hipMemcpyAsync(out, dl::ptc_act(c, n, n->nlayers), nb, hipMemcpyDeviceToDevice, s));
+    API_END
+}
+
+dirac_status ptc_backward(dirac_ctx *c, dirac_ptc *n, void *grad_in, const void *in, const void *grad_out,
+                          void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    require(n != nullptr, "network is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = native_bytes(c, DIRAC_F32, 0);
+    check_dev(in, nb, "in");
+    check_dev(grad_out, nb, "grad_out");
+    if (grad_in) {
+        check_dev(grad_in, nb, "grad_in");
+        check_no_alias(grad_in, nb, in, nb);
+        check_no_alias(grad_in, nb, grad_out, nb);
+    }
+    dl::ptc_ensure_acts(c, n);
+    HIP_CHECK(hipMemcpyAsync(dl::ptc_act(c, n, 0), in, nb, hipMemcpyDeviceToDevice, s));
+    dl::ptc_forward_acts(c, n, s);
+    dl::ptc_backward_acts(c, n, grad_out, grad_in, s);
+    API_END
+}
+
+dirac_status ptc_adam_step(dirac_ptc *n, double lr, void *stream) {
+    API_BEGIN
+    require(n != nullptr, "network is NULL");
+    require(std::isfinite(lr) && lr > 0.0, "learning rate must be positive");
+    dl::ptc_adam(n, lr, (hipStream_t)stream);
+    API_END
+}
+
+dirac_status ptc_train_step(dirac_ctx *c, dirac_ptc *n, const void *const *r, const void *const *e, int nbatch,
+                            double lr, double *loss, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    require(n != nullptr && r != nullptr && e != nullptr && loss != nullptr, "NULL argument");
+    require(nbatch >= 1, "nbatch must be positive");
+    require(std::isfinite(lr) && lr > 0.0, "learning rate must be positive");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = native_bytes(c, DIRAC_F32, 0);
+    for (int i = 0; i < nbatch; ++i) {
+        check_dev(r[i], nb, "r[i]");
+        check_dev(e[i], nb, "e[i]");
+    }
+    dl::ptc_ensure_acts(c, n);
+    dl::ensure_work(c, 1, DIRAC_F32, 2);
+    n->grad_zero(s);
+    dl::Blas &B = c->work->blas;
+    double *sc = (double *)B.scal.p + 15000;
+    const double scale = 1.0 / (24.0 * (double)c->vh);
+    double total = 0.0;
+    void *g = c->work->P.p;  // dL/dy* of the current pair (F32 full)
+    for (int i = 0; i < nbatch; ++i) {
+        HIP_CHECK(hipMemcpyAsync(dl::ptc_act(c, n, 0), r[i], nb, hipMemcpyDeviceToDevice, s));
+        dl::ptc_forward_acts(c, n, s);
+        const void *y = dl::ptc_act(c, n, n->nlayers);
+        B.mdot(DIRAC_F32, 2, e[i], 0, 1, e[i], sc, scale, s);
+        double ne2 = 0.0;
+        HIP_CHECK(hipMemcpyAsync(&ne2, sc, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        require(std::isfinite(ne2) && ne2 > 0.0, "target e is zero or not finite", DIRAC_ENONFINITE);
+        // g = (y - e) / (|e|^2 nbatch), with |.|^2 in the normalised norm (the factor cancels in L)
+        const double f = 1.0 / (ne2 / scale * nbatch);
+        B.lincomb(DIRAC_F32, DIRAC_F32, DIRAC_F32, 2, g, nullptr, f, y, -f, e[i], sc + 2, 1.0, s);
+        double gn = 0.0;
+        HIP_CHECK(hipMemcpyAsync(&gn, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        total += gn / (f * f) / (ne2 / scale) / nbatch;  // |y - e|^2 / |e|^2 / nbatch
+        dl::ptc_backward_acts(c, n, g, nullptr, s);
+    }
+    dl::ptc_adam(n, lr, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    *loss = total;
+    require(std::isfinite(total), "non-finite loss", DIRAC_ENONFINITE);
     API_END
 }
 

@@ -112,7 +112,7 @@ void full_apply(dirac_ctx *c, void *out, const void *in, int dagger, dirac_prec 
 
 // solver.hip
 void free_solver_work(dirac_ctx *c);
-void ensure_work(dirac_ctx *c, int restart, dirac_prec inner);
+void ensure_work(dirac_ctx *c, int restart, dirac_prec inner, int nh);
 void *solver_full64(dirac_ctx *c, int k);  // NATIVE FP64 full vectors: 0 = b, 1 = x, 2 = scratch
 dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, dirac_solve_info *info,
                           hipStream_t s);

@@ -14,20 +14,13 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <functional>
 #include <vector>
 
 #include "blas.h"
+#include "ptc.h"
 
 namespace dl {
-
-struct SolverWork {
-    Blas blas;
-    DevBuf P, Q, r, e, b;   // inner solver, inner precision
-    DevBuf h64[4];          // FP64 half vectors: eta-hat, x_e, r, tmp
-    DevBuf f64[3];          // FP64 full vectors: b, x, r
-    int m = 0;
-    dirac_prec pr = DIRAC_F64;
-};
 
 namespace {
 
@@ -37,9 +30,12 @@ constexpr int kMaxRestart = 64;
 
 struct GcrOut {
     int iters = 0, restarts = 0;
-    bool converged = false, nonfinite = false;
+    bool converged = false, nonfinite = false, stagnated = false;
     double rnorm = 0.0;  // normalised norm of the last true residual
 };
+
+// p = M(r) for flexible GCR; vectors in the solve precision and shape
+using Precond = std::function<void(void *p, const void *r)>;
 
 double *sc_ptr(SolverWork &w, int slot) { return (double *)w.blas.scal.p + slot; }
 
@@ -54,7 +50,7 @@ double read_scalar(SolverWork &w, int slot, hipStream_t s) {
 
 // Solver buffers; they only grow, so a later call with a wider precision or a longer
 // restart reallocates (contents are not kept across calls).
-void ensure_work(dirac_ctx *c, int m, dirac_prec inner) {
+void ensure_work(dirac_ctx *c, int m, dirac_prec inner, int nh) {
     if (!c->work) {
         c->work = new SolverWork();
         c->work->blas.c = c;
@@ -64,7 +60,7 @@ void ensure_work(dirac_ctx *c, int m, dirac_prec inner) {
     const size_t half64 = (size_t)24 * 8 * c->g.vhp;
     for (auto &b : w.h64) b.alloc(half64);
     for (auto &b : w.f64) b.alloc(2 * half64);
-    const size_t hb = (size_t)24 * real_size(inner) * c->g.vhp;
+    const size_t hb = (size_t)nh * 24 * real_size(inner) * c->g.vhp;
     w.P.alloc(hb * (m + 1));
     w.Q.alloc(hb * m);
     w.r.alloc(hb);
@@ -76,22 +72,29 @@ void ensure_work(dirac_ctx *c, int m, dirac_prec inner) {
 
 namespace {
 
-// GCR(m) on D-hat in precision pr: x (half, pr) solves D-hat x = b (half, pr) to
-// |b - D-hat x| <= target (normalised norm).  x holds the initial guess when x0.
+// GCR(m) in precision pr on D-hat (half vectors) or, when `full`, on D (full vectors): x solves
+// A x = b to |b - A x| <= target (normalised norm); x holds the initial guess when x0.  With a
+// preconditioner M the directions are p_k = M(r_k) (flexible GCR).  When min_red > 0 a cycle
+// that reduces the residual by less than that factor ends the solve (stagnated).
 GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, bool x0, double target, int m,
-           int max_iter, hipStream_t s) {
+           int max_iter, hipStream_t s, bool full = false, const Precond *M = nullptr, double min_red = 0.0) {
     Blas &B = w.blas;
     const double scale = 1.0 / (24.0 * (double)c->vh);
-    const size_t hb = (size_t)24 * real_size(pr) * c->g.vhp;
+    const int nh = full ? 2 : 1;
+    const size_t hb = (size_t)nh * 24 * real_size(pr) * c->g.vhp;
+    auto apply = [&](void *out, const void *in) {
+        if (full) full_apply(c, out, in, 0, pr, s);
+        else schur_apply(c, out, in, 0, pr, s);
+    };
     char *P = (char *)w.P.p, *Q = (char *)w.Q.p;
     void *r = w.r.p;
     GcrOut out;
     if (x0) {
-        schur_apply(c, Q, x, 0, pr, s);
-        B.lincomb(pr, pr, pr, 1, r, nullptr, 1.0, b, -1.0, Q, sc_ptr(w, S_RED + 4), scale, s);
+        apply(Q, x);
+        B.lincomb(pr, pr, pr, nh, r, nullptr, 1.0, b, -1.0, Q, sc_ptr(w, S_RED + 4), scale, s);
     } else {
-        B.lincomb(pr, pr, pr, 1, x, nullptr, 0.0, b, 0.0, nullptr, nullptr, 1.0, s);
-        B.lincomb(pr, pr, pr, 1, r, nullptr, 1.0, b, 0.0, nullptr, sc_ptr(w, S_RED + 4), scale, s);
+        B.lincomb(pr, pr, pr, nh, x, nullptr, 0.0, b, 0.0, nullptr, nullptr, 1.0, s);
+        B.lincomb(pr, pr, pr, nh, r, nullptr, 1.0, b, 0.0, nullptr, sc_ptr(w, S_RED + 4), scale, s);
     }
     double rn2 = read_scalar(w, S_RED + 4, s);
     if (read_scalar(w, S_RED + 5, s) != 0.0 || !std::isfinite(rn2)) {
@@ -105,16 +108,20 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
     }
     std::vector<double> gam(m), alp(2 * m), beta(2 * m * m), cc(2 * m);
     while (out.iters < max_iter) {
-        B.lincomb(pr, pr, pr, 1, P, nullptr, 1.0, r, 0.0, nullptr, nullptr, 1.0, s);
+        const double cycle_start = out.rnorm;
+        if (M) (*M)(P, r);
+        else B.lincomb(pr, pr, pr, nh, P, nullptr, 1.0, r, 0.0, nullptr, nullptr, 1.0, s);
         int n = 0;
         for (int k = 0; k < m; ++k) {
             char *qk = Q + k * hb;
-            schur_apply(c, qk, P + k * hb, 0, pr, s);
+            apply(qk, P + k * hb);
             double *bcol = sc_ptr(w, S_BETA + 2 * kMaxRestart * k);
-            if (k > 0) B.mdot(pr, 1, Q, hb, k, qk, bcol, scale, s);
-            B.maxpy_dot(pr, 1, Q, hb, k, bcol, qk, r, sc_ptr(w, S_RED), scale, s);
+            if (k > 0) B.mdot(pr, nh, Q, hb, k, qk, bcol, scale, s);
+            B.maxpy_dot(pr, nh, Q, hb, k, bcol, qk, r, sc_ptr(w, S_RED), scale, s);
             B.gcr_scalars(sc_ptr(w, S_RED), sc_ptr(w, S_SC), sc_ptr(w, S_GAM), sc_ptr(w, S_ALP), k, s);
-            B.gcr_update(pr, 1, sc_ptr(w, S_SC), qk, r, P + (k + 1) * hb, sc_ptr(w, S_RED + 4), scale, s);
+            // the next direction is r itself (copied by the update) or M(r)
+            B.gcr_update(pr, nh, sc_ptr(w, S_SC), qk, r, M ? nullptr : P + (k + 1) * hb, sc_ptr(w, S_RED + 4),
+                         scale, s);
             rn2 = read_scalar(w, S_RED + 4, s);
             ++out.iters;
             n = k + 1;
@@ -122,7 +129,8 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
                 out.nonfinite = true;
                 return out;
             }
-            if (std::sqrt(rn2) <= target || out.iters >= max_iter) break;
+            if (std::sqrt(rn2) <= target || out.iters >= max_iter || k + 1 == m) break;
+            if (M) (*M)(P + (k + 1) * hb, r);
         }
         // back-substitution: alpha_j = c_j gamma_j + sum_{k > j} c_k beta_jk
         HIP_CHECK(hipMemcpyAsync(gam.data(), sc_ptr(w, S_GAM), n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -141,10 +149,10 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
             cc[2 * j + 1] = acc.imag();
         }
         HIP_CHECK(hipMemcpyAsync(sc_ptr(w, S_C), cc.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice, s));
-        B.axpy_multi(pr, pr, 1, x, P, hb, n, sc_ptr(w, S_C), 1.0, s);
+        B.axpy_multi(pr, pr, nh, x, P, hb, n, sc_ptr(w, S_C), 1.0, s);
         // true residual of the updated iterate
-        schur_apply(c, Q, x, 0, pr, s);
-        B.lincomb(pr, pr, pr, 1, r, nullptr, 1.0, b, -1.0, Q, sc_ptr(w, S_RED + 4), scale, s);
+        apply(Q, x);
+        B.lincomb(pr, pr, pr, nh, r, nullptr, 1.0, b, -1.0, Q, sc_ptr(w, S_RED + 4), scale, s);
         rn2 = read_scalar(w, S_RED + 4, s);
         if (!std::isfinite(rn2) || read_scalar(w, S_RED + 5, s) != 0.0) {
             out.nonfinite = true;
@@ -153,6 +161,10 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
         out.rnorm = std::sqrt(rn2);
         if (out.rnorm <= target) {
             out.converged = true;
+            break;
+        }
+        if (min_red > 0.0 && !(out.rnorm * min_red <= cycle_start)) {
+            out.stagnated = true;
             break;
         }
         if (out.iters < max_iter) ++out.restarts;
@@ -164,7 +176,8 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
 
 void check_solver_params(const dirac_solver_params *p) {
     require(p != nullptr, "solver params are NULL");
-    require(p->method >= DIRAC_SOLVER_CGLS && p->method <= DIRAC_SOLVER_MIXED_GCR, "unknown solver method");
+    require(p->method >= DIRAC_SOLVER_CGLS && p->method <= DIRAC_SOLVER_FGCR_PTC, "unknown solver method");
+    require(p->method != DIRAC_SOLVER_FGCR_PTC || p->ptc != nullptr, "FGCR_PTC needs a network (ptc)");
     require(std::isfinite(p->tol) && p->tol > 0.0 && p->tol < 1.0, "tol must be in (0, 1)");
     require(p->max_iter > 0, "max_iter must be positive");
     if (p->method != DIRAC_SOLVER_CGLS) require(p->restart >= 1 && p->restart <= kMaxRestart, "restart must be 1..64");
@@ -195,7 +208,9 @@ void free_solver_work(dirac_ctx *c) {
     c->work = nullptr;
 }
 
-// Even-odd solve of D x = b on NATIVE FP64 full vectors (b, x in w.f64[0], w.f64[1]).
+// Solve D x = b on NATIVE FP64 full vectors (b, x in w.f64[0], w.f64[1]): even-odd GCR,
+// defect correction, or flexible GCR on the full D with a PTC preconditioner that falls back to
+// even-odd GCR from its current iterate.
 dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, dirac_solve_info *info,
                           hipStream_t s) {
     ensure_prec(c, DIRAC_F64, s);
@@ -220,76 +235,110 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
         return DIRAC_OK;
     }
     const double target = p->tol * bn;
-    // eta-hat_e = b_e - D_eo A_oo^-1 b_o
-    clover_apply(c, t64, bo, 1, 1, DIRAC_F64, s);
-    hop_apply(c, r64, t64, nullptr, 0, HOP_PLAIN, -0.5, 0, DIRAC_F64, s);
-    B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, eta, nullptr, 1.0, be, -1.0, r64, nullptr, 1.0, s);
-
     dirac_status st = DIRAC_OK;
-    if (p->method == DIRAC_SOLVER_GCR) {
-        // the iterate lives directly in the even half of x
-        GcrOut g = gcr(c, w, DIRAC_F64, xe, eta, x0, target, p->restart, p->max_iter, s);
-        info->iters = g.iters;
+    int iters = 0;
+    bool done = false;
+
+    if (p->method == DIRAC_SOLVER_FGCR_PTC) {
+        dirac_ptc *net = const_cast<dirac_ptc *>(p->ptc);
+        require(net->ch[0] == 1 && net->ch[net->nlayers] == 1, "the PTC network must map 1 channel to 1 channel");
+        ptc_ensure_acts(c, net);
+        ensure_work(c, p->restart, DIRAC_F64, 2);
+        float *a_in = ptc_act(c, net, 0), *a_out = ptc_act(c, net, net->nlayers);
+        // p = N(r): FP64 -> FP32 activations -> network -> FP64 (the network is linear: no scaling needed)
+        const Precond M = [&](void *pv, const void *rv) {
+            B.lincomb(DIRAC_F32, DIRAC_F64, DIRAC_F64, 2, a_in, nullptr, 1.0, rv, 0.0, nullptr, nullptr, 1.0, s);
+            ptc_forward_acts(c, net, s);
+            B.lincomb(DIRAC_F64, DIRAC_F32, DIRAC_F64, 2, pv, nullptr, 1.0, a_out, 0.0, nullptr, nullptr, 1.0, s);
+        };
+        GcrOut g = gcr(c, w, DIRAC_F64, xf, bf, x0, target, p->restart, p->max_iter, s, true, &M, 2.0);
+        iters = g.iters;
         info->restarts = g.restarts;
-        if (g.nonfinite) st = DIRAC_ENONFINITE;
-        else if (!g.converged) st = DIRAC_ENOCONV;
-    } else {
-        // defect correction around an inner GCR in precision `cur`
-        dirac_prec cur = inner;
-        double dtol = p->inner_tol > 0.0 ? p->inner_tol : default_inner_tol(cur);
-        if (!x0) B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, xe, nullptr, 0.0, eta, 0.0, nullptr, nullptr, 1.0, s);
-        schur_apply(c, t64, xe, 0, DIRAC_F64, s);
-        B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, r64, nullptr, 1.0, eta, -1.0, t64, sc_ptr(w, S_MISC + 2),
-                  scale, s);
-        double rn = std::sqrt(read_scalar(w, S_MISC + 2, s));
-        int iters = 0;
-        while (rn > target) {
-            if (iters >= p->max_iter) { st = DIRAC_ENOCONV; break; }
-            if (!std::isfinite(rn)) { st = DIRAC_ENONFINITE; break; }
-            if (cur == DIRAC_F64) {  // fallback: plain FP64 GCR from the current iterate
-                info->fell_back = 1;
-                ensure_work(c, p->restart, DIRAC_F64);
-                GcrOut g = gcr(c, w, DIRAC_F64, xe, eta, true, target, p->restart, p->max_iter - iters, s);
-                iters += g.iters;
-                info->restarts += g.restarts;
-                if (g.nonfinite) st = DIRAC_ENONFINITE;
-                else if (!g.converged) st = DIRAC_ENOCONV;
-                break;
-            }
-            ensure_prec(c, cur, s);
-            ensure_work(c, p->restart, cur);
-            // r_lo = r64 / rn (unit normalised RMS), inner solve, x_e += rn e_lo
-            B.lincomb(cur, DIRAC_F64, DIRAC_F64, 1, w.b.p, nullptr, 1.0 / rn, r64, 0.0, nullptr, nullptr, 1.0, s);
-            GcrOut g = gcr(c, w, cur, w.e.p, w.b.p, false, dtol, p->restart, p->max_iter - iters, s);
+        if (g.converged) {
+            done = true;
+        } else if (iters >= p->max_iter) {
+            st = DIRAC_ENOCONV;
+            done = true;
+        } else {
+            // a cycle gained less than 2x (or met a non-finite value): plain even-odd GCR from here
+            info->fell_back = 1;
+            x0 = !g.nonfinite;
+        }
+    }
+
+    if (!done) {
+        // eta-hat_e = b_e - D_eo A_oo^-1 b_o
+        clover_apply(c, t64, bo, 1, 1, DIRAC_F64, s);
+        hop_apply(c, r64, t64, nullptr, 0, HOP_PLAIN, -0.5, 0, DIRAC_F64, s);
+        B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, eta, nullptr, 1.0, be, -1.0, r64, nullptr, 1.0, s);
+        ensure_work(c, p->restart, inner, 1);
+        if (p->method == DIRAC_SOLVER_GCR || p->method == DIRAC_SOLVER_FGCR_PTC) {
+            // the iterate lives directly in the even half of x
+            GcrOut g = gcr(c, w, DIRAC_F64, xe, eta, x0, target, p->restart, p->max_iter - iters, s);
             iters += g.iters;
             info->restarts += g.restarts;
-            ++info->outer;
-            if (!g.nonfinite) {
-                B.set(sc_ptr(w, S_C), 1.0, s);
-                B.set(sc_ptr(w, S_C + 1), 0.0, s);
-                B.axpy_multi(DIRAC_F64, cur, 1, xe, w.e.p, 0, 1, sc_ptr(w, S_C), rn, s);
-            }
+            if (g.nonfinite) st = DIRAC_ENONFINITE;
+            else if (!g.converged) st = DIRAC_ENOCONV;
+        } else {
+            // defect correction around an inner GCR in precision `cur`
+            dirac_prec cur = inner;
+            double dtol = p->inner_tol > 0.0 ? p->inner_tol : default_inner_tol(cur);
+            if (!x0)
+                B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, xe, nullptr, 0.0, eta, 0.0, nullptr, nullptr, 1.0, s);
             schur_apply(c, t64, xe, 0, DIRAC_F64, s);
             B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, r64, nullptr, 1.0, eta, -1.0, t64, sc_ptr(w, S_MISC + 2),
                       scale, s);
-            const double rn_new = std::sqrt(read_scalar(w, S_MISC + 2, s));
-            if (g.nonfinite || !(rn_new < 0.5 * rn)) {
-                cur = cur == DIRAC_F32 ? DIRAC_F64 : DIRAC_F32;  // raise the inner precision
-                dtol = p->inner_tol > 0.0 && cur == DIRAC_F32 ? std::max(p->inner_tol, 1e-5) : default_inner_tol(cur);
+            double rn = std::sqrt(read_scalar(w, S_MISC + 2, s));
+            while (rn > target) {
+                if (iters >= p->max_iter) { st = DIRAC_ENOCONV; break; }
+                if (!std::isfinite(rn)) { st = DIRAC_ENONFINITE; break; }
+                if (cur == DIRAC_F64) {  // fallback: plain FP64 GCR from the current iterate
+                    info->fell_back = 1;
+                    ensure_work(c, p->restart, DIRAC_F64, 1);
+                    GcrOut g = gcr(c, w, DIRAC_F64, xe, eta, true, target, p->restart, p->max_iter - iters, s);
+                    iters += g.iters;
+                    info->restarts += g.restarts;
+                    if (g.nonfinite) st = DIRAC_ENONFINITE;
+                    else if (!g.converged) st = DIRAC_ENOCONV;
+                    break;
+                }
+                ensure_prec(c, cur, s);
+                ensure_work(c, p->restart, cur, 1);
+                // r_lo = r64 / rn (unit normalised RMS), inner solve, x_e += rn e_lo
+                B.lincomb(cur, DIRAC_F64, DIRAC_F64, 1, w.b.p, nullptr, 1.0 / rn, r64, 0.0, nullptr, nullptr, 1.0, s);
+                GcrOut g = gcr(c, w, cur, w.e.p, w.b.p, false, dtol, p->restart, p->max_iter - iters, s);
+                iters += g.iters;
+                info->restarts += g.restarts;
+                ++info->outer;
+                if (!g.nonfinite) {
+                    B.set(sc_ptr(w, S_C), 1.0, s);
+                    B.set(sc_ptr(w, S_C + 1), 0.0, s);
+                    B.axpy_multi(DIRAC_F64, cur, 1, xe, w.e.p, 0, 1, sc_ptr(w, S_C), rn, s);
+                }
+                schur_apply(c, t64, xe, 0, DIRAC_F64, s);
+                B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, r64, nullptr, 1.0, eta, -1.0, t64,
+                          sc_ptr(w, S_MISC + 2), scale, s);
+                const double rn_new = std::sqrt(read_scalar(w, S_MISC + 2, s));
+                if (g.nonfinite || !(rn_new < 0.5 * rn)) {
+                    cur = cur == DIRAC_F32 ? DIRAC_F64 : DIRAC_F32;  // raise the inner precision
+                    dtol = p->inner_tol > 0.0 && cur == DIRAC_F32 ? std::max(p->inner_tol, 1e-5)
+                                                                   : default_inner_tol(cur);
+                }
+                rn = rn_new;
             }
-            rn = rn_new;
         }
-        info->iters = iters;
+        // x_o = A_oo^-1 (b_o - D_oe x_e)
+        hop_apply(c, t64, xe, nullptr, 1, HOP_PLAIN, -0.5, 0, DIRAC_F64, s);
+        B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, r64, nullptr, 1.0, bo, -1.0, t64, nullptr, 1.0, s);
+        clover_apply(c, xo, r64, 1, 1, DIRAC_F64, s);
     }
-    // x_o = A_oo^-1 (b_o - D_oe x_e)
-    hop_apply(c, t64, xe, nullptr, 1, HOP_PLAIN, -0.5, 0, DIRAC_F64, s);
-    B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, r64, nullptr, 1.0, bo, -1.0, t64, nullptr, 1.0, s);
-    clover_apply(c, xo, r64, 1, 1, DIRAC_F64, s);
+    info->iters = iters;
     // a-posteriori check: |b - D x| / |b| in FP64
     full_apply(c, rf, xf, 0, DIRAC_F64, s);
     B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 2, rf, nullptr, 1.0, bf, -1.0, rf, sc_ptr(w, S_MISC + 4), scale, s);
     info->true_rel_res = std::sqrt(read_scalar(w, S_MISC + 4, s)) / bn;
     if (st == DIRAC_OK && !(info->true_rel_res < p->tol)) st = DIRAC_ENOCONV;
+    if (!std::isfinite(info->true_rel_res)) st = DIRAC_ENONFINITE;
     return st;
 }
 

@@ -1,0 +1,95 @@
+"""Pins of the oracle's parallel-transport convolution network: it reduces to D, its transports
+are adjoint pairs, its gradients match central finite differences, and it is gauge equivariant."""
+import numpy as np
+
+import gen
+from oracle import dirac, geometry as geo, ptc
+
+
+def fields(L=(2, 2, 2, 4), csw=0.0, cq=0.0, seed=3):
+    return dirac.Fields(gen.su3_field(L, 0.5, seed), gen.u1_field(L, 0.3, seed),
+                        dirac.Params(L, 0.124, csw, cq, -1, (np.pi, 0.5, 0.0, -0.3)))
+
+
+def test_single_layer_equals_dirac_without_clover():
+    f = fields()
+    psi = gen.gaussian_spinor(f.p.dims, 1)
+    y = ptc.layer(f, ptc.dirac_as_layer(f), [psi])[0]
+    assert np.abs(y - dirac.apply_D(f, psi)).max() < 1e-13
+
+
+def test_transport_adjoint_pairs():
+    f = fields()
+    x, y = gen.gaussian_spinor(f.p.dims, 2), gen.gaussian_spinor(f.p.dims, 3)
+    for p in range(ptc.NPATH):
+        lhs = np.vdot(y, ptc.transport(f, x, p))
+        rhs = np.vdot(ptc.transport(f, y, ptc.ADJ[p]), x)
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def _loss(f, ws, r, e):
+    y, _ = ptc.forward(f, ws, r)
+    d = y - e
+    return np.vdot(d, d).real / np.vdot(e, e).real
+
+
+def test_gradients_match_finite_differences():
+    f = fields()
+    r, e = gen.gaussian_spinor(f.p.dims, 4), gen.gaussian_spinor(f.p.dims, 5)
+    ws = ptc.init_weights((1, 2, 1), seed=1, scale=0.5)
+    L, g = ptc.loss_and_grads(f, ws, [(r, e)])
+    assert abs(L - _loss(f, ws, r, e)) < 1e-12
+    rng = np.random.default_rng(0)
+    h = 1e-6
+    for l in range(len(ws)):
+        for _ in range(6):
+            idx = tuple(rng.integers(0, n) for n in ws[l].shape)
+            for part, unit in ((0, 1.0), (1, 1j)):
+                wp = [w.copy() for w in ws]
+                wm = [w.copy() for w in ws]
+                wp[l][idx] += h * unit
+                wm[l][idx] -= h * unit
+                fd = (_loss(f, wp, r, e) - _loss(f, wm, r, e)) / (2 * h)
+                an = 2 * (g[l][idx].real if part == 0 else g[l][idx].imag)
+                assert abs(fd - an) < 1e-7 * max(1.0, abs(an)), (l, idx, part, fd, an)
+    # input gradient
+    y, acts = ptc.forward(f, ws, r)
+    ne2 = np.vdot(e, e).real
+    gr, _ = ptc.backward(f, ws, acts, (y - e) / ne2)
+    for _ in range(4):
+        idx = (rng.integers(0, f.V), rng.integers(0, 4), rng.integers(0, 3))
+        for unit in (1.0, 1j):
+            rp, rm = r.copy(), r.copy()
+            rp[idx] += h * unit
+            rm[idx] -= h * unit
+            fd = (_loss(f, ws, rp, e) - _loss(f, ws, rm, e)) / (2 * h)
+            an = 2 * (gr[idx].real if unit == 1.0 else gr[idx].imag)
+            assert abs(fd - an) < 1e-7 * max(1.0, abs(an))
+
+
+def test_gauge_equivariance():
+    f = fields(csw=1.0, cq=1.0)
+    L = f.p.dims
+    W, lam = gen.gauge_transform(L, 11)
+    sites = np.arange(f.V)
+    U2, th2 = np.empty_like(f.U), np.empty_like(f.theta)
+    for mu in range(4):
+        fw = geo.shift(sites, L, mu, 1)
+        U2[:, mu] = W @ f.U[:, mu] @ np.conj(np.swapaxes(W[fw], 1, 2))
+        th2[:, mu] = f.theta[:, mu] + lam - lam[fw]
+    f2 = dirac.Fields(U2, th2, f.p)
+    tr = lambda v: np.exp(1j * f.p.qhat * lam)[:, None, None] * np.einsum("nab,nsb->nsa", W, v)  # noqa: E731
+    ws = ptc.init_weights((1, 2, 1), seed=2, scale=0.5)
+    r = gen.gaussian_spinor(L, 6)
+    y1, _ = ptc.forward(f2, ws, tr(r))
+    y0, _ = ptc.forward(f, ws, r)
+    assert np.abs(y1 - tr(y0)).max() < 1e-12 * np.abs(y0).max()
+
+
+def test_adam_first_step_moves_by_lr_against_gradient_sign():
+    ws = [np.array([[1.0 + 2.0j, -0.5j]])]
+    g = [np.array([[0.3 - 0.1j, 2.0 + 0.0j]])]
+    new = ptc.Adam(ws, lr=0.01).step(ws, g)[0]
+    # first Adam step: m/sqrt(v) = sign(g) per real component (up to eps)
+    expect = ws[0] - 0.01 * (np.sign(g[0].real) + 1j * np.sign(g[0].imag))
+    assert np.abs(new - expect).max() < 1e-8
