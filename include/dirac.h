@@ -201,6 +201,19 @@ typedef struct {
 dirac_status dirac_solve(dirac_ctx *ctx, void *x, const void *b, dirac_layout layout,
                          const dirac_solver_params *params, dirac_solve_info *info, void *stream);
 
+/* Batched solves: nlat lattices (one context each; uneven sizes and parameters allowed),
+ * nrhs right-hand sides per lattice.  x[l] and b[l] hold nrhs full-lattice FP64 vectors in
+ * `layout`, one after another.  method GCR or MIXED_GCR.  All right-hand sides of a lattice
+ * advance together: every kernel of an iteration covers all of them in one launch (the
+ * multi-RHS hop reads each link once per site block and serves it to every right-hand side
+ * from L2), converged systems are frozen by a device-side mask, and the launch sequence of
+ * each iteration is captured once into a hipGraph and replayed.  The lattices run
+ * concurrently, one host thread and one stream each, queued after the work already on
+ * `stream`.  info has nlat * nrhs entries (lattice-major).  Blocking. */
+dirac_status dirac_solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x, const void *const *b, int nrhs,
+                                 dirac_layout layout, const dirac_solver_params *params, dirac_solve_info *info,
+                                 void *stream);
+
 /* ---------------------------------------------------------------- learned preconditioner
  * A gauge-covariant parallel-transport convolution (PTC) network N (a reading of the
  * learned part; the paper has none):

@@ -193,6 +193,27 @@ class Dirac:
         return info
 
 
+def solve_batched(ops, xs, bs, nrhs, method=GCR, tol=1e-10, restart=32, max_iter=100000, layout="lex",
+                  inner_prec="f32", inner_tol=None, stream=None):
+    """Solve D_l x = b for nrhs right-hand sides on each lattice l (ops: Dirac objects).
+    xs[l], bs[l]: tensors holding nrhs full-lattice FP64 vectors in `layout`.  Returns a list
+    (per lattice) of lists (per right-hand side) of SolveInfo."""
+    lib = _lib.load()
+    n = len(ops)
+    sp = SolverParams()
+    sp.method, sp.restart, sp.max_iter, sp.tol = int(method), int(restart), int(max_iter), float(tol)
+    sp.inner_prec = _prec(inner_prec)
+    sp.inner_tol = float(inner_tol) if inner_tol is not None else 0.0
+    sp.x0_given, sp.precision, sp.ptc = 0, F64, None
+    ctx = (ctypes.c_void_p * n)(*[D._ctx.value for D in ops])
+    xa = (ctypes.c_void_p * n)(*[_ptr(x, nrhs * D._vec_bytes("f64", layout, 0)).value for x, D in zip(xs, ops)])
+    ba = (ctypes.c_void_p * n)(*[_ptr(b, nrhs * D._vec_bytes("f64", layout, 0)).value for b, D in zip(bs, ops)])
+    infos = (SolveInfo * (n * nrhs))()
+    _lib.check(lib.dirac_solve_batched(ctx, n, xa, ba, int(nrhs), _layout(layout), ctypes.byref(sp), infos,
+                                       _stream(stream)))
+    return [[infos[l * nrhs + r] for r in range(nrhs)] for l in range(n)]
+
+
 class PTC:
     """Parallel-transport convolution network (the learned preconditioner), e.g. channels (1, 8, 8, 1).
 

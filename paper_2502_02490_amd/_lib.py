@@ -17,7 +17,7 @@ CGLS, GCR, MIXED_GCR, FGCR_PTC = 0, 1, 2, 3
 # every symbol declared in include/dirac.h
 EXPORTS = ["dirac_create", "dirac_destroy", "dirac_load_clover", "dirac_get_clover", "clover_invert",
            "dirac_native_bytes", "dirac_import", "dirac_export", "dirac_apply", "dirac_apply_eo",
-           "dirac_apply_hop", "dirac_apply_clover", "dirac_solve", "dirac_last_error",
+           "dirac_apply_hop", "dirac_apply_clover", "dirac_solve", "dirac_solve_batched", "dirac_last_error",
            "ptc_create", "ptc_destroy", "ptc_num_weights", "ptc_set_weights", "ptc_get_weights", "ptc_get_grad",
            "ptc_zero_grad", "ptc_forward", "ptc_backward", "ptc_adam_step", "ptc_train_step"]
 
@@ -72,6 +72,7 @@ def load(path: str = LIB_PATH):
     lib.dirac_apply_hop.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_apply_clover.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(SolverParams), ctypes.POINTER(SolveInfo), vp]
+    lib.dirac_solve_batched.argtypes = [vp, i, vp, vp, i, i, ctypes.POINTER(SolverParams), vp, vp]
     lib.dirac_last_error.restype = ctypes.c_char_p
     lib.ptc_create.argtypes = [vp, i, ctypes.POINTER(vp)]
     lib.ptc_destroy.argtypes = [vp]

@@ -155,6 +155,7 @@ dirac_status dirac_destroy(dirac_ctx *c) {
     API_BEGIN
     if (!c) return DIRAC_OK;
     (void)hipDeviceSynchronize();
+    dl::free_bwork(c);
     dl::free_solver_work(c);
     c->U_lex.release();
     c->theta_lex.release();
@@ -353,6 +354,32 @@ dirac_status dirac_solve(dirac_ctx *c, void *x, const void *b, dirac_layout lay,
     API_END
 }
 
+dirac_status dirac_solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x, const void *const *b, int nrhs,
+                                 dirac_layout lay, const dirac_solver_params *p, dirac_solve_info *info,
+                                 void *stream) {
+    API_BEGIN
+    require(ctx != nullptr && x != nullptr && b != nullptr && info != nullptr, "NULL argument");
+    require(nlat >= 1 && nlat <= 64, "nlat must be 1..64");
+    require(nrhs >= 1 && nrhs <= 64, "nrhs must be 1..64");
+    dl::check_solver_params(p);
+    require(p->method == DIRAC_SOLVER_GCR || p->method == DIRAC_SOLVER_MIXED_GCR,
+            "batched solves run GCR or MIXED_GCR");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_NATIVE, "unknown layout");
+    for (int l = 0; l < nlat; ++l) {
+        check_ctx(ctx[l]);
+        for (int k = 0; k < l; ++k) require(ctx[k] != ctx[l], "each lattice needs its own context");
+        const size_t nb = (size_t)nrhs *
+                          (lay == DIRAC_LAYOUT_NATIVE ? native_bytes(ctx[l], DIRAC_F64, 0) : user_bytes(ctx[l], DIRAC_F64, 0));
+        check_dev(b[l], nb, "b[l]");
+        check_dev(x[l], nb, "x[l]");
+        check_no_alias(x[l], nb, b[l], nb);
+    }
+    std::string err;
+    const dirac_status st = dl::solve_batched(ctx, nlat, x, b, nrhs, lay, p, info, (hipStream_t)stream, err);
+    if (st != DIRAC_OK) return fail(st, err);
+    API_END
+}
+
 // ---------------------------------------------------------------- learned preconditioner
 dirac_status ptc_create(const int *channels, int nlayers, dirac_ptc **out) {
     API_BEGIN
@@ -486,7 +513,7 @@ dirac_status ptc_train_step(dirac_ctx *c, dirac_ptc *n, const void *const *r, co
     dl::ensure_work(c, 1, DIRAC_F32, 2);
     n->grad_zero(s);
     dl::Blas &B = c->work->blas;
-    double *sc = (double *)B.scal.p + 15000;
+    double *sc = (double *)B.scal.p + dl::kSysScal - 16;  // free slots at the end of the scalar block
     const double scale = 1.0 / (24.0 * (double)c->vh);
     double total = 0.0;
     void *g = c->work->P.p;  // dL/dy* of the current pair (F32 full)
@@ -494,7 +521,7 @@ dirac_status ptc_train_step(dirac_ctx *c, dirac_ptc *n, const void *const *r, co
         HIP_CHECK(hipMemcpyAsync(dl::ptc_act(c, n, 0), r[i], nb, hipMemcpyDeviceToDevice, s));
         dl::ptc_forward_acts(c, n, s);
         const void *y = dl::ptc_act(c, n, n->nlayers);
-        B.mdot(DIRAC_F32, 2, e[i], 0, 1, e[i], sc, scale, s);
+        B.mdot(DIRAC_F32, 2, e[i], 1, e[i], sc, scale, s);
         double ne2 = 0.0;
         HIP_CHECK(hipMemcpyAsync(&ne2, sc, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));

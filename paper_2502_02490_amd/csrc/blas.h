@@ -11,27 +11,41 @@
 
 namespace dl {
 
+// A batch of nrhs systems sharing one lattice: vector r of an argument is r vectors after its
+// base, basis vector j of system r is (j * nrhs + r) vectors after the base, and system r's
+// device scalars are r * sstride doubles after a scalar pointer.  Systems with active[r] = 0
+// are skipped.  The default is one system.
+struct BatchSpec {
+    int nrhs = 1;
+    const int *active = nullptr;
+    int sstride = 0;
+};
+
+constexpr int kSysScal = 8768;  // device scalar doubles per system: GCR(64) coefficients and 64 free slots
+
 struct Blas {
     dirac_ctx *c = nullptr;
     DevBuf part, scal;
 
-    void reserve(int64_t nsites_max, int kmax);
+    void reserve(int64_t nsites_max, int kmax, int nrhs = 1);
     // out[j] = scale <Q_j, q>, j < k (complex, 2 doubles each)
-    void mdot(dirac_prec pr, int nh, const void *Q, size_t qstride_bytes, int k, const void *q, double *out_dev,
-              double scale, hipStream_t s);
+    void mdot(dirac_prec pr, int nh, const void *Q, int k, const void *q, double *out_dev, double scale, hipStream_t s,
+              const BatchSpec &bs = BatchSpec());
     // q -= sum_j coef_j Q_j; out = scale {|q|^2, <q, r>}
-    void maxpy_dot(dirac_prec pr, int nh, const void *Q, size_t qstride_bytes, int k, const double *coef_dev, void *q,
-                   const void *r, double *out_dev, double scale, hipStream_t s);
-    void gcr_scalars(const double *red, double *sc, double *gam, double *alp, int k, hipStream_t s);
+    void maxpy_dot(dirac_prec pr, int nh, const void *Q, int k, const double *coef_dev, void *q, const void *r,
+                   double *out_dev, double scale, hipStream_t s, const BatchSpec &bs = BatchSpec());
+    void gcr_scalars(const double *red, double *sc, double *gam, double *alp, int k, hipStream_t s,
+                     const BatchSpec &bs = BatchSpec());
     // q /= gamma; r -= alpha q; pnext = r; out = scale |r|^2
     void gcr_update(dirac_prec pr, int nh, const double *sc, void *q, void *r, void *pnext, double *out_dev,
-                    double scale, hipStream_t s);
-    // x += xscale sum_j coef_j P_j
-    void axpy_multi(dirac_prec px, dirac_prec pp, int nh, void *x, const void *P, size_t pstride_bytes, int k,
-                    const double *coef_dev, double xscale, hipStream_t s);
+                    double scale, hipStream_t s, const BatchSpec &bs = BatchSpec());
+    // x += xscale sum_j coef_j P_j (xscale_r = xscales[r * sstride] when given)
+    void axpy_multi(dirac_prec px, dirac_prec pp, int nh, void *x, const void *P, int k, const double *coef_dev,
+                    double xscale, hipStream_t s, const BatchSpec &bs = BatchSpec(), const double *xscales = nullptr);
     // out = alpha a + beta b; copy2 = out; out_dev = scale {|out|^2, nonfinite flag}
     void lincomb(dirac_prec po, dirac_prec pa, dirac_prec pb, int nh, void *out, void *copy2, double alpha,
-                 const void *a, double beta, const void *b, double *out_dev, double scale, hipStream_t s);
+                 const void *a, double beta, const void *b, double *out_dev, double scale, hipStream_t s,
+                 const BatchSpec &bs = BatchSpec(), const double *alphas = nullptr);
     void cgls_xs(int nh, const double *rho, const double *wn, void *x, const void *p, void *sv, const void *w,
                  double *out_dev, hipStream_t s);
     void cgls_p(int nh, const double *rho_new, const double *rho_old, void *p, const void *r, hipStream_t s);

@@ -73,20 +73,42 @@ DEV void group_sum(double v[N], double *lds /* [N][kRed / 64] */) {
     }
 }
 
-// partials[blk][j] (complex) = sum over the group's sites of <Q_j, q>, j < k
+// A batch of nrhs independent systems: vector r of an argument v is v + r * vs (vs = the
+// vector length in 16-byte units), basis vector j of system r is Q + (j * nrhs + r) * vs;
+// system r's device scalars start r * sstride doubles after a scalar pointer.  Work-group b
+// works on system b / nb; systems whose `active` flag is 0 are skipped entirely.
+struct Bat {
+    int n, vh, nb, nrhs, sstride;
+    const int *active;
+};
+
 template <typename S>
-__global__ __launch_bounds__(kRed) void k_mdot(int n, int vh, const typename St<S>::vec *Q, size_t qstride, int k,
+DEV size_t vstride(const Bat &b) {
+    return (size_t)(b.n / b.vh) * (24 / St<S>::W) * (size_t)padded_sites(b.vh);
+}
+DEV bool sys_of(const Bat &b, int &r, int &t) {
+    r = blockIdx.x / b.nb;
+    t = (blockIdx.x - r * b.nb) * kRed + threadIdx.x;
+    return !b.active || b.active[r];
+}
+
+// partials[sys][blk][j] (complex) = sum over the group's sites of <Q_j, q>, j < k
+template <typename S>
+__global__ __launch_bounds__(kRed) void k_mdot(Bat B, const typename St<S>::vec *Q, int k,
                                                const typename St<S>::vec *q, double2 *partials) {
     __shared__ double lds[2 * kRed / 64];
-    const int t = blockIdx.x * kRed + threadIdx.x;
+    int r, t;
+    if (!sys_of(B, r, t)) return;
+    const size_t vs = vstride<S>(B);
+    q += r * vs;
     double a[24];
-    const bool on = t < n;
-    if (on) ld<S>(q, t, vh, a);
+    const bool on = t < B.n;
+    if (on) ld<S>(q, t, B.vh, a);
     for (int j = 0; j < k; ++j) {
         double v[2] = {0.0, 0.0};
         if (on) {
             double b[24];
-            ld<S>(Q + j * qstride, t, vh, b);
+            ld<S>(Q + ((size_t)j * B.nrhs + r) * vs, t, B.vh, b);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 v[0] = fma(b[2 * c], a[2 * c], v[0]);
@@ -101,42 +123,49 @@ __global__ __launch_bounds__(kRed) void k_mdot(int n, int vh, const typename St<
     }
 }
 
-// out[j] = scale * sum_b partials[b][j] (b ascending), nc doubles per entry
+// out_r[j] = scale * sum_b partials[r][b][j] (b ascending), nc doubles per entry; grid (nent, nrhs)
 __global__ __launch_bounds__(kRed) void k_reduce(int nblk, int nent, int nc, const double *partials, double scale,
-                                                 double *out) {
+                                                 double *out, int sstride, const int *active) {
     __shared__ double lds[4 * kRed / 64];
-    const int j = blockIdx.x;
+    const int j = blockIdx.x, r = blockIdx.y;
+    if (active && !active[r]) return;
+    partials += (size_t)r * nblk * nent * nc;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblk; b += kRed)
         for (int c = 0; c < nc; ++c) v[c] += partials[((size_t)b * nent + j) * nc + c];
     group_sum<4>(v, lds);
     if (threadIdx.x == 0)
-        for (int c = 0; c < nc; ++c) out[j * nc + c] = scale * v[c];
+        for (int c = 0; c < nc; ++c) out[(size_t)r * sstride + j * nc + c] = scale * v[c];
 }
 
 // q -= sum_j coef_j Q_j (coef complex double in device memory); partials: |q|^2, <q, r>
 template <typename S>
-__global__ __launch_bounds__(kRed) void k_maxpy_dot(int n, int vh, const typename St<S>::vec *Q, size_t qstride,
-                                                    int k, const double2 *coef, typename St<S>::vec *q,
-                                                    const typename St<S>::vec *r, double *partials) {
+__global__ __launch_bounds__(kRed) void k_maxpy_dot(Bat B, const typename St<S>::vec *Q, int k, const double *coef,
+                                                    typename St<S>::vec *q, const typename St<S>::vec *rv,
+                                                    double *partials) {
     __shared__ double lds[3 * kRed / 64];
-    const int t = blockIdx.x * kRed + threadIdx.x;
+    int r, t;
+    if (!sys_of(B, r, t)) return;
+    const size_t vs = vstride<S>(B);
+    q += r * vs;
+    rv += r * vs;
+    const double2 *cf = reinterpret_cast<const double2 *>(coef + (size_t)r * B.sstride);
     double v[3] = {0.0, 0.0, 0.0};
-    if (t < n) {
+    if (t < B.n) {
         double a[24], b[24];
-        ld<S>(q, t, vh, a);
+        ld<S>(q, t, B.vh, a);
         for (int j = 0; j < k; ++j) {
-            const double2 cj = coef[j];
-            ld<S>(Q + j * qstride, t, vh, b);
+            const double2 cj = cf[j];
+            ld<S>(Q + ((size_t)j * B.nrhs + r) * vs, t, B.vh, b);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 a[2 * c] -= cj.x * b[2 * c] - cj.y * b[2 * c + 1];
                 a[2 * c + 1] -= cj.x * b[2 * c + 1] + cj.y * b[2 * c];
             }
         }
-        st<S>(q, t, vh, a);
-        ld<S>(q, t, vh, a);  // the stored (rounded) q is what the recurrence uses
-        ld<S>(r, t, vh, b);
+        st<S>(q, t, B.vh, a);
+        ld<S>(q, t, B.vh, a);  // the stored (rounded) q is what the recurrence uses
+        ld<S>(rv, t, B.vh, b);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             v[0] += a[2 * c] * a[2 * c] + a[2 * c + 1] * a[2 * c + 1];
@@ -149,32 +178,38 @@ __global__ __launch_bounds__(kRed) void k_maxpy_dot(int n, int vh, const typenam
         for (int c = 0; c < 3; ++c) partials[(size_t)blockIdx.x * 3 + c] = v[c];
 }
 
-// q_hat = q / gamma -> qout; r -= alpha q_hat; pnext = r (if given); partial |r|^2.
+// q_hat = q / gamma -> q; r -= alpha q_hat; pnext = r (if given); partial |r|^2.
 // sc = {1/gamma, alpha.re, alpha.im} in device memory.
 template <typename S>
-__global__ __launch_bounds__(kRed) void k_gcr_update(int n, int vh, const double *sc, typename St<S>::vec *q,
-                                                     typename St<S>::vec *r, typename St<S>::vec *pnext,
+__global__ __launch_bounds__(kRed) void k_gcr_update(Bat B, const double *sc, typename St<S>::vec *q,
+                                                     typename St<S>::vec *rv, typename St<S>::vec *pnext,
                                                      double *partials) {
     __shared__ double lds[kRed / 64];
-    const int t = blockIdx.x * kRed + threadIdx.x;
+    int r, t;
+    if (!sys_of(B, r, t)) return;
+    const size_t vs = vstride<S>(B);
+    q += r * vs;
+    rv += r * vs;
+    if (pnext) pnext += r * vs;
+    sc += (size_t)r * B.sstride;
     double v[1] = {0.0};
-    if (t < n) {
+    if (t < B.n) {
         const double ig = sc[0], ar = sc[1], ai = sc[2];
         double a[24], b[24];
-        ld<S>(q, t, vh, a);
+        ld<S>(q, t, B.vh, a);
 #pragma unroll
         for (int c = 0; c < 24; ++c) a[c] *= ig;
-        st<S>(q, t, vh, a);
-        ld<S>(q, t, vh, a);
-        ld<S>(r, t, vh, b);
+        st<S>(q, t, B.vh, a);
+        ld<S>(q, t, B.vh, a);
+        ld<S>(rv, t, B.vh, b);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             b[2 * c] -= ar * a[2 * c] - ai * a[2 * c + 1];
             b[2 * c + 1] -= ar * a[2 * c + 1] + ai * a[2 * c];
         }
-        st<S>(r, t, vh, b);
-        if (pnext) st<S>(pnext, t, vh, b);
-        ld<S>(r, t, vh, b);
+        st<S>(rv, t, B.vh, b);
+        if (pnext) st<S>(pnext, t, B.vh, b);
+        ld<S>(rv, t, B.vh, b);
 #pragma unroll
         for (int c = 0; c < 24; ++c) v[0] += b[c] * b[c];
     }
@@ -182,49 +217,59 @@ __global__ __launch_bounds__(kRed) void k_gcr_update(int n, int vh, const double
     if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
 }
 
-// x += sum_j coef_j P_j (x and P may have different precisions)
+// x += xscale_r sum_j coef_j P_j (x and P may have different precisions)
 template <typename SX, typename SP>
-__global__ __launch_bounds__(kRed) void k_axpy_multi(int n, int vh, typename St<SX>::vec *x,
-                                                     const typename St<SP>::vec *P, size_t pstride, int k,
-                                                     const double2 *coef, double xscale) {
-    const int t = blockIdx.x * kRed + threadIdx.x;
-    if (t >= n) return;
+__global__ __launch_bounds__(kRed) void k_axpy_multi(Bat B, typename St<SX>::vec *x, const typename St<SP>::vec *P,
+                                                     int k, const double *coef, double xscale,
+                                                     const double *xscales) {
+    int r, t;
+    if (!sys_of(B, r, t) || t >= B.n) return;
+    x += r * vstride<SX>(B);
+    const size_t vp = vstride<SP>(B);
+    const double2 *cf = reinterpret_cast<const double2 *>(coef + (size_t)r * B.sstride);
+    const double xs = xscales ? xscales[(size_t)r * B.sstride] : xscale;
     double a[24], b[24];
-    ld<SX>(x, t, vh, a);
+    ld<SX>(x, t, B.vh, a);
     for (int j = 0; j < k; ++j) {
-        const double2 cj = coef[j];
-        ld<SP>(P + j * pstride, t, vh, b);
+        const double2 cj = cf[j];
+        ld<SP>(P + ((size_t)j * B.nrhs + r) * vp, t, B.vh, b);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            a[2 * c] += xscale * (cj.x * b[2 * c] - cj.y * b[2 * c + 1]);
-            a[2 * c + 1] += xscale * (cj.x * b[2 * c + 1] + cj.y * b[2 * c]);
+            a[2 * c] += xs * (cj.x * b[2 * c] - cj.y * b[2 * c + 1]);
+            a[2 * c + 1] += xs * (cj.x * b[2 * c + 1] + cj.y * b[2 * c]);
         }
     }
-    st<SX>(x, t, vh, a);
+    st<SX>(x, t, B.vh, a);
 }
 
-// out = alpha a + beta b (converted to the output precision); optional copy2 = out; partial |out|^2
+// out = alpha_r a + beta b (converted to the output precision); optional copy2 = out; partial |out|^2
+// and a non-finite flag.  alpha_r = alphas[r * sstride] when alphas is given.
 template <typename SO, typename SA, typename SB>
-__global__ __launch_bounds__(kRed) void k_lincomb(int n, int vh, typename St<SO>::vec *out,
-                                                  typename St<SO>::vec *copy2, double alpha,
-                                                  const typename St<SA>::vec *a, double beta,
-                                                  const typename St<SB>::vec *b, double *partials) {
+__global__ __launch_bounds__(kRed) void k_lincomb(Bat B, typename St<SO>::vec *out, typename St<SO>::vec *copy2,
+                                                  double alpha, const double *alphas, const typename St<SA>::vec *a,
+                                                  double beta, const typename St<SB>::vec *b, double *partials) {
     __shared__ double lds[2 * kRed / 64];
-    const int t = blockIdx.x * kRed + threadIdx.x;
+    int r, t;
+    if (!sys_of(B, r, t)) return;
+    out += r * vstride<SO>(B);
+    if (copy2) copy2 += r * vstride<SO>(B);
+    a += r * vstride<SA>(B);
+    if (b) b += r * vstride<SB>(B);
+    const double al = alphas ? alphas[(size_t)r * B.sstride] : alpha;
     double v[2] = {0.0, 0.0};
-    if (t < n) {
+    if (t < B.n) {
         double x[24], y[24];
-        ld<SA>(a, t, vh, x);
+        ld<SA>(a, t, B.vh, x);
         if (b) {
-            ld<SB>(b, t, vh, y);
+            ld<SB>(b, t, B.vh, y);
 #pragma unroll
-            for (int c = 0; c < 24; ++c) x[c] = alpha * x[c] + beta * y[c];
+            for (int c = 0; c < 24; ++c) x[c] = al * x[c] + beta * y[c];
         } else {
 #pragma unroll
-            for (int c = 0; c < 24; ++c) x[c] = alpha * x[c];
+            for (int c = 0; c < 24; ++c) x[c] = al * x[c];
         }
-        st<SO>(out, t, vh, x);
-        if (copy2) st<SO>(copy2, t, vh, x);
+        st<SO>(out, t, B.vh, x);
+        if (copy2) st<SO>(copy2, t, B.vh, x);
         bool fin = true;
 #pragma unroll
         for (int c = 0; c < 24; ++c) {
@@ -287,19 +332,23 @@ __global__ __launch_bounds__(kRed) void k_cgls_p(int n, int vh, const double *rh
     st<S>(p, t, vh, a);
 }
 
-// GCR scalars after k_maxpy_dot: red = {|q|^2, re <q,r>, im <q,r>}
-// out: sc = {1/gamma, alpha}, gamma_k, alpha_k stored at slot k
-__global__ void k_gcr_scalars(const double *red, double *sc, double *gam, double2 *alp, int k) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double n2 = red[0];
+// GCR scalars after k_maxpy_dot, per system r (thread r): red = {|q|^2, re <q,r>, im <q,r>};
+// out: sc = {1/gamma, alpha}, gamma_k and alpha_k stored at slot k
+__global__ void k_gcr_scalars(int nrhs, int sstride, const int *active, const double *red, double *sc, double *gam,
+                              double *alp, int k) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs || (active && !active[r])) return;
+    const size_t o = (size_t)r * sstride;
+    const double n2 = red[o];
     const double g = sqrt(n2);
     const double ig = g > 0.0 ? 1.0 / g : 0.0;
-    const double ar = red[1] * ig, ai = red[2] * ig;  // <q_hat, r>
-    sc[0] = ig;
-    sc[1] = ar;
-    sc[2] = ai;
-    gam[k] = g;
-    alp[k] = make_double2(ar, ai);
+    const double ar = red[o + 1] * ig, ai = red[o + 2] * ig;  // <q_hat, r>
+    sc[o] = ig;
+    sc[o + 1] = ar;
+    sc[o + 2] = ai;
+    gam[o + k] = g;
+    alp[o + 2 * k] = ar;
+    alp[o + 2 * k + 1] = ai;
 }
 
 __global__ void k_set(double *p, double v) {
@@ -308,8 +357,6 @@ __global__ void k_set(double *p, double v) {
 __global__ void k_copy_scalar(const double *src, double *dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = src[0];
 }
-
-template <typename S> struct Tag {};
 
 }  // namespace
 
@@ -325,63 +372,78 @@ int blas_grid(int64_t nsites) { return (int)((nsites + kRed - 1) / kRed); }
         default: throw Error(DIRAC_EINVAL, "unknown precision");                           \
     }
 
-void Blas::reserve(int64_t nsites_max, int kmax) {
+void Blas::reserve(int64_t nsites_max, int kmax, int nrhs) {
     const size_t nb = (size_t)blas_grid(nsites_max);
-    part.alloc(nb * (size_t)std::max(kmax, 4) * 2 * sizeof(double) + 64);
-    scal.alloc(16384 * sizeof(double));
+    part.alloc(nb * (size_t)nrhs * (size_t)std::max(kmax, 4) * 2 * sizeof(double) + 64);
+    scal.alloc((size_t)std::max(nrhs, 1) * kSysScal * sizeof(double));
 }
 
-void Blas::mdot(dirac_prec pr, int nh, const void *Q, size_t qstride_bytes, int k, const void *q, double *out_dev,
-                double scale, hipStream_t s) {
-    const int vh = (int)c->vh, n = nh * vh, nb = blas_grid(n);
-#define FN(S)                                                                                         \
-    k_mdot<S><<<nb, kRed, 0, s>>>(n, vh, (const typename St<S>::vec *)Q,                              \
-                                  qstride_bytes / sizeof(typename St<S>::vec), k,                    \
-                                  (const typename St<S>::vec *)q, (double2 *)part.p);
+namespace {
+Bat make_bat(const dirac_ctx *c, int nh, const BatchSpec &bs) {
+    Bat b;
+    b.vh = (int)c->vh;
+    b.n = nh * b.vh;
+    b.nb = blas_grid(b.n);
+    b.nrhs = bs.nrhs;
+    b.sstride = bs.sstride;
+    b.active = bs.active;
+    return b;
+}
+}  // namespace
+
+void Blas::mdot(dirac_prec pr, int nh, const void *Q, int k, const void *q, double *out_dev, double scale,
+                hipStream_t s, const BatchSpec &bs) {
+    const Bat b = make_bat(c, nh, bs);
+#define FN(S)                                                                                        \
+    k_mdot<S><<<b.nb * b.nrhs, kRed, 0, s>>>(b, (const typename St<S>::vec *)Q, k,                    \
+                                             (const typename St<S>::vec *)q, (double2 *)part.p);
     DISPATCH_PREC(pr, FN)
 #undef FN
-    k_reduce<<<k, kRed, 0, s>>>(nb, k, 2, (const double *)part.p, scale, out_dev);
+    k_reduce<<<dim3(k, b.nrhs), kRed, 0, s>>>(b.nb, k, 2, (const double *)part.p, scale, out_dev, b.sstride,
+                                              b.active);
     HIP_CHECK(hipGetLastError());
 }
 
-void Blas::maxpy_dot(dirac_prec pr, int nh, const void *Q, size_t qstride_bytes, int k, const double *coef_dev,
-                     void *q, const void *r, double *out_dev, double scale, hipStream_t s) {
-    const int vh = (int)c->vh, n = nh * vh, nb = blas_grid(n);
-#define FN(S)                                                                                               \
-    k_maxpy_dot<S><<<nb, kRed, 0, s>>>(n, vh, (const typename St<S>::vec *)Q,                               \
-                                       qstride_bytes / sizeof(typename St<S>::vec), k,                      \
-                                       (const double2 *)coef_dev, (typename St<S>::vec *)q,                 \
-                                       (const typename St<S>::vec *)r, (double *)part.p);
+void Blas::maxpy_dot(dirac_prec pr, int nh, const void *Q, int k, const double *coef_dev, void *q, const void *r,
+                     double *out_dev, double scale, hipStream_t s, const BatchSpec &bs) {
+    const Bat b = make_bat(c, nh, bs);
+#define FN(S)                                                                                            \
+    k_maxpy_dot<S><<<b.nb * b.nrhs, kRed, 0, s>>>(b, (const typename St<S>::vec *)Q, k, coef_dev,         \
+                                                  (typename St<S>::vec *)q, (const typename St<S>::vec *)r, \
+                                                  (double *)part.p);
     DISPATCH_PREC(pr, FN)
 #undef FN
-    k_reduce<<<1, kRed, 0, s>>>(nb, 1, 3, (const double *)part.p, scale, out_dev);
+    k_reduce<<<dim3(1, b.nrhs), kRed, 0, s>>>(b.nb, 1, 3, (const double *)part.p, scale, out_dev, b.sstride,
+                                              b.active);
     HIP_CHECK(hipGetLastError());
 }
 
-void Blas::gcr_scalars(const double *red, double *sc, double *gam, double *alp, int k, hipStream_t s) {
-    k_gcr_scalars<<<1, 1, 0, s>>>(red, sc, gam, (double2 *)alp, k);
+void Blas::gcr_scalars(const double *red, double *sc, double *gam, double *alp, int k, hipStream_t s,
+                       const BatchSpec &bs) {
+    k_gcr_scalars<<<(bs.nrhs + 63) / 64, 64, 0, s>>>(bs.nrhs, bs.sstride, bs.active, red, sc, gam, alp, k);
     HIP_CHECK(hipGetLastError());
 }
 
 void Blas::gcr_update(dirac_prec pr, int nh, const double *sc, void *q, void *r, void *pnext, double *out_dev,
-                      double scale, hipStream_t s) {
-    const int vh = (int)c->vh, n = nh * vh, nb = blas_grid(n);
-#define FN(S)                                                                                            \
-    k_gcr_update<S><<<nb, kRed, 0, s>>>(n, vh, sc, (typename St<S>::vec *)q, (typename St<S>::vec *)r,    \
-                                        (typename St<S>::vec *)pnext, (double *)part.p);
+                      double scale, hipStream_t s, const BatchSpec &bs) {
+    const Bat b = make_bat(c, nh, bs);
+#define FN(S)                                                                                                   \
+    k_gcr_update<S><<<b.nb * b.nrhs, kRed, 0, s>>>(b, sc, (typename St<S>::vec *)q, (typename St<S>::vec *)r,    \
+                                                   (typename St<S>::vec *)pnext, (double *)part.p);
     DISPATCH_PREC(pr, FN)
 #undef FN
-    k_reduce<<<1, kRed, 0, s>>>(nb, 1, 1, (const double *)part.p, scale, out_dev);
+    k_reduce<<<dim3(1, b.nrhs), kRed, 0, s>>>(b.nb, 1, 1, (const double *)part.p, scale, out_dev, b.sstride,
+                                              b.active);
     HIP_CHECK(hipGetLastError());
 }
 
-void Blas::axpy_multi(dirac_prec px, dirac_prec pp, int nh, void *x, const void *P, size_t pstride_bytes, int k,
-                      const double *coef_dev, double xscale, hipStream_t s) {
-    const int vh = (int)c->vh, n = nh * vh, nb = blas_grid(n);
-#define FN2(SX, SP)                                                                                           \
-    k_axpy_multi<SX, SP><<<nb, kRed, 0, s>>>(n, vh, (typename St<SX>::vec *)x, (const typename St<SP>::vec *)P, \
-                                             pstride_bytes / sizeof(typename St<SP>::vec), k,                \
-                                             (const double2 *)coef_dev, xscale);
+void Blas::axpy_multi(dirac_prec px, dirac_prec pp, int nh, void *x, const void *P, int k, const double *coef_dev,
+                      double xscale, hipStream_t s, const BatchSpec &bs, const double *xscales) {
+    const Bat b = make_bat(c, nh, bs);
+#define FN2(SX, SP)                                                                                              \
+    k_axpy_multi<SX, SP><<<b.nb * b.nrhs, kRed, 0, s>>>(b, (typename St<SX>::vec *)x,                             \
+                                                        (const typename St<SP>::vec *)P, k, coef_dev, xscale,     \
+                                                        xscales);
 #define FN(SP)                                                                                     \
     if (px == DIRAC_F64) { FN2(double, SP) } else if (px == DIRAC_F32) { FN2(float, SP) }          \
     else if (px == DIRAC_F16) { FN2(__half, SP) } else { FN2(__hip_bfloat16, SP) }
@@ -391,18 +453,19 @@ void Blas::axpy_multi(dirac_prec px, dirac_prec pp, int nh, void *x, const void 
     HIP_CHECK(hipGetLastError());
 }
 
-// out = alpha a + beta b (b may be NULL), copy2 = out if given; returns |out|^2 * scale and a
+// out = alpha a + beta b (b may be NULL), copy2 = out if given; writes scale |out|^2 and a
 // non-finite flag into out_dev[0..1] when out_dev is given.
 void Blas::lincomb(dirac_prec po, dirac_prec pa, dirac_prec pb, int nh, void *out, void *copy2, double alpha,
-                   const void *a, double beta, const void *b, double *out_dev, double scale, hipStream_t s) {
-    const int vh = (int)c->vh, n = nh * vh, nb = blas_grid(n);
+                   const void *a, double beta, const void *b, double *out_dev, double scale, hipStream_t s,
+                   const BatchSpec &bs, const double *alphas) {
+    const Bat bt = make_bat(c, nh, bs);
     double *pp = out_dev ? (double *)part.p : nullptr;
-#define FN3(SO, SA, SB)                                                                                      \
-    k_lincomb<SO, SA, SB><<<nb, kRed, 0, s>>>(n, vh, (typename St<SO>::vec *)out, (typename St<SO>::vec *)copy2, \
-                                              alpha, (const typename St<SA>::vec *)a, beta,                  \
-                                              (const typename St<SB>::vec *)b, pp);
-    auto same = [&](dirac_prec x, dirac_prec y) { return x == y; };
-    if (same(po, pa) && same(pa, pb)) {
+#define FN3(SO, SA, SB)                                                                                           \
+    k_lincomb<SO, SA, SB><<<bt.nb * bt.nrhs, kRed, 0, s>>>(bt, (typename St<SO>::vec *)out,                       \
+                                                           (typename St<SO>::vec *)copy2, alpha, alphas,          \
+                                                           (const typename St<SA>::vec *)a, beta,                 \
+                                                           (const typename St<SB>::vec *)b, pp);
+    if (po == pa && pa == pb) {
 #define FN(S) FN3(S, S, S)
         DISPATCH_PREC(po, FN)
 #undef FN
@@ -418,7 +481,9 @@ void Blas::lincomb(dirac_prec po, dirac_prec pa, dirac_prec pb, int nh, void *ou
         throw Error(DIRAC_EUNSUPPORTED, "lincomb precision combination");
     }
 #undef FN3
-    if (out_dev) k_reduce<<<1, kRed, 0, s>>>(nb, 1, 2, (const double *)part.p, scale, out_dev);
+    if (out_dev)
+        k_reduce<<<dim3(1, bt.nrhs), kRed, 0, s>>>(bt.nb, 1, 2, (const double *)part.p, scale, out_dev, bt.sstride,
+                                                   bt.active);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -427,7 +492,7 @@ void Blas::cgls_xs(int nh, const double *rho, const double *wn, void *x, const v
     const int vh = (int)c->vh, n = nh * vh, nb = blas_grid(n);
     k_cgls_xs<double><<<nb, kRed, 0, s>>>(n, vh, rho, wn, (double2 *)x, (const double2 *)p, (double2 *)sv,
                                           (const double2 *)w, (double *)part.p);
-    k_reduce<<<1, kRed, 0, s>>>(nb, 1, 1, (const double *)part.p, 1.0, out_dev);
+    k_reduce<<<dim3(1, 1), kRed, 0, s>>>(nb, 1, 1, (const double *)part.p, 1.0, out_dev, 0, nullptr);
     HIP_CHECK(hipGetLastError());
 }
 

@@ -274,12 +274,14 @@ __global__ __launch_bounds__(kBlock) void k_clover_invert(Geom g, int p, const d
 }
 
 template <typename S, int INV>
-__global__ __launch_bounds__(kBlock) void k_clover_apply(int vh, const typename St<S>::vec *__restrict__ in,
+__global__ __launch_bounds__(kBlock) void k_clover_apply(int vh, size_t vs, const typename St<S>::vec *__restrict__ in,
                                                           const typename St<S>::vec *__restrict__ A,
                                                           typename St<S>::vec *__restrict__ out) {
     using T = typename St<S>::acc;
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= vh) return;
+    in += blockIdx.y * vs;  // right-hand side blockIdx.y
+    out += blockIdx.y * vs;
     T r[24], pk[72];
     load_field<S, 24>(in, (uint32_t)i, r);
     load_field<S, 72>(A, (uint32_t)i, pk);
@@ -294,14 +296,17 @@ __global__ __launch_bounds__(kBlock) void k_clover_apply(int vh, const typename 
 }
 
 template <typename S>
-void clover_apply_t(dirac_ctx *c, void *out, const void *in, int parity, int inverse, dirac_prec pr, hipStream_t s) {
+void clover_apply_t(dirac_ctx *c, void *out, const void *in, int parity, int inverse, dirac_prec pr, hipStream_t s,
+                    int nrhs) {
     PrecFields &f = c->f[pr];
     const void *A = inverse ? f.clinv[parity].p : f.clov[parity].p;
     using V = typename St<S>::vec;
+    const size_t vs = (size_t)(24 / St<S>::W) * c->g.vhp;
+    const dim3 grid(grid_for(c->vh), nrhs);
     if (inverse)
-        k_clover_apply<S, 1><<<grid_for(c->vh), kBlock, 0, s>>>((int)c->vh, (const V *)in, (const V *)A, (V *)out);
+        k_clover_apply<S, 1><<<grid, kBlock, 0, s>>>((int)c->vh, vs, (const V *)in, (const V *)A, (V *)out);
     else
-        k_clover_apply<S, 0><<<grid_for(c->vh), kBlock, 0, s>>>((int)c->vh, (const V *)in, (const V *)A, (V *)out);
+        k_clover_apply<S, 0><<<grid, kBlock, 0, s>>>((int)c->vh, vs, (const V *)in, (const V *)A, (V *)out);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -342,16 +347,17 @@ int64_t clover_invert_parity(dirac_ctx *c, int p, hipStream_t s) {
     return h == big ? -1 : (int64_t)h;
 }
 
-void clover_apply(dirac_ctx *c, void *out, const void *in, int parity, int inverse, dirac_prec pr, hipStream_t s) {
+void clover_apply(dirac_ctx *c, void *out, const void *in, int parity, int inverse, dirac_prec pr, hipStream_t s,
+                  int nrhs) {
     require(parity == 0 || parity == 1, "parity must be 0 (even) or 1 (odd)");
     ensure_prec(c, pr, s);
     PrecFields &f = c->f[pr];
     require(!inverse || f.inv_ready[parity], "clover inverse of this parity not computed; call clover_invert");
     switch (pr) {
-        case DIRAC_F64: clover_apply_t<double>(c, out, in, parity, inverse, pr, s); break;
-        case DIRAC_F32: clover_apply_t<float>(c, out, in, parity, inverse, pr, s); break;
-        case DIRAC_F16: clover_apply_t<__half>(c, out, in, parity, inverse, pr, s); break;
-        case DIRAC_BF16: clover_apply_t<__hip_bfloat16>(c, out, in, parity, inverse, pr, s); break;
+        case DIRAC_F64: clover_apply_t<double>(c, out, in, parity, inverse, pr, s, nrhs); break;
+        case DIRAC_F32: clover_apply_t<float>(c, out, in, parity, inverse, pr, s, nrhs); break;
+        case DIRAC_F16: clover_apply_t<__half>(c, out, in, parity, inverse, pr, s, nrhs); break;
+        case DIRAC_BF16: clover_apply_t<__hip_bfloat16>(c, out, in, parity, inverse, pr, s, nrhs); break;
         default: throw Error(DIRAC_EINVAL, "unknown precision");
     }
 }

@@ -18,6 +18,9 @@ struct HopArgs {
     Geom g;
     int p;           // output parity
     int nb8;         // work-groups launched (multiple of 8), for the XCD-contiguous order
+    int nrhs;        // right-hand sides: vector r of in / out / chi is r * vs vectors after the base
+    size_t vs;       // 16-byte vectors per half-lattice spinor
+    const int *active;  // per right-hand side, NULL = all
     const typename St<S>::vec *in;     // parity 1 - p, 24 reals per site
     const typename Lk<S>::vec *links;  // parity p, [8 dir][12 / W][vh]
     const typename Lk<S>::om *omega;   // parity p, [8 dir][vh]
@@ -114,10 +117,19 @@ DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<
 template <typename S, int DAG, int MODE, int XCD>
 __global__ __launch_bounds__(kBlock) void k_hop(HopArgs<S> a) {
     using T = typename St<S>::acc;
-    const int blk = XCD ? xcd_block(a.nb8) : (int)blockIdx.x;
+    // logical work-group -> (site block, right-hand side), right-hand side fastest so that the
+    // right-hand sides of a site block run close in time on one XCD and share its links in L2
+    const int lb = XCD ? xcd_block(a.nb8) : (int)blockIdx.x;
+    const int rhs = lb % a.nrhs, blk = lb / a.nrhs;
+    if (a.active && !a.active[rhs]) return;
     const int ii = blk * kBlock + threadIdx.x;
     if (ii >= a.g.vh) return;
     const uint32_t i = (uint32_t)ii;
+    if (rhs) {
+        a.in += rhs * a.vs;
+        a.out += rhs * a.vs;
+        if (a.chi) a.chi += rhs * a.vs;
+    }
     int x[4];
     site_coords(a.g, ii, a.p, x);
     C<T> acc[12];
@@ -173,23 +185,27 @@ bool use_xcd_order() {
 
 template <typename S, int DAG, int MODE>
 void launch_hop(HopArgs<S> a, hipStream_t s) {
+    const int nb = grid_for(a.g.vh) * a.nrhs;
     if (use_xcd_order()) {
-        a.nb8 = grid_xcd(a.g.vh);
+        a.nb8 = (nb + 7) & ~7;
         k_hop<S, DAG, MODE, 1><<<a.nb8, kBlock, 0, s>>>(a);
     } else {
-        a.nb8 = grid_for(a.g.vh);
+        a.nb8 = nb;
         k_hop<S, DAG, MODE, 0><<<a.nb8, kBlock, 0, s>>>(a);
     }
 }
 
 template <typename S>
 void hop_t(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopMode mode, double coef, int dagger,
-           dirac_prec pr, hipStream_t s) {
+           dirac_prec pr, hipStream_t s, int nrhs, const int *active) {
     PrecFields &f = c->f[pr];
     HopArgs<S> a;
     a.g = c->g;
     a.p = p;
     a.nb8 = 0;
+    a.nrhs = nrhs;
+    a.vs = (size_t)(24 / St<S>::W) * c->g.vhp;
+    a.active = active;
     a.in = (const typename St<S>::vec *)in;
     a.links = (const typename Lk<S>::vec *)f.links[p].p;
     a.omega = (const typename Lk<S>::om *)f.omega[p].p;
@@ -212,29 +228,31 @@ void hop_t(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopM
 }  // namespace
 
 void hop_apply(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopMode mode, double coef, int dagger,
-               dirac_prec pr, hipStream_t s) {
+               dirac_prec pr, hipStream_t s, int nrhs, const int *active) {
+    require(nrhs >= 1, "nrhs must be positive");
     require(p == 0 || p == 1, "parity must be 0 (even) or 1 (odd)");
     ensure_prec(c, pr, s);
     PrecFields &f = c->f[pr];
     require(mode != HOP_INV || f.inv_ready[p], "clover inverse of this parity not computed; call clover_invert");
     switch (pr) {
-        case DIRAC_F64: hop_t<double>(c, out, in, chi, p, mode, coef, dagger, pr, s); break;
-        case DIRAC_F32: hop_t<float>(c, out, in, chi, p, mode, coef, dagger, pr, s); break;
-        case DIRAC_F16: hop_t<__half>(c, out, in, chi, p, mode, coef, dagger, pr, s); break;
-        case DIRAC_BF16: hop_t<__hip_bfloat16>(c, out, in, chi, p, mode, coef, dagger, pr, s); break;
+        case DIRAC_F64: hop_t<double>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active); break;
+        case DIRAC_F32: hop_t<float>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active); break;
+        case DIRAC_F16: hop_t<__half>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active); break;
+        case DIRAC_BF16: hop_t<__hip_bfloat16>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active); break;
         default: throw Error(DIRAC_EINVAL, "unknown precision");
     }
 }
 
 // D-hat in_e = A_ee in_e - D_eo A_oo^-1 D_oe in_e, D_eo = -H_eo / 2:
 //   t_o = A_oo^-1 (-1/2 H_oe in_e);   out_e = A_ee in_e + 1/2 H_eo t_o
-void schur_apply(dirac_ctx *c, void *out_e, const void *in_e, int dagger, dirac_prec pr, hipStream_t s) {
+void schur_apply(dirac_ctx *c, void *out_e, const void *in_e, int dagger, dirac_prec pr, hipStream_t s, int nrhs,
+                 const int *active) {
     ensure_prec(c, pr, s);
     PrecFields &f = c->f[pr];
     require(f.inv_ready[1], "odd-site clover inverse not available (clover_invert failed or was not run)");
-    f.tmp_half.alloc((size_t)24 * real_size(pr) * c->g.vhp);
-    hop_apply(c, f.tmp_half.p, in_e, nullptr, 1, HOP_INV, -0.5, dagger, pr, s);
-    hop_apply(c, out_e, f.tmp_half.p, in_e, 0, HOP_CLOV, 0.5, dagger, pr, s);
+    f.tmp_half.alloc((size_t)nrhs * 24 * real_size(pr) * c->g.vhp);
+    hop_apply(c, f.tmp_half.p, in_e, nullptr, 1, HOP_INV, -0.5, dagger, pr, s, nrhs, active);
+    hop_apply(c, out_e, f.tmp_half.p, in_e, 0, HOP_CLOV, 0.5, dagger, pr, s, nrhs, active);
 }
 
 // D in: out_p = A_pp in_p - 1/2 H in_{1-p} for both parities (NATIVE full vectors).

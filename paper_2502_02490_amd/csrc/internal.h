@@ -65,6 +65,7 @@ struct PrecFields {
 };
 
 struct SolverWork;  // solver.hip
+struct BWork;       // batched.hip
 
 }  // namespace dl
 
@@ -77,6 +78,7 @@ struct dirac_ctx {
     dl::DevBuf flags;              // small device scratch: flags, maxima
     dl::DevBuf red;                // reduction partials
     dl::SolverWork *work = nullptr;
+    dl::BWork *bwork = nullptr;
 };
 
 namespace dl {
@@ -100,14 +102,18 @@ void clover_export(dirac_ctx *c, double *user, int inverse, dirac_layout lay, hi
 // clover.hip
 void clover_build(dirac_ctx *c, hipStream_t s);
 int64_t clover_invert_parity(dirac_ctx *c, int parity, hipStream_t s);  // returns first singular Lambda or -1
-void clover_apply(dirac_ctx *c, void *out, const void *in, int parity, int inverse, dirac_prec pr, hipStream_t s);
+void clover_apply(dirac_ctx *c, void *out, const void *in, int parity, int inverse, dirac_prec pr, hipStream_t s,
+                  int nrhs = 1);
 
 // hop.hip
 enum HopMode { HOP_PLAIN = 0, HOP_INV = 1, HOP_CLOV = 2 };
 // out_p = mode(coef * H in_{1-p}); HOP_INV applies A_pp^-1 after, HOP_CLOV adds A_pp chi_p.
+// nrhs right-hand sides: vector r of out / in / chi is r half-lattice vectors after the base;
+// right-hand sides whose active flag is 0 are skipped.
 void hop_apply(dirac_ctx *c, void *out, const void *in, const void *chi, int out_parity, HopMode mode, double coef,
-               int dagger, dirac_prec pr, hipStream_t s);
-void schur_apply(dirac_ctx *c, void *out_e, const void *in_e, int dagger, dirac_prec pr, hipStream_t s);
+               int dagger, dirac_prec pr, hipStream_t s, int nrhs = 1, const int *active = nullptr);
+void schur_apply(dirac_ctx *c, void *out_e, const void *in_e, int dagger, dirac_prec pr, hipStream_t s, int nrhs = 1,
+                 const int *active = nullptr);
 void full_apply(dirac_ctx *c, void *out, const void *in, int dagger, dirac_prec pr, hipStream_t s);
 
 // solver.hip
@@ -118,5 +124,11 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
                           hipStream_t s);
 dirac_status solve_cgls(dirac_ctx *c, const dirac_solver_params *p, bool x0, dirac_solve_info *info, hipStream_t s);
 void check_solver_params(const dirac_solver_params *p);
+
+// batched.hip
+void free_bwork(dirac_ctx *c);
+dirac_status solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x, const void *const *b, int nrhs,
+                           dirac_layout lay, const dirac_solver_params *p, dirac_solve_info *info, hipStream_t user,
+                           std::string &err);
 
 }  // namespace dl

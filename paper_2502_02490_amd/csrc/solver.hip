@@ -116,8 +116,8 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
             char *qk = Q + k * hb;
             apply(qk, P + k * hb);
             double *bcol = sc_ptr(w, S_BETA + 2 * kMaxRestart * k);
-            if (k > 0) B.mdot(pr, nh, Q, hb, k, qk, bcol, scale, s);
-            B.maxpy_dot(pr, nh, Q, hb, k, bcol, qk, r, sc_ptr(w, S_RED), scale, s);
+            if (k > 0) B.mdot(pr, nh, Q, k, qk, bcol, scale, s);
+            B.maxpy_dot(pr, nh, Q, k, bcol, qk, r, sc_ptr(w, S_RED), scale, s);
             B.gcr_scalars(sc_ptr(w, S_RED), sc_ptr(w, S_SC), sc_ptr(w, S_GAM), sc_ptr(w, S_ALP), k, s);
             // the next direction is r itself (copied by the update) or M(r)
             B.gcr_update(pr, nh, sc_ptr(w, S_SC), qk, r, M ? nullptr : P + (k + 1) * hb, sc_ptr(w, S_RED + 4),
@@ -149,7 +149,7 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
             cc[2 * j + 1] = acc.imag();
         }
         HIP_CHECK(hipMemcpyAsync(sc_ptr(w, S_C), cc.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice, s));
-        B.axpy_multi(pr, pr, nh, x, P, hb, n, sc_ptr(w, S_C), 1.0, s);
+        B.axpy_multi(pr, pr, nh, x, P, n, sc_ptr(w, S_C), 1.0, s);
         // true residual of the updated iterate
         apply(Q, x);
         B.lincomb(pr, pr, pr, nh, r, nullptr, 1.0, b, -1.0, Q, sc_ptr(w, S_RED + 4), scale, s);
@@ -226,7 +226,7 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
     require(c->f[DIRAC_F64].inv_ready[1], "odd-site clover inverse not available (singular block?)");
 
     // |b|^2 (normalised by the half-vector length, like every norm below)
-    B.mdot(DIRAC_F64, 2, bf, 0, 1, bf, sc_ptr(w, S_MISC), scale, s);
+    B.mdot(DIRAC_F64, 2, bf, 1, bf, sc_ptr(w, S_MISC), scale, s);
     const double bn = std::sqrt(read_scalar(w, S_MISC, s));
     require(std::isfinite(bn), "right-hand side holds NaN or Inf", DIRAC_ENONFINITE);
     if (bn == 0.0) {
@@ -313,7 +313,7 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
                 if (!g.nonfinite) {
                     B.set(sc_ptr(w, S_C), 1.0, s);
                     B.set(sc_ptr(w, S_C + 1), 0.0, s);
-                    B.axpy_multi(DIRAC_F64, cur, 1, xe, w.e.p, 0, 1, sc_ptr(w, S_C), rn, s);
+                    B.axpy_multi(DIRAC_F64, cur, 1, xe, w.e.p, 1, sc_ptr(w, S_C), rn, s);
                 }
                 schur_apply(c, t64, xe, 0, DIRAC_F64, s);
                 B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, r64, nullptr, 1.0, eta, -1.0, t64,
@@ -354,7 +354,7 @@ dirac_status solve_cgls(dirac_ctx *c, const dirac_solver_params *p, bool x0, dir
     w.P.alloc(3 * full64);
     char *rv = (char *)w.P.p, *pv = rv + full64, *wv = pv + full64;
     double *rho = sc_ptr(w, S_MISC + 8), *rho_new = sc_ptr(w, S_MISC + 10), *wn = sc_ptr(w, S_MISC + 12);
-    B.mdot(DIRAC_F64, 2, bf, 0, 1, bf, sc_ptr(w, S_MISC), scale, s);
+    B.mdot(DIRAC_F64, 2, bf, 1, bf, sc_ptr(w, S_MISC), scale, s);
     const double bn = std::sqrt(read_scalar(w, S_MISC, s));
     require(std::isfinite(bn), "right-hand side holds NaN or Inf", DIRAC_ENONFINITE);
     if (!x0) B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 2, xf, nullptr, 0.0, bf, 0.0, nullptr, nullptr, 1.0, s);
@@ -371,13 +371,13 @@ dirac_status solve_cgls(dirac_ctx *c, const dirac_solver_params *p, bool x0, dir
         if (it > 0) ++info->restarts;
         full_apply(c, rv, sv, 1, DIRAC_F64, s);
         B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 2, pv, nullptr, 1.0, rv, 0.0, nullptr, nullptr, 1.0, s);
-        B.mdot(DIRAC_F64, 2, rv, 0, 1, rv, rho, scale, s);
+        B.mdot(DIRAC_F64, 2, rv, 1, rv, rho, scale, s);
         while (it < p->max_iter) {
             full_apply(c, wv, pv, 0, DIRAC_F64, s);
-            B.mdot(DIRAC_F64, 2, wv, 0, 1, wv, wn, scale, s);
+            B.mdot(DIRAC_F64, 2, wv, 1, wv, wn, scale, s);
             B.cgls_xs(2, rho, wn, xf, pv, sv, wv, sc_ptr(w, S_MISC + 6), s);
             full_apply(c, rv, sv, 1, DIRAC_F64, s);
-            B.mdot(DIRAC_F64, 2, rv, 0, 1, rv, rho_new, scale, s);
+            B.mdot(DIRAC_F64, 2, rv, 1, rv, rho_new, scale, s);
             B.cgls_p(2, rho_new, rho, pv, rv, s);
             B.copy_scalar(rho_new, rho, s);
             ++it;
