@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve timings")
     ap.add_argument("--no-48", action="store_true", help="skip the 48^3x96 mixed-precision solves")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run 5 plain device copies of 768 MiB (a known-size kernel for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the operator runs on a single MI355X (multi-GPU halo exchange is "
@@ -129,6 +131,16 @@ def main():
     y = torch.empty_like(x)
     torch.cuda.synchronize()
 
+    if args.copy_calibration:
+        # a plain copy of exactly 768 MiB read + 768 MiB written per launch, to scale the
+        # FETCH_SIZE / WRITE_SIZE counters of a profiled run
+        src = torch.ones(768 * 2**20 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # ---- timed region: K Schur applies (FP64, NATIVE)
     schur = lambda: D.apply_eo(ye, xe, "f64", "native")  # noqa: E731
     for _ in range(args.warmup):
@@ -150,6 +162,17 @@ def main():
     log(f"[bench] hop+clover kernel FP64: {k_dur * 1e6:.1f} us/launch, {k_gbs:.0f} GB/s")
 
     extra = {}
+    # every launch shape of the hop kernel, FP64 Schur (the tuner's choice is what the timed loop used)
+    shapes = {}
+    for shape in range(8):
+        os.environ["DIRAC_HOP_SHAPE"] = str(shape)
+        for _ in range(3):
+            schur()
+        ts = timed(schur, max(10, args.steps // 4), stream)
+        shapes[shape] = round(SCHUR_REALS * 8 * vh * max(10, args.steps // 4) / ts / 1e9, 1)
+    del os.environ["DIRAC_HOP_SHAPE"]
+    extra["schur_f64_GBps_by_shape"] = shapes
+    log(f"[bench] Schur FP64 GB/s by launch shape {shapes}")
     # FP32 Schur
     x32 = D.to_native(torch.from_numpy(psi.astype(np.complex64)).cuda(), "f32", "lex")
     xe32 = x32[: x32.numel() // 2].clone()

@@ -7,6 +7,9 @@
 // half-spinor, multiplies by the link (two stored rows, third rebuilt, phase exp(+-i omega)),
 // and accumulates the reconstructed spinor.  The dagger, gamma_5 H gamma_5, flips the
 // projector signs.  Epilogues: HOP_INV applies A_pp^-1 to the result, HOP_CLOV adds A_pp chi.
+#include <cstdio>
+#include <type_traits>
+
 #include "dirac_ops.h"
 #include "internal.h"
 
@@ -17,7 +20,8 @@ template <typename S>
 struct HopArgs {
     Geom g;
     int p;           // output parity
-    int nb8;         // work-groups launched (multiple of 8), for the XCD-contiguous order
+    int nb8;         // work-groups launched (a multiple of 8 with the XCD-contiguous order)
+    int xcd;         // 1: XCD-contiguous work-group order
     int nrhs;        // right-hand sides: vector r of in / out / chi is r * vs vectors after the base
     size_t vs;       // 16-byte vectors per half-lattice spinor
     const int *active;  // per right-hand side, NULL = all
@@ -69,8 +73,12 @@ DEV C<T> cmul_unit(T cr, T ci, C<T> z) { return mk(cr * z.r - ci * z.i, cr * z.i
 // the direction a uniform run-time value: straight-line code lets the compiler issue the
 // loads of all eight neighbours up front, which needs more registers than a lane has
 // (spills, one wave per SIMD).  The loop keeps one neighbour's data live at a time.
+// With `tile` (the t-tiled kernel) the two time-direction neighbours come from LDS: slot
+// `tslot` - 1 / + 1 of the tile holds the input block of the previous / next time slice at the
+// same spatial block, and the neighbour sits at the same lane.
 template <typename S, int DAG>
-DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<S>::acc> acc[12]) {
+DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<S>::acc> acc[12],
+                 const typename St<S>::vec *tile = nullptr, int tslot = 0) {
     using T = typename St<S>::acc;
     const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
 #pragma nounroll
@@ -89,7 +97,9 @@ DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<
         const T c1r = mu == 0 ? T(-1) : mu == 2 ? T(1) : T(0), c1i = mu == 1 ? T(-1) : mu == 3 ? T(1) : T(0);
         C<T> psi[12], h[6], u[6], w[6];
         T co, si;
-        load_spinor<S>(a.in, j, psi);
+        if (tile && mu == 0) load_spinor<S>(tile + (size_t)(tslot + (back ? -1 : 1)) * (24 / St<S>::W) * kSB,
+                                            i & (kSB - 1), psi);
+        else load_spinor<S>(a.in, j, psi);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const C<T> l0 = psi[6 + c], l1 = psi[9 + c];
@@ -114,28 +124,22 @@ DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<
     }
 }
 
-template <typename S, int DAG, int MODE, int XCD>
-__global__ __launch_bounds__(kBlock) void k_hop(HopArgs<S> a) {
+// Launch shapes of the hop kernel: work-group size BS and an occupancy hint WPE (minimum waves
+// per SIMD the register allocation must allow; 0 = compiler default).  All shapes compute the
+// same sums in the same order, so their results are bitwise identical; the tuner only picks the
+// fastest (see tune.cpp).
+// Everything of one output site after the work assignment: the 8 neighbours, the scale, the
+// clover epilogue / prologue and the store.
+template <typename S, int DAG, int MODE>
+DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, int tslot) {
     using T = typename St<S>::acc;
-    // logical work-group -> (site block, right-hand side), right-hand side fastest so that the
-    // right-hand sides of a site block run close in time on one XCD and share its links in L2
-    const int lb = XCD ? xcd_block(a.nb8) : (int)blockIdx.x;
-    const int rhs = lb % a.nrhs, blk = lb / a.nrhs;
-    if (a.active && !a.active[rhs]) return;
-    const int ii = blk * kBlock + threadIdx.x;
-    if (ii >= a.g.vh) return;
     const uint32_t i = (uint32_t)ii;
-    if (rhs) {
-        a.in += rhs * a.vs;
-        a.out += rhs * a.vs;
-        if (a.chi) a.chi += rhs * a.vs;
-    }
     int x[4];
     site_coords(a.g, ii, a.p, x);
     C<T> acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = mk(T(0), T(0));
-    hop_all<S, DAG>(a, x, i, acc);
+    hop_all<S, DAG>(a, x, i, acc, tile, tslot);
     C<T> y[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) y[k] = a.coef * acc[k];
@@ -174,24 +178,105 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs<S> a) {
     store_field<S, 24>(a.out, i, r);
 }
 
-bool use_xcd_order() {
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("DIRAC_XCD_ORDER");
-        v = e ? atoi(e) != 0 : 1;
+template <typename S, int DAG, int MODE, int BS, int WPE>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_hop(HopArgs<S> a) {
+    // logical work-group -> (site block, right-hand side), right-hand side fastest so that the
+    // right-hand sides of a site block run close in time on one XCD and share its links in L2
+    const int lb = a.xcd ? xcd_block(a.nb8) : (int)blockIdx.x;
+    const int rhs = lb % a.nrhs, blk = lb / a.nrhs;
+    if (a.active && !a.active[rhs]) return;
+    const int ii = blk * BS + threadIdx.x;
+    if (ii >= a.g.vh) return;
+    if (rhs) {
+        a.in += rhs * a.vs;
+        a.out += rhs * a.vs;
+        if (a.chi) a.chi += rhs * a.vs;
     }
-    return v != 0;
+    hop_site<S, DAG, MODE>(a, ii, nullptr, 0);
+}
+
+// Time-tiled variant: a work-group of TT wavefronts takes one spatial block of 64 sites in TT
+// consecutive time slices.  Each wavefront stages the input block of its slice in LDS, the
+// first and last also the blocks of the slices just outside the tile (periodic in time), so
+// both time-direction neighbours of every site are read from LDS and each input block is
+// fetched once per tile instead of three times (its own slice and the slices above and
+// below).  Needs (L1 L2 L3 / 2) % 64 == 0 and L0 % TT == 0.
+template <typename S, int DAG, int MODE, int TT>
+__global__ __launch_bounds__(64 * TT) void k_hop_t(HopArgs<S> a) {
+    using V = typename St<S>::vec;
+    constexpr int NP = 24 / St<S>::W;
+    __shared__ V tile[(TT + 2) * NP * kSB];
+    const int lb = a.xcd ? xcd_block(a.nb8) : (int)blockIdx.x;
+    const int nsb = a.g.vh / (a.g.L[0] * kSB);  // site blocks per time slice
+    const int rhs = lb % a.nrhs, wg = lb / a.nrhs;
+    const int sb = wg % nsb, t0 = (wg / nsb) * TT;
+    if (t0 >= a.g.L[0]) return;
+    if (a.active && !a.active[rhs]) return;
+    if (rhs) {
+        a.in += rhs * a.vs;
+        a.out += rhs * a.vs;
+        if (a.chi) a.chi += rhs * a.vs;
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & (kSB - 1);
+    auto stage = [&](int slot, int t) {
+        const V *src = a.in + ((size_t)(t * nsb + sb) * NP) * kSB + lane;
+        V *dst = tile + (size_t)slot * NP * kSB + lane;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) dst[k * kSB] = src[k * kSB];
+    };
+    stage(w + 1, t0 + w);
+    if (w == 0) stage(0, t0 == 0 ? a.g.L[0] - 1 : t0 - 1);
+    if (w == TT - 1) stage(TT + 1, t0 + TT == a.g.L[0] ? 0 : t0 + TT);
+    __syncthreads();
+    const int ii = ((t0 + w) * nsb + sb) * kSB + lane;
+    hop_site<S, DAG, MODE>(a, ii, tile, w + 1);
+}
+
+struct HopShape {
+    int bs, wpe, xcd, tt;
+};
+// shape 0 is the default; occupancy hints only where the default leaves fewer than 4 waves/SIMD;
+// shapes with tt > 0 are the time-tiled kernel (bs = 64 tt)
+const HopShape kShapes[] = {{256, 0, 1, 0}, {256, 0, 0, 0}, {128, 0, 1, 0}, {64, 0, 1, 0},
+                            {256, 0, 1, 4}, {512, 0, 1, 8}, {256, 3, 1, 0}, {128, 3, 1, 0}};
+template <typename S> constexpr int num_shapes() { return std::is_same<S, double>::value ? 8 : 6; }
+bool tiled_ok(const Geom &g, int tt) {
+    const int ns = g.vh / g.L[0];
+    return ns % kSB == 0 && g.L[0] % tt == 0;
+}
+
+template <typename S, int DAG, int MODE, int BS, int WPE>
+void launch_shape(HopArgs<S> a, int xcd, hipStream_t s) {
+    const int nb = (a.g.vh + BS - 1) / BS * a.nrhs;
+    a.xcd = xcd;
+    a.nb8 = xcd ? (nb + 7) & ~7 : nb;
+    k_hop<S, DAG, MODE, BS, WPE><<<a.nb8, BS, 0, s>>>(a);
+}
+
+template <typename S, int DAG, int MODE, int TT>
+void launch_tiled(HopArgs<S> a, hipStream_t s) {
+    const int nb = (a.g.L[0] / TT) * (a.g.vh / (a.g.L[0] * kSB)) * a.nrhs;
+    a.xcd = 1;
+    a.nb8 = (nb + 7) & ~7;
+    k_hop_t<S, DAG, MODE, TT><<<a.nb8, 64 * TT, 0, s>>>(a);
 }
 
 template <typename S, int DAG, int MODE>
-void launch_hop(HopArgs<S> a, hipStream_t s) {
-    const int nb = grid_for(a.g.vh) * a.nrhs;
-    if (use_xcd_order()) {
-        a.nb8 = (nb + 7) & ~7;
-        k_hop<S, DAG, MODE, 1><<<a.nb8, kBlock, 0, s>>>(a);
-    } else {
-        a.nb8 = nb;
-        k_hop<S, DAG, MODE, 0><<<a.nb8, kBlock, 0, s>>>(a);
+void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
+    const HopShape h = kShapes[shape];
+    if (h.tt && !tiled_ok(a.g, h.tt)) shape = 0;  // the tile does not fit this lattice
+    switch (shape) {
+        case 0: case 1: launch_shape<S, DAG, MODE, 256, 0>(a, h.xcd, s); break;
+        case 2: launch_shape<S, DAG, MODE, 128, 0>(a, h.xcd, s); break;
+        case 3: launch_shape<S, DAG, MODE, 64, 0>(a, h.xcd, s); break;
+        case 4: launch_tiled<S, DAG, MODE, 4>(a, s); break;
+        case 5: launch_tiled<S, DAG, MODE, 8>(a, s); break;
+        case 6:
+            if constexpr (std::is_same<S, double>::value) launch_shape<S, DAG, MODE, 256, 3>(a, h.xcd, s);
+            break;
+        default:
+            if constexpr (std::is_same<S, double>::value) launch_shape<S, DAG, MODE, 128, 3>(a, h.xcd, s);
+            break;
     }
 }
 
@@ -213,16 +298,23 @@ void hop_t(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopM
     a.chi = (const typename St<S>::vec *)chi;
     a.out = (typename St<S>::vec *)out;
     a.coef = (typename St<S>::acc)coef;
-    if (dagger) {
-        if (mode == HOP_PLAIN) launch_hop<S, 1, HOP_PLAIN>(a, s);
-        else if (mode == HOP_INV) launch_hop<S, 1, HOP_INV>(a, s);
-        else launch_hop<S, 1, HOP_CLOV>(a, s);
-    } else {
-        if (mode == HOP_PLAIN) launch_hop<S, 0, HOP_PLAIN>(a, s);
-        else if (mode == HOP_INV) launch_hop<S, 0, HOP_INV>(a, s);
-        else launch_hop<S, 0, HOP_CLOV>(a, s);
-    }
-    HIP_CHECK(hipGetLastError());
+    a.xcd = 1;
+    auto launch = [&](int shape) {
+        if (dagger) {
+            if (mode == HOP_PLAIN) launch_hop<S, 1, HOP_PLAIN>(a, shape, s);
+            else if (mode == HOP_INV) launch_hop<S, 1, HOP_INV>(a, shape, s);
+            else launch_hop<S, 1, HOP_CLOV>(a, shape, s);
+        } else {
+            if (mode == HOP_PLAIN) launch_hop<S, 0, HOP_PLAIN>(a, shape, s);
+            else if (mode == HOP_INV) launch_hop<S, 0, HOP_INV>(a, shape, s);
+            else launch_hop<S, 0, HOP_CLOV>(a, shape, s);
+        }
+        HIP_CHECK(hipGetLastError());
+    };
+    char key[160];
+    snprintf(key, sizeof key, "k_hop|%s|dag%d|mode%d|%dx%dx%dx%d|nrhs%d", prec_name(pr), dagger, (int)mode,
+             c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3], nrhs);
+    launch(tuned_choice(key, num_shapes<S>(), launch, s));
 }
 
 }  // namespace

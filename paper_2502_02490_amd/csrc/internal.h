@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <stdexcept>
 #include <string>
 
@@ -65,7 +66,12 @@ struct PrecFields {
 };
 
 struct SolverWork;  // solver.hip
-struct BWork;       // batched.hip
+struct BWork;       // tune.hip: launch-shape tuner (see there)
+const char *prec_name(dirac_prec pr);
+int tuned_choice(const char *key, int nshapes, const std::function<void(int)> &launch, hipStream_t s);
+int tuned_lookup(const char *key);  // -1 when the key has not been tuned
+
+// batched.hip
 
 }  // namespace dl
 
@@ -124,6 +130,11 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
                           hipStream_t s);
 dirac_status solve_cgls(dirac_ctx *c, const dirac_solver_params *p, bool x0, dirac_solve_info *info, hipStream_t s);
 void check_solver_params(const dirac_solver_params *p);
+
+// tune.hip: launch-shape tuner (see there)
+const char *prec_name(dirac_prec pr);
+int tuned_choice(const char *key, int nshapes, const std::function<void(int)> &launch, hipStream_t s);
+int tuned_lookup(const char *key);  // -1 when the key has not been tuned
 
 // batched.hip
 void free_bwork(dirac_ctx *c);

@@ -166,3 +166,32 @@ def test_schur_32c64_sampled_sites(qhat):
         assert rel(g32[pick], exp32) <= 1e-6
     finally:
         c.D.close()
+
+
+def test_hop_launch_shapes_bitwise_identical(monkeypatch):
+    """Every launch shape the tuner may pick (work-group size, occupancy hint, work-group order,
+    time-tiled LDS staging) gives bitwise the same Schur output, in every precision."""
+    need_gpu()
+    c = Case((8, 4, 8, 8), seed=55, qhat=2)  # (L1 L2 L3 / 2) % 64 == 0 and L0 % 8 == 0: tiles fit
+    try:
+        psi_e = c.spinor(3)[c.even]
+        for prec in ("f64", "f32", "f16", "bf16"):
+            nat = c.D.to_native(to_dev(psi_e.astype(np.complex64) if prec == "f32" else psi_e), prec, "eo", sites=1)
+            ref = None
+            for shape in range(8):
+                monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
+                out = c.D.native_empty(prec, 1)
+                c.D.apply_eo(out, nat, prec, "native")
+                full = c.D.native_empty(prec, 0)
+                c.D.apply(full, torch.cat([nat, nat]), prec, "native", dagger=True)
+                if ref is None:
+                    ref = (out.clone(), full.clone())
+                else:
+                    assert torch.equal(out, ref[0]) and torch.equal(full, ref[1]), (prec, shape)
+        exp = odirac.apply_schur(c.f, psi_e)
+        monkeypatch.setenv("DIRAC_HOP_SHAPE", "5")
+        out = torch.empty_like(to_dev(psi_e))
+        c.D.apply_eo(out, to_dev(psi_e), "f64", "eo")
+        assert rel(out.cpu().numpy(), exp) <= 1e-13
+    finally:
+        c.D.close()
