@@ -93,6 +93,120 @@ def solve_suite(D, b, inner_precs):
     return res
 
 
+BATCH_DIMS = [(8, 8, 8, 8), (12, 12, 12, 12)] + [(32, 16, 16, 16)] * 3 + [(48, 24, 24, 24)] * 3
+
+
+def batched_suite():
+    """12 spin-colour point sources (at the origin) on each of 8 lattices of uneven size, kappa_j =
+    0.120 + 0.005 j / 7, eps = 0.5, c_sw = 1.6, c_sw^QED = 1.0, qhat = -1, seeds 401 + j; FP64
+    defect correction around batched FP32 GCR(32), to 1e-10; compared with the 96 plain FP64
+    even-odd GCR(32) solves done one after another on the same GPU."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2502_02490_amd as P
+
+    ops, bs = [], []
+    for j, d in enumerate(BATCH_DIMS):
+        U = gen.su3_field(d, EPS, 401 + j)
+        th = gen.u1_field(d, 0.3, 401 + j)
+        ops.append(P.Dirac(torch.from_numpy(U).cuda(), torch.from_numpy(th).cuda(), d, 0.120 + 0.005 * j / 7, CSW,
+                           CSW_QED, QHAT))
+        V = math.prod(d)
+        b = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device="cuda")
+        for s_ in range(4):
+            for a in range(3):
+                b[3 * s_ + a, 0, s_, a] = 1.0
+        bs.append(b)
+    xs = [torch.zeros_like(b) for b in bs]
+    P.solve_batched(ops, xs, bs, 12, method=P.MIXED_GCR, inner_prec="f32", tol=1e-10)  # tuning, graphs
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = P.solve_batched(ops, xs, bs, 12, method=P.MIXED_GCR, inner_prec="f32", tol=1e-10)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    err, iters = 0.0, 0
+    for D, b, x in zip(ops, bs, xs):
+        for r in range(12):
+            y = torch.zeros_like(b[r])
+            inf = D.solve(y, b[r].contiguous(), method=P.GCR, tol=1e-10, restart=32)
+            iters += inf.iters
+            err = max(err, (torch.linalg.vector_norm(x[r] - y) / torch.linalg.vector_norm(y)).item())
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    worst = max(i.true_rel_res for row in infos for i in row)
+    for D in ops:
+        D.close()
+    return {"lattices": ["x".join(map(str, d)) for d in BATCH_DIMS], "nrhs": 12,
+            "batched_mixed_f32_seconds": round(t_batched, 4), "sequential_fp64_gcr_seconds": round(t_seq, 4),
+            "speedup_vs_sequential_fp64": round(t_seq / t_batched, 3), "worst_true_rel_res": worst,
+            "max_rel_diff_vs_fp64": err, "fp64_total_iters": iters,
+            "inner_iters_per_lattice": [max(i.iters for i in row) for row in infos]}
+
+
+PTC_TRAIN_DIMS = (32, 16, 16, 16)
+PTC_KAPPA = 0.1245
+
+
+def ptc_suite(pairs_per_field: int, epochs: int, checkpoint: str | None):
+    """Learned preconditioner: a (1, 8, 8, 1)-channel PTC network trained on pairs from four
+    16^3 x 32 fields (seeds 501..504, eps = 0.5, kappa = 0.1245, c_sw = 1.6, c_sw^QED = 1.0,
+    qhat = -1), then deployed in flexible GCR on a 32^3 x 64 field (seed 505) against plain
+    FP64 even-odd GCR(32), both to 1e-10.  Pair generation and training time are reported
+    apart from the solves."""
+    import torch
+
+    import gen
+    import paper_2502_02490_amd as P
+    from paper_2502_02490_amd import ptc_train as T
+
+    res = {"train_lattice": "x".join(map(str, PTC_TRAIN_DIMS)), "fields": 4, "channels": [1, 8, 8, 1]}
+    ops_pairs, held = [], []
+    t0 = time.perf_counter()
+    for j in range(4):
+        d = PTC_TRAIN_DIMS
+        D = P.Dirac(torch.from_numpy(gen.su3_field(d, EPS, 501 + j)).cuda(),
+                    torch.from_numpy(gen.u1_field(d, 0.3, 501 + j)).cuda(), d, PTC_KAPPA, CSW, CSW_QED, QHAT)
+        rs, es = T.generate_pairs(D, pairs_per_field, seed=501 + j, log=log)
+        ops_pairs.append((D, rs, es))
+        hr, he = T.generate_pairs(D, 12, seed=10501 + j)
+        held.append((D, hr, he))
+        log(f"[ptc] field {j}: {len(rs)} pairs ({time.perf_counter() - t0:.1f} s)")
+    res["pairs"] = sum(len(rs) for _, rs, _ in ops_pairs)
+    res["pair_generation_seconds"] = round(time.perf_counter() - t0, 2)
+    net = P.PTC((1, 8, 8, 1))
+    net.set_weights(T.init_weights((1, 8, 8, 1), seed=7))
+    res["held_out_loss_init"] = T.evaluate(held, net)
+    t1 = time.perf_counter()
+    hist = T.train(ops_pairs, net, epochs=epochs, batch=16, lr=2e-3, seed=11, lr_decay=0.8,
+                   log=lambda m: log("[ptc] " + m))
+    res["training_seconds"] = round(time.perf_counter() - t1, 2)
+    res["train_loss_by_epoch"] = [round(h, 5) for h in hist]
+    res["held_out_loss"] = T.evaluate(held, net)
+    log(f"[ptc] held-out loss {res['held_out_loss_init']:.4f} -> {res['held_out_loss']:.4f}")
+    if checkpoint:
+        T.save_checkpoint(checkpoint, net, epochs, 11, meta={"pairs": res["pairs"], "train": res["train_lattice"]})
+    for D, _, _ in ops_pairs:
+        D.close()
+    del ops_pairs, held
+    torch.cuda.empty_cache()
+    d = DIMS
+    D = P.Dirac(torch.from_numpy(gen.su3_field(d, EPS, 505)).cuda(), torch.from_numpy(gen.u1_field(d, 0.3, 505)).cuda(),
+                d, PTC_KAPPA, CSW, CSW_QED, QHAT)
+    b = torch.from_numpy(gen.gaussian_spinor(d, 505)).cuda()
+    T.compare_solvers(D, net, b, tol=1e-10)  # warm-up (tuning, work buffers)
+    res["deploy_32c64"] = T.compare_solvers(D, net, b, tol=1e-10, reps=2)
+    log(f"[ptc] deploy {res['deploy_32c64']}")
+    g, f = res["deploy_32c64"]["eo_gcr"], res["deploy_32c64"]["fgcr_ptc"]
+    res["speedup_vs_eo_gcr"] = round(g["seconds"] / f["seconds"], 3)
+    D.close()
+    net.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +215,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve timings")
     ap.add_argument("--no-48", action="store_true", help="skip the 48^3x96 mixed-precision solves")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 8-lattice x 12-RHS batched solve")
+    ap.add_argument("--ptc", action="store_true",
+                    help="also train the PTC preconditioner (2000 pairs on 16^3x32) and deploy it on 32^3x64")
+    ap.add_argument("--ptc-pairs", type=int, default=500, help="training pairs per 16^3x32 field")
+    ap.add_argument("--ptc-epochs", type=int, default=8)
+    ap.add_argument("--ptc-checkpoint", default=None, help="write the trained weights and Adam state here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 5 plain device copies of 768 MiB (a known-size kernel for HBM counter calibration)")
     args = ap.parse_args()
@@ -226,6 +346,13 @@ def main():
         solves["48^3x96"] = solve_suite(D3, torch.from_numpy(b3).cuda(), ("f32", "f16", "bf16"))
         log(f"[bench] solves 48^3x96 {solves['48^3x96']}")
         D3.close()
+
+    if not args.no_solve and not args.no_batched:
+        solves["batched_8lat_12rhs"] = batched_suite()
+        log(f"[bench] batched {solves['batched_8lat_12rhs']}")
+
+    if args.ptc:
+        solves["ptc_learned_preconditioner"] = ptc_suite(args.ptc_pairs, args.ptc_epochs, args.ptc_checkpoint)
 
     cpu = None
     if not args.no_cpu_baseline:

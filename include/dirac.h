@@ -239,6 +239,10 @@ dirac_status ptc_forward(dirac_ctx *ctx, dirac_ptc *net, void *out, const void *
 dirac_status ptc_backward(dirac_ctx *ctx, dirac_ptc *net, void *grad_in, const void *in, const void *grad_out,
                           void *stream);
 dirac_status ptc_adam_step(dirac_ptc *net, double lr, void *stream);
+/* Adam state (first and second moments, n floats each, same order as the weights, and the
+ * step count) for checkpoint and resume.  ptc_set_adam_state after ptc_set_weights. */
+dirac_status ptc_get_adam_state(const dirac_ptc *net, float *host_m, float *host_v, size_t n, int *step);
+dirac_status ptc_set_adam_state(dirac_ptc *net, const float *host_m, const float *host_v, size_t n, int step);
 /* One minibatch step: zero the gradient, accumulate over the nbatch pairs (r[i], e[i])
  * (NATIVE F32 full vectors), take one Adam step; *loss = L before the step.  Blocking. */
 dirac_status ptc_train_step(dirac_ctx *ctx, dirac_ptc *net, const void *const *r, const void *const *e, int nbatch,

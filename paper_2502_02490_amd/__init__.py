@@ -283,6 +283,27 @@ class PTC:
     def adam_step(self, lr, stream=None):
         _lib.check(self.lib.ptc_adam_step(self._net, float(lr), _stream(stream)))
 
+    def get_adam_state(self):
+        """(first moments, second moments, step): moments as float32 arrays in weight order."""
+        import numpy as np
+
+        m = np.empty(self.n, dtype=np.float32)
+        v = np.empty(self.n, dtype=np.float32)
+        step = ctypes.c_int()
+        _lib.check(self.lib.ptc_get_adam_state(self._net, m.ctypes.data_as(ctypes.c_void_p),
+                                               v.ctypes.data_as(ctypes.c_void_p), self.n, ctypes.byref(step)))
+        return m, v, step.value
+
+    def set_adam_state(self, m, v, step: int):
+        import numpy as np
+
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        if m.size != self.n or v.size != self.n:
+            raise ValueError("moment sizes do not match the network")
+        _lib.check(self.lib.ptc_set_adam_state(self._net, m.ctypes.data_as(ctypes.c_void_p),
+                                               v.ctypes.data_as(ctypes.c_void_p), self.n, int(step)))
+
     def train_step(self, D: Dirac, rs, es, lr, stream=None) -> float:
         nb = D.native_bytes("f32", 0)
         n = len(rs)

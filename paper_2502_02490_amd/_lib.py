@@ -19,7 +19,8 @@ EXPORTS = ["dirac_create", "dirac_destroy", "dirac_load_clover", "dirac_get_clov
            "dirac_native_bytes", "dirac_import", "dirac_export", "dirac_apply", "dirac_apply_eo",
            "dirac_apply_hop", "dirac_apply_clover", "dirac_solve", "dirac_solve_batched", "dirac_last_error",
            "ptc_create", "ptc_destroy", "ptc_num_weights", "ptc_set_weights", "ptc_get_weights", "ptc_get_grad",
-           "ptc_zero_grad", "ptc_forward", "ptc_backward", "ptc_adam_step", "ptc_train_step"]
+           "ptc_zero_grad", "ptc_forward", "ptc_backward", "ptc_adam_step", "ptc_get_adam_state", "ptc_set_adam_state",
+           "ptc_train_step"]
 
 
 class Params(ctypes.Structure):
@@ -85,6 +86,8 @@ def load(path: str = LIB_PATH):
     lib.ptc_forward.argtypes = [vp, vp, vp, vp, vp]
     lib.ptc_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.ptc_adam_step.argtypes = [vp, ctypes.c_double, vp]
+    lib.ptc_get_adam_state.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int)]
+    lib.ptc_set_adam_state.argtypes = [vp, vp, vp, ctypes.c_size_t, i]
     lib.ptc_train_step.argtypes = [vp, vp, vp, vp, i, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
     for name in EXPORTS:
         if name not in ("dirac_native_bytes", "dirac_last_error", "ptc_num_weights"):

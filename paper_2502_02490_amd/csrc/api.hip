@@ -444,6 +444,32 @@ dirac_status ptc_get_grad(const dirac_ptc *n, float *host_g, size_t cnt) {
     API_END
 }
 
+dirac_status ptc_get_adam_state(const dirac_ptc *n, float *host_m, float *host_v, size_t cnt, int *step) {
+    API_BEGIN
+    require(n != nullptr && host_m != nullptr && host_v != nullptr && step != nullptr, "NULL argument");
+    require(cnt == 2 * n->total, "moment count must equal ptc_num_weights");
+    HIP_CHECK(hipDeviceSynchronize());
+    HIP_CHECK(hipMemcpy(host_m, n->m.p, cnt * sizeof(float), hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(host_v, n->v.p, cnt * sizeof(float), hipMemcpyDeviceToHost));
+    *step = n->step;
+    API_END
+}
+
+dirac_status ptc_set_adam_state(dirac_ptc *n, const float *host_m, const float *host_v, size_t cnt, int step) {
+    API_BEGIN
+    require(n != nullptr && host_m != nullptr && host_v != nullptr, "NULL argument");
+    require(cnt == 2 * n->total, "moment count must equal ptc_num_weights");
+    require(step >= 0, "step must not be negative");
+    for (size_t i = 0; i < cnt; ++i)
+        require(std::isfinite(host_m[i]) && std::isfinite(host_v[i]) && host_v[i] >= 0.0f,
+                "moments must be finite, second moments non-negative");
+    HIP_CHECK(hipDeviceSynchronize());
+    HIP_CHECK(hipMemcpy(n->m.p, host_m, cnt * sizeof(float), hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(n->v.p, host_v, cnt * sizeof(float), hipMemcpyHostToDevice));
+    n->step = step;
+    API_END
+}
+
 dirac_status ptc_zero_grad(dirac_ptc *n, void *stream) {
     API_BEGIN
     require(n != nullptr, "network is NULL");

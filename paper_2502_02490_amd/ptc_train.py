@@ -1,0 +1,154 @@
+"""Training driver of the learned preconditioner (a parallel-transport convolution network).
+
+Training pairs (r, e) with e = D^-1 r come from the library's own FP64 solver.  For a Gaussian
+right-hand side b with solution x* (FP64 even-odd GCR to 1e-12), the iterate x_k after k GCR
+iterations from zero has residual r_k = b - D x_k and error e_k = x* - x_k, and D e_k = r_k.
+k = 0 gives the broadband pair (b, x*); larger k give the low-mode dominated residuals a
+flexible GCR hands its preconditioner late in a solve.  Each pair is scaled so that |e| = 1
+(the network is linear and the loss is scale free).
+
+The loss is mean_i |N(r_i) - e_i|^2 / |e_i|^2; ptc_train_step runs the forward pass, the
+loss, the input and weight gradients and one Adam step in the library's kernels.  Minibatches
+are drawn from one gauge field at a time (the network transports with that field's links).
+
+Checkpoints are .npz files without pickled objects: a JSON header (version, channels, dtype,
+Adam step, epochs done, shuffling seed, free-form metadata) and float32 arrays of weights and
+Adam moments, so that a resumed run continues bit-for-bit where it stopped.
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import GCR, FGCR_PTC, Dirac, PTC
+
+CHECKPOINT_VERSION = 1
+DEFAULT_SNAPSHOTS = (0, 2, 4, 8, 16, 32)
+
+
+def generate_pairs(D: Dirac, n_pairs: int, seed: int, snapshots=DEFAULT_SNAPSHOTS, restart: int = 32, log=None):
+    """n_pairs (r, e) pairs on the lattice of D as NATIVE F32 full vectors (two lists)."""
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    rs, es = [], []
+    t0 = time.perf_counter()
+    while len(rs) < n_pairs:
+        b = torch.randn((D.V, 4, 3), dtype=torch.complex128, generator=g).cuda()
+        xs = torch.zeros_like(b)
+        D.solve(xs, b, method=GCR, tol=1e-12, restart=restart)
+        for k in snapshots:
+            if len(rs) == n_pairs:
+                break
+            if k == 0:
+                r, e = b, xs
+            else:
+                xk = torch.zeros_like(b)
+                D.solve(xk, b, method=GCR, tol=1e-12, max_iter=k, restart=restart, raise_on_noconv=False)
+                dx = torch.empty_like(b)
+                D.apply(dx, xk)
+                r, e = b - dx, xs - xk
+            s = 1.0 / torch.linalg.vector_norm(e).item()
+            rs.append(D.to_native((r * s).to(torch.complex64), "f32", "lex"))
+            es.append(D.to_native((e * s).to(torch.complex64), "f32", "lex"))
+        if log and len(rs) % (10 * len(snapshots)) < len(snapshots):
+            log(f"pairs {len(rs)}/{n_pairs} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return rs, es
+
+
+def init_weights(channels, seed: int, scale: float = 0.1):
+    """Small random complex weights (N(0, scale^2 / (9 c_in)) per real part) plus, on the
+    unshifted path, 1/c of the identity from channel min(c, c') to min(c, c'), so that the
+    untrained network is close to a multiple of the identity map."""
+    rng = np.random.default_rng(seed)
+    ws = []
+    for cin, cout in zip(channels[:-1], channels[1:]):
+        s = scale / math.sqrt(9 * cin)
+        w = s * (rng.normal(size=(9, cout, cin, 4, 4)) + 1j * rng.normal(size=(9, cout, cin, 4, 4)))
+        for c in range(cout):
+            w[0, c, c % cin] += np.eye(4) / (cin if cin > cout else 1)
+        ws.append(w.astype(np.complex64))
+    return ws
+
+
+def evaluate(ops_pairs, net: PTC):
+    """Mean loss |N(r) - e|^2 / |e|^2 over all pairs, without an update (held-out pairs)."""
+    tot, n = 0.0, 0
+    for D, rs, es in ops_pairs:
+        y = D.native_empty("f32")
+        for r, e in zip(rs, es):
+            net.forward(D, y, r)
+            yl = D.from_native(y, "f32", "lex").to(torch.complex128)
+            el = D.from_native(e, "f32", "lex").to(torch.complex128)
+            tot += (torch.linalg.vector_norm(yl - el) ** 2 / torch.linalg.vector_norm(el) ** 2).item()
+            n += 1
+    return tot / max(n, 1)
+
+
+def train(ops_pairs, net: PTC, epochs: int, batch: int, lr: float, seed: int = 0, start_epoch: int = 0,
+          log=None, lr_decay: float = 1.0):
+    """ops_pairs: list of (Dirac, rs, es).  Epoch ep shuffles with a generator seeded by
+    (seed, ep), so that a run resumed at start_epoch repeats the same minibatches.  The
+    learning rate of epoch ep is lr * lr_decay**ep.  Returns the mean loss of every epoch."""
+    history = []
+    for ep in range(start_epoch, epochs):
+        rng = np.random.default_rng([seed, ep])
+        batches = []
+        for j, (_, rs, _) in enumerate(ops_pairs):
+            idx = rng.permutation(len(rs))
+            batches += [(j, idx[k:k + batch]) for k in range(0, len(idx), batch)]
+        order = rng.permutation(len(batches))
+        tot, n = 0.0, 0
+        t0 = time.perf_counter()
+        lr_ep = lr * lr_decay ** ep
+        for bi in order:
+            j, sel = batches[bi]
+            D, rs, es = ops_pairs[j]
+            loss = net.train_step(D, [rs[i] for i in sel], [es[i] for i in sel], lr_ep)
+            tot += loss * len(sel)
+            n += len(sel)
+        history.append(tot / n)
+        if log:
+            log(f"epoch {ep}: loss {history[-1]:.5f} lr {lr_ep:.2e} ({time.perf_counter() - t0:.1f} s)")
+    return history
+
+
+def save_checkpoint(path: str, net: PTC, epochs_done: int, seed: int, meta: dict | None = None):
+    ws = net.get_weights()
+    m, v, step = net.get_adam_state()
+    header = {"version": CHECKPOINT_VERSION, "channels": list(net.channels), "dtype": "complex64",
+              "adam_step": step, "epochs_done": epochs_done, "shuffle_seed": seed, "meta": meta or {}}
+    arrays = {f"layer{k}": w for k, w in enumerate(ws)}
+    np.savez(path, header=np.frombuffer(json.dumps(header).encode(), dtype=np.uint8), adam_m=m, adam_v=v,
+             **arrays)
+
+
+def load_checkpoint(path: str):
+    """Returns (PTC with the stored weights and Adam state, header dict)."""
+    with np.load(path, allow_pickle=False) as z:
+        header = json.loads(bytes(z["header"]).decode())
+        if header.get("version") != CHECKPOINT_VERSION:
+            raise ValueError(f"unsupported checkpoint version {header.get('version')}")
+        net = PTC(tuple(header["channels"]))
+        net.set_weights([z[f"layer{k}"] for k in range(len(header["channels"]) - 1)])
+        net.set_adam_state(z["adam_m"], z["adam_v"], int(header["adam_step"]))
+    return net, header
+
+
+def compare_solvers(D: Dirac, net: PTC, b: torch.Tensor, tol: float = 1e-10, restart: int = 32, reps: int = 1):
+    """Solve D x = b with FGCR + network and with plain even-odd FP64 GCR; returns a dict of
+    iterations, seconds (best of reps) and residuals for both."""
+    out = {}
+    for name, kw in (("eo_gcr", dict(method=GCR)), ("fgcr_ptc", dict(method=FGCR_PTC, ptc=net))):
+        best = None
+        for _ in range(reps):
+            x = torch.zeros_like(b)
+            info = D.solve(x, b, tol=tol, restart=restart, max_iter=20000, **kw)
+            if best is None or info.seconds < best.seconds:
+                best = info
+        out[name] = {"iters": best.iters, "restarts": best.restarts, "seconds": best.seconds,
+                     "true_rel_res": best.true_rel_res, "fell_back": bool(best.fell_back)}
+    return out

@@ -162,3 +162,47 @@ def test_fgcr_ptc_solves_and_falls_back(case):
     x = torch.zeros_like(b)
     info = c.D.solve(x, b, method=P.FGCR_PTC, ptc=net, tol=1e-12)
     assert rel(x.cpu().numpy(), exact) < 1e-9 and info.true_rel_res < 1e-12
+
+
+def test_checkpoint_resume_is_exact(tmp_path):
+    """Weights and Adam state written mid-training and read back give bitwise the same weights
+    after further steps as the uninterrupted run; NaN weights make FGCR fall back."""
+    need_gpu()
+    from paper_2502_02490_amd import ptc_train as T
+
+    c = Case((4, 2, 2, 4), seed=62)
+    net = P.PTC((1, 4, 1))
+    net2 = None
+    try:
+        rs, es = T.generate_pairs(c.D, 6, seed=3, snapshots=(0, 2, 4))
+        ops = [(c.D, rs, es)]
+        net.set_weights(T.init_weights((1, 4, 1), seed=1))
+        T.train(ops, net, epochs=2, batch=3, lr=1e-2, seed=5)
+        ck = str(tmp_path / "ptc.npz")
+        T.save_checkpoint(ck, net, epochs_done=2, seed=5, meta={"note": "test"})
+        T.train(ops, net, epochs=4, batch=3, lr=1e-2, seed=5, start_epoch=2)
+        net2, head = T.load_checkpoint(ck)
+        assert head["epochs_done"] == 2 and head["adam_step"] == 4 and head["meta"]["note"] == "test"
+        T.train(ops, net2, epochs=4, batch=3, lr=1e-2, seed=5, start_epoch=head["epochs_done"])
+        for a, b in zip(net.get_weights(), net2.get_weights()):
+            assert np.array_equal(a, b)
+        m1, v1, s1 = net.get_adam_state()
+        m2, v2, s2 = net2.get_adam_state()
+        assert s1 == s2 == 8 and np.array_equal(m1, m2) and np.array_equal(v1, v2)
+        # non-finite weights: the preconditioner output is not finite, the solver falls back
+        bad = net2.get_weights()
+        bad[0][:] = np.nan
+        net2.set_weights(bad)
+        b = to_dev(c.spinor(1))
+        x = torch.zeros_like(b)
+        info = c.D.solve(x, b, method=P.FGCR_PTC, ptc=net2, tol=1e-12)
+        assert info.fell_back == 1 and info.true_rel_res < 1e-12
+        with pytest.raises(P.DiracError):
+            m, v, _ = net2.get_adam_state()
+            v[0] = -1.0
+            net2.set_adam_state(m, v, 3)
+    finally:
+        net.close()
+        if net2 is not None:
+            net2.close()
+        c.D.close()
