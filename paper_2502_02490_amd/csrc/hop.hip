@@ -7,6 +7,7 @@
 // half-spinor, multiplies by the link (two stored rows, third rebuilt, phase exp(+-i omega)),
 // and accumulates the reconstructed spinor.  The dagger, gamma_5 H gamma_5, flips the
 // projector signs.  Epilogues: HOP_INV applies A_pp^-1 to the result, HOP_CLOV adds A_pp chi.
+#include <algorithm>
 #include <cstdio>
 #include <type_traits>
 
@@ -195,6 +196,36 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
     hop_site<S, DAG, MODE>(a, ii, nullptr, 0);
 }
 
+// Persistent variant: a grid of a few work-groups per compute unit sweeps the logical blocks
+// in order (block lb + k * gridDim.x in step k).  Every compute unit works on the same narrow
+// band of the lattice at a time, so the lattice window in flight on each XCD, and with it the
+// data streamed through its L2 between two reads of one input spinor by different neighbours,
+// is set by the grid rather than by the register-limited occupancy.
+// With XCD the grid (a multiple of 8) is split by XCD instead: the work-groups of XCD k sweep
+// the k-th contiguous eighth of the logical blocks.
+template <typename S, int DAG, int MODE, int BS, int XCD>
+__global__ __launch_bounds__(BS) void k_hop_p(HopArgs<S> a, int nlog) {
+    const int region = XCD ? (nlog + 7) >> 3 : nlog;
+    const int first = XCD ? (int)(blockIdx.x & 7) * region : 0;
+    const int stride = XCD ? (int)(gridDim.x >> 3) : (int)gridDim.x;
+#pragma nounroll
+    for (int j = XCD ? (int)(blockIdx.x >> 3) : (int)blockIdx.x; j < region; j += stride) {
+        const int lb = first + j;
+        if (lb >= nlog) break;
+        const int rhs = lb % a.nrhs, blk = lb / a.nrhs;
+        if (a.active && !a.active[rhs]) continue;
+        const int ii = blk * BS + threadIdx.x;
+        if (ii >= a.g.vh) continue;
+        HopArgs<S> b = a;
+        if (rhs) {
+            b.in += rhs * a.vs;
+            b.out += rhs * a.vs;
+            if (b.chi) b.chi += rhs * a.vs;
+        }
+        hop_site<S, DAG, MODE>(b, ii, nullptr, 0);
+    }
+}
+
 // Time-tiled variant: a work-group of TT wavefronts takes one spatial block of 64 sites in TT
 // consecutive time slices.  Each wavefront stages the input block of its slice in LDS, the
 // first and last also the blocks of the slices just outside the tile (periodic in time), so
@@ -232,14 +263,64 @@ __global__ __launch_bounds__(64 * TT) void k_hop_t(HopArgs<S> a) {
     hop_site<S, DAG, MODE>(a, ii, tile, w + 1);
 }
 
+// Persistent form of the time-tiled kernel: the grid sweeps the tiles in order, spatial block
+// fastest, so one band of TT time slices is in flight at a time.
+template <typename S, int DAG, int MODE, int TT>
+__global__ __launch_bounds__(64 * TT) void k_hop_tp(HopArgs<S> a, int nwg) {
+    using V = typename St<S>::vec;
+    constexpr int NP = 24 / St<S>::W;
+    __shared__ V tile[(TT + 2) * NP * kSB];
+    const int nsb = a.g.vh / (a.g.L[0] * kSB);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & (kSB - 1);
+#pragma nounroll
+    for (int lb = blockIdx.x; lb < nwg; lb += gridDim.x) {
+        const int rhs = lb % a.nrhs, wg = lb / a.nrhs;
+        if (a.active && !a.active[rhs]) continue;  // uniform over the work-group
+        const int sb = wg % nsb, t0 = (wg / nsb) * TT;
+        HopArgs<S> b = a;
+        if (rhs) {
+            b.in += rhs * a.vs;
+            b.out += rhs * a.vs;
+            if (b.chi) b.chi += rhs * a.vs;
+        }
+        auto stage = [&](int slot, int t) {
+            const V *src = b.in + ((size_t)(t * nsb + sb) * NP) * kSB + lane;
+            V *dst = tile + (size_t)slot * NP * kSB + lane;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) dst[k * kSB] = src[k * kSB];
+        };
+        __syncthreads();  // the previous tile has been consumed
+        stage(w + 1, t0 + w);
+        if (w == 0) stage(0, t0 == 0 ? a.g.L[0] - 1 : t0 - 1);
+        if (w == TT - 1) stage(TT + 1, t0 + TT == a.g.L[0] ? 0 : t0 + TT);
+        __syncthreads();
+        hop_site<S, DAG, MODE>(b, ((t0 + w) * nsb + sb) * kSB + lane, tile, w + 1);
+    }
+}
+
 struct HopShape {
-    int bs, wpe, xcd, tt;
+    int bs, wpe, xcd, tt, pers;
 };
-// shape 0 is the default; occupancy hints only where the default leaves fewer than 4 waves/SIMD;
-// shapes with tt > 0 are the time-tiled kernel (bs = 64 tt)
-const HopShape kShapes[] = {{256, 0, 1, 0}, {256, 0, 0, 0}, {128, 0, 1, 0}, {64, 0, 1, 0},
-                            {256, 0, 1, 4}, {512, 0, 1, 8}, {256, 3, 1, 0}, {128, 3, 1, 0}};
-template <typename S> constexpr int num_shapes() { return std::is_same<S, double>::value ? 8 : 6; }
+// shape 0 is the default; shapes with tt > 0 are the time-tiled kernel (bs = 64 tt); pers > 0 is
+// the persistent kernel with pers work-groups per compute unit; occupancy hints (wpe, FP64 only,
+// where the default leaves fewer than 4 waves per SIMD) come last
+const HopShape kShapes[] = {{256, 0, 1, 0, 0}, {256, 0, 0, 0, 0}, {128, 0, 1, 0, 0}, {64, 0, 1, 0, 0},
+                            {256, 0, 1, 4, 0}, {512, 0, 1, 8, 0}, {256, 0, 0, 0, 1}, {512, 0, 0, 0, 1},
+                            {256, 0, 0, 0, 2}, {256, 0, 1, 0, 1}, {256, 0, 0, 4, 1}, {512, 0, 0, 8, 1},
+                            {256, 3, 1, 0, 0}, {128, 3, 1, 0, 0}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+template <typename S> constexpr int num_shapes() { return std::is_same<S, double>::value ? kNumShapes : kNumShapes - 2; }
+
+int compute_units() {
+    static int n = 0;
+    if (!n) {
+        int dev = 0, v = 0;
+        HIP_CHECK(hipGetDevice(&dev));
+        HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev));
+        n = v > 0 ? v : 256;
+    }
+    return n;
+}
 bool tiled_ok(const Geom &g, int tt) {
     const int ns = g.vh / g.L[0];
     return ns % kSB == 0 && g.L[0] % tt == 0;
@@ -251,6 +332,26 @@ void launch_shape(HopArgs<S> a, int xcd, hipStream_t s) {
     a.xcd = xcd;
     a.nb8 = xcd ? (nb + 7) & ~7 : nb;
     k_hop<S, DAG, MODE, BS, WPE><<<a.nb8, BS, 0, s>>>(a);
+}
+
+template <typename S, int DAG, int MODE, int BS>
+void launch_persistent(HopArgs<S> a, int per_cu, int xcd, hipStream_t s) {
+    const int nlog = (a.g.vh + BS - 1) / BS * a.nrhs;
+    int grid = std::min(nlog, per_cu * compute_units());
+    if (xcd) grid = std::max(8, grid & ~7);
+    a.xcd = xcd;
+    a.nb8 = grid;
+    if (xcd) k_hop_p<S, DAG, MODE, BS, 1><<<grid, BS, 0, s>>>(a, nlog);
+    else k_hop_p<S, DAG, MODE, BS, 0><<<grid, BS, 0, s>>>(a, nlog);
+}
+
+template <typename S, int DAG, int MODE, int TT>
+void launch_tiled_persistent(HopArgs<S> a, int per_cu, hipStream_t s) {
+    const int nwg = (a.g.L[0] / TT) * (a.g.vh / (a.g.L[0] * kSB)) * a.nrhs;
+    const int grid = std::min(nwg, per_cu * compute_units());
+    a.xcd = 0;
+    a.nb8 = grid;
+    k_hop_tp<S, DAG, MODE, TT><<<grid, 64 * TT, 0, s>>>(a, nwg);
 }
 
 template <typename S, int DAG, int MODE, int TT>
@@ -271,7 +372,11 @@ void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
         case 3: launch_shape<S, DAG, MODE, 64, 0>(a, h.xcd, s); break;
         case 4: launch_tiled<S, DAG, MODE, 4>(a, s); break;
         case 5: launch_tiled<S, DAG, MODE, 8>(a, s); break;
-        case 6:
+        case 6: case 8: case 9: launch_persistent<S, DAG, MODE, 256>(a, h.pers, h.xcd, s); break;
+        case 7: launch_persistent<S, DAG, MODE, 512>(a, h.pers, h.xcd, s); break;
+        case 10: launch_tiled_persistent<S, DAG, MODE, 4>(a, h.pers, s); break;
+        case 11: launch_tiled_persistent<S, DAG, MODE, 8>(a, h.pers, s); break;
+        case 12:
             if constexpr (std::is_same<S, double>::value) launch_shape<S, DAG, MODE, 256, 3>(a, h.xcd, s);
             break;
         default:

@@ -89,12 +89,16 @@ def evaluate(ops_pairs, net: PTC):
 
 
 def train(ops_pairs, net: PTC, epochs: int, batch: int, lr: float, seed: int = 0, start_epoch: int = 0,
-          log=None, lr_decay: float = 1.0):
+          log=None, lr_decay: float = 1.0, time_budget: float | None = None):
     """ops_pairs: list of (Dirac, rs, es).  Epoch ep shuffles with a generator seeded by
     (seed, ep), so that a run resumed at start_epoch repeats the same minibatches.  The
-    learning rate of epoch ep is lr * lr_decay**ep.  Returns the mean loss of every epoch."""
+    learning rate of epoch ep is lr * lr_decay**ep.  With time_budget (seconds) no new epoch
+    starts once the budget is spent.  Returns the mean loss of every epoch run."""
     history = []
+    t_start = time.perf_counter()
     for ep in range(start_epoch, epochs):
+        if time_budget is not None and history and time.perf_counter() - t_start > time_budget:
+            break
         rng = np.random.default_rng([seed, ep])
         batches = []
         for j, (_, rs, _) in enumerate(ops_pairs):

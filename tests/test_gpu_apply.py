@@ -170,7 +170,8 @@ def test_schur_32c64_sampled_sites(qhat):
 
 def test_hop_launch_shapes_bitwise_identical(monkeypatch):
     """Every launch shape the tuner may pick (work-group size, occupancy hint, work-group order,
-    time-tiled LDS staging) gives bitwise the same Schur output, in every precision."""
+    time-tiled LDS staging, persistent sweeps) gives bitwise the same Schur output, in every
+    precision."""
     need_gpu()
     c = Case((8, 4, 8, 8), seed=55, qhat=2)  # (L1 L2 L3 / 2) % 64 == 0 and L0 % 8 == 0: tiles fit
     try:
@@ -178,7 +179,7 @@ def test_hop_launch_shapes_bitwise_identical(monkeypatch):
         for prec in ("f64", "f32", "f16", "bf16"):
             nat = c.D.to_native(to_dev(psi_e.astype(np.complex64) if prec == "f32" else psi_e), prec, "eo", sites=1)
             ref = None
-            for shape in range(8):
+            for shape in range(14):
                 monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
                 out = c.D.native_empty(prec, 1)
                 c.D.apply_eo(out, nat, prec, "native")
