@@ -52,29 +52,51 @@ def transport(f: dirac.Fields, psi: np.ndarray, p: int) -> np.ndarray:
     return b[:, None, None] * np.einsum("nab,nsb->nsa", Vd, psi[nb])
 
 
-def layer(f: dirac.Fields, W: np.ndarray, xs) -> list:
-    """y_c = sum_{c', p} W[p, c, c'] T_p x_{c'}; xs a list of n_in fields, W [9, n_out, n_in, 4, 4]."""
+def round_bf16(a: np.ndarray) -> np.ndarray:
+    """Each real component rounded to the nearest BF16 value (8 significant bits, ties to even),
+    taken from its FP32 value: the precision in which the network's matrix-core inputs are formed."""
+    a = np.asarray(a)
+    cplx = np.iscomplexobj(a)
+    f = np.ascontiguousarray(a.view(np.float64) if cplx else a.astype(np.float64)).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)
+    nan = np.isnan(f)
+    out = r.view(np.float32).astype(np.float64)
+    out[nan] = np.nan
+    return out.view(np.complex128).reshape(a.shape) if cplx else out.reshape(a.shape)
+
+
+def layer(f: dirac.Fields, W: np.ndarray, xs, bf16_inputs: bool = False) -> list:
+    """y_c = sum_{c', p} W[p, c, c'] T_p x_{c'}; xs a list of n_in fields, W [9, n_out, n_in, 4, 4].
+    With bf16_inputs each transported field T_p x_{c'} is rounded to BF16 before the spin
+    contraction (the form the matrix-core kernel computes)."""
     n_out, n_in = W.shape[1], W.shape[2]
     assert len(xs) == n_in
     ys = [np.zeros_like(xs[0]) for _ in range(n_out)]
     for cp in range(n_in):
         for p in range(NPATH):
             t = transport(f, xs[cp], p)
+            if bf16_inputs:
+                t = round_bf16(t)
             for c in range(n_out):
                 ys[c] += np.einsum("st,ntc->nsc", W[p, c, cp], t)
     return ys
 
 
-def forward(f: dirac.Fields, weights, r: np.ndarray):
+def forward(f: dirac.Fields, weights, r: np.ndarray, bf16_inputs: bool = False):
     """N(r) and the activations of every layer (inputs of layer l are acts[l])."""
     acts = [[r]]
     for W in weights:
-        acts.append(layer(f, W, acts[-1]))
+        acts.append(layer(f, W, acts[-1], bf16_inputs))
     return acts[-1][0], acts
 
 
-def backward(f: dirac.Fields, weights, acts, g_out: np.ndarray):
-    """Given g = dL/dN(r)*, return (dL/dr*, [dL/dW*] per layer)."""
+def backward(f: dirac.Fields, weights, acts, g_out: np.ndarray, bf16_inputs: bool = False):
+    """Given g = dL/dN(r)*, return (dL/dr*, [dL/dW*] per layer).  With bf16_inputs the input
+    gradient is formed as the matrix-core kernel forms it: each transported gradient
+    T_{adj p} g_c is rounded to BF16, then contracted with W[p, c, c']^dag (spin matrices commute
+    with the transports, so without rounding this equals T_p^dag W^dag g).  The weight gradient
+    is exact in both cases."""
     grads = [None] * len(weights)
     g = [g_out]
     for l in range(len(weights) - 1, -1, -1):
@@ -89,12 +111,19 @@ def backward(f: dirac.Fields, weights, acts, g_out: np.ndarray):
                 for c in range(n_out):
                     # dL/dW*[p, c, c'] = sum_{x, colour} g_c (T_p x_{c'})^dag
                     gW[p, c, cp] += np.einsum("nsa,nta->st", g[c], np.conj(t))
-        for cp in range(n_in):
-            for p in range(NPATH):
-                acc = np.zeros_like(xs[0])
-                for c in range(n_out):
-                    acc += np.einsum("ts,nta->nsa", np.conj(W[p, c, cp]), g[c])  # W^dag g
-                gx[cp] += transport(f, acc, ADJ[p])  # T_p^dag = T_{ADJ[p]}
+        if bf16_inputs:
+            for c in range(n_out):
+                for p in range(NPATH):
+                    t = round_bf16(transport(f, g[c], ADJ[p]))
+                    for cp in range(n_in):
+                        gx[cp] += np.einsum("ts,nta->nsa", np.conj(W[p, c, cp]), t)
+        else:
+            for cp in range(n_in):
+                for p in range(NPATH):
+                    acc = np.zeros_like(xs[0])
+                    for c in range(n_out):
+                        acc += np.einsum("ts,nta->nsa", np.conj(W[p, c, cp]), g[c])  # W^dag g
+                    gx[cp] += transport(f, acc, ADJ[p])  # T_p^dag = T_{ADJ[p]}
         grads[l] = gW
         g = gx
     return g[0], grads

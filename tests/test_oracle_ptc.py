@@ -93,3 +93,67 @@ def test_adam_first_step_moves_by_lr_against_gradient_sign():
     # first Adam step: m/sqrt(v) = sign(g) per real component (up to eps)
     expect = ws[0] - 0.01 * (np.sign(g[0].real) + 1j * np.sign(g[0].imag))
     assert np.abs(new - expect).max() < 1e-8
+
+
+def test_round_bf16_known_values():
+    """Round-to-nearest-even on 8 significant bits, from the FP32 value."""
+    e = 2.0 ** -8
+    vals = np.array([1.0, 1 + e, 1 + 1.5 * e, 1 + 0.5 * e, 1 + 2 * e + e, -1.5, 3.0, 1 + e + 2.0 ** -30,
+                     2.0 ** -130, np.inf, -np.inf, 65504.0, 1 + 2 * e])
+    want = np.array([1.0, 1.0, 1 + 2 * e, 1.0, 1 + 4 * e, -1.5, 3.0, 1.0, 2.0 ** -130, np.inf, -np.inf, 65536.0,
+                     1 + 2 * e])
+    got = ptc.round_bf16(vals)
+    assert np.array_equal(got, want)
+    assert np.isnan(ptc.round_bf16(np.array([np.nan]))[0])
+    z = ptc.round_bf16(np.array([(1 + 1.5 * e) - 1j * (1 + 0.5 * e)]))
+    assert z[0] == (1 + 2 * e) - 1j
+
+
+def _exact_fields(L=(2, 2, 2, 4)):
+    """Unit links, zero angles, phases 0 / pi: every transport of an integer field is a
+    small-integer field (up to the 1e-16 imaginary part of exp(i pi)), so rounding to BF16
+    changes nothing beyond that."""
+    V = int(np.prod(L))
+    U = np.broadcast_to(np.eye(3, dtype=np.complex128), (V, 4, 3, 3)).copy()
+    th = np.zeros((V, 4))
+    return dirac.Fields(U, th, dirac.Params(L, 0.124, 0.0, 0.0, -1, (np.pi, 0.0, np.pi, 0.0)))
+
+
+def test_bf16_inputs_exact_when_transports_are_representable():
+    f = _exact_fields()
+    rng = np.random.default_rng(7)
+    r = (rng.integers(-20, 20, size=(f.V, 4, 3)) + 1j * rng.integers(-20, 20, size=(f.V, 4, 3))).astype(np.complex128)
+    g = (rng.integers(-20, 20, size=(f.V, 4, 3)) + 1j * rng.integers(-20, 20, size=(f.V, 4, 3))).astype(np.complex128)
+    ws = ptc.init_weights((1, 3, 2, 1), seed=2, scale=1.0)
+    y0, a0 = ptc.forward(f, ws, r)
+    # the first layer sees integer transports: identical; later layers see non-integer inputs
+    l1 = ptc.layer(f, ws[0], [r], bf16_inputs=True)
+    assert all(np.abs(u - v).max() <= 1e-13 * np.abs(v).max() for u, v in zip(l1, a0[1]))
+    # backward of a single layer with an integer gradient: the rounded form equals the exact one
+    W = ws[2]  # 2 -> 1: input gradient of a 1-channel output gradient
+    acts = [[r, 2 * r], ptc.layer(f, W, [r, 2 * r])]
+    gx_exact, gw_exact = ptc.backward(f, [W], acts, g)
+    gx_round, gw_round = ptc.backward(f, [W], acts, g, bf16_inputs=True)
+    assert np.abs(gx_round - gx_exact).max() <= 1e-12 * np.abs(gx_exact).max()
+    assert np.array_equal(gw_round[0], gw_exact[0])
+    # a plausible slip in the rounded branch (dagger dropped) is caught
+    Wbad = [np.swapaxes(W, -1, -2)]
+    gx_bad, _ = ptc.backward(f, Wbad, acts, g, bf16_inputs=True)
+    assert np.abs(gx_bad - gx_exact).max() > 1e-3 * np.abs(gx_exact).max()
+
+
+def test_bf16_inputs_error_is_bounded_by_the_unit_roundoff():
+    """On a random field the rounded network differs from the exact one by about 2^-9 per
+    element of every transported input (and no more than 2^-8 relative in norm)."""
+    f = fields()
+    r = gen.gaussian_spinor(f.p.dims, 8)
+    g = gen.gaussian_spinor(f.p.dims, 9)
+    ws = ptc.init_weights((1, 2, 1), seed=3, scale=1.0)
+    y, acts = ptc.forward(f, ws, r)
+    yr, actsr = ptc.forward(f, ws, r, bf16_inputs=True)
+    d = np.linalg.norm(yr - y) / np.linalg.norm(y)
+    assert 1e-5 < d < 2.0 ** -7
+    gx, _ = ptc.backward(f, ws, acts, g)
+    gxr, _ = ptc.backward(f, ws, acts, g, bf16_inputs=True)
+    d = np.linalg.norm(gxr - gx) / np.linalg.norm(gx)
+    assert 1e-5 < d < 2.0 ** -7
