@@ -34,7 +34,9 @@ HOP_SHAPES = ["k_hop bs256 xcd-order", "k_hop bs256", "k_hop bs128 xcd-order", "
               "k_hop_t tt4 (time-tiled LDS)", "k_hop_t tt8 (time-tiled LDS)", "k_hop_p bs256 1/CU (persistent)",
               "k_hop_p bs512 1/CU (persistent)", "k_hop_p bs256 2/CU (persistent)",
               "k_hop_p bs256 1/CU xcd-regions (persistent)", "k_hop_tp tt4 1/CU (persistent time-tiled)",
-              "k_hop_tp tt8 1/CU (persistent time-tiled)", "k_hop bs256 3 waves/SIMD", "k_hop bs128 3 waves/SIMD"]
+              "k_hop_tp tt8 1/CU (persistent time-tiled)", "k_hop_ps bs256 1/CU (XCD slab sweep)",
+              "k_hop_ps bs256 2/CU (XCD slab sweep)", "k_hop_ps bs128 2/CU (XCD slab sweep)",
+              "k_hop bs256 3 waves/SIMD", "k_hop bs128 3 waves/SIMD"]
 
 
 def log(*a):
@@ -156,6 +158,9 @@ def batched_suite():
 
 
 PTC_TRAIN_DIMS = (32, 16, 16, 16)
+# spin contractions of the (1, 8, 8, 1) network per site: 9 paths x c_in x c_out x 16 spin
+# entries x 3 colours complex multiply-adds (8 real flops each)
+PTC_FLOP_PER_SITE = 8 * 9 * 16 * 3 * (1 * 8 + 8 * 8 + 8 * 1)
 PTC_KAPPA = 0.1245
 
 
@@ -205,6 +210,18 @@ def ptc_suite(pairs_per_field: int, epochs: int, checkpoint: str | None):
     D = P.Dirac(torch.from_numpy(gen.su3_field(d, EPS, 505)).cuda(), torch.from_numpy(gen.u1_field(d, 0.3, 505)).cuda(),
                 d, PTC_KAPPA, CSW, CSW_QED, QHAT)
     b = torch.from_numpy(gen.gaussian_spinor(d, 505)).cuda()
+    # one network application on 32^3 x 64: the three layers on the matrix cores
+    vin = D.to_native(b.to(torch.complex64), "f32", "lex")
+    vout = torch.empty_like(vin)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        net.forward(D, vout, vin)
+    t_fwd = timed(lambda: net.forward(D, vout, vin), 10, stream) / 10
+    flop = PTC_FLOP_PER_SITE * math.prod(d)
+    res["forward_32c64_ms"] = round(t_fwd * 1e3, 3)
+    res["forward_32c64_contraction_TFLOPs"] = round(flop / t_fwd / 1e12, 1)
+    log(f"[ptc] forward 32^3x64: {t_fwd * 1e3:.2f} ms, {flop / t_fwd / 1e12:.1f} TFLOP/s in the spin contractions")
+    del vin, vout
     T.compare_solvers(D, net, b, tol=1e-10)  # warm-up (tuning, work buffers)
     res["deploy_32c64"] = T.compare_solvers(D, net, b, tol=1e-10, reps=2)
     log(f"[ptc] deploy {res['deploy_32c64']}")
@@ -306,7 +323,7 @@ def main():
         log(f"[bench] tuner choice not readable: {e}")
     # every launch shape of the hop kernel, FP64 Schur (the tuner's choice is what the timed loop used)
     shapes = {}
-    for shape in range(14):
+    for shape in range(17):
         os.environ["DIRAC_HOP_SHAPE"] = str(shape)
         for _ in range(3):
             schur()

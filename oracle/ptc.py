@@ -129,17 +129,17 @@ def backward(f: dirac.Fields, weights, acts, g_out: np.ndarray, bf16_inputs: boo
     return g[0], grads
 
 
-def loss_and_grads(f: dirac.Fields, weights, pairs):
+def loss_and_grads(f: dirac.Fields, weights, pairs, bf16_inputs: bool = False):
     """L = mean_i |N(r_i) - e_i|^2 / |e_i|^2 and dL/dW* per layer."""
     total = 0.0
     gsum = [np.zeros_like(W) for W in weights]
     n = len(pairs)
     for r, e in pairs:
-        y, acts = forward(f, weights, r)
+        y, acts = forward(f, weights, r, bf16_inputs)
         ne2 = np.vdot(e, e).real
         d = y - e
         total += np.vdot(d, d).real / ne2 / n
-        _, gw = backward(f, weights, acts, d / ne2 / n)
+        _, gw = backward(f, weights, acts, d / ne2 / n, bf16_inputs)
         for k in range(len(weights)):
             gsum[k] += gw[k]
     return total, gsum

@@ -406,7 +406,8 @@ dirac_status ptc_destroy(dirac_ptc *n) {
     API_BEGIN
     if (!n) return DIRAC_OK;
     (void)hipDeviceSynchronize();
-    for (dl::DevBuf *b : {&n->w, &n->wbf, &n->wt, &n->grad, &n->m, &n->v, &n->acts, &n->gbuf, &n->part}) b->release();
+    for (dl::DevBuf *b : {&n->w, &n->wbf, &n->wt, &n->grad, &n->m, &n->v, &n->acts, &n->gbuf, &n->part, &n->afw, &n->afb})
+        b->release();
     delete n;
     API_END
 }

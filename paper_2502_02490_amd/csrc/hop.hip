@@ -226,6 +226,35 @@ __global__ __launch_bounds__(BS) void k_hop_p(HopArgs<S> a, int nlog) {
     }
 }
 
+// Slab sweep: XCD k (work-groups b with b % 8 == k) owns the time slices [k L0 / 8, (k + 1) L0 / 8)
+// and walks them with time faster than x1: the work-groups of one XCD in flight together cover a
+// few (t, x1) planes of all its time slices, so the neighbours in every direction but across the
+// slab's time boundaries are read by the same XCD within a short window and hit in its L2.
+// Needs L0 % 8 == 0 and the sites of one parity in a (t, x1) plane a multiple of BS.
+template <typename S, int DAG, int MODE, int BS>
+__global__ __launch_bounds__(BS) void k_hop_ps(HopArgs<S> a, int nper) {
+    const int xcd = (int)(blockIdx.x & 7);
+    const int T8 = a.g.L[0] >> 3;
+    const int plane = a.g.vh / (a.g.L[0] * a.g.L[1]);
+    const int cpp = plane / BS;
+#pragma nounroll
+    for (int j = (int)(blockIdx.x >> 3); j < nper; j += (int)(gridDim.x >> 3)) {
+        const int rhs = j % a.nrhs;
+        int r = j / a.nrhs;
+        const int h = r % cpp;
+        r /= cpp;
+        const int t = xcd * T8 + r % T8, x1 = r / T8;
+        if (a.active && !a.active[rhs]) continue;
+        HopArgs<S> b = a;
+        if (rhs) {
+            b.in += rhs * a.vs;
+            b.out += rhs * a.vs;
+            if (b.chi) b.chi += rhs * a.vs;
+        }
+        hop_site<S, DAG, MODE>(b, (t * a.g.L[1] + x1) * plane + h * BS + (int)threadIdx.x, nullptr, 0);
+    }
+}
+
 // Time-tiled variant: a work-group of TT wavefronts takes one spatial block of 64 sites in TT
 // consecutive time slices.  Each wavefront stages the input block of its slice in LDS, the
 // first and last also the blocks of the slices just outside the tile (periodic in time), so
@@ -299,15 +328,16 @@ __global__ __launch_bounds__(64 * TT) void k_hop_tp(HopArgs<S> a, int nwg) {
 }
 
 struct HopShape {
-    int bs, wpe, xcd, tt, pers;
+    int bs, wpe, xcd, tt, pers, slab;
 };
 // shape 0 is the default; shapes with tt > 0 are the time-tiled kernel (bs = 64 tt); pers > 0 is
 // the persistent kernel with pers work-groups per compute unit; occupancy hints (wpe, FP64 only,
 // where the default leaves fewer than 4 waves per SIMD) come last
-const HopShape kShapes[] = {{256, 0, 1, 0, 0}, {256, 0, 0, 0, 0}, {128, 0, 1, 0, 0}, {64, 0, 1, 0, 0},
-                            {256, 0, 1, 4, 0}, {512, 0, 1, 8, 0}, {256, 0, 0, 0, 1}, {512, 0, 0, 0, 1},
-                            {256, 0, 0, 0, 2}, {256, 0, 1, 0, 1}, {256, 0, 0, 4, 1}, {512, 0, 0, 8, 1},
-                            {256, 3, 1, 0, 0}, {128, 3, 1, 0, 0}};
+const HopShape kShapes[] = {{256, 0, 1, 0, 0, 0}, {256, 0, 0, 0, 0, 0}, {128, 0, 1, 0, 0, 0}, {64, 0, 1, 0, 0, 0},
+                            {256, 0, 1, 4, 0, 0}, {512, 0, 1, 8, 0, 0}, {256, 0, 0, 0, 1, 0}, {512, 0, 0, 0, 1, 0},
+                            {256, 0, 0, 0, 2, 0}, {256, 0, 1, 0, 1, 0}, {256, 0, 0, 4, 1, 0}, {512, 0, 0, 8, 1, 0},
+                            {256, 0, 0, 0, 1, 1}, {256, 0, 0, 0, 2, 1}, {128, 0, 0, 0, 2, 1},
+                            {256, 3, 1, 0, 0, 0}, {128, 3, 1, 0, 0, 0}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 template <typename S> constexpr int num_shapes() { return std::is_same<S, double>::value ? kNumShapes : kNumShapes - 2; }
 
@@ -320,6 +350,11 @@ int compute_units() {
         n = v > 0 ? v : 256;
     }
     return n;
+}
+bool slab_ok(const Geom &g, int bs) {
+    if (g.L[0] % 8) return false;
+    const int plane = g.vh / (g.L[0] * g.L[1]);
+    return plane % bs == 0;
 }
 bool tiled_ok(const Geom &g, int tt) {
     const int ns = g.vh / g.L[0];
@@ -345,6 +380,16 @@ void launch_persistent(HopArgs<S> a, int per_cu, int xcd, hipStream_t s) {
     else k_hop_p<S, DAG, MODE, BS, 0><<<grid, BS, 0, s>>>(a, nlog);
 }
 
+template <typename S, int DAG, int MODE, int BS>
+void launch_slab(HopArgs<S> a, int per_cu, hipStream_t s) {
+    const int plane = a.g.vh / (a.g.L[0] * a.g.L[1]);
+    const int nper = (a.g.L[0] / 8) * a.g.L[1] * (plane / BS) * a.nrhs;
+    const int grid = 8 * std::max(1, std::min(nper, per_cu * compute_units() / 8));
+    a.xcd = 0;
+    a.nb8 = grid;
+    k_hop_ps<S, DAG, MODE, BS><<<grid, BS, 0, s>>>(a, nper);
+}
+
 template <typename S, int DAG, int MODE, int TT>
 void launch_tiled_persistent(HopArgs<S> a, int per_cu, hipStream_t s) {
     const int nwg = (a.g.L[0] / TT) * (a.g.vh / (a.g.L[0] * kSB)) * a.nrhs;
@@ -366,6 +411,7 @@ template <typename S, int DAG, int MODE>
 void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
     const HopShape h = kShapes[shape];
     if (h.tt && !tiled_ok(a.g, h.tt)) shape = 0;  // the tile does not fit this lattice
+    if (h.slab && !slab_ok(a.g, h.bs)) shape = 0;
     switch (shape) {
         case 0: case 1: launch_shape<S, DAG, MODE, 256, 0>(a, h.xcd, s); break;
         case 2: launch_shape<S, DAG, MODE, 128, 0>(a, h.xcd, s); break;
@@ -376,7 +422,9 @@ void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
         case 7: launch_persistent<S, DAG, MODE, 512>(a, h.pers, h.xcd, s); break;
         case 10: launch_tiled_persistent<S, DAG, MODE, 4>(a, h.pers, s); break;
         case 11: launch_tiled_persistent<S, DAG, MODE, 8>(a, h.pers, s); break;
-        case 12:
+        case 12: case 13: launch_slab<S, DAG, MODE, 256>(a, h.pers, s); break;
+        case 14: launch_slab<S, DAG, MODE, 128>(a, h.pers, s); break;
+        case 15:
             if constexpr (std::is_same<S, double>::value) launch_shape<S, DAG, MODE, 256, 3>(a, h.xcd, s);
             break;
         default:

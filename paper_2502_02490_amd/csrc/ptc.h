@@ -15,6 +15,8 @@ struct dirac_ptc {
     dl::DevBuf m, v;           // Adam moments (FP32, per real parameter)
     dl::DevBuf acts, gbuf;     // activations of every layer, two gradient buffers
     dl::DevBuf part;           // weight-gradient partials per 64-site tile
+    dl::DevBuf afw, afb;       // matrix-core A fragments: forward layers, adjoint (input-gradient) layers
+    size_t afw_off[8] = {0}, afb_off[8] = {0};  // first fragment (uint4) of each layer
     int step = 0;
     void grad_zero(hipStream_t s) { (void)hipMemsetAsync(grad.p, 0, total * 8, s); }
 };

@@ -79,51 +79,121 @@ DEV void transport_site(const PtcGeom &a, const float4 *xc, int p, uint32_t i, c
     }
 }
 
-// y_c = sum_{c', p} W[p][c][c'] T_p x_{c'}; W BF16 complex pairs [9][nout][nin][4][4]
-template <int NOUT>
-__global__ __launch_bounds__(256) void k_ptc_layer(PtcGeom a, int nin, const float4 *__restrict__ xin,
-                                                   const uint32_t *__restrict__ W, float4 *__restrict__ yout) {
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= 2 * a.g.vh) return;
-    const int p = s >= a.g.vh;
-    const uint32_t i = (uint32_t)(s - p * a.g.vh);
-    int x[4];
-    site_coords(a.g, (int)i, p, x);
-    C<float> acc[NOUT][12];
+// ------------------------------------------------------------------ matrix-core layer
+// The layer as a real GEMM on the 16x16x32 BF16 matrix cores (FP32 accumulation):
+//   rows    m = 8 c + 2 sigma + ri_out          (output channel, spin, re/im)
+//   columns n = (site, colour)                  (16 sites of a wavefront per tile, one colour per tile)
+//   depth   k = 8 pair + 2 tau + ri_in,  pair = path * n_in + c'
+// with the real embedding of the complex weights: (re, re) = (im, im) = Re W, (re, im) = -Im W,
+// (im, re) = Im W.  A K step of 32 holds four (path, c') pairs; the lanes with k group g = lane / 16
+// compute the transport T_path x_c' of pair 4 q + g at their site, and its 4 spins of colour a
+// are exactly their 8 B-operand values for colour tile a, so each transport is computed once.
+// The A operand (weights) is prepared once per weight update in the lane order of the
+// instruction (row lane % 16, depth 8 (lane / 16) + j) and staged in LDS per work-group.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+DEV uint32_t bf16_bits(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // NaN stays NaN
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// A fragments of one layer: Af[(q * nm + t) * 64 + lane] = 8 BF16 values (uint4), q < nk, t < nm.
+// W holds BF16 (re, im) pairs [9][nout][nin][4][4].
+__global__ void k_ptc_afrag(int nin, int nout, int nk, int nm, const uint32_t *__restrict__ W,
+                            uint4 *__restrict__ Af) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nk * nm * 64) return;
+    const int lane = e & 63, t = (e >> 6) % nm, q = (e >> 6) / nm;
+    const int m = 16 * t + (lane & 15), pair = 4 * q + (lane >> 4);
+    const int c = m >> 3, sg = (m >> 1) & 3, rio = m & 1;
+    uint32_t v[4] = {0u, 0u, 0u, 0u};
+    if (c < nout && pair < kPaths * nin) {
+        const int path = pair / nin, cp = pair % nin;
+        const uint32_t *w = W + ((size_t)(path * nout + c) * nin + cp) * 16 + sg * 4;
 #pragma unroll
-    for (int c = 0; c < NOUT; ++c)
-#pragma unroll
-        for (int k = 0; k < 12; ++k) acc[c][k] = mk(0.f, 0.f);
-    const size_t chan4 = a.chan / 4;
-#pragma nounroll
-    for (int cp = 0; cp < nin; ++cp) {
-#pragma nounroll
-        for (int path = 0; path < kPaths; ++path) {
-            C<float> t[12];
-            transport_site(a, xin + cp * chan4, p, i, x, path, t);
-#pragma unroll
-            for (int c = 0; c < NOUT; ++c) {
-                const uint32_t *w = W + ((size_t)(path * NOUT + c) * nin + cp) * 16;
-#pragma unroll
-                for (int ss = 0; ss < 4; ++ss)
-#pragma unroll
-                    for (int tt = 0; tt < 4; ++tt) {
-                        float wr, wi;
-                        bf2(w[ss * 4 + tt], wr, wi);
-                        const C<float> wc = mk(wr, wi);
-#pragma unroll
-                        for (int col = 0; col < 3; ++col) madd(acc[c][3 * ss + col], wc, t[3 * tt + col]);
-                    }
-            }
+        for (int tau = 0; tau < 4; ++tau) {
+            const uint32_t re = w[tau] & 0xffffu, im = w[tau] >> 16;
+            // (ri_out, ri_in = 0) and (ri_out, ri_in = 1)
+            const uint32_t lo = rio ? im : re, hi = rio ? re : (im ^ 0x8000u);
+            v[tau] = lo | (hi << 16);
         }
     }
-    const size_t hv = (size_t)6 * a.g.vhp;
+    Af[e] = make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+// One layer on the matrix cores.  Persistent: the grid's work-groups (4 wavefronts, 16 sites
+// each) sweep the 64-site blocks of both parities; the A fragments are staged once per
+// work-group.  NIN input channels, NM = ceil(8 NOUT / 16) row tiles.
+template <int NIN, int NM>
+__global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, const uint4 *__restrict__ Af,
+                                                        const float4 *__restrict__ xin,
+                                                        float4 *__restrict__ yout) {
+    constexpr int NPAIR = kPaths * NIN, NK = (NPAIR + 3) / 4;
+    __shared__ uint4 af[NK * NM * 64];
+    for (int e = threadIdx.x; e < NK * NM * 64; e += 256) af[e] = Af[e];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, sl = lane & 15;
+    const int nbp = (a.g.vh + 63) / 64;
+    const size_t chan4 = a.chan / 4, hv = (size_t)6 * a.g.vhp;
+#pragma nounroll
+    for (int blk = blockIdx.x; blk < 2 * nbp; blk += gridDim.x) {
+        const int p = blk >= nbp;
+        const int i = (blk - p * nbp) * 64 + wave * 16 + sl;
+        const bool on = i < a.g.vh;
+        int x[4] = {0, 0, 0, 0};
+        if (on) site_coords(a.g, i, p, x);
+        f32x4_t acc[NM][3];
 #pragma unroll
-    for (int c = 0; c < NOUT; ++c) {
-        float r[24];
+        for (int t = 0; t < NM; ++t)
 #pragma unroll
-        for (int k = 0; k < 12; ++k) { r[2 * k] = acc[c][k].r; r[2 * k + 1] = acc[c][k].i; }
-        store_field<float, 24>(yout + c * chan4 + p * hv, i, r);
+            for (int col = 0; col < 3; ++col) acc[t][col] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma nounroll
+        for (int q = 0; q < NK; ++q) {
+            const int pair = 4 * q + g;
+            C<float> tr[12];
+            if (on && pair < NPAIR) {
+                transport_site(a, xin + (size_t)(pair % NIN) * chan4, p, (uint32_t)i, x, pair / NIN, tr);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) tr[k] = mk(0.f, 0.f);
+            }
+            bf16x8_t b[3];
+#pragma unroll
+            for (int col = 0; col < 3; ++col) {
+                uint4 u;
+                u.x = bf16_bits(tr[col].r) | (bf16_bits(tr[col].i) << 16);
+                u.y = bf16_bits(tr[3 + col].r) | (bf16_bits(tr[3 + col].i) << 16);
+                u.z = bf16_bits(tr[6 + col].r) | (bf16_bits(tr[6 + col].i) << 16);
+                u.w = bf16_bits(tr[9 + col].r) | (bf16_bits(tr[9 + col].i) << 16);
+                b[col] = __builtin_bit_cast(bf16x8_t, u);
+            }
+#pragma unroll
+            for (int t = 0; t < NM; ++t) {
+                const bf16x8_t A = __builtin_bit_cast(bf16x8_t, af[(q * NM + t) * 64 + lane]);
+#pragma unroll
+                for (int col = 0; col < 3; ++col)
+                    acc[t][col] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, b[col], acc[t][col], 0, 0, 0);
+            }
+        }
+        if (!on) continue;
+        // lane (g, site) holds rows m = 16 t + 4 g + r, r < 4: channel 2 t + g / 2, spins
+        // 2 (g & 1) + r / 2, re/im r & 1 -- twelve consecutive reals (three planes) of one spinor
+#pragma unroll
+        for (int t = 0; t < NM; ++t) {
+            const int c = 2 * t + (g >> 1);
+            if (c >= nout) continue;
+            float r[12];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                for (int col = 0; col < 3; ++col) r[6 * (rr >> 1) + 2 * col + (rr & 1)] = acc[t][col][rr];
+            float4 *dst = site_ptr(yout + (size_t)c * chan4 + p * hv, (uint32_t)i, 6) + 3 * (g & 1) * kSB;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dst[k * kSB] = make_float4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]);
+        }
     }
 }
 
@@ -227,18 +297,48 @@ __global__ void k_adjoint_weights(int nout, int nin, const uint32_t *__restrict_
     Wt[k] = w ^ 0x80000000u;                                                              // conjugate
 }
 
-template <int NOUT>
-void launch_layer(const PtcGeom &a, int nin, const void *x, const void *W, void *y, hipStream_t s) {
-    k_ptc_layer<NOUT><<<(2 * a.g.vh + 255) / 256, 256, 0, s>>>(a, nin, (const float4 *)x, (const uint32_t *)W,
-                                                             (float4 *)y);
+int compute_units() {
+    static int n = 0;
+    if (!n) {
+        int dev = 0, v = 0;
+        HIP_CHECK(hipGetDevice(&dev));
+        HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev));
+        n = v > 0 ? v : 256;
+    }
+    return n;
 }
-void layer_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const void *W, void *y, hipStream_t s) {
-    switch (nout) {
-        case 1: launch_layer<1>(a, nin, x, W, y, s); break;
-        case 2: launch_layer<2>(a, nin, x, W, y, s); break;
-        case 4: launch_layer<4>(a, nin, x, W, y, s); break;
-        case 8: launch_layer<8>(a, nin, x, W, y, s); break;
-        default: throw Error(DIRAC_EUNSUPPORTED, "PTC output channels must be 1, 2, 4 or 8");
+int row_tiles(int nout) { return (8 * nout + 15) / 16; }
+int k_steps(int nin) { return (kPaths * nin + 3) / 4; }
+size_t afrag_count(int nin, int nout) { return (size_t)k_steps(nin) * row_tiles(nout) * 64; }
+
+void build_afrags(int nin, int nout, const uint32_t *W, uint4 *Af, hipStream_t s) {
+    const int n = (int)afrag_count(nin, nout);
+    k_ptc_afrag<<<(n + 255) / 256, 256, 0, s>>>(nin, nout, k_steps(nin), row_tiles(nout), W, Af);
+    HIP_CHECK(hipGetLastError());
+}
+
+template <int NIN, int NM>
+void launch_layer(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, hipStream_t s) {
+    const int nblk = 2 * (int)((a.g.vh + 63) / 64);
+    const int grid = std::min(nblk, 2 * compute_units());
+    k_ptc_layer_mfma<NIN, NM><<<grid, 256, 0, s>>>(a, nout, Af, (const float4 *)x, (float4 *)y);
+}
+template <int NIN>
+void launch_layer_nm(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, hipStream_t s) {
+    switch (row_tiles(nout)) {
+        case 1: launch_layer<NIN, 1>(a, nout, Af, x, y, s); break;
+        case 2: launch_layer<NIN, 2>(a, nout, Af, x, y, s); break;
+        default: launch_layer<NIN, 4>(a, nout, Af, x, y, s); break;
+    }
+}
+// y = layer(x) with the A fragments Af of a (nin -> nout) layer
+void layer_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const uint4 *Af, void *y, hipStream_t s) {
+    switch (nin) {
+        case 1: launch_layer_nm<1>(a, nout, Af, x, y, s); break;
+        case 2: launch_layer_nm<2>(a, nout, Af, x, y, s); break;
+        case 4: launch_layer_nm<4>(a, nout, Af, x, y, s); break;
+        case 8: launch_layer_nm<8>(a, nout, Af, x, y, s); break;
+        default: throw Error(DIRAC_EUNSUPPORTED, "PTC channel counts must be 1, 2, 4 or 8");
     }
     HIP_CHECK(hipGetLastError());
 }
@@ -281,6 +381,15 @@ void ptc_alloc(dirac_ptc *n) {
         tot += ptc_nweights(n, l);
     }
     n->total = tot;  // complex entries
+    size_t fw = 0, fb = 0;
+    for (int l = 0; l < n->nlayers; ++l) {
+        n->afw_off[l] = fw;
+        n->afb_off[l] = fb;
+        fw += afrag_count(n->ch[l], n->ch[l + 1]);
+        fb += afrag_count(n->ch[l + 1], n->ch[l]);
+    }
+    n->afw.alloc(fw * sizeof(uint4));
+    n->afb.alloc(fb * sizeof(uint4));
     n->w.alloc(tot * 8);
     n->wbf.alloc(tot * 4);
     n->wt.alloc(tot * 4);
@@ -295,10 +404,18 @@ void ptc_alloc(dirac_ptc *n) {
     n->step = 0;
 }
 
+// forward A fragments of every layer from the BF16 working weights
+static void refresh_afrags(dirac_ptc *n, hipStream_t s) {
+    for (int l = 0; l < n->nlayers; ++l)
+        build_afrags(n->ch[l], n->ch[l + 1], (const uint32_t *)n->wbf.p + n->off[l], (uint4 *)n->afw.p + n->afw_off[l],
+                     s);
+}
+
 void ptc_refresh_bf16(dirac_ptc *n, hipStream_t s) {
     const int nr = (int)(2 * n->total);
     k_to_bf16<<<(nr + 255) / 256, 256, 0, s>>>(nr, (const float *)n->w.p, (uint16_t *)n->wbf.p);
     HIP_CHECK(hipGetLastError());
+    refresh_afrags(n, s);
 }
 
 void ptc_ensure_acts(dirac_ctx *c, dirac_ptc *n) {
@@ -326,7 +443,7 @@ float *ptc_act(dirac_ctx *c, dirac_ptc *n, int l) {
 void ptc_forward_acts(dirac_ctx *c, dirac_ptc *n, hipStream_t s) {
     PtcGeom a = geom_of(c, s);
     for (int l = 0; l < n->nlayers; ++l)
-        layer_dispatch(a, n->ch[l], n->ch[l + 1], ptc_act(c, n, l), (const uint32_t *)n->wbf.p + n->off[l],
+        layer_dispatch(a, n->ch[l], n->ch[l + 1], ptc_act(c, n, l), (const uint4 *)n->afw.p + n->afw_off[l],
                        ptc_act(c, n, l + 1), s);
 }
 
@@ -351,8 +468,10 @@ void ptc_backward_acts(dirac_ctx *c, dirac_ptc *n, const void *g_out, void *gin,
         k_adjoint_weights<<<(nw + 255) / 256, 256, 0, s>>>(nout, nin, (const uint32_t *)n->wbf.p + n->off[l],
                                                            (uint32_t *)n->wt.p + n->off[l]);
         HIP_CHECK(hipGetLastError());
+        uint4 *afb = (uint4 *)n->afb.p + n->afb_off[l];
+        build_afrags(nout, nin, (const uint32_t *)n->wt.p + n->off[l], afb, s);
         void *dst = l == 0 ? gin : (void *)gB;
-        layer_dispatch(a, nout, nin, gA, (const uint32_t *)n->wt.p + n->off[l], dst, s);
+        layer_dispatch(a, nout, nin, gA, afb, dst, s);
         std::swap(gA, gB);
     }
 }
@@ -365,6 +484,7 @@ void ptc_adam(dirac_ptc *n, double lr, hipStream_t s) {
     k_adam<<<(nr + 255) / 256, 256, 0, s>>>(nr, (float *)n->w.p, (const float *)n->grad.p, (float *)n->m.p,
                                            (float *)n->v.p, (uint16_t *)n->wbf.p, (float)lr, b1, b2, eps, c1, c2);
     HIP_CHECK(hipGetLastError());
+    refresh_afrags(n, s);
 }
 
 }  // namespace dl

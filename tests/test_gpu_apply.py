@@ -173,13 +173,15 @@ def test_hop_launch_shapes_bitwise_identical(monkeypatch):
     time-tiled LDS staging, persistent sweeps) gives bitwise the same Schur output, in every
     precision."""
     need_gpu()
-    c = Case((8, 4, 8, 8), seed=55, qhat=2)  # (L1 L2 L3 / 2) % 64 == 0 and L0 % 8 == 0: tiles fit
+    # L0 % 8 == 0, (L1 L2 L3 / 2) % 64 == 0 and (L2 L3 / 2) % 256 == 0: the time tiles and the
+    # slab sweeps fit, so every shape runs its own kernel
+    c = Case((8, 2, 16, 32), seed=55, qhat=2)
     try:
         psi_e = c.spinor(3)[c.even]
         for prec in ("f64", "f32", "f16", "bf16"):
             nat = c.D.to_native(to_dev(psi_e.astype(np.complex64) if prec == "f32" else psi_e), prec, "eo", sites=1)
             ref = None
-            for shape in range(14):
+            for shape in range(17):
                 monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
                 out = c.D.native_empty(prec, 1)
                 c.D.apply_eo(out, nat, prec, "native")

@@ -1,7 +1,14 @@
 """GPU parallel-transport convolution network against the FP64 oracle (forward, input and
 weight gradients, one training step), and the flexible-GCR deployment with its fallback.
-The GPU uses BF16 working weights and FP32 activations; the oracle is given the same
-BF16-rounded weights, so the remaining difference is FP32 rounding."""
+
+The GPU layer runs on the BF16 matrix cores: BF16 working weights, each transported input
+rounded to BF16 from its FP32 value, FP32 accumulation.  The oracle is given the same
+BF16-rounded weights and rounds its transported inputs the same way (bf16_inputs=True).  What
+remains is FP32 arithmetic, and the rare element whose BF16 rounding goes the other way because
+the FP32 transport and the FP64 one straddle a rounding boundary (about 5e-5 of the elements,
+each off by one BF16 step, 2^-8 relative): a few 1e-5 in norm.  The bar, 3e-4, is ten times
+below the 3e-3 by which the rounded network differs from the unrounded one, so a kernel that
+skipped or misplaced the rounding would fail it."""
 import math
 
 import numpy as np
@@ -51,10 +58,12 @@ def test_forward_matches_oracle(case):
     net.set_weights(ws)
     wq = [bf16(w) for w in ws]
     r = c.spinor(7).astype(np.complex64).astype(np.complex128)
-    y, _ = optc.forward(c.f, wq, r)
+    y, _ = optc.forward(c.f, wq, r, bf16_inputs=True)
     out = c.D.native_empty("f32")
     net.forward(c.D, out, to_f32_native(c.D, r))
-    assert rel(from_f32_native(c.D, out), y) < 2e-5
+    err = rel(from_f32_native(c.D, out), y)
+    flush(f"[gpu] ptc forward vs oracle (BF16 inputs) {err:.2e}")
+    assert err < 3e-4
 
 
 def test_backward_matches_oracle(case):
@@ -64,15 +73,17 @@ def test_backward_matches_oracle(case):
     wq = [bf16(w) for w in ws]
     r = c.spinor(8).astype(np.complex64).astype(np.complex128)
     g = c.spinor(9).astype(np.complex64).astype(np.complex128)
-    _, acts = optc.forward(c.f, wq, r)
-    gx, gW = optc.backward(c.f, wq, acts, g)
+    _, acts = optc.forward(c.f, wq, r, bf16_inputs=True)
+    gx, gW = optc.backward(c.f, wq, acts, g, bf16_inputs=True)
     net.zero_grad()
     gin = c.D.native_empty("f32")
     net.backward(c.D, gin, to_f32_native(c.D, r), to_f32_native(c.D, g))
-    assert rel(from_f32_native(c.D, gin), gx) < 2e-5
+    err = rel(from_f32_native(c.D, gin), gx)
+    flush(f"[gpu] ptc input gradient vs oracle (BF16 inputs) {err:.2e}")
+    assert err < 3e-4
     got = net.get_grad()
     for l in range(3):
-        assert rel(got[l], gW[l]) < 2e-5, l
+        assert rel(got[l], gW[l]) < 3e-4, l
 
 
 def test_dirac_as_single_layer():
@@ -85,7 +96,10 @@ def test_dirac_as_single_layer():
         psi = c.spinor(3).astype(np.complex64).astype(np.complex128)
         out = c.D.native_empty("f32")
         net.forward(c.D, out, to_f32_native(c.D, psi))
-        assert rel(from_f32_native(c.D, out), odirac.apply_D(c.f, psi)) < 1e-6
+        got = from_f32_native(c.D, out)
+        # the weights are exact in BF16; the transported inputs are rounded to BF16
+        assert rel(got, optc.layer(c.f, optc.dirac_as_layer(c.f), [psi], bf16_inputs=True)[0]) < 3e-4
+        assert rel(got, odirac.apply_D(c.f, psi)) < 2.0 ** -7
     finally:
         net.close()
         c.D.close()
@@ -98,12 +112,12 @@ def test_train_step_loss_and_update(case):
     wq = [bf16(w) for w in ws]
     pairs = [(c.spinor(20 + k).astype(np.complex64).astype(np.complex128),
               c.spinor(30 + k).astype(np.complex64).astype(np.complex128)) for k in range(2)]
-    L, g = optc.loss_and_grads(c.f, wq, pairs)
+    L, g = optc.loss_and_grads(c.f, wq, pairs, bf16_inputs=True)
     rs = [to_f32_native(c.D, r) for r, _ in pairs]
     es = [to_f32_native(c.D, e) for _, e in pairs]
     lr = 1e-3
     loss = net.train_step(c.D, rs, es, lr)
-    assert abs(loss - L) < 1e-5 * L
+    assert abs(loss - L) < 1e-3 * L
     new = net.get_weights()
     ref = optc.Adam(ws, lr=lr).step(ws, g)  # first Adam step: -lr sign(gradient) per real part
     for l in range(3):
