@@ -225,8 +225,9 @@ def ptc_suite(pairs_per_field: int, epochs: int, checkpoint: str | None):
     T.compare_solvers(D, net, b, tol=1e-10)  # warm-up (tuning, work buffers)
     res["deploy_32c64"] = T.compare_solvers(D, net, b, tol=1e-10, reps=2)
     log(f"[ptc] deploy {res['deploy_32c64']}")
-    g, f = res["deploy_32c64"]["eo_gcr"], res["deploy_32c64"]["fgcr_ptc"]
-    res["speedup_vs_eo_gcr"] = round(g["seconds"] / f["seconds"], 3)
+    dep = res["deploy_32c64"]
+    for k in ("fgcr_ptc", "fgcr_ptc_eo"):
+        res[f"{k}_speedup_vs_eo_gcr"] = round(dep["eo_gcr"]["seconds"] / dep[k]["seconds"], 3)
     D.close()
     net.close()
     return res

@@ -165,7 +165,8 @@ typedef enum {
     DIRAC_SOLVER_CGLS = 0,      /* CG on D^dag D, full lattice, FP64 */
     DIRAC_SOLVER_GCR = 1,       /* even-odd GCR(restart), FP64 */
     DIRAC_SOLVER_MIXED_GCR = 2, /* FP64 defect correction around an inner_prec even-odd GCR */
-    DIRAC_SOLVER_FGCR_PTC = 3   /* flexible GCR on the full D with a PTC network as preconditioner */
+    DIRAC_SOLVER_FGCR_PTC = 3,  /* flexible GCR on the full D with a PTC network as preconditioner */
+    DIRAC_SOLVER_FGCR_PTC_EO = 4 /* flexible GCR on D-hat, preconditioner r_e -> even half of N(r_e, 0) */
 } dirac_solver;
 
 typedef struct dirac_ptc dirac_ptc;  /* parallel-transport convolution network (see below) */
@@ -179,7 +180,7 @@ typedef struct {
     double inner_tol;    /* MIXED_GCR: relative reduction asked of each inner solve */
     int x0_given;        /* 1: x holds the initial guess */
     int precision;       /* GCR / CGLS: dirac_prec of the whole solve (F64 only) */
-    const dirac_ptc *ptc; /* FGCR_PTC: the preconditioner network (trained weights) */
+    const dirac_ptc *ptc; /* FGCR_PTC(_EO): the preconditioner network (trained weights) */
 } dirac_solver_params;
 
 typedef struct {
@@ -194,10 +195,13 @@ typedef struct {
 /* Solve D psi = eta.  x (solution) and b (right-hand side) are full-lattice FP64
  * vectors in `layout`.  GCR and MIXED_GCR run on the even-odd Schur system and
  * reconstruct the odd half; CGLS runs on the full D; FGCR_PTC runs flexible GCR
- * on the full D with p_k = N(r_k) and falls back to even-odd GCR from the current
- * iterate (info.fell_back = 1) when a cycle reduces the residual by less than 2x
- * or meets a non-finite value.  Blocking.  Returns DIRAC_ENOCONV (x = last
- * iterate) when max_iter is reached first. */
+ * on the full D with p_k = N(r_k); FGCR_PTC_EO runs it on the Schur system with
+ * p_k = [N(r_k, 0)]_e (the even half of the network applied to the even residual
+ * extended by zero, an approximation of (D^-1)_ee = D-hat^-1) and reconstructs the
+ * odd half.  Both fall back to even-odd GCR from the current iterate
+ * (info.fell_back = 1) when a cycle reduces the residual by less than 2x or meets a
+ * non-finite value.  Blocking.  Returns DIRAC_ENOCONV (x = last iterate) when
+ * max_iter is reached first. */
 dirac_status dirac_solve(dirac_ctx *ctx, void *x, const void *b, dirac_layout layout,
                          const dirac_solver_params *params, dirac_solve_info *info, void *stream);
 

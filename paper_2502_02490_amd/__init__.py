@@ -12,7 +12,7 @@ import math
 import torch
 
 from . import _lib
-from ._lib import (BF16, CGLS, EO, F16, F32, F64, FGCR_PTC, GCR, LEX, MIXED_GCR, NATIVE,  # noqa: F401
+from ._lib import (BF16, CGLS, EO, F16, F32, F64, FGCR_PTC, FGCR_PTC_EO, GCR, LEX, MIXED_GCR, NATIVE,  # noqa: F401
                    DiracError, SolveInfo, SolverParams)
 
 _TORCH_REAL = {F64: torch.float64, F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}

@@ -12,7 +12,7 @@ STATUS_NAMES = ["DIRAC_OK", "DIRAC_EINVAL", "DIRAC_ENOMEM", "DIRAC_EHIP", "DIRAC
                 "DIRAC_ENONFINITE", "DIRAC_EUNSUPPORTED"]
 F64, F32, F16, BF16 = 0, 1, 2, 3
 LEX, EO, NATIVE = 0, 1, 2
-CGLS, GCR, MIXED_GCR, FGCR_PTC = 0, 1, 2, 3
+CGLS, GCR, MIXED_GCR, FGCR_PTC, FGCR_PTC_EO = 0, 1, 2, 3, 4
 
 # every symbol declared in include/dirac.h
 EXPORTS = ["dirac_create", "dirac_destroy", "dirac_load_clover", "dirac_get_clover", "clover_invert",

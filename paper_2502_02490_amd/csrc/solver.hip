@@ -176,8 +176,9 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
 
 void check_solver_params(const dirac_solver_params *p) {
     require(p != nullptr, "solver params are NULL");
-    require(p->method >= DIRAC_SOLVER_CGLS && p->method <= DIRAC_SOLVER_FGCR_PTC, "unknown solver method");
-    require(p->method != DIRAC_SOLVER_FGCR_PTC || p->ptc != nullptr, "FGCR_PTC needs a network (ptc)");
+    require(p->method >= DIRAC_SOLVER_CGLS && p->method <= DIRAC_SOLVER_FGCR_PTC_EO, "unknown solver method");
+    require((p->method != DIRAC_SOLVER_FGCR_PTC && p->method != DIRAC_SOLVER_FGCR_PTC_EO) || p->ptc != nullptr,
+            "FGCR_PTC needs a network (ptc)");
     require(std::isfinite(p->tol) && p->tol > 0.0 && p->tol < 1.0, "tol must be in (0, 1)");
     require(p->max_iter > 0, "max_iter must be positive");
     if (p->method != DIRAC_SOLVER_CGLS) require(p->restart >= 1 && p->restart <= kMaxRestart, "restart must be 1..64");
@@ -271,8 +272,39 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
         clover_apply(c, t64, bo, 1, 1, DIRAC_F64, s);
         hop_apply(c, r64, t64, nullptr, 0, HOP_PLAIN, -0.5, 0, DIRAC_F64, s);
         B.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, eta, nullptr, 1.0, be, -1.0, r64, nullptr, 1.0, s);
+        bool plain = true;
+        if (p->method == DIRAC_SOLVER_FGCR_PTC_EO) {
+            dirac_ptc *net = const_cast<dirac_ptc *>(p->ptc);
+            require(net->ch[0] == 1 && net->ch[net->nlayers] == 1, "the PTC network must map 1 channel to 1 channel");
+            ptc_ensure_acts(c, net);
+            ensure_work(c, p->restart, DIRAC_F64, 1);
+            float *a_in = ptc_act(c, net, 0), *a_out = ptc_act(c, net, net->nlayers);
+            const size_t half32 = (size_t)24 * c->g.vhp;  // floats in one parity of a NATIVE F32 vector
+            // p_e = [N(r_e, 0)]_e
+            const Precond M = [&](void *pv, const void *rv) {
+                B.lincomb(DIRAC_F32, DIRAC_F64, DIRAC_F64, 1, a_in, nullptr, 1.0, rv, 0.0, nullptr, nullptr, 1.0, s);
+                HIP_CHECK(hipMemsetAsync(a_in + half32, 0, half32 * sizeof(float), s));
+                ptc_forward_acts(c, net, s);
+                B.lincomb(DIRAC_F64, DIRAC_F32, DIRAC_F64, 1, pv, nullptr, 1.0, a_out, 0.0, nullptr, nullptr, 1.0, s);
+            };
+            GcrOut g = gcr(c, w, DIRAC_F64, xe, eta, x0, target, p->restart, p->max_iter, s, false, &M, 2.0);
+            iters = g.iters;
+            info->restarts = g.restarts;
+            if (g.converged) {
+                plain = false;
+            } else if (iters >= p->max_iter) {
+                st = DIRAC_ENOCONV;
+                plain = false;
+            } else {
+                info->fell_back = 1;
+                x0 = !g.nonfinite;
+            }
+        }
         ensure_work(c, p->restart, inner, 1);
-        if (p->method == DIRAC_SOLVER_GCR || p->method == DIRAC_SOLVER_FGCR_PTC) {
+        if (!plain) {
+            // solved by the flexible GCR above
+        } else if (p->method == DIRAC_SOLVER_GCR || p->method == DIRAC_SOLVER_FGCR_PTC ||
+                   p->method == DIRAC_SOLVER_FGCR_PTC_EO) {
             // the iterate lives directly in the even half of x
             GcrOut g = gcr(c, w, DIRAC_F64, xe, eta, x0, target, p->restart, p->max_iter - iters, s);
             iters += g.iters;

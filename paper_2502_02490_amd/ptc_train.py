@@ -24,7 +24,7 @@ import time
 import numpy as np
 import torch
 
-from . import GCR, FGCR_PTC, Dirac, PTC
+from . import FGCR_PTC, FGCR_PTC_EO, GCR, PTC, Dirac
 
 CHECKPOINT_VERSION = 1
 DEFAULT_SNAPSHOTS = (0, 2, 4, 8, 16, 32)
@@ -143,10 +143,12 @@ def load_checkpoint(path: str):
 
 
 def compare_solvers(D: Dirac, net: PTC, b: torch.Tensor, tol: float = 1e-10, restart: int = 32, reps: int = 1):
-    """Solve D x = b with FGCR + network and with plain even-odd FP64 GCR; returns a dict of
-    iterations, seconds (best of reps) and residuals for both."""
+    """Solve D x = b with plain even-odd FP64 GCR, flexible GCR on D with the network, and
+    flexible GCR on D-hat with the network's even block; returns a dict of iterations, seconds
+    (best of reps) and residuals for each."""
     out = {}
-    for name, kw in (("eo_gcr", dict(method=GCR)), ("fgcr_ptc", dict(method=FGCR_PTC, ptc=net))):
+    for name, kw in (("eo_gcr", dict(method=GCR)), ("fgcr_ptc", dict(method=FGCR_PTC, ptc=net)),
+                     ("fgcr_ptc_eo", dict(method=FGCR_PTC_EO, ptc=net))):
         best = None
         for _ in range(reps):
             x = torch.zeros_like(b)

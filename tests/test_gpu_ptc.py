@@ -158,24 +158,32 @@ def test_training_reduces_loss():
         c.D.close()
 
 
-def test_fgcr_ptc_solves_and_falls_back(case):
+@pytest.mark.parametrize("method", ["full", "eo"])
+def test_fgcr_ptc_solves_and_falls_back(case, method):
     c, net = case
+    m = P.FGCR_PTC if method == "full" else P.FGCR_PTC_EO
     eta = c.spinor(50)
     exact, _ = osolvers.solve_eo(c.f, eta, 1e-13)
     b = to_dev(eta)
     # zero weights: N(r) = 0 gives no direction; the solver must fall back and still converge
     net.set_weights([np.zeros(s, dtype=np.complex64) for s in net.shapes()])
     x = torch.zeros_like(b)
-    info = c.D.solve(x, b, method=P.FGCR_PTC, ptc=net, tol=1e-12)
+    info = c.D.solve(x, b, method=m, ptc=net, tol=1e-12)
     assert info.fell_back == 1 and rel(x.cpu().numpy(), exact) < 1e-9
-    # the D-like layer stack (identity network: W_0 = 1 in the middle) is a fine preconditioner direction
+    # the identity network (W_0 = 1 on one channel) is a fine preconditioner direction
     ws = [np.zeros(s, dtype=np.complex64) for s in net.shapes()]
     for w in ws:
         w[0, 0, 0] = np.eye(4)
     net.set_weights(ws)
     x = torch.zeros_like(b)
-    info = c.D.solve(x, b, method=P.FGCR_PTC, ptc=net, tol=1e-12)
+    info = c.D.solve(x, b, method=m, ptc=net, tol=1e-12)
     assert rel(x.cpu().numpy(), exact) < 1e-9 and info.true_rel_res < 1e-12
+    if method == "eo":
+        # the identity network returns r rounded to BF16: flexible GCR on D-hat then needs about
+        # as many iterations as plain GCR
+        x2 = torch.zeros_like(b)
+        info2 = c.D.solve(x2, b, method=P.GCR, tol=1e-12)
+        assert abs(info.iters - info2.iters) <= max(2, info2.iters // 10) and info.fell_back == 0
 
 
 def test_checkpoint_resume_is_exact(tmp_path):
