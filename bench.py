@@ -36,6 +36,8 @@ HOP_SHAPES = ["k_hop bs256 xcd-order", "k_hop bs256", "k_hop bs128 xcd-order", "
               "k_hop_p bs256 1/CU xcd-regions (persistent)", "k_hop_tp tt4 1/CU (persistent time-tiled)",
               "k_hop_tp tt8 1/CU (persistent time-tiled)", "k_hop_ps bs256 1/CU (XCD slab sweep)",
               "k_hop_ps bs256 2/CU (XCD slab sweep)", "k_hop_ps bs128 2/CU (XCD slab sweep)",
+              "k_hop_p bs256 1/CU 2 neighbours/iteration (persistent)",
+              "k_hop_p bs256 2/CU 2 neighbours/iteration (persistent)",
               "k_hop bs256 3 waves/SIMD", "k_hop bs128 3 waves/SIMD"]
 
 
@@ -183,12 +185,17 @@ def ptc_suite(pairs_per_field: int, epochs: int, checkpoint: str | None):
         d = PTC_TRAIN_DIMS
         D = P.Dirac(torch.from_numpy(gen.su3_field(d, EPS, 501 + j)).cuda(),
                     torch.from_numpy(gen.u1_field(d, 0.3, 501 + j)).cuda(), d, PTC_KAPPA, CSW, CSW_QED, QHAT)
-        rs, es = T.generate_pairs(D, pairs_per_field, seed=501 + j, log=log)
-        ops_pairs.append((D, rs, es))
-        hr, he = T.generate_pairs(D, 12, seed=10501 + j)
-        held.append((D, hr, he))
+        # half from truncated FP64 solves (low-mode dominated errors), half e ~ Gaussian with
+        # r = D e (high-mode dominated): both are exact (r, D^-1 r) pairs
+        rs, es = T.generate_pairs(D, pairs_per_field // 2, seed=501 + j, log=log)
+        ra, ea = T.generate_apply_pairs(D, pairs_per_field - pairs_per_field // 2, seed=601 + j)
+        ops_pairs.append((D, rs + ra, es + ea))
+        hr, he = T.generate_pairs(D, 6, seed=10501 + j)
+        har, hae = T.generate_apply_pairs(D, 6, seed=10601 + j)
+        held.append((D, hr + har, he + hae))
         log(f"[ptc] field {j}: {len(rs)} pairs ({time.perf_counter() - t0:.1f} s)")
     res["pairs"] = sum(len(rs) for _, rs, _ in ops_pairs)
+    res["pair_kinds"] = "half truncated FP64 GCR solves (e = x* - x_k), half Gaussian e with r = D e"
     res["pair_generation_seconds"] = round(time.perf_counter() - t0, 2)
     net = P.PTC((1, 8, 8, 1))
     net.set_weights(T.init_weights((1, 8, 8, 1), seed=7))
@@ -324,7 +331,7 @@ def main():
         log(f"[bench] tuner choice not readable: {e}")
     # every launch shape of the hop kernel, FP64 Schur (the tuner's choice is what the timed loop used)
     shapes = {}
-    for shape in range(17):
+    for shape in range(19):
         os.environ["DIRAC_HOP_SHAPE"] = str(shape)
         for _ in range(3):
             schur()

@@ -165,6 +165,7 @@ dirac_status dirac_destroy(dirac_ctx *c) {
         }
         f.tmp_half.release(); f.user_in.release(); f.user_out.release();
     }
+    for (auto &b : c->ptc_links) b.release();
     c->flags.release();
     c->red.release();
     delete c;

@@ -70,57 +70,72 @@ DEV void load_link(const HopArgs<S> &a, int dir, uint32_t i, C<typename St<S>::a
 template <typename T>
 DEV C<T> cmul_unit(T cr, T ci, C<T> z) { return mk(cr * z.r - ci * z.i, cr * z.i + ci * z.r); }
 
-// The 8 neighbours (n = 2 mu + back) run as iterations of a loop that is not unrolled, with
-// the direction a uniform run-time value: straight-line code lets the compiler issue the
-// loads of all eight neighbours up front, which needs more registers than a lane has
-// (spills, one wave per SIMD).  The loop keeps one neighbour's data live at a time.
-// With `tile` (the t-tiled kernel) the two time-direction neighbours come from LDS: slot
-// `tslot` - 1 / + 1 of the tile holds the input block of the previous / next time slice at the
-// same spatial block, and the neighbour sits at the same lane.
+// One neighbour direction n = 2 mu + back of the hopping sum at site i (coordinates x, row =
+// index of its (x0, x1, x2) row), accumulated into acc.  With `tile` the time-direction neighbour
+// comes from LDS: slot `tslot` - 1 / + 1 of the tile holds the input block of the previous / next
+// time slice at the same spatial block, and the neighbour sits at the same lane.
 template <typename S, int DAG>
+DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n, C<typename St<S>::acc> acc[12],
+                 const typename St<S>::vec *tile, int tslot) {
+    using T = typename St<S>::acc;
+    const int mu = n >> 1, back = n & 1;
+    const int xm = mu == 0 ? x[0] : mu == 1 ? x[1] : mu == 2 ? x[2] : x[3];
+    const int Lm = mu == 0 ? a.g.L[0] : mu == 1 ? a.g.L[1] : mu == 2 ? a.g.L[2] : a.g.L[3];
+    const int xn = back ? (xm == 0 ? Lm - 1 : xm - 1) : (xm + 1 == Lm ? 0 : xm + 1);
+    const int rs = mu == 0 ? a.g.L[1] * a.g.L[2] : mu == 1 ? a.g.L[2] : 1;
+    const uint32_t j = mu == 3 ? (uint32_t)(row * a.g.h3 + (xn >> 1))
+                               : (uint32_t)((row + (xn - xm) * rs) * a.g.h3 + (x[3] >> 1));
+    // projector sign: forward (1 + SF gamma), backward (1 - SF gamma); SF = -1 for D, +1 for D^dag
+    const T sg = (DAG ? T(1) : T(-1)) * (back ? T(-1) : T(1));
+    const int sw = (mu == 1 || mu == 2);
+    const T c0r = (mu == 0 || mu == 2) ? T(-1) : T(0), c0i = (mu == 1 || mu == 3) ? T(-1) : T(0);
+    const T c1r = mu == 0 ? T(-1) : mu == 2 ? T(1) : T(0), c1i = mu == 1 ? T(-1) : mu == 3 ? T(1) : T(0);
+    C<T> psi[12], h[6], u[6], w[6];
+    T co, si;
+    if (tile && mu == 0) load_spinor<S>(tile + (size_t)(tslot + (back ? -1 : 1)) * (24 / St<S>::W) * kSB,
+                                        i & (kSB - 1), psi);
+    else load_spinor<S>(a.in, j, psi);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const C<T> l0 = psi[6 + c], l1 = psi[9 + c];
+        const C<T> e0 = cmul_unit(c0r, c0i, sw ? l1 : l0);
+        const C<T> e1 = cmul_unit(c1r, c1i, sw ? l0 : l1);
+        h[c] = mk(fma(sg, e0.r, psi[c].r), fma(sg, e0.i, psi[c].i));
+        h[3 + c] = mk(fma(sg, e1.r, psi[3 + c].r), fma(sg, e1.i, psi[3 + c].i));
+    }
+    load_link(a, n, i, u, co, si);
+    if (back) link_adj_mul(u, co, si, h, w);
+    else link_mul(u, co, si, h, w);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[c] = acc[c] + w[c];
+        acc[3 + c] = acc[3 + c] + w[3 + c];
+        const C<T> t0 = cmul_unit(c0r, -c0i, w[c]);      // conj(c_0) w_0 -> lower spin p_0
+        const C<T> t1 = cmul_unit(c1r, -c1i, w[3 + c]);  // conj(c_1) w_1 -> lower spin p_1
+        const C<T> l0 = sw ? t1 : t0, l1 = sw ? t0 : t1;
+        acc[6 + c] = mk(fma(sg, l0.r, acc[6 + c].r), fma(sg, l0.i, acc[6 + c].i));
+        acc[9 + c] = mk(fma(sg, l1.r, acc[9 + c].r), fma(sg, l1.i, acc[9 + c].i));
+    }
+}
+
+// The 8 neighbours run as iterations of a loop that is not unrolled, with the direction a
+// uniform run-time value: straight-line code lets the compiler issue the loads of all eight
+// neighbours up front, which needs more registers than a lane has (spills, one wave per SIMD).
+// NPI = 1 keeps one neighbour's data live at a time; NPI = 2 takes the forward and backward
+// neighbour of one mu per iteration, so each wave has twice the loads in flight.  The sums are
+// accumulated in the same order either way.
+template <typename S, int DAG, int NPI>
 DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<S>::acc> acc[12],
                  const typename St<S>::vec *tile = nullptr, int tslot = 0) {
-    using T = typename St<S>::acc;
     const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
+    if constexpr (NPI == 1) {
 #pragma nounroll
-    for (int n = 0; n < 8; ++n) {
-        const int mu = n >> 1, back = n & 1;
-        const int xm = mu == 0 ? x[0] : mu == 1 ? x[1] : mu == 2 ? x[2] : x[3];
-        const int Lm = mu == 0 ? a.g.L[0] : mu == 1 ? a.g.L[1] : mu == 2 ? a.g.L[2] : a.g.L[3];
-        const int xn = back ? (xm == 0 ? Lm - 1 : xm - 1) : (xm + 1 == Lm ? 0 : xm + 1);
-        const int rs = mu == 0 ? a.g.L[1] * a.g.L[2] : mu == 1 ? a.g.L[2] : 1;
-        const uint32_t j = mu == 3 ? (uint32_t)(row * a.g.h3 + (xn >> 1))
-                                   : (uint32_t)((row + (xn - xm) * rs) * a.g.h3 + (x[3] >> 1));
-        // projector sign: forward (1 + SF gamma), backward (1 - SF gamma); SF = -1 for D, +1 for D^dag
-        const T sg = (DAG ? T(1) : T(-1)) * (back ? T(-1) : T(1));
-        const int sw = (mu == 1 || mu == 2);
-        const T c0r = (mu == 0 || mu == 2) ? T(-1) : T(0), c0i = (mu == 1 || mu == 3) ? T(-1) : T(0);
-        const T c1r = mu == 0 ? T(-1) : mu == 2 ? T(1) : T(0), c1i = mu == 1 ? T(-1) : mu == 3 ? T(1) : T(0);
-        C<T> psi[12], h[6], u[6], w[6];
-        T co, si;
-        if (tile && mu == 0) load_spinor<S>(tile + (size_t)(tslot + (back ? -1 : 1)) * (24 / St<S>::W) * kSB,
-                                            i & (kSB - 1), psi);
-        else load_spinor<S>(a.in, j, psi);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const C<T> l0 = psi[6 + c], l1 = psi[9 + c];
-            const C<T> e0 = cmul_unit(c0r, c0i, sw ? l1 : l0);
-            const C<T> e1 = cmul_unit(c1r, c1i, sw ? l0 : l1);
-            h[c] = mk(fma(sg, e0.r, psi[c].r), fma(sg, e0.i, psi[c].i));
-            h[3 + c] = mk(fma(sg, e1.r, psi[3 + c].r), fma(sg, e1.i, psi[3 + c].i));
-        }
-        load_link(a, n, i, u, co, si);
-        if (back) link_adj_mul(u, co, si, h, w);
-        else link_mul(u, co, si, h, w);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            acc[c] = acc[c] + w[c];
-            acc[3 + c] = acc[3 + c] + w[3 + c];
-            const C<T> t0 = cmul_unit(c0r, -c0i, w[c]);      // conj(c_0) w_0 -> lower spin p_0
-            const C<T> t1 = cmul_unit(c1r, -c1i, w[3 + c]);  // conj(c_1) w_1 -> lower spin p_1
-            const C<T> l0 = sw ? t1 : t0, l1 = sw ? t0 : t1;
-            acc[6 + c] = mk(fma(sg, l0.r, acc[6 + c].r), fma(sg, l0.i, acc[6 + c].i));
-            acc[9 + c] = mk(fma(sg, l1.r, acc[9 + c].r), fma(sg, l1.i, acc[9 + c].i));
+        for (int n = 0; n < 8; ++n) hop_dir<S, DAG>(a, x, row, i, n, acc, tile, tslot);
+    } else {
+#pragma nounroll
+        for (int mu = 0; mu < 4; ++mu) {
+            hop_dir<S, DAG>(a, x, row, i, 2 * mu, acc, tile, tslot);
+            hop_dir<S, DAG>(a, x, row, i, 2 * mu + 1, acc, tile, tslot);
         }
     }
 }
@@ -131,7 +146,7 @@ DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<
 // fastest (see tune.cpp).
 // Everything of one output site after the work assignment: the 8 neighbours, the scale, the
 // clover epilogue / prologue and the store.
-template <typename S, int DAG, int MODE>
+template <typename S, int DAG, int MODE, int NPI = 1>
 DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, int tslot) {
     using T = typename St<S>::acc;
     const uint32_t i = (uint32_t)ii;
@@ -140,7 +155,7 @@ DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, 
     C<T> acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = mk(T(0), T(0));
-    hop_all<S, DAG>(a, x, i, acc, tile, tslot);
+    hop_all<S, DAG, NPI>(a, x, i, acc, tile, tslot);
     C<T> y[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) y[k] = a.coef * acc[k];
@@ -203,7 +218,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
 // is set by the grid rather than by the register-limited occupancy.
 // With XCD the grid (a multiple of 8) is split by XCD instead: the work-groups of XCD k sweep
 // the k-th contiguous eighth of the logical blocks.
-template <typename S, int DAG, int MODE, int BS, int XCD>
+template <typename S, int DAG, int MODE, int BS, int XCD, int NPI>
 __global__ __launch_bounds__(BS) void k_hop_p(HopArgs<S> a, int nlog) {
     const int region = XCD ? (nlog + 7) >> 3 : nlog;
     const int first = XCD ? (int)(blockIdx.x & 7) * region : 0;
@@ -222,7 +237,7 @@ __global__ __launch_bounds__(BS) void k_hop_p(HopArgs<S> a, int nlog) {
             b.out += rhs * a.vs;
             if (b.chi) b.chi += rhs * a.vs;
         }
-        hop_site<S, DAG, MODE>(b, ii, nullptr, 0);
+        hop_site<S, DAG, MODE, NPI>(b, ii, nullptr, 0);
     }
 }
 
@@ -328,16 +343,17 @@ __global__ __launch_bounds__(64 * TT) void k_hop_tp(HopArgs<S> a, int nwg) {
 }
 
 struct HopShape {
-    int bs, wpe, xcd, tt, pers, slab;
+    int bs, wpe, xcd, tt, pers, slab, npi;
 };
 // shape 0 is the default; shapes with tt > 0 are the time-tiled kernel (bs = 64 tt); pers > 0 is
 // the persistent kernel with pers work-groups per compute unit; occupancy hints (wpe, FP64 only,
 // where the default leaves fewer than 4 waves per SIMD) come last
-const HopShape kShapes[] = {{256, 0, 1, 0, 0, 0}, {256, 0, 0, 0, 0, 0}, {128, 0, 1, 0, 0, 0}, {64, 0, 1, 0, 0, 0},
-                            {256, 0, 1, 4, 0, 0}, {512, 0, 1, 8, 0, 0}, {256, 0, 0, 0, 1, 0}, {512, 0, 0, 0, 1, 0},
-                            {256, 0, 0, 0, 2, 0}, {256, 0, 1, 0, 1, 0}, {256, 0, 0, 4, 1, 0}, {512, 0, 0, 8, 1, 0},
-                            {256, 0, 0, 0, 1, 1}, {256, 0, 0, 0, 2, 1}, {128, 0, 0, 0, 2, 1},
-                            {256, 3, 1, 0, 0, 0}, {128, 3, 1, 0, 0, 0}};
+const HopShape kShapes[] = {
+    {256, 0, 1, 0, 0, 0, 1}, {256, 0, 0, 0, 0, 0, 1}, {128, 0, 1, 0, 0, 0, 1}, {64, 0, 1, 0, 0, 0, 1},
+    {256, 0, 1, 4, 0, 0, 1}, {512, 0, 1, 8, 0, 0, 1}, {256, 0, 0, 0, 1, 0, 1}, {512, 0, 0, 0, 1, 0, 1},
+    {256, 0, 0, 0, 2, 0, 1}, {256, 0, 1, 0, 1, 0, 1}, {256, 0, 0, 4, 1, 0, 1}, {512, 0, 0, 8, 1, 0, 1},
+    {256, 0, 0, 0, 1, 1, 1}, {256, 0, 0, 0, 2, 1, 1}, {128, 0, 0, 0, 2, 1, 1}, {256, 0, 0, 0, 1, 0, 2},
+    {256, 0, 0, 0, 2, 0, 2}, {256, 3, 1, 0, 0, 0, 1}, {128, 3, 1, 0, 0, 0, 1}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 template <typename S> constexpr int num_shapes() { return std::is_same<S, double>::value ? kNumShapes : kNumShapes - 2; }
 
@@ -369,15 +385,15 @@ void launch_shape(HopArgs<S> a, int xcd, hipStream_t s) {
     k_hop<S, DAG, MODE, BS, WPE><<<a.nb8, BS, 0, s>>>(a);
 }
 
-template <typename S, int DAG, int MODE, int BS>
+template <typename S, int DAG, int MODE, int BS, int NPI = 1>
 void launch_persistent(HopArgs<S> a, int per_cu, int xcd, hipStream_t s) {
     const int nlog = (a.g.vh + BS - 1) / BS * a.nrhs;
     int grid = std::min(nlog, per_cu * compute_units());
     if (xcd) grid = std::max(8, grid & ~7);
     a.xcd = xcd;
     a.nb8 = grid;
-    if (xcd) k_hop_p<S, DAG, MODE, BS, 1><<<grid, BS, 0, s>>>(a, nlog);
-    else k_hop_p<S, DAG, MODE, BS, 0><<<grid, BS, 0, s>>>(a, nlog);
+    if (xcd) k_hop_p<S, DAG, MODE, BS, 1, NPI><<<grid, BS, 0, s>>>(a, nlog);
+    else k_hop_p<S, DAG, MODE, BS, 0, NPI><<<grid, BS, 0, s>>>(a, nlog);
 }
 
 template <typename S, int DAG, int MODE, int BS>
@@ -424,7 +440,8 @@ void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
         case 11: launch_tiled_persistent<S, DAG, MODE, 8>(a, h.pers, s); break;
         case 12: case 13: launch_slab<S, DAG, MODE, 256>(a, h.pers, s); break;
         case 14: launch_slab<S, DAG, MODE, 128>(a, h.pers, s); break;
-        case 15:
+        case 15: case 16: launch_persistent<S, DAG, MODE, 256, 2>(a, h.pers, 0, s); break;
+        case 17:
             if constexpr (std::is_same<S, double>::value) launch_shape<S, DAG, MODE, 256, 3>(a, h.xcd, s);
             break;
         default:

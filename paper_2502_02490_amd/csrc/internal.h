@@ -81,6 +81,8 @@ struct dirac_ctx {
     int64_t V, vh;
     dl::DevBuf U_lex, theta_lex;   // FP64 copies of the gauge input (clover rebuild, precision copies)
     dl::PrecFields f[4];           // indexed by dirac_prec
+    dl::DevBuf ptc_links[2];       // full FP32 links with phases for the PTC network (built on first use)
+    bool ptc_links_ready = false;
     dl::DevBuf flags;              // small device scratch: flags, maxima
     dl::DevBuf red;                // reduction partials
     dl::SolverWork *work = nullptr;

@@ -27,56 +27,139 @@ constexpr int kTile = 64;  // sites per work-group of the weight-gradient kernel
 
 struct PtcGeom {
     Geom g;
-    const float4 *links[2];  // FP32 links per parity: [8 dir][3 planes] blocked
-    const float *omega[2];   // [8 dir][vhp]
-    size_t chan;             // floats per channel (a full NATIVE FP32 vector)
+    const float4 *flinks[2];  // per parity: full FP32 links F = e^{i omega} U, [8 dir][5 planes] blocked
+    size_t chan;              // floats per channel (a full NATIVE FP32 vector)
 };
 
-DEV void bf2(uint32_t w, float &re, float &im) {
-    re = __uint_as_float(w << 16);
-    im = __uint_as_float(w & 0xffff0000u);
+// The network's transports use the links with the U(1) and boundary phase folded in and the
+// third row rebuilt, F_n(x) = e^{i omega_n(x)} U_n(x) as 9 complex numbers (row-major, 18 floats
+// in 5 planes of float4, the last two floats unused), built once per context: the hop kernel's
+// compressed form would cost a sincos and a cross product in every one of the 9 * c_in
+// transports of a site.
+constexpr int kFullPlanes = 5;
+
+__global__ void k_full_links(Geom g, int p, const float4 *__restrict__ links, const float *__restrict__ omega,
+                             float4 *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.vh) return;
+    const size_t vhp = (size_t)g.vhp;
+#pragma unroll 1
+    for (int n = 0; n < 8; ++n) {
+        const float4 *lb = site_ptr(links + (size_t)n * 3 * vhp, (uint32_t)i, 3);
+        float u12[12];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Lk<float>::unpack(lb[k * kSB], u12 + 4 * k);
+        C<float> u[6], r2[3];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) u[k] = mk(u12[2 * k], u12[2 * k + 1]);
+        third_row(u, r2);
+        float si, co;
+        sc(omega[(size_t)n * vhp + i], si, co);
+        const C<float> ph = mk(co, si);
+        float f[20];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const C<float> v = ph * u[k];
+            f[2 * k] = v.r;
+            f[2 * k + 1] = v.i;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const C<float> v = ph * r2[k];
+            f[12 + 2 * k] = v.r;
+            f[13 + 2 * k] = v.i;
+        }
+        f[18] = f[19] = 0.f;
+        float4 *ob = site_ptr(out + (size_t)n * kFullPlanes * vhp, (uint32_t)i, kFullPlanes);
+#pragma unroll
+        for (int k = 0; k < kFullPlanes; ++k) ob[k * kSB] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+    }
 }
 
-// t = T_path x_c (full spinor, 12 complex) at site (p, i) with coordinates x
-DEV void transport_site(const PtcGeom &a, const float4 *xc, int p, uint32_t i, const int x[4], int path,
-                        C<float> t[12]) {
+// Raw data of one transport: the (neighbour's) spinor and, for a hop, the full link.
+struct TRaw {
+    float4 sp[6];
+    float4 lk[kFullPlanes];
+};
+
+// Load what T_path x_c needs at site (p, i) with coordinates x.  Every field of r is written on
+// every path (the link is zero for the unshifted path), so the compiler keeps r in registers.
+DEV void transport_load(const PtcGeom &a, const float4 *xc, int p, uint32_t i, const int x[4], int path, TRaw &r) {
     const size_t hv = (size_t)6 * a.g.vhp;  // float4 per half vector
-    if (path == 0) {
-        float r[24];
-        load_field<float, 24>(xc + p * hv, i, r);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) t[k] = mk(r[2 * k], r[2 * k + 1]);
-        return;
-    }
-    const int n = path - 1;  // direction index 2 mu + back
+    const int n = path - 1;                 // direction index 2 mu + back (path > 0)
     const int mu = n >> 1, back = n & 1;
     int y[4] = {x[0], x[1], x[2], x[3]};
-    const int xm = mu == 0 ? x[0] : mu == 1 ? x[1] : mu == 2 ? x[2] : x[3];
-    const int Lm = a.g.L[mu];
-    const int xn = back ? (xm == 0 ? Lm - 1 : xm - 1) : (xm + 1 == Lm ? 0 : xm + 1);
-    if (mu == 0) y[0] = xn; else if (mu == 1) y[1] = xn; else if (mu == 2) y[2] = xn; else y[3] = xn;
-    const uint32_t j = (uint32_t)half_index(a.g, y);
-    float r[24];
-    load_field<float, 24>(xc + (1 - p) * hv, j, r);
-    C<float> psi[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = mk(r[2 * k], r[2 * k + 1]);
-    const float4 *lb = site_ptr(a.links[p] + (size_t)n * 3 * a.g.vhp, i, 3);
-    float u12[12];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) Lk<float>::unpack(lb[k * kSB], u12 + 4 * k);
-    C<float> u[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) u[k] = mk(u12[2 * k], u12[2 * k + 1]);
-    float si, co;
-    sc(a.omega[p][(size_t)n * a.g.vhp + i], si, co);
-    if (back) {
-        link_adj_mul(u, co, si, psi, t);
-        link_adj_mul(u, co, si, psi + 6, t + 6);
-    } else {
-        link_mul(u, co, si, psi, t);
-        link_mul(u, co, si, psi + 6, t + 6);
+    if (path > 0) {
+        const int xm = mu == 0 ? x[0] : mu == 1 ? x[1] : mu == 2 ? x[2] : x[3];
+        const int Lm = mu == 0 ? a.g.L[0] : mu == 1 ? a.g.L[1] : mu == 2 ? a.g.L[2] : a.g.L[3];
+        const int xn = back ? (xm == 0 ? Lm - 1 : xm - 1) : (xm + 1 == Lm ? 0 : xm + 1);
+        if (mu == 0) y[0] = xn; else if (mu == 1) y[1] = xn; else if (mu == 2) y[2] = xn; else y[3] = xn;
     }
+    const uint32_t j = path > 0 ? (uint32_t)half_index(a.g, y) : i;
+    const int q = path > 0 ? 1 - p : p;
+    const float4 *b = site_ptr(xc + q * hv, j, 6);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.sp[k] = b[k * kSB];
+    if (path > 0) {
+        const float4 *lb = site_ptr(a.flinks[p] + (size_t)n * kFullPlanes * a.g.vhp, i, kFullPlanes);
+#pragma unroll
+        for (int k = 0; k < kFullPlanes; ++k) r.lk[k] = lb[k * kSB];
+    } else {
+#pragma unroll
+        for (int k = 0; k < kFullPlanes; ++k) r.lk[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+DEV void unpack4(const float4 *v, int nv, float *o) {
+#pragma unroll
+    for (int k = 0; k < nv; ++k) {
+        o[4 * k] = v[k].x;
+        o[4 * k + 1] = v[k].y;
+        o[4 * k + 2] = v[k].z;
+        o[4 * k + 3] = v[k].w;
+    }
+}
+
+DEV void transport_compute(const TRaw &r, int path, C<float> t[12]) {
+    float sp[24];
+    unpack4(r.sp, 6, sp);
+    if (path == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) t[k] = mk(sp[2 * k], sp[2 * k + 1]);
+        return;
+    }
+    float lf[20];
+    unpack4(r.lk, kFullPlanes, lf);
+    C<float> f[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) f[k] = mk(lf[2 * k], lf[2 * k + 1]);
+    const bool back = ((path - 1) & 1) != 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        C<float> ps[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) ps[b] = mk(sp[6 * s + 2 * b], sp[6 * s + 2 * b + 1]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            C<float> acc = mk(0.f, 0.f);
+            if (back) {
+#pragma unroll
+                for (int b = 0; b < 3; ++b) cmadd(acc, f[3 * b + a], ps[b]);  // conj(F_ba) psi_b
+            } else {
+#pragma unroll
+                for (int b = 0; b < 3; ++b) madd(acc, f[3 * a + b], ps[b]);
+            }
+            t[3 * s + a] = acc;
+        }
+    }
+}
+
+// t = T_path x_c at site (p, i)
+DEV void transport_site(const PtcGeom &a, const float4 *xc, int p, uint32_t i, const int x[4], int path,
+                        C<float> t[12]) {
+    TRaw r;
+    transport_load(a, xc, p, i, x, path, r);
+    transport_compute(r, path, t);
 }
 
 // ------------------------------------------------------------------ matrix-core layer
@@ -92,12 +175,6 @@ DEV void transport_site(const PtcGeom &a, const float4 *xc, int p, uint32_t i, c
 // instruction (row lane % 16, depth 8 (lane / 16) + j) and staged in LDS per work-group.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
-
-DEV uint32_t bf16_bits(float f) {
-    const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // NaN stays NaN
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
 
 // A fragments of one layer: Af[(q * nm + t) * 64 + lane] = 8 BF16 values (uint4), q < nk, t < nm.
 // W holds BF16 (re, im) pairs [9][nout][nin][4][4].
@@ -150,12 +227,22 @@ __global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, con
         for (int t = 0; t < NM; ++t)
 #pragma unroll
             for (int col = 0; col < 3; ++col) acc[t][col] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        // software pipeline: the loads of K step q + 1 are issued before the transport and the
+        // matrix-core work of step q
+        TRaw cur, nxt;
+        auto load = [&](int q, TRaw &r) {
+            const int pair = 4 * q + g;
+            if (on && pair < NPAIR)
+                transport_load(a, xin + (size_t)(pair % NIN) * chan4, p, (uint32_t)i, x, pair / NIN, r);
+        };
+        load(0, cur);
 #pragma nounroll
         for (int q = 0; q < NK; ++q) {
+            if (q + 1 < NK) load(q + 1, nxt);
             const int pair = 4 * q + g;
             C<float> tr[12];
             if (on && pair < NPAIR) {
-                transport_site(a, xin + (size_t)(pair % NIN) * chan4, p, (uint32_t)i, x, pair / NIN, tr);
+                transport_compute(cur, pair / NIN, tr);
             } else {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) tr[k] = mk(0.f, 0.f);
@@ -163,12 +250,11 @@ __global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, con
             bf16x8_t b[3];
 #pragma unroll
             for (int col = 0; col < 3; ++col) {
-                uint4 u;
-                u.x = bf16_bits(tr[col].r) | (bf16_bits(tr[col].i) << 16);
-                u.y = bf16_bits(tr[3 + col].r) | (bf16_bits(tr[3 + col].i) << 16);
-                u.z = bf16_bits(tr[6 + col].r) | (bf16_bits(tr[6 + col].i) << 16);
-                u.w = bf16_bits(tr[9 + col].r) | (bf16_bits(tr[9 + col].i) << 16);
-                b[col] = __builtin_bit_cast(bf16x8_t, u);
+#pragma unroll
+                for (int tau = 0; tau < 4; ++tau) {
+                    b[col][2 * tau] = (__bf16)tr[3 * tau + col].r;  // round to nearest even
+                    b[col][2 * tau + 1] = (__bf16)tr[3 * tau + col].i;
+                }
             }
 #pragma unroll
             for (int t = 0; t < NM; ++t) {
@@ -177,6 +263,7 @@ __global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, con
                 for (int col = 0; col < 3; ++col)
                     acc[t][col] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, b[col], acc[t][col], 0, 0, 0);
             }
+            cur = nxt;
         }
         if (!on) continue;
         // lane (g, site) holds rows m = 16 t + 4 g + r, r < 4: channel 2 t + g / 2, spins
@@ -360,12 +447,20 @@ void wgrad_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const vo
 
 PtcGeom geom_of(dirac_ctx *c, hipStream_t s) {
     ensure_prec(c, DIRAC_F32, s);
+    if (!c->ptc_links_ready) {
+        const size_t per = (size_t)8 * kFullPlanes * c->g.vhp * sizeof(float4);
+        for (int p = 0; p < 2; ++p) {
+            c->ptc_links[p].alloc(per);
+            k_full_links<<<grid_for(c->vh), kBlock, 0, s>>>(c->g, p, (const float4 *)c->f[DIRAC_F32].links[p].p,
+                                                            (const float *)c->f[DIRAC_F32].omega[p].p,
+                                                            (float4 *)c->ptc_links[p].p);
+            HIP_CHECK(hipGetLastError());
+        }
+        c->ptc_links_ready = true;
+    }
     PtcGeom a;
     a.g = c->g;
-    for (int p = 0; p < 2; ++p) {
-        a.links[p] = (const float4 *)c->f[DIRAC_F32].links[p].p;
-        a.omega[p] = (const float *)c->f[DIRAC_F32].omega[p].p;
-    }
+    for (int p = 0; p < 2; ++p) a.flinks[p] = (const float4 *)c->ptc_links[p].p;
     a.chan = (size_t)48 * c->g.vhp;
     return a;
 }

@@ -59,6 +59,22 @@ def generate_pairs(D: Dirac, n_pairs: int, seed: int, snapshots=DEFAULT_SNAPSHOT
     return rs, es
 
 
+def generate_apply_pairs(D: Dirac, n_pairs: int, seed: int):
+    """n_pairs (r, e) pairs with a Gaussian e and r = D e (one operator application each, no
+    solve): the error distribution of a converged smoother, dominated by the high modes."""
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    rs, es = [], []
+    for _ in range(n_pairs):
+        e = torch.randn((D.V, 4, 3), dtype=torch.complex128, generator=g).cuda()
+        r = torch.empty_like(e)
+        D.apply(r, e)
+        s = 1.0 / torch.linalg.vector_norm(e).item()
+        rs.append(D.to_native((r * s).to(torch.complex64), "f32", "lex"))
+        es.append(D.to_native((e * s).to(torch.complex64), "f32", "lex"))
+    torch.cuda.synchronize()
+    return rs, es
+
+
 def init_weights(channels, seed: int, scale: float = 0.1):
     """Small random complex weights (N(0, scale^2 / (9 c_in)) per real part) plus, on the
     unshifted path, 1/c of the identity from channel min(c, c') to min(c, c'), so that the
