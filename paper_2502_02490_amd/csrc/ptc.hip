@@ -284,45 +284,55 @@ __global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, con
     }
 }
 
-// Partial weight gradient of one 64-site tile: part[tile][path][c][c'][s][t] (complex float)
+// Partial weight gradient of one 64-site tile: part[tile][path][c][c'][s][t] (complex float).
+// Four wavefronts per work-group: the gradient of the tile (all output channels) is staged in
+// LDS once; then each wavefront takes one (path, c') pair at a time, computes its transport at
+// the 64 sites into its own LDS slot and reduces the 16 NOUT outputs of that pair over the tile
+// (sites, then colours, in index order: deterministic).
 template <int NOUT>
-__global__ __launch_bounds__(kTile) void k_ptc_wgrad(PtcGeom a, int nin, const float4 *__restrict__ xin,
-                                                     const float4 *__restrict__ g, float2 *__restrict__ part) {
+__global__ __launch_bounds__(256) void k_ptc_wgrad(PtcGeom a, int nin, const float4 *__restrict__ xin,
+                                                   const float4 *__restrict__ g, float2 *__restrict__ part) {
     __shared__ C<float> gs[NOUT][kTile][12];
-    __shared__ C<float> ts[kTile][12];
-    const int s = blockIdx.x * kTile + threadIdx.x;
+    __shared__ C<float> ts[4][kTile][12];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
+    const int s = blockIdx.x * kTile + lane;
     const bool on = s < 2 * a.g.vh;
     const int p = on && s >= a.g.vh;
     const uint32_t i = on ? (uint32_t)(s - p * a.g.vh) : 0u;
     int x[4] = {0, 0, 0, 0};
     if (on) site_coords(a.g, (int)i, p, x);
     const size_t chan4 = a.chan / 4, hv = (size_t)6 * a.g.vhp;
-#pragma unroll
-    for (int c = 0; c < NOUT; ++c) {
+    for (int c = wave; c < NOUT; c += 4) {
         float r[24];
         if (on) load_field<float, 24>(g + c * chan4 + p * hv, i, r);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) gs[c][threadIdx.x][k] = on ? mk(r[2 * k], r[2 * k + 1]) : mk(0.f, 0.f);
+        for (int k = 0; k < 12; ++k) gs[c][lane][k] = on ? mk(r[2 * k], r[2 * k + 1]) : mk(0.f, 0.f);
     }
-    const int nout_st = NOUT * 16;  // outputs (c, s, t) of one (path, c') pair
+    const int npair = kPaths * nin;
 #pragma nounroll
-    for (int cp = 0; cp < nin; ++cp) {
-#pragma nounroll
-        for (int path = 0; path < kPaths; ++path) {
-            C<float> t[12];
-            if (on) transport_site(a, xin + cp * chan4, p, i, x, path, t);
-            __syncthreads();
+    for (int base = 0; base < npair; base += 4) {
+        const int pr = base + wave;
+        const int path = pr / nin, cp = pr % nin;
+        C<float> t[12];
+        if (on && pr < npair) {
+            transport_site(a, xin + cp * chan4, p, i, x, path, t);
+        } else {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) ts[threadIdx.x][k] = on ? t[k] : mk(0.f, 0.f);
-            __syncthreads();
-            for (int o = threadIdx.x; o < nout_st; o += kTile) {
+            for (int k = 0; k < 12; ++k) t[k] = mk(0.f, 0.f);
+        }
+        __syncthreads();  // the previous pairs' reads of ts (and the staging of gs) are done
+#pragma unroll
+        for (int k = 0; k < 12; ++k) ts[wave][lane][k] = t[k];
+        __syncthreads();
+        if (pr < npair) {
+            for (int o = lane; o < NOUT * 16; o += kTile) {
                 const int c = o >> 4, ss = (o >> 2) & 3, tt = o & 3;
                 C<float> acc = mk(0.f, 0.f);
                 for (int xs = 0; xs < kTile; ++xs)
 #pragma unroll
                     for (int col = 0; col < 3; ++col) {
                         // g_c[s, col] conj(t[t, col])
-                        const C<float> gv = gs[c][xs][3 * ss + col], tv = ts[xs][3 * tt + col];
+                        const C<float> gv = gs[c][xs][3 * ss + col], tv = ts[wave][xs][3 * tt + col];
                         acc.r += gv.r * tv.r + gv.i * tv.i;
                         acc.i += gv.i * tv.r - gv.r * tv.i;
                     }
@@ -431,7 +441,7 @@ void layer_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const ui
 }
 template <int NOUT>
 void launch_wgrad(const PtcGeom &a, int nin, const void *x, const void *g, void *part, hipStream_t s) {
-    k_ptc_wgrad<NOUT><<<(2 * a.g.vh + kTile - 1) / kTile, kTile, 0, s>>>(a, nin, (const float4 *)x,
+    k_ptc_wgrad<NOUT><<<(2 * a.g.vh + kTile - 1) / kTile, 256, 0, s>>>(a, nin, (const float4 *)x,
                                                                        (const float4 *)g, (float2 *)part);
 }
 void wgrad_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const void *g, void *part, hipStream_t s) {
