@@ -38,6 +38,9 @@ HOP_SHAPES = ["k_hop bs256 xcd-order", "k_hop bs256", "k_hop bs128 xcd-order", "
               "k_hop_ps bs256 2/CU (XCD slab sweep)", "k_hop_ps bs128 2/CU (XCD slab sweep)",
               "k_hop_p bs256 1/CU 2 neighbours/iteration (persistent)",
               "k_hop_p bs256 2/CU 2 neighbours/iteration (persistent)",
+              "k_hop_p bs256 1/CU streaming hints (persistent)",
+              "k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persistent)",
+              "k_hop_p bs256 2/CU streaming hints (persistent)",
               "k_hop bs256 3 waves/SIMD", "k_hop bs128 3 waves/SIMD"]
 
 
@@ -309,15 +312,18 @@ def main():
     y = torch.empty_like(x)
     torch.cuda.synchronize()
 
-    if args.copy_calibration:
-        # a plain copy of exactly 768 MiB read + 768 MiB written per launch, to scale the
-        # FETCH_SIZE / WRITE_SIZE counters of a profiled run
-        src = torch.ones(768 * 2**20 // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    # a plain device copy of exactly 768 MiB read + 768 MiB written per launch: its rate is the
+    # practical ceiling of a streaming kernel, and in a profiled run (--copy-calibration, five
+    # copies) it scales the FETCH_SIZE / WRITE_SIZE counters
+    src = torch.ones(768 * 2**20 // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ncopy = 5 if args.copy_calibration else 10
+    t_copy = timed(lambda: dst.copy_(src), ncopy, stream)
+    copy_gbs = 2 * src.numel() * 8 * ncopy / t_copy / 1e9
+    log(f"[bench] device copy 768 MiB: {copy_gbs:.0f} GB/s (read + write)")
+    del src, dst
+    torch.cuda.synchronize()
 
     # ---- timed region: K Schur applies (FP64, NATIVE)
     schur = lambda: D.apply_eo(ye, xe, "f64", "native")  # noqa: E731
@@ -352,7 +358,7 @@ def main():
         log(f"[bench] tuner choice not readable: {e}")
     # every launch shape of the hop kernel, FP64 Schur (the tuner's choice is what the timed loop used)
     shapes = {}
-    for shape in range(19):
+    for shape in range(22):
         os.environ["DIRAC_HOP_SHAPE"] = str(shape)
         for _ in range(3):
             schur()
@@ -453,6 +459,7 @@ def main():
                      "traffic_over_algorithmic": (round(traffic / (CLOV_HOP_REALS * 8 * vh), 3)
                                                   if traffic else None)},
         "schur_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+        "device_copy_GBps": round(copy_gbs, 1),
         "gflops_schur": round(FLOP_SCHUR * vh * args.steps / t_schur / 1e9, 1),
         **extra,
         "solve": solves,

@@ -123,6 +123,44 @@ DEV void store_planes(typename St<S>::vec *__restrict__ base, int np, int p0, ui
     for (int k = 0; k < N / W; ++k) q[k * kSB] = St<S>::pack(o + k * W);
 }
 // whole-field shorthands: N reals per site in N / W planes
+// Loads and stores with a non-temporal (streaming) hint, for data a kernel touches once, so that
+// it does not displace data that other work-items of the kernel read again from the caches.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+template <int B> struct RawOf;
+template <> struct RawOf<16> { using type = u32x4_t; };
+template <> struct RawOf<8> { using type = u32x2_t; };
+template <typename V> DEV V ld_stream(const V *p) {
+    using R = typename RawOf<sizeof(V)>::type;
+    return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const R *>(p)));
+}
+DEV double ld_stream(const double *p) { return __builtin_nontemporal_load(p); }
+DEV float ld_stream(const float *p) { return __builtin_nontemporal_load(p); }
+template <typename V> DEV void st_stream(V *p, const V &v) {
+    using R = typename RawOf<sizeof(V)>::type;
+    __builtin_nontemporal_store(__builtin_bit_cast(R, v), reinterpret_cast<R *>(p));
+}
+
+template <typename S, int N, bool NT>
+DEV void load_planes_h(const typename St<S>::vec *__restrict__ base, int np, int p0, uint32_t s,
+                       typename St<S>::acc *o) {
+    constexpr int W = St<S>::W;
+    const typename St<S>::vec *q = site_ptr(base, s, np) + p0 * kSB;
+#pragma unroll
+    for (int k = 0; k < N / W; ++k) St<S>::unpack(NT ? ld_stream(q + k * kSB) : q[k * kSB], o + k * W);
+}
+template <typename S, int N, bool NT>
+DEV void store_field_h(typename St<S>::vec *__restrict__ base, uint32_t s, const typename St<S>::acc *o) {
+    constexpr int W = St<S>::W;
+    typename St<S>::vec *q = site_ptr(base, s, N / W);
+#pragma unroll
+    for (int k = 0; k < N / W; ++k) {
+        const typename St<S>::vec v = St<S>::pack(o + k * W);
+        if constexpr (NT) st_stream(q + k * kSB, v);
+        else q[k * kSB] = v;
+    }
+}
+
 template <typename S, int N>
 DEV void load_field(const typename St<S>::vec *__restrict__ base, uint32_t s, typename St<S>::acc *o) {
     load_planes<S, N>(base, N / St<S>::W, 0, s, o);

@@ -44,7 +44,7 @@ DEV void load_spinor(const typename St<S>::vec *__restrict__ base, uint32_t s, C
     for (int k = 0; k < 12; ++k) psi[k] = mk(r[2 * k], r[2 * k + 1]);
 }
 
-template <typename S>
+template <typename S, bool NT>
 DEV void load_link(const HopArgs<S> &a, int dir, uint32_t i, C<typename St<S>::acc> u[6], typename St<S>::acc &co,
                    typename St<S>::acc &si) {
     using T = typename St<S>::acc;
@@ -55,10 +55,11 @@ DEV void load_link(const HopArgs<S> &a, int dir, uint32_t i, C<typename St<S>::a
     const LV *b = site_ptr(a.links + (size_t)dir * (12 / W) * vhp, i, 12 / W);
     T r[12];
 #pragma unroll
-    for (int k = 0; k < 12 / W; ++k) Lk<S>::unpack(b[k * kSB], r + k * W);
+    for (int k = 0; k < 12 / W; ++k) Lk<S>::unpack(NT ? ld_stream(b + k * kSB) : b[k * kSB], r + k * W);
 #pragma unroll
     for (int k = 0; k < 6; ++k) u[k] = mk(r[2 * k], r[2 * k + 1]);
-    const T w = (T)a.omega[(size_t)dir * vhp + i];
+    const OM *om = a.omega + (size_t)dir * vhp + i;
+    const T w = (T)(NT ? ld_stream(om) : *om);
     sc(w, si, co);
 }
 
@@ -74,7 +75,7 @@ DEV C<T> cmul_unit(T cr, T ci, C<T> z) { return mk(cr * z.r - ci * z.i, cr * z.i
 // index of its (x0, x1, x2) row), accumulated into acc.  With `tile` the time-direction neighbour
 // comes from LDS: slot `tslot` - 1 / + 1 of the tile holds the input block of the previous / next
 // time slice at the same spatial block, and the neighbour sits at the same lane.
-template <typename S, int DAG>
+template <typename S, int DAG, bool NT>
 DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n, C<typename St<S>::acc> acc[12],
                  const typename St<S>::vec *tile, int tslot) {
     using T = typename St<S>::acc;
@@ -103,7 +104,7 @@ DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n
         h[c] = mk(fma(sg, e0.r, psi[c].r), fma(sg, e0.i, psi[c].i));
         h[3 + c] = mk(fma(sg, e1.r, psi[3 + c].r), fma(sg, e1.i, psi[3 + c].i));
     }
-    load_link(a, n, i, u, co, si);
+    load_link<S, NT>(a, n, i, u, co, si);
     if (back) link_adj_mul(u, co, si, h, w);
     else link_mul(u, co, si, h, w);
 #pragma unroll
@@ -124,18 +125,18 @@ DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n
 // NPI = 1 keeps one neighbour's data live at a time; NPI = 2 takes the forward and backward
 // neighbour of one mu per iteration, so each wave has twice the loads in flight.  The sums are
 // accumulated in the same order either way.
-template <typename S, int DAG, int NPI>
+template <typename S, int DAG, int NPI, bool NT>
 DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<S>::acc> acc[12],
                  const typename St<S>::vec *tile = nullptr, int tslot = 0) {
     const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
     if constexpr (NPI == 1) {
 #pragma nounroll
-        for (int n = 0; n < 8; ++n) hop_dir<S, DAG>(a, x, row, i, n, acc, tile, tslot);
+        for (int n = 0; n < 8; ++n) hop_dir<S, DAG, NT>(a, x, row, i, n, acc, tile, tslot);
     } else {
 #pragma nounroll
         for (int mu = 0; mu < 4; ++mu) {
-            hop_dir<S, DAG>(a, x, row, i, 2 * mu, acc, tile, tslot);
-            hop_dir<S, DAG>(a, x, row, i, 2 * mu + 1, acc, tile, tslot);
+            hop_dir<S, DAG, NT>(a, x, row, i, 2 * mu, acc, tile, tslot);
+            hop_dir<S, DAG, NT>(a, x, row, i, 2 * mu + 1, acc, tile, tslot);
         }
     }
 }
@@ -146,7 +147,8 @@ DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<
 // fastest (see tune.cpp).
 // Everything of one output site after the work assignment: the 8 neighbours, the scale, the
 // clover epilogue / prologue and the store.
-template <typename S, int DAG, int MODE, int NPI = 1>
+// NT: links, clover field, chi and the output, each touched once, carry a streaming hint.
+template <typename S, int DAG, int MODE, int NPI = 1, bool NT = false>
 DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, int tslot) {
     using T = typename St<S>::acc;
     const uint32_t i = (uint32_t)ii;
@@ -155,7 +157,7 @@ DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, 
     C<T> acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = mk(T(0), T(0));
-    hop_all<S, DAG, NPI>(a, x, i, acc, tile, tslot);
+    hop_all<S, DAG, NPI, NT>(a, x, i, acc, tile, tslot);
     C<T> y[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) y[k] = a.coef * acc[k];
@@ -167,14 +169,19 @@ DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, 
         constexpr bool split = (36 % W) == 0;
         T pk[split ? 36 : 72];
         C<T> t[6], chi[12];
-        if constexpr (MODE == HOP_CLOV) load_spinor<S>(a.chi, i, chi);
+        if constexpr (MODE == HOP_CLOV) {
+            T cr[24];
+            load_planes_h<S, 24, NT>(a.chi, 24 / W, 0, i, cr);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) chi[k] = mk(cr[2 * k], cr[2 * k + 1]);
+        }
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) {
             const T *q = pk;
             if constexpr (split) {
-                load_planes<S, 36>(a.clov, 72 / W, blk * (36 / W), i, pk);
+                load_planes_h<S, 36, NT>(a.clov, 72 / W, blk * (36 / W), i, pk);
             } else {
-                if (blk == 0) load_field<S, 72>(a.clov, i, pk);
+                if (blk == 0) load_planes_h<S, 72, NT>(a.clov, 72 / W, 0, i, pk);
                 q = pk + 36 * blk;
             }
             if constexpr (MODE == HOP_INV) {
@@ -191,7 +198,7 @@ DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, 
     T r[24];
 #pragma unroll
     for (int k = 0; k < 12; ++k) { r[2 * k] = y[k].r; r[2 * k + 1] = y[k].i; }
-    store_field<S, 24>(a.out, i, r);
+    store_field_h<S, 24, NT>(a.out, i, r);
 }
 
 template <typename S, int DAG, int MODE, int BS, int WPE>
@@ -218,7 +225,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
 // is set by the grid rather than by the register-limited occupancy.
 // With XCD the grid (a multiple of 8) is split by XCD instead: the work-groups of XCD k sweep
 // the k-th contiguous eighth of the logical blocks.
-template <typename S, int DAG, int MODE, int BS, int XCD, int NPI>
+template <typename S, int DAG, int MODE, int BS, int XCD, int NPI, bool NT>
 __global__ __launch_bounds__(BS) void k_hop_p(HopArgs<S> a, int nlog) {
     const int region = XCD ? (nlog + 7) >> 3 : nlog;
     const int first = XCD ? (int)(blockIdx.x & 7) * region : 0;
@@ -237,7 +244,7 @@ __global__ __launch_bounds__(BS) void k_hop_p(HopArgs<S> a, int nlog) {
             b.out += rhs * a.vs;
             if (b.chi) b.chi += rhs * a.vs;
         }
-        hop_site<S, DAG, MODE, NPI>(b, ii, nullptr, 0);
+        hop_site<S, DAG, MODE, NPI, NT>(b, ii, nullptr, 0);
     }
 }
 
@@ -343,17 +350,18 @@ __global__ __launch_bounds__(64 * TT) void k_hop_tp(HopArgs<S> a, int nwg) {
 }
 
 struct HopShape {
-    int bs, wpe, xcd, tt, pers, slab, npi;
+    int bs, wpe, xcd, tt, pers, slab, npi, nt;
 };
 // shape 0 is the default; shapes with tt > 0 are the time-tiled kernel (bs = 64 tt); pers > 0 is
 // the persistent kernel with pers work-groups per compute unit; occupancy hints (wpe, FP64 only,
 // where the default leaves fewer than 4 waves per SIMD) come last
 const HopShape kShapes[] = {
-    {256, 0, 1, 0, 0, 0, 1}, {256, 0, 0, 0, 0, 0, 1}, {128, 0, 1, 0, 0, 0, 1}, {64, 0, 1, 0, 0, 0, 1},
-    {256, 0, 1, 4, 0, 0, 1}, {512, 0, 1, 8, 0, 0, 1}, {256, 0, 0, 0, 1, 0, 1}, {512, 0, 0, 0, 1, 0, 1},
-    {256, 0, 0, 0, 2, 0, 1}, {256, 0, 1, 0, 1, 0, 1}, {256, 0, 0, 4, 1, 0, 1}, {512, 0, 0, 8, 1, 0, 1},
-    {256, 0, 0, 0, 1, 1, 1}, {256, 0, 0, 0, 2, 1, 1}, {128, 0, 0, 0, 2, 1, 1}, {256, 0, 0, 0, 1, 0, 2},
-    {256, 0, 0, 0, 2, 0, 2}, {256, 3, 1, 0, 0, 0, 1}, {128, 3, 1, 0, 0, 0, 1}};
+    {256, 0, 1, 0, 0, 0, 1, 0}, {256, 0, 0, 0, 0, 0, 1, 0}, {128, 0, 1, 0, 0, 0, 1, 0}, {64, 0, 1, 0, 0, 0, 1, 0},
+    {256, 0, 1, 4, 0, 0, 1, 0}, {512, 0, 1, 8, 0, 0, 1, 0}, {256, 0, 0, 0, 1, 0, 1, 0}, {512, 0, 0, 0, 1, 0, 1, 0},
+    {256, 0, 0, 0, 2, 0, 1, 0}, {256, 0, 1, 0, 1, 0, 1, 0}, {256, 0, 0, 4, 1, 0, 1, 0}, {512, 0, 0, 8, 1, 0, 1, 0},
+    {256, 0, 0, 0, 1, 1, 1, 0}, {256, 0, 0, 0, 2, 1, 1, 0}, {128, 0, 0, 0, 2, 1, 1, 0}, {256, 0, 0, 0, 1, 0, 2, 0},
+    {256, 0, 0, 0, 2, 0, 2, 0}, {256, 0, 0, 0, 1, 0, 1, 1}, {256, 0, 0, 0, 1, 0, 2, 1}, {256, 0, 0, 0, 2, 0, 1, 1},
+    {256, 3, 1, 0, 0, 0, 1, 0}, {128, 3, 1, 0, 0, 0, 1, 0}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 template <typename S> constexpr int num_shapes() { return std::is_same<S, double>::value ? kNumShapes : kNumShapes - 2; }
 
@@ -385,15 +393,15 @@ void launch_shape(HopArgs<S> a, int xcd, hipStream_t s) {
     k_hop<S, DAG, MODE, BS, WPE><<<a.nb8, BS, 0, s>>>(a);
 }
 
-template <typename S, int DAG, int MODE, int BS, int NPI = 1>
+template <typename S, int DAG, int MODE, int BS, int NPI = 1, bool NT = false>
 void launch_persistent(HopArgs<S> a, int per_cu, int xcd, hipStream_t s) {
     const int nlog = (a.g.vh + BS - 1) / BS * a.nrhs;
     int grid = std::min(nlog, per_cu * compute_units());
     if (xcd) grid = std::max(8, grid & ~7);
     a.xcd = xcd;
     a.nb8 = grid;
-    if (xcd) k_hop_p<S, DAG, MODE, BS, 1, NPI><<<grid, BS, 0, s>>>(a, nlog);
-    else k_hop_p<S, DAG, MODE, BS, 0, NPI><<<grid, BS, 0, s>>>(a, nlog);
+    if (xcd) k_hop_p<S, DAG, MODE, BS, 1, NPI, NT><<<grid, BS, 0, s>>>(a, nlog);
+    else k_hop_p<S, DAG, MODE, BS, 0, NPI, NT><<<grid, BS, 0, s>>>(a, nlog);
 }
 
 template <typename S, int DAG, int MODE, int BS>
@@ -441,7 +449,9 @@ void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
         case 12: case 13: launch_slab<S, DAG, MODE, 256>(a, h.pers, s); break;
         case 14: launch_slab<S, DAG, MODE, 128>(a, h.pers, s); break;
         case 15: case 16: launch_persistent<S, DAG, MODE, 256, 2>(a, h.pers, 0, s); break;
-        case 17:
+        case 17: case 19: launch_persistent<S, DAG, MODE, 256, 1, true>(a, h.pers, 0, s); break;
+        case 18: launch_persistent<S, DAG, MODE, 256, 2, true>(a, h.pers, 0, s); break;
+        case 20:
             if constexpr (std::is_same<S, double>::value) launch_shape<S, DAG, MODE, 256, 3>(a, h.xcd, s);
             break;
         default:
