@@ -17,6 +17,10 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit fusing of a * b + c: which products the compiler would fuse depends on the
+    # surrounding code, so kernel variants computing the same sums (the hop kernel's launch
+    # shapes) could differ in the last bit; fused multiply-adds are written out as fma()
+    "-ffp-contract=off",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]

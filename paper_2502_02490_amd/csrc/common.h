@@ -19,12 +19,12 @@ template <typename T> DEV cx<T> mk(T r, T i) { return cx<T>{r, i}; }
 template <typename T> DEV cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
 template <typename T> DEV cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
 template <typename T> DEV cx<T> operator-(cx<T> a) { return {-a.r, -a.i}; }
-template <typename T> DEV cx<T> operator*(cx<T> a, cx<T> b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+template <typename T> DEV cx<T> operator*(cx<T> a, cx<T> b) { return {fma(a.r, b.r, -a.i * b.i), fma(a.r, b.i, a.i * b.r)}; }
 template <typename T> DEV cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
 template <typename T> DEV cx<T> conj(cx<T> a) { return {a.r, -a.i}; }
 template <typename T> DEV cx<T> times_i(cx<T> a) { return {-a.i, a.r}; }      // i a
 template <typename T> DEV cx<T> times_mi(cx<T> a) { return {a.i, -a.r}; }     // -i a
-template <typename T> DEV cx<T> conj_mul(cx<T> a, cx<T> b) { return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r}; }  // conj(a) b
+template <typename T> DEV cx<T> conj_mul(cx<T> a, cx<T> b) { return {fma(a.r, b.r, a.i * b.i), fma(a.r, b.i, -a.i * b.r)}; }  // conj(a) b
 template <typename T> DEV void madd(cx<T> &acc, cx<T> a, cx<T> b) {  // acc += a b
     acc.r = fma(a.r, b.r, acc.r); acc.r = fma(-a.i, b.i, acc.r);
     acc.i = fma(a.r, b.i, acc.i); acc.i = fma(a.i, b.r, acc.i);
