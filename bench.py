@@ -397,6 +397,19 @@ def main():
         th_ = timed(sh, args.steps, stream)
         extra[f"schur_{pr}_GBps"] = round(SCHUR_REALS * 2 * vh * args.steps / th_ / 1e9, 1)
         extra[f"schur_{pr}_us"] = round(th_ / args.steps * 1e6, 1)
+    # 12 right-hand sides at once (FP32): links and clover read once per site block for all of
+    # them; algorithmic bytes per even site 12 x 120 spinor reals + 208 link + 144 clover reals
+    nr = 12
+    x12 = torch.cat([xe32] * nr)
+    y12 = torch.empty_like(x12)
+    m12 = lambda: D.apply_eo_multi(y12, x12, nr, "f32")  # noqa: E731
+    for _ in range(3):
+        m12()
+    t12 = timed(m12, max(10, args.steps // 4), stream) / max(10, args.steps // 4)
+    extra["schur_f32_12rhs_us_per_rhs"] = round(t12 / nr * 1e6, 1)
+    extra["schur_f32_12rhs_GBps"] = round((nr * 120 + 352) * 4 * vh / t12 / 1e9, 1)
+    extra["schur_f32_12rhs_speedup_per_rhs"] = round(extra["schur_f32_us"] / extra["schur_f32_12rhs_us_per_rhs"], 2)
+    del x12, y12
     # standalone hop and clover (FP64)
     ho = torch.empty_like(xe)
     hop = lambda: D.apply_hop(ho, xe, 1, "f64")  # noqa: E731

@@ -151,6 +151,15 @@ dirac_status dirac_apply(dirac_ctx *ctx, void *out, const void *in, dirac_prec p
 dirac_status dirac_apply_eo(dirac_ctx *ctx, void *out_e, const void *in_e, dirac_prec prec, dirac_layout layout,
                             int dagger, void *stream);
 
+/* D-hat on nrhs even half-vectors at once (the paper solves many right-hand sides on one gauge
+ * field, Sec. 2): in and out hold nrhs NATIVE half vectors of `prec` back to back (vector r
+ * starts r * dirac_native_bytes(ctx, prec, 1) bytes after the base), out must not overlap in.
+ * Each kernel covers all right-hand sides in one launch, so every link and clover entry is
+ * read from HBM once per site block and served to the others from L2.  Results equal nrhs
+ * calls of dirac_apply_eo bit for bit.  Asynchronous on `stream`. */
+dirac_status dirac_apply_eo_multi(dirac_ctx *ctx, void *out, const void *in, int nrhs, dirac_prec prec, int dagger,
+                                  void *stream);
+
 /* out_p = D_{p,1-p} in_{1-p} = -1/2 H in (the hopping term between parities), NATIVE
  * half-vectors; out_parity selects p.  dagger = 1 gives gamma_5 D_{p,1-p} gamma_5. */
 dirac_status dirac_apply_hop(dirac_ctx *ctx, void *out, const void *in, int out_parity, dirac_prec prec,

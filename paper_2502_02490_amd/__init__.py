@@ -145,6 +145,13 @@ class Dirac:
                                            int(dagger), _stream(stream)))
         return out
 
+    def apply_eo_multi(self, out, inp, nrhs: int, prec="f64", dagger=False, stream=None):
+        """out[r] = D-hat inp[r] for nrhs NATIVE half vectors stored back to back."""
+        nb = self.native_bytes(prec, 1) * int(nrhs)
+        _lib.check(self.lib.dirac_apply_eo_multi(self._ctx, _ptr(out, nb), _ptr(inp, nb), int(nrhs), _prec(prec),
+                                                 int(dagger), _stream(stream)))
+        return out
+
     def apply_hop(self, out, inp, out_parity: int, prec="f64", dagger=False, stream=None):
         """out_p = D_{p,1-p} inp = -1/2 H inp (NATIVE half-vectors)."""
         nb = self.native_bytes(prec, 1)

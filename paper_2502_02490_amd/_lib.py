@@ -16,7 +16,7 @@ CGLS, GCR, MIXED_GCR, FGCR_PTC, FGCR_PTC_EO = 0, 1, 2, 3, 4
 
 # every symbol declared in include/dirac.h
 EXPORTS = ["dirac_create", "dirac_destroy", "dirac_load_clover", "dirac_get_clover", "clover_invert",
-           "dirac_native_bytes", "dirac_import", "dirac_export", "dirac_apply", "dirac_apply_eo",
+           "dirac_native_bytes", "dirac_import", "dirac_export", "dirac_apply", "dirac_apply_eo", "dirac_apply_eo_multi",
            "dirac_apply_hop", "dirac_apply_clover", "dirac_solve", "dirac_solve_batched", "dirac_last_error",
            "ptc_create", "ptc_destroy", "ptc_num_weights", "ptc_set_weights", "ptc_get_weights", "ptc_get_grad",
            "ptc_zero_grad", "ptc_forward", "ptc_backward", "ptc_adam_step", "ptc_get_adam_state", "ptc_set_adam_state",
@@ -70,6 +70,7 @@ def load(path: str = LIB_PATH):
     lib.dirac_export.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_apply.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_apply_eo.argtypes = [vp, vp, vp, i, i, i, vp]
+    lib.dirac_apply_eo_multi.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_apply_hop.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_apply_clover.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(SolverParams), ctypes.POINTER(SolveInfo), vp]

@@ -288,6 +288,20 @@ dirac_status dirac_apply_eo(dirac_ctx *c, void *out, const void *in, dirac_prec 
     API_END
 }
 
+dirac_status dirac_apply_eo_multi(dirac_ctx *c, void *out, const void *in, int nrhs, dirac_prec pr, int dagger,
+                                  void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_prec(pr);
+    require(nrhs >= 1 && nrhs <= 4096, "nrhs must be 1..4096");
+    const size_t nb = native_bytes(c, pr, 1) * (size_t)nrhs;
+    check_dev(in, nb, "in");
+    check_dev(out, nb, "out");
+    check_no_alias(out, nb, in, nb);
+    dl::schur_apply(c, out, in, dagger != 0, pr, (hipStream_t)stream, nrhs, nullptr);
+    API_END
+}
+
 dirac_status dirac_apply_hop(dirac_ctx *c, void *out, const void *in, int out_parity, dirac_prec pr, int dagger,
                              void *stream) {
     API_BEGIN
