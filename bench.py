@@ -30,34 +30,33 @@ FLOP_SCHUR, FLOP_HOP, FLOP_CLOVER = 3672, 1320, 504
 
 
 # launch shapes of the hop kernel, in the library's order (index = the tuner's choice)
-HOP_SHAPES = ["k_hop bs256 xcd-order", "k_hop bs256", "k_hop bs128 xcd-order", "k_hop bs64 xcd-order",
-              "k_hop_t tt4 (time-tiled LDS)", "k_hop_t tt8 (time-tiled LDS)", "k_hop_p bs256 1/CU (persistent)",
-              "k_hop_p bs512 1/CU (persistent)", "k_hop_p bs256 2/CU (persistent)",
-              "k_hop_p bs256 1/CU xcd-regions (persistent)", "k_hop_tp tt4 1/CU (persistent time-tiled)",
-              "k_hop_tp tt8 1/CU (persistent time-tiled)", "k_hop_ps bs256 1/CU (XCD slab sweep)",
-              "k_hop_ps bs256 2/CU (XCD slab sweep)", "k_hop_ps bs128 2/CU (XCD slab sweep)",
-              "k_hop_p bs256 1/CU 2 neighbours/iteration (persistent)",
-              "k_hop_p bs256 2/CU 2 neighbours/iteration (persistent)",
-              "k_hop_p bs256 1/CU streaming hints (persistent)",
-              "k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persistent)",
-              "k_hop_p bs256 2/CU streaming hints (persistent)",
-              "k_hop bs256 3 waves/SIMD", "k_hop bs128 3 waves/SIMD"]
-
+HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persistent)",
+              "k_hop_p bs256 1/CU streaming hints (persistent)", "k_hop_p bs256 2/CU streaming hints (persistent)",
+              "k_hop_p bs256 1/CU (persistent)", "k_hop_p bs256 1/CU 2 neighbours/iteration (persistent)",
+              "k_hop bs256 xcd-order", "k_hop bs256", "k_hop bs128 xcd-order", "k_hop bs64 xcd-order",
+              "k_hop_t tt4 (time-tiled LDS)", "k_hop_t tt8 (time-tiled LDS)", "k_hop_p bs512 1/CU (persistent)",
+              "k_hop_p bs256 2/CU (persistent)", "k_hop_p bs256 1/CU xcd-regions (persistent)",
+              "k_hop_tp tt4 1/CU (persistent time-tiled)", "k_hop_tp tt8 1/CU (persistent time-tiled)",
+              "k_hop_ps bs256 1/CU (XCD slab sweep)", "k_hop_ps bs256 2/CU (XCD slab sweep)",
+              "k_hop_ps bs128 2/CU (XCD slab sweep)", "k_hop_p bs256 2/CU 2 neighbours/iteration (persistent)"]
 
 # HBM bytes per launch of the FP64 hop + A chi kernel on 32^3 x 64 (calibrated FETCH_SIZE +
 # WRITE_SIZE from rocprofv3 counter runs; summary and commands in
 # profiles/hop_fp64_32c64_hbm_traffic.txt), by launch shape.  A shape missing here, or a kernel
 # changed since the counters were taken, reports null.
 HOP_CLOV_TRAFFIC_32C64 = {
-    "k_hop_p bs256 1/CU (persistent)": 2.610e9 + 0.201e9,
-    "k_hop_p bs256 1/CU 2 neighbours/iteration (persistent)": 2.637e9 + 0.201e9,
-    "k_hop_p bs512 1/CU (persistent)": 2.926e9 + 0.201e9,
-    "k_hop_p bs256 1/CU xcd-regions (persistent)": 2.355e9 + 0.201e9,
-    "k_hop_ps bs256 1/CU (XCD slab sweep)": 2.342e9 + 0.201e9,
-    "k_hop_ps bs128 2/CU (XCD slab sweep)": 2.397e9 + 0.201e9,
-    "k_hop_tp tt4 1/CU (persistent time-tiled)": 2.314e9 + 0.201e9,
-    "k_hop_t tt4 (time-tiled LDS)": 2.546e9 + 0.201e9,
-    "k_hop_t tt8 (time-tiled LDS)": 2.646e9 + 0.201e9,
+    "k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persistent)": 2.479e9 + 0.201e9,
+    "k_hop_p bs256 1/CU streaming hints (persistent)": 2.477e9 + 0.201e9,
+    "k_hop_p bs256 2/CU streaming hints (persistent)": 2.620e9 + 0.201e9,
+    "k_hop_p bs256 1/CU (persistent)": 2.606e9 + 0.201e9,
+    "k_hop_p bs256 1/CU 2 neighbours/iteration (persistent)": 2.624e9 + 0.201e9,
+    "k_hop_p bs512 1/CU (persistent)": 2.938e9 + 0.201e9,
+    "k_hop_p bs256 1/CU xcd-regions (persistent)": 2.376e9 + 0.201e9,
+    "k_hop_ps bs256 1/CU (XCD slab sweep)": 2.348e9 + 0.201e9,
+    "k_hop_ps bs128 2/CU (XCD slab sweep)": 2.423e9 + 0.201e9,
+    "k_hop_tp tt4 1/CU (persistent time-tiled)": 2.320e9 + 0.201e9,
+    "k_hop_t tt4 (time-tiled LDS)": 2.570e9 + 0.201e9,
+    "k_hop_t tt8 (time-tiled LDS)": 2.665e9 + 0.201e9,
 }
 
 
@@ -360,15 +359,15 @@ def main():
     try:
         with open(os.environ["DIRAC_TUNE_CACHE"]) as fh:
             choices = json.load(fh)
-        key = "k_hop|f64|dag0|mode2|" + "x".join(map(str, DIMS)) + "|nrhs1|gfx950"
+        key = "hop-v2|f64|dag0|mode2|" + "x".join(map(str, DIMS)) + "|nrhs1|gfx950"
         chosen = int(choices[key])
         extra["tuned_hop_shapes"] = {k.split("|", 1)[1].rsplit("|", 1)[0]: HOP_SHAPES[v] for k, v in choices.items()
-                                     if k.startswith("k_hop|") and "x".join(map(str, DIMS)) in k}
+                                     if k.startswith("hop-v2|") and "x".join(map(str, DIMS)) in k}
     except (OSError, KeyError, ValueError) as e:
         log(f"[bench] tuner choice not readable: {e}")
     # every launch shape of the hop kernel, FP64 Schur (the tuner's choice is what the timed loop used)
     shapes = {}
-    for shape in range(22):
+    for shape in range(len(HOP_SHAPES)):
         os.environ["DIRAC_HOP_SHAPE"] = str(shape)
         for _ in range(3):
             schur()

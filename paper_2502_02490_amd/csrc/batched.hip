@@ -122,6 +122,10 @@ BOut gcr_batched(Lat &L, dirac_prec pr, void *x, const void *b, const std::vecto
         w.graphs.assign(m, nullptr);
         w.graph_key = key;
     }
+    // the launch-shape tuner cannot time candidates inside a capture: one eager operator
+    // application (on the residual, into basis slot 0, which iteration 0 overwrites) lets it
+    // choose before the graphs are recorded
+    if (use_graph && !w.graphs[0]) schur_apply(c, Q, r, 0, pr, s, R, act);
     auto iteration = [&](int k) {
         char *qk = Q + k * kb;
         schur_apply(c, qk, P + k * kb, 0, pr, s, R, act);

@@ -141,13 +141,11 @@ DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<
     }
 }
 
-// Launch shapes of the hop kernel: work-group size BS and an occupancy hint WPE (minimum waves
-// per SIMD the register allocation must allow; 0 = compiler default).  All shapes compute the
-// same sums in the same order, so their results are bitwise identical; the tuner only picks the
-// fastest (see tune.cpp).
 // Everything of one output site after the work assignment: the 8 neighbours, the scale, the
-// clover epilogue / prologue and the store.
-// NT: links, clover field, chi and the output, each touched once, carry a streaming hint.
+// clover epilogue / prologue and the store.  Every kernel below (the launch shapes) runs this
+// same code per site, so all shapes give bitwise identical results; the tuner only picks the
+// fastest.  NT: links, clover field, chi and the output, each touched once, carry a streaming
+// hint.
 template <typename S, int DAG, int MODE, int NPI = 1, bool NT = false>
 DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, int tslot) {
     using T = typename St<S>::acc;
@@ -201,8 +199,8 @@ DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, 
     store_field_h<S, 24, NT>(a.out, i, r);
 }
 
-template <typename S, int DAG, int MODE, int BS, int WPE>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_hop(HopArgs<S> a) {
+template <typename S, int DAG, int MODE, int BS>
+__global__ __launch_bounds__(BS) void k_hop(HopArgs<S> a) {
     // logical work-group -> (site block, right-hand side), right-hand side fastest so that the
     // right-hand sides of a site block run close in time on one XCD and share its links in L2
     const int lb = a.xcd ? xcd_block(a.nb8) : (int)blockIdx.x;
@@ -350,20 +348,21 @@ __global__ __launch_bounds__(64 * TT) void k_hop_tp(HopArgs<S> a, int nwg) {
 }
 
 struct HopShape {
-    int bs, wpe, xcd, tt, pers, slab, npi, nt;
+    int bs, xcd, tt, pers, slab, npi, nt;
 };
-// shape 0 is the default; shapes with tt > 0 are the time-tiled kernel (bs = 64 tt); pers > 0 is
-// the persistent kernel with pers work-groups per compute unit; occupancy hints (wpe, FP64 only,
-// where the default leaves fewer than 4 waves per SIMD) come last
+// Shape 0 is the default (used when tuning is off, and inside a graph capture before the key
+// was tuned): the persistent sweep, one 256-wide work-group per compute unit, two neighbours per
+// loop iteration, streaming hints.  tt > 0: the time-tiled kernel (bs = 64 tt); pers > 0: a
+// persistent grid of pers work-groups per compute unit (xcd: each XCD sweeps its own eighth);
+// slab: the XCD slab sweep; npi: neighbours per loop iteration; nt: streaming hints.
 const HopShape kShapes[] = {
-    {256, 0, 1, 0, 0, 0, 1, 0}, {256, 0, 0, 0, 0, 0, 1, 0}, {128, 0, 1, 0, 0, 0, 1, 0}, {64, 0, 1, 0, 0, 0, 1, 0},
-    {256, 0, 1, 4, 0, 0, 1, 0}, {512, 0, 1, 8, 0, 0, 1, 0}, {256, 0, 0, 0, 1, 0, 1, 0}, {512, 0, 0, 0, 1, 0, 1, 0},
-    {256, 0, 0, 0, 2, 0, 1, 0}, {256, 0, 1, 0, 1, 0, 1, 0}, {256, 0, 0, 4, 1, 0, 1, 0}, {512, 0, 0, 8, 1, 0, 1, 0},
-    {256, 0, 0, 0, 1, 1, 1, 0}, {256, 0, 0, 0, 2, 1, 1, 0}, {128, 0, 0, 0, 2, 1, 1, 0}, {256, 0, 0, 0, 1, 0, 2, 0},
-    {256, 0, 0, 0, 2, 0, 2, 0}, {256, 0, 0, 0, 1, 0, 1, 1}, {256, 0, 0, 0, 1, 0, 2, 1}, {256, 0, 0, 0, 2, 0, 1, 1},
-    {256, 3, 1, 0, 0, 0, 1, 0}, {128, 3, 1, 0, 0, 0, 1, 0}};
+    {256, 0, 0, 1, 0, 2, 1}, {256, 0, 0, 1, 0, 1, 1}, {256, 0, 0, 2, 0, 1, 1}, {256, 0, 0, 1, 0, 1, 0},
+    {256, 0, 0, 1, 0, 2, 0}, {256, 1, 0, 0, 0, 1, 0}, {256, 0, 0, 0, 0, 1, 0}, {128, 1, 0, 0, 0, 1, 0},
+    {64, 1, 0, 0, 0, 1, 0},  {256, 1, 4, 0, 0, 1, 0}, {512, 1, 8, 0, 0, 1, 0}, {512, 0, 0, 1, 0, 1, 0},
+    {256, 0, 0, 2, 0, 1, 0}, {256, 1, 0, 1, 0, 1, 0}, {256, 0, 4, 1, 0, 1, 0}, {512, 0, 8, 1, 0, 1, 0},
+    {256, 0, 0, 1, 1, 1, 0}, {256, 0, 0, 2, 1, 1, 0}, {128, 0, 0, 2, 1, 1, 0}, {256, 0, 0, 2, 0, 2, 0}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-template <typename S> constexpr int num_shapes() { return std::is_same<S, double>::value ? kNumShapes : kNumShapes - 2; }
+template <typename S> constexpr int num_shapes() { return kNumShapes; }
 
 int compute_units() {
     static int n = 0;
@@ -385,12 +384,12 @@ bool tiled_ok(const Geom &g, int tt) {
     return ns % kSB == 0 && g.L[0] % tt == 0;
 }
 
-template <typename S, int DAG, int MODE, int BS, int WPE>
+template <typename S, int DAG, int MODE, int BS>
 void launch_shape(HopArgs<S> a, int xcd, hipStream_t s) {
     const int nb = (a.g.vh + BS - 1) / BS * a.nrhs;
     a.xcd = xcd;
     a.nb8 = xcd ? (nb + 7) & ~7 : nb;
-    k_hop<S, DAG, MODE, BS, WPE><<<a.nb8, BS, 0, s>>>(a);
+    k_hop<S, DAG, MODE, BS><<<a.nb8, BS, 0, s>>>(a);
 }
 
 template <typename S, int DAG, int MODE, int BS, int NPI = 1, bool NT = false>
@@ -433,30 +432,29 @@ void launch_tiled(HopArgs<S> a, hipStream_t s) {
 
 template <typename S, int DAG, int MODE>
 void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
-    const HopShape h = kShapes[shape];
-    if (h.tt && !tiled_ok(a.g, h.tt)) shape = 0;  // the tile does not fit this lattice
-    if (h.slab && !slab_ok(a.g, h.bs)) shape = 0;
-    switch (shape) {
-        case 0: case 1: launch_shape<S, DAG, MODE, 256, 0>(a, h.xcd, s); break;
-        case 2: launch_shape<S, DAG, MODE, 128, 0>(a, h.xcd, s); break;
-        case 3: launch_shape<S, DAG, MODE, 64, 0>(a, h.xcd, s); break;
-        case 4: launch_tiled<S, DAG, MODE, 4>(a, s); break;
-        case 5: launch_tiled<S, DAG, MODE, 8>(a, s); break;
-        case 6: case 8: case 9: launch_persistent<S, DAG, MODE, 256>(a, h.pers, h.xcd, s); break;
-        case 7: launch_persistent<S, DAG, MODE, 512>(a, h.pers, h.xcd, s); break;
-        case 10: launch_tiled_persistent<S, DAG, MODE, 4>(a, h.pers, s); break;
-        case 11: launch_tiled_persistent<S, DAG, MODE, 8>(a, h.pers, s); break;
-        case 12: case 13: launch_slab<S, DAG, MODE, 256>(a, h.pers, s); break;
-        case 14: launch_slab<S, DAG, MODE, 128>(a, h.pers, s); break;
-        case 15: case 16: launch_persistent<S, DAG, MODE, 256, 2>(a, h.pers, 0, s); break;
-        case 17: case 19: launch_persistent<S, DAG, MODE, 256, 1, true>(a, h.pers, 0, s); break;
-        case 18: launch_persistent<S, DAG, MODE, 256, 2, true>(a, h.pers, 0, s); break;
-        case 20:
-            if constexpr (std::is_same<S, double>::value) launch_shape<S, DAG, MODE, 256, 3>(a, h.xcd, s);
-            break;
-        default:
-            if constexpr (std::is_same<S, double>::value) launch_shape<S, DAG, MODE, 128, 3>(a, h.xcd, s);
-            break;
+    HopShape h = kShapes[shape];
+    if ((h.tt && !tiled_ok(a.g, h.tt)) || (h.slab && !slab_ok(a.g, h.bs))) h = kShapes[0];  // does not fit
+    if (h.tt) {
+        if (h.pers) {
+            if (h.tt == 4) launch_tiled_persistent<S, DAG, MODE, 4>(a, h.pers, s);
+            else launch_tiled_persistent<S, DAG, MODE, 8>(a, h.pers, s);
+        } else {
+            if (h.tt == 4) launch_tiled<S, DAG, MODE, 4>(a, s);
+            else launch_tiled<S, DAG, MODE, 8>(a, s);
+        }
+    } else if (h.slab) {
+        if (h.bs == 256) launch_slab<S, DAG, MODE, 256>(a, h.pers, s);
+        else launch_slab<S, DAG, MODE, 128>(a, h.pers, s);
+    } else if (h.pers) {
+        if (h.bs == 512) launch_persistent<S, DAG, MODE, 512>(a, h.pers, h.xcd, s);
+        else if (h.nt && h.npi == 2) launch_persistent<S, DAG, MODE, 256, 2, true>(a, h.pers, 0, s);
+        else if (h.nt) launch_persistent<S, DAG, MODE, 256, 1, true>(a, h.pers, 0, s);
+        else if (h.npi == 2) launch_persistent<S, DAG, MODE, 256, 2>(a, h.pers, 0, s);
+        else launch_persistent<S, DAG, MODE, 256>(a, h.pers, h.xcd, s);
+    } else {
+        if (h.bs == 256) launch_shape<S, DAG, MODE, 256>(a, h.xcd, s);
+        else if (h.bs == 128) launch_shape<S, DAG, MODE, 128>(a, h.xcd, s);
+        else launch_shape<S, DAG, MODE, 64>(a, h.xcd, s);
     }
 }
 
@@ -492,7 +490,7 @@ void hop_t(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopM
         HIP_CHECK(hipGetLastError());
     };
     char key[160];
-    snprintf(key, sizeof key, "k_hop|%s|dag%d|mode%d|%dx%dx%dx%d|nrhs%d", prec_name(pr), dagger, (int)mode,
+    snprintf(key, sizeof key, "hop-v2|%s|dag%d|mode%d|%dx%dx%dx%d|nrhs%d", prec_name(pr), dagger, (int)mode,
              c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3], nrhs);
     launch(tuned_choice(key, num_shapes<S>(), launch, s));
 }
