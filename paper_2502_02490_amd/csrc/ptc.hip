@@ -103,7 +103,7 @@ DEV void transport_load(const PtcGeom &a, const float4 *xc, int p, uint32_t i, c
     if (path > 0) {
         const float4 *lb = site_ptr(a.flinks[p] + (size_t)n * kFullPlanes * a.g.vhp, i, kFullPlanes);
 #pragma unroll
-        for (int k = 0; k < kFullPlanes; ++k) r.lk[k] = lb[k * kSB];
+        for (int k = 0; k < kFullPlanes; ++k) r.lk[k] = ld_stream(lb + k * kSB);  // read-once stream
     } else {
 #pragma unroll
         for (int k = 0; k < kFullPlanes; ++k) r.lk[k] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -279,7 +279,8 @@ __global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, con
                 for (int col = 0; col < 3; ++col) r[6 * (rr >> 1) + 2 * col + (rr & 1)] = acc[t][col][rr];
             float4 *dst = site_ptr(yout + (size_t)c * chan4 + p * hv, (uint32_t)i, 6) + 3 * (g & 1) * kSB;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) dst[k * kSB] = make_float4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]);
+            for (int k = 0; k < 3; ++k)
+                st_stream(dst + k * kSB, make_float4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]));
         }
     }
 }

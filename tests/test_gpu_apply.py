@@ -207,15 +207,16 @@ def test_multi_rhs_schur_equals_single(case, prec):
     vecs = [case.spinor(40 + r)[case.even] for r in range(3)]
     nats = [D.to_native(to_dev(v.astype(np.complex64) if prec == "f32" else v), prec, "eo", sites=1) for v in vecs]
     inp = torch.cat(nats)
-    out = torch.empty_like(inp)
+    # outputs start zeroed: the padding sites of a NATIVE vector are never written
+    out = torch.zeros_like(inp)
     D.apply_eo_multi(out, inp, 3, prec)
     n = nats[0].numel()
     for r in range(3):
-        one = D.native_empty(prec, 1)
+        one = torch.zeros_like(nats[r])
         D.apply_eo(one, nats[r], prec, "native")
         assert torch.equal(out[r * n:(r + 1) * n], one), r
-    dag = torch.empty_like(inp)
+    dag = torch.zeros_like(inp)
     D.apply_eo_multi(dag, inp, 3, prec, dagger=True)
-    one = D.native_empty(prec, 1)
+    one = torch.zeros_like(nats[2])
     D.apply_eo(one, nats[2], prec, "native", dagger=True)
     assert torch.equal(dag[2 * n:], one)
