@@ -38,7 +38,9 @@ HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persis
               "k_hop_p bs256 2/CU (persistent)", "k_hop_p bs256 1/CU xcd-regions (persistent)",
               "k_hop_tp tt4 1/CU (persistent time-tiled)", "k_hop_tp tt8 1/CU (persistent time-tiled)",
               "k_hop_ps bs256 1/CU (XCD slab sweep)", "k_hop_ps bs256 2/CU (XCD slab sweep)",
-              "k_hop_ps bs128 2/CU (XCD slab sweep)", "k_hop_p bs256 2/CU 2 neighbours/iteration (persistent)"]
+              "k_hop_ps bs128 2/CU (XCD slab sweep)", "k_hop_p bs256 2/CU 2 neighbours/iteration (persistent)",
+              "k_hop_mr 2 RHS/work-item 1/CU streaming hints", "k_hop_mr 4 RHS/work-item 1/CU streaming hints",
+              "k_hop_mr 2 RHS/work-item 2/CU streaming hints"]
 
 # HBM bytes per launch of the FP64 hop + A chi kernel on 32^3 x 64 (calibrated FETCH_SIZE +
 # WRITE_SIZE from rocprofv3 counter runs; summary and commands in
@@ -411,6 +413,13 @@ def main():
     extra["schur_f32_12rhs_us_per_rhs"] = round(t12 / nr * 1e6, 1)
     extra["schur_f32_12rhs_GBps"] = round((nr * 120 + 352) * 4 * vh / t12 / 1e9, 1)
     extra["schur_f32_12rhs_speedup_per_rhs"] = round(extra["schur_f32_us"] / extra["schur_f32_12rhs_us_per_rhs"], 2)
+    by_shape = {}
+    for shape in range(len(HOP_SHAPES)):
+        os.environ["DIRAC_HOP_SHAPE"] = str(shape)
+        m12()
+        by_shape[shape] = round(timed(m12, 10, stream) / 10 / nr * 1e6, 1)
+    del os.environ["DIRAC_HOP_SHAPE"]
+    extra["schur_f32_12rhs_us_per_rhs_by_shape"] = by_shape
     del x12, y12
     # standalone hop and clover (FP64)
     ho = torch.empty_like(xe)

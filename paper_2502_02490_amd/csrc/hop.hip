@@ -71,31 +71,28 @@ DEV void load_link(const HopArgs<S> &a, int dir, uint32_t i, C<typename St<S>::a
 template <typename T>
 DEV C<T> cmul_unit(T cr, T ci, C<T> z) { return mk(cr * z.r - ci * z.i, cr * z.i + ci * z.r); }
 
-// One neighbour direction n = 2 mu + back of the hopping sum at site i (coordinates x, row =
-// index of its (x0, x1, x2) row), accumulated into acc.  With `tile` the time-direction neighbour
-// comes from LDS: slot `tslot` - 1 / + 1 of the tile holds the input block of the previous / next
-// time slice at the same spatial block, and the neighbour sits at the same lane.
-template <typename S, int DAG, bool NT>
-DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n, C<typename St<S>::acc> acc[12],
-                 const typename St<S>::vec *tile, int tslot) {
-    using T = typename St<S>::acc;
+// Index of the neighbour of site (x, row) in direction n = 2 mu + back, in the other parity.
+template <typename S>
+DEV uint32_t neighbour(const HopArgs<S> &a, const int x[4], int row, int n) {
     const int mu = n >> 1, back = n & 1;
     const int xm = mu == 0 ? x[0] : mu == 1 ? x[1] : mu == 2 ? x[2] : x[3];
     const int Lm = mu == 0 ? a.g.L[0] : mu == 1 ? a.g.L[1] : mu == 2 ? a.g.L[2] : a.g.L[3];
     const int xn = back ? (xm == 0 ? Lm - 1 : xm - 1) : (xm + 1 == Lm ? 0 : xm + 1);
     const int rs = mu == 0 ? a.g.L[1] * a.g.L[2] : mu == 1 ? a.g.L[2] : 1;
-    const uint32_t j = mu == 3 ? (uint32_t)(row * a.g.h3 + (xn >> 1))
-                               : (uint32_t)((row + (xn - xm) * rs) * a.g.h3 + (x[3] >> 1));
+    return mu == 3 ? (uint32_t)(row * a.g.h3 + (xn >> 1)) : (uint32_t)((row + (xn - xm) * rs) * a.g.h3 + (x[3] >> 1));
+}
+
+// acc += the direction-n term for the neighbour spinor psi and the link (u, co, si): project to
+// a half-spinor, multiply by the link (or its adjoint), reconstruct.
+template <typename T, int DAG>
+DEV void accumulate_dir(int n, const C<T> psi[12], const C<T> u[6], T co, T si, C<T> acc[12]) {
+    const int mu = n >> 1, back = n & 1;
     // projector sign: forward (1 + SF gamma), backward (1 - SF gamma); SF = -1 for D, +1 for D^dag
     const T sg = (DAG ? T(1) : T(-1)) * (back ? T(-1) : T(1));
     const int sw = (mu == 1 || mu == 2);
     const T c0r = (mu == 0 || mu == 2) ? T(-1) : T(0), c0i = (mu == 1 || mu == 3) ? T(-1) : T(0);
     const T c1r = mu == 0 ? T(-1) : mu == 2 ? T(1) : T(0), c1i = mu == 1 ? T(-1) : mu == 3 ? T(1) : T(0);
-    C<T> psi[12], h[6], u[6], w[6];
-    T co, si;
-    if (tile && mu == 0) load_spinor<S>(tile + (size_t)(tslot + (back ? -1 : 1)) * (24 / St<S>::W) * kSB,
-                                        i & (kSB - 1), psi);
-    else load_spinor<S>(a.in, j, psi);
+    C<T> h[6], w[6];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const C<T> l0 = psi[6 + c], l1 = psi[9 + c];
@@ -104,7 +101,6 @@ DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n
         h[c] = mk(fma(sg, e0.r, psi[c].r), fma(sg, e0.i, psi[c].i));
         h[3 + c] = mk(fma(sg, e1.r, psi[3 + c].r), fma(sg, e1.i, psi[3 + c].i));
     }
-    load_link<S, NT>(a, n, i, u, co, si);
     if (back) link_adj_mul(u, co, si, h, w);
     else link_mul(u, co, si, h, w);
 #pragma unroll
@@ -117,6 +113,24 @@ DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n
         acc[6 + c] = mk(fma(sg, l0.r, acc[6 + c].r), fma(sg, l0.i, acc[6 + c].i));
         acc[9 + c] = mk(fma(sg, l1.r, acc[9 + c].r), fma(sg, l1.i, acc[9 + c].i));
     }
+}
+
+// One neighbour direction n = 2 mu + back of the hopping sum at site i (coordinates x, row =
+// index of its (x0, x1, x2) row), accumulated into acc.  With `tile` the time-direction neighbour
+// comes from LDS: slot `tslot` - 1 / + 1 of the tile holds the input block of the previous / next
+// time slice at the same spatial block, and the neighbour sits at the same lane.
+template <typename S, int DAG, bool NT>
+DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n, C<typename St<S>::acc> acc[12],
+                 const typename St<S>::vec *tile, int tslot) {
+    using T = typename St<S>::acc;
+    const int mu = n >> 1, back = n & 1;
+    C<T> psi[12], u[6];
+    T co, si;
+    if (tile && mu == 0) load_spinor<S>(tile + (size_t)(tslot + (back ? -1 : 1)) * (24 / St<S>::W) * kSB,
+                                        i & (kSB - 1), psi);
+    else load_spinor<S>(a.in, neighbour(a, x, row, n), psi);
+    load_link<S, NT>(a, n, i, u, co, si);
+    accumulate_dir<T, DAG>(n, psi, u, co, si, acc);
 }
 
 // The 8 neighbours run as iterations of a loop that is not unrolled, with the direction a
@@ -246,6 +260,122 @@ __global__ __launch_bounds__(BS) void k_hop_p(HopArgs<S> a, int nlog) {
     }
 }
 
+// Several right-hand sides per work-item: work-item (site, chunk) computes right-hand sides
+// rhs0 .. rhs0 + NR - 1 of its site, reading each link and the clover block once for all of them
+// (in registers) while every right-hand side's spinors are read exactly as in the one-RHS
+// kernel; the per-right-hand-side sums run in the same order, so the results are bitwise those
+// of the one-RHS kernel.  Right-hand sides at or beyond a.nrhs, or inactive, are skipped.
+template <typename S, int DAG, int MODE, int NR, bool NT>
+DEV void hop_site_mr(const HopArgs<S> &a, int ii, int rhs0) {
+    using T = typename St<S>::acc;
+    using V = typename St<S>::vec;
+    constexpr int W = St<S>::W;
+    const uint32_t i = (uint32_t)ii;
+    int x[4];
+    site_coords(a.g, ii, a.p, x);
+    const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
+    bool on[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) on[r] = rhs0 + r < a.nrhs && (!a.active || a.active[rhs0 + r]);
+    C<T> acc[NR][12];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[r][k] = mk(T(0), T(0));
+#pragma nounroll
+    for (int n = 0; n < 8; ++n) {
+        C<T> u[6];
+        T co, si;
+        load_link<S, NT>(a, n, i, u, co, si);
+        const uint32_t j = neighbour(a, x, row, n);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (!on[r]) continue;
+            C<T> psi[12];
+            load_spinor<S>(a.in + (size_t)(rhs0 + r) * a.vs, j, psi);
+            accumulate_dir<T, DAG>(n, psi, u, co, si, acc[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[r][k] = a.coef * acc[r][k];
+    if constexpr (MODE != HOP_PLAIN) {
+        // one chirality block (36 packed reals) of the clover field at a time where 36 reals are
+        // whole planes (FP64, FP32); with 8 reals per plane (16-bit storage) all 72 at once
+        constexpr bool split = (36 % W) == 0;
+        auto apply_block = [&](const T *q, int blk, int r, const C<T> *chi) {
+            C<T> t[6];
+            if constexpr (MODE == HOP_INV) {
+                block_mul(q, acc[r] + 6 * blk, t);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) acc[r][6 * blk + k] = t[k];
+            } else {
+                block_mul(q, chi, t);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) acc[r][6 * blk + k] = acc[r][6 * blk + k] + t[k];
+            }
+        };
+        if constexpr (split) {
+            T pk[36];
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk) {
+                load_planes_h<S, 36, NT>(a.clov, 72 / W, blk * (36 / W), i, pk);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    if (!on[r]) continue;
+                    C<T> chi[6];
+                    if constexpr (MODE == HOP_CLOV) {
+                        T cr[12];
+                        load_planes_h<S, 12, NT>(a.chi + (size_t)(rhs0 + r) * a.vs, 24 / W, blk * (12 / W), i, cr);
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) chi[k] = mk(cr[2 * k], cr[2 * k + 1]);
+                    }
+                    apply_block(pk, blk, r, chi);
+                }
+            }
+        } else {
+            T pk[72];
+            load_planes_h<S, 72, NT>(a.clov, 72 / W, 0, i, pk);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (!on[r]) continue;
+                C<T> chi[12];
+                if constexpr (MODE == HOP_CLOV) {
+                    T cr[24];
+                    load_planes_h<S, 24, NT>(a.chi + (size_t)(rhs0 + r) * a.vs, 24 / W, 0, i, cr);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) chi[k] = mk(cr[2 * k], cr[2 * k + 1]);
+                }
+                apply_block(pk, 0, r, chi);
+                apply_block(pk + 36, 1, r, chi + 6);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (!on[r]) continue;
+        T o[24];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) { o[2 * k] = acc[r][k].r; o[2 * k + 1] = acc[r][k].i; }
+        store_field_h<S, 24, NT>((V *)(a.out + (size_t)(rhs0 + r) * a.vs), i, o);
+    }
+}
+
+// Persistent sweep over (site block, chunk of NR right-hand sides), chunk fastest, so the chunks
+// of one site block run back to back on one XCD and share its links and clover block in L2.
+template <typename S, int DAG, int MODE, int BS, int NR, bool NT>
+__global__ __launch_bounds__(BS) void k_hop_mr(HopArgs<S> a, int nlog) {
+    const int nch = (a.nrhs + NR - 1) / NR;
+#pragma nounroll
+    for (int lb = blockIdx.x; lb < nlog; lb += gridDim.x) {
+        const int ch = lb % nch, blk = lb / nch;
+        const int ii = blk * BS + threadIdx.x;
+        if (ii >= a.g.vh) continue;
+        hop_site_mr<S, DAG, MODE, NR, NT>(a, ii, ch * NR);
+    }
+}
+
 // Slab sweep: XCD k (work-groups b with b % 8 == k) owns the time slices [k L0 / 8, (k + 1) L0 / 8)
 // and walks them with time faster than x1: the work-groups of one XCD in flight together cover a
 // few (t, x1) planes of all its time slices, so the neighbours in every direction but across the
@@ -348,19 +478,21 @@ __global__ __launch_bounds__(64 * TT) void k_hop_tp(HopArgs<S> a, int nwg) {
 }
 
 struct HopShape {
-    int bs, xcd, tt, pers, slab, npi, nt;
+    int bs, xcd, tt, pers, slab, npi, nt, mr;
 };
 // Shape 0 is the default (used when tuning is off, and inside a graph capture before the key
 // was tuned): the persistent sweep, one 256-wide work-group per compute unit, two neighbours per
 // loop iteration, streaming hints.  tt > 0: the time-tiled kernel (bs = 64 tt); pers > 0: a
 // persistent grid of pers work-groups per compute unit (xcd: each XCD sweeps its own eighth);
-// slab: the XCD slab sweep; npi: neighbours per loop iteration; nt: streaming hints.
+// slab: the XCD slab sweep; npi: neighbours per loop iteration; nt: streaming hints; mr: right-hand
+// sides per work-item (the links and clover block read once for all of them).
 const HopShape kShapes[] = {
-    {256, 0, 0, 1, 0, 2, 1}, {256, 0, 0, 1, 0, 1, 1}, {256, 0, 0, 2, 0, 1, 1}, {256, 0, 0, 1, 0, 1, 0},
-    {256, 0, 0, 1, 0, 2, 0}, {256, 1, 0, 0, 0, 1, 0}, {256, 0, 0, 0, 0, 1, 0}, {128, 1, 0, 0, 0, 1, 0},
-    {64, 1, 0, 0, 0, 1, 0},  {256, 1, 4, 0, 0, 1, 0}, {512, 1, 8, 0, 0, 1, 0}, {512, 0, 0, 1, 0, 1, 0},
-    {256, 0, 0, 2, 0, 1, 0}, {256, 1, 0, 1, 0, 1, 0}, {256, 0, 4, 1, 0, 1, 0}, {512, 0, 8, 1, 0, 1, 0},
-    {256, 0, 0, 1, 1, 1, 0}, {256, 0, 0, 2, 1, 1, 0}, {128, 0, 0, 2, 1, 1, 0}, {256, 0, 0, 2, 0, 2, 0}};
+    {256, 0, 0, 1, 0, 2, 1, 1}, {256, 0, 0, 1, 0, 1, 1, 1}, {256, 0, 0, 2, 0, 1, 1, 1}, {256, 0, 0, 1, 0, 1, 0, 1},
+    {256, 0, 0, 1, 0, 2, 0, 1}, {256, 1, 0, 0, 0, 1, 0, 1}, {256, 0, 0, 0, 0, 1, 0, 1}, {128, 1, 0, 0, 0, 1, 0, 1},
+    {64, 1, 0, 0, 0, 1, 0, 1},  {256, 1, 4, 0, 0, 1, 0, 1}, {512, 1, 8, 0, 0, 1, 0, 1}, {512, 0, 0, 1, 0, 1, 0, 1},
+    {256, 0, 0, 2, 0, 1, 0, 1}, {256, 1, 0, 1, 0, 1, 0, 1}, {256, 0, 4, 1, 0, 1, 0, 1}, {512, 0, 8, 1, 0, 1, 0, 1},
+    {256, 0, 0, 1, 1, 1, 0, 1}, {256, 0, 0, 2, 1, 1, 0, 1}, {128, 0, 0, 2, 1, 1, 0, 1}, {256, 0, 0, 2, 0, 2, 0, 1},
+    {256, 0, 0, 1, 0, 1, 1, 2}, {256, 0, 0, 1, 0, 1, 1, 4}, {256, 0, 0, 2, 0, 1, 1, 2}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 template <typename S> constexpr int num_shapes() { return kNumShapes; }
 
@@ -413,6 +545,16 @@ void launch_slab(HopArgs<S> a, int per_cu, hipStream_t s) {
     k_hop_ps<S, DAG, MODE, BS><<<grid, BS, 0, s>>>(a, nper);
 }
 
+template <typename S, int DAG, int MODE, int NR>
+void launch_multi(HopArgs<S> a, int per_cu, hipStream_t s) {
+    const int nch = (a.nrhs + NR - 1) / NR;
+    const int nlog = (a.g.vh + 255) / 256 * nch;
+    const int grid = std::min(nlog, per_cu * compute_units());
+    a.xcd = 0;
+    a.nb8 = grid;
+    k_hop_mr<S, DAG, MODE, 256, NR, true><<<grid, 256, 0, s>>>(a, nlog);
+}
+
 template <typename S, int DAG, int MODE, int TT>
 void launch_tiled_persistent(HopArgs<S> a, int per_cu, hipStream_t s) {
     const int nwg = (a.g.L[0] / TT) * (a.g.vh / (a.g.L[0] * kSB)) * a.nrhs;
@@ -434,7 +576,15 @@ template <typename S, int DAG, int MODE>
 void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
     HopShape h = kShapes[shape];
     if ((h.tt && !tiled_ok(a.g, h.tt)) || (h.slab && !slab_ok(a.g, h.bs))) h = kShapes[0];  // does not fit
-    if (h.tt) {
+    if (h.mr > 1) {
+        // two right-hand sides per work-item in FP64 (four would not fit the registers)
+        if constexpr (std::is_same<S, double>::value) {
+            launch_multi<S, DAG, MODE, 2>(a, h.pers, s);
+        } else {
+            if (h.mr == 2) launch_multi<S, DAG, MODE, 2>(a, h.pers, s);
+            else launch_multi<S, DAG, MODE, 4>(a, h.pers, s);
+        }
+    } else if (h.tt) {
         if (h.pers) {
             if (h.tt == 4) launch_tiled_persistent<S, DAG, MODE, 4>(a, h.pers, s);
             else launch_tiled_persistent<S, DAG, MODE, 8>(a, h.pers, s);

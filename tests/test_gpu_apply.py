@@ -181,7 +181,7 @@ def test_hop_launch_shapes_bitwise_identical(monkeypatch):
         for prec in ("f64", "f32", "f16", "bf16"):
             nat = c.D.to_native(to_dev(psi_e.astype(np.complex64) if prec == "f32" else psi_e), prec, "eo", sites=1)
             ref = None
-            for shape in range(20):
+            for shape in range(23):
                 monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
                 out = c.D.native_empty(prec, 1)
                 c.D.apply_eo(out, nat, prec, "native")
@@ -201,22 +201,30 @@ def test_hop_launch_shapes_bitwise_identical(monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-def test_multi_rhs_schur_equals_single(case, prec):
-    """dirac_apply_eo_multi on 3 right-hand sides equals three single applies bit for bit."""
+def test_multi_rhs_schur_equals_single(case, prec, monkeypatch):
+    """dirac_apply_eo_multi on 5 right-hand sides equals five single applies bit for bit, with
+    the tuner's shape and with the shapes that take 2 or 4 right-hand sides per work-item (5 is
+    a multiple of neither, so the last chunk is partial)."""
     D = case.D
-    vecs = [case.spinor(40 + r)[case.even] for r in range(3)]
+    nr = 5
+    vecs = [case.spinor(40 + r)[case.even] for r in range(nr)]
     nats = [D.to_native(to_dev(v.astype(np.complex64) if prec == "f32" else v), prec, "eo", sites=1) for v in vecs]
     inp = torch.cat(nats)
-    # outputs start zeroed: the padding sites of a NATIVE vector are never written
-    out = torch.zeros_like(inp)
-    D.apply_eo_multi(out, inp, 3, prec)
     n = nats[0].numel()
-    for r in range(3):
-        one = torch.zeros_like(nats[r])
+    singles = []
+    for r in range(nr):
+        one = torch.zeros_like(nats[r])  # padding sites of a NATIVE vector are never written
         D.apply_eo(one, nats[r], prec, "native")
-        assert torch.equal(out[r * n:(r + 1) * n], one), r
-    dag = torch.zeros_like(inp)
-    D.apply_eo_multi(dag, inp, 3, prec, dagger=True)
-    one = torch.zeros_like(nats[2])
-    D.apply_eo(one, nats[2], prec, "native", dagger=True)
-    assert torch.equal(dag[2 * n:], one)
+        singles.append(one)
+    one_dag = torch.zeros_like(nats[nr - 1])
+    D.apply_eo(one_dag, nats[nr - 1], prec, "native", dagger=True)
+    for shape in (None, 20, 21, 22):
+        if shape is not None:
+            monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
+        out = torch.zeros_like(inp)
+        D.apply_eo_multi(out, inp, nr, prec)
+        for r in range(nr):
+            assert torch.equal(out[r * n:(r + 1) * n], singles[r]), (shape, r)
+        dag = torch.zeros_like(inp)
+        D.apply_eo_multi(dag, inp, nr, prec, dagger=True)
+        assert torch.equal(dag[(nr - 1) * n:], one_dag), shape
