@@ -56,11 +56,19 @@ template <> struct St<__half> {
 #pragma unroll
         for (int k = 0; k < 4; ++k) { float2 f = __half22float2(h[k]); o[2 * k] = f.x; o[2 * k + 1] = f.y; }
     }
+    // The values are rounded to FP32 first and then to FP16 (the C++ semantics).  The empty asm
+    // keeps the compiler from merging the last multiply-add of a value with its FP16 conversion
+    // into one mixed-precision instruction that rounds once: it does so in some kernels and not
+    // in others, and two kernels computing the same sums would then disagree in the last bit.
     static DEV vec pack(const acc *o) {
         vec v;
         __half2 *h = reinterpret_cast<__half2 *>(&v);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) h[k] = __floats2half2_rn(o[2 * k], o[2 * k + 1]);
+        for (int k = 0; k < 4; ++k) {
+            float a = o[2 * k], b = o[2 * k + 1];
+            asm volatile("" : "+v"(a), "+v"(b));
+            h[k] = __floats2half2_rn(a, b);
+        }
         return v;
     }
 };
