@@ -144,6 +144,7 @@ template <typename V> DEV V ld_stream(const V *p) {
 }
 DEV double ld_stream(const double *p) { return __builtin_nontemporal_load(p); }
 DEV float ld_stream(const float *p) { return __builtin_nontemporal_load(p); }
+DEV uint32_t ld_stream(const uint32_t *p) { return __builtin_nontemporal_load(p); }
 template <typename V> DEV void st_stream(V *p, const V &v) {
     using R = typename RawOf<sizeof(V)>::type;
     __builtin_nontemporal_store(__builtin_bit_cast(R, v), reinterpret_cast<R *>(p));
@@ -228,16 +229,30 @@ DEV int xcd_block(int nb8) {
 template <typename S> struct Lk;
 template <> struct Lk<double> {
     using vec = double2; using om = double; using acc = double; static constexpr int W = 2;
+    static constexpr bool phase_pair = false;  // om is the angle omega itself
     static DEV void unpack(const vec &v, acc *o) { o[0] = v.x; o[1] = v.y; }
     static DEV vec pack(const double *o) { return make_double2(o[0], o[1]); }
 };
 template <> struct Lk<float> {
     using vec = float4; using om = float; using acc = float; static constexpr int W = 4;
+    static constexpr bool phase_pair = false;
     static DEV void unpack(const vec &v, acc *o) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
     static DEV vec pack(const double *o) { return make_float4((float)o[0], (float)o[1], (float)o[2], (float)o[3]); }
 };
+// 16-bit links store the phase as (cos omega, sin omega) in the same 16-bit format (low half cos,
+// high half sin): 4 bytes, like an FP32 angle, and no sincos in the kernel.
 template <> struct Lk<__half> {
-    using vec = uint2; using om = float; using acc = float; static constexpr int W = 4;
+    using vec = uint2; using om = uint32_t; using acc = float; static constexpr int W = 4;
+    static constexpr bool phase_pair = true;
+    static DEV void phase(om w, acc &co, acc &si) {
+        const float2 f = __half22float2(*reinterpret_cast<const __half2 *>(&w));
+        co = f.x;
+        si = f.y;
+    }
+    static DEV om pack_phase(float co, float si) {
+        const __half2 h = __floats2half2_rn(co, si);
+        return *reinterpret_cast<const uint32_t *>(&h);
+    }
     static DEV void unpack(const vec &v, acc *o) {
         const __half2 *h = reinterpret_cast<const __half2 *>(&v);
         float2 a = __half22float2(h[0]), b = __half22float2(h[1]);
@@ -252,7 +267,15 @@ template <> struct Lk<__half> {
     }
 };
 template <> struct Lk<__hip_bfloat16> {
-    using vec = uint2; using om = float; using acc = float; static constexpr int W = 4;
+    using vec = uint2; using om = uint32_t; using acc = float; static constexpr int W = 4;
+    static constexpr bool phase_pair = true;
+    static DEV void phase(om w, acc &co, acc &si) {
+        co = __uint_as_float(w << 16);
+        si = __uint_as_float(w & 0xffff0000u);
+    }
+    static DEV om pack_phase(float co, float si) {
+        return St<__hip_bfloat16>::rne(co) | (St<__hip_bfloat16>::rne(si) << 16);
+    }
     static DEV void unpack(const vec &v, acc *o) {
         o[0] = __uint_as_float(v.x << 16); o[1] = __uint_as_float(v.x & 0xffff0000u);
         o[2] = __uint_as_float(v.y << 16); o[3] = __uint_as_float(v.y & 0xffff0000u);

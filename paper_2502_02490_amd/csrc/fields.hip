@@ -3,6 +3,7 @@
 // layout, link compression, and lower-precision copies of the operator fields.
 #include <cstring>
 
+#include "dirac_ops.h"
 #include "internal.h"
 
 namespace dl {
@@ -85,7 +86,13 @@ __global__ __launch_bounds__(kBlock) void k_convert_links(int vh, int vhp, const
         typename Lk<S>::vec *d0 = site_ptr(dst + (size_t)dir * (12 / W) * n, (uint32_t)i, 12 / W);
 #pragma unroll
         for (int k = 0; k < 12 / W; ++k) d0[k * kSB] = Lk<S>::pack(r + k * W);
-        om_dst[(size_t)dir * n + i] = (typename Lk<S>::om)om_src[(size_t)dir * n + i];
+        if constexpr (Lk<S>::phase_pair) {
+            double si, co;
+            sc(om_src[(size_t)dir * n + i], si, co);  // FP64, then rounded once to the 16-bit format
+            om_dst[(size_t)dir * n + i] = Lk<S>::pack_phase((float)co, (float)si);
+        } else {
+            om_dst[(size_t)dir * n + i] = (typename Lk<S>::om)om_src[(size_t)dir * n + i];
+        }
     }
 }
 

@@ -59,8 +59,9 @@ DEV void load_link(const HopArgs<S> &a, int dir, uint32_t i, C<typename St<S>::a
 #pragma unroll
     for (int k = 0; k < 6; ++k) u[k] = mk(r[2 * k], r[2 * k + 1]);
     const OM *om = a.omega + (size_t)dir * vhp + i;
-    const T w = (T)(NT ? ld_stream(om) : *om);
-    sc(w, si, co);
+    const OM w = NT ? ld_stream(om) : *om;
+    if constexpr (Lk<S>::phase_pair) Lk<S>::phase(w, co, si);
+    else sc((T)w, si, co);
 }
 
 // Spin structure of gamma_mu = [[0, e_mu], [e_mu^dag, 0]]: e_mu is monomial, row k has its
