@@ -38,6 +38,17 @@ DEV void ld(const typename St<S>::vec *p, int t, int vh, double *o) {
 #pragma unroll
     for (int k = 0; k < 24; ++k) o[k] = (double)r[k];
 }
+// The same load with a streaming hint: for the Krylov basis vectors, which a kernel reads once
+// (so they do not push the vectors it writes and reads back out of L2).
+template <typename S>
+DEV void ld_basis(const typename St<S>::vec *p, int t, int vh, double *o) {
+    uint32_t i;
+    const typename St<S>::vec *b = blk_base<S>(p, t, vh, i);
+    typename St<S>::acc r[24];
+    load_planes_h<S, 24, true>(b, 24 / St<S>::W, 0, i, r);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) o[k] = (double)r[k];
+}
 template <typename S>
 DEV void st(typename St<S>::vec *p, int t, int vh, const double *o) {
     uint32_t i;
@@ -108,7 +119,7 @@ __global__ __launch_bounds__(kRed) void k_mdot(Bat B, const typename St<S>::vec 
         double v[2] = {0.0, 0.0};
         if (on) {
             double b[24];
-            ld<S>(Q + ((size_t)j * B.nrhs + r) * vs, t, B.vh, b);
+            ld_basis<S>(Q + ((size_t)j * B.nrhs + r) * vs, t, B.vh, b);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 v[0] = fma(b[2 * c], a[2 * c], v[0]);
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(kRed) void k_maxpy_dot(Bat B, const typename St<S>:
         ld<S>(q, t, B.vh, a);
         for (int j = 0; j < k; ++j) {
             const double2 cj = cf[j];
-            ld<S>(Q + ((size_t)j * B.nrhs + r) * vs, t, B.vh, b);
+            ld_basis<S>(Q + ((size_t)j * B.nrhs + r) * vs, t, B.vh, b);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 a[2 * c] -= cj.x * b[2 * c] - cj.y * b[2 * c + 1];
@@ -232,7 +243,7 @@ __global__ __launch_bounds__(kRed) void k_axpy_multi(Bat B, typename St<SX>::vec
     ld<SX>(x, t, B.vh, a);
     for (int j = 0; j < k; ++j) {
         const double2 cj = cf[j];
-        ld<SP>(P + ((size_t)j * B.nrhs + r) * vp, t, B.vh, b);
+        ld_basis<SP>(P + ((size_t)j * B.nrhs + r) * vp, t, B.vh, b);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             a[2 * c] += xs * (cj.x * b[2 * c] - cj.y * b[2 * c + 1]);
