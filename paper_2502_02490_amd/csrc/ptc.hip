@@ -166,9 +166,9 @@ DEV void transport_site(const PtcGeom &a, const float4 *xc, int p, uint32_t i, c
 // The layer as a real GEMM on the 16x16x32 BF16 matrix cores (FP32 accumulation):
 //   rows    m = 8 c + 2 sigma + ri_out          (output channel, spin, re/im)
 //   columns n = (site, colour)                  (16 sites of a wavefront per tile, one colour per tile)
-//   depth   k = 8 pair + 2 tau + ri_in,  pair = c' * 9 + path (input channel major: the 9
-//           transports of one input channel run in consecutive K steps, so its activations
-//           are read by all paths while they are still in the caches)
+//   depth   k = 8 pair + 2 tau + ri_in,  pair = path * n_in + c' (path major: the four pairs of
+//           a K step share one link, which the four lane groups load in one instruction; the
+//           input-channel-major order was measured 1.5x slower)
 // with the real embedding of the complex weights: (re, re) = (im, im) = Re W, (re, im) = -Im W,
 // (im, re) = Im W.  A K step of 32 holds four (path, c') pairs; the lanes with k group g = lane / 16
 // compute the transport T_path x_c' of pair 4 q + g at their site, and its 4 spins of colour a
@@ -189,7 +189,7 @@ __global__ void k_ptc_afrag(int nin, int nout, int nk, int nm, const uint32_t *_
     const int c = m >> 3, sg = (m >> 1) & 3, rio = m & 1;
     uint32_t v[4] = {0u, 0u, 0u, 0u};
     if (c < nout && pair < kPaths * nin) {
-        const int path = pair % kPaths, cp = pair / kPaths;
+        const int path = pair / nin, cp = pair % nin;
         const uint32_t *w = W + ((size_t)(path * nout + c) * nin + cp) * 16 + sg * 4;
 #pragma unroll
         for (int tau = 0; tau < 4; ++tau) {
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, con
         auto load = [&](int q, TRaw &r) {
             const int pair = 4 * q + g;
             if (on && pair < NPAIR)
-                transport_load(a, xin + (size_t)(pair / kPaths) * chan4, p, (uint32_t)i, x, pair % kPaths, r);
+                transport_load(a, xin + (size_t)(pair % NIN) * chan4, p, (uint32_t)i, x, pair / NIN, r);
         };
         load(0, cur);
 #pragma nounroll
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, con
             const int pair = 4 * q + g;
             C<float> tr[12];
             if (on && pair < NPAIR) {
-                transport_compute(cur, pair % kPaths, tr);
+                transport_compute(cur, pair / NIN, tr);
             } else {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) tr[k] = mk(0.f, 0.f);
