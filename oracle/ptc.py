@@ -83,11 +83,36 @@ def layer(f: dirac.Fields, W: np.ndarray, xs, bf16_inputs: bool = False) -> list
     return ys
 
 
-def forward(f: dirac.Fields, weights, r: np.ndarray, bf16_inputs: bool = False):
-    """N(r) and the activations of every layer (inputs of layer l are acts[l])."""
+def layer_contract_first(f: dirac.Fields, W: np.ndarray, xs, bf16_inputs: bool = False) -> list:
+    """The same layer summed in the other order: z_{p,c} = sum_{c'} W[p, c, c'] x_{c'} at every
+    site, then y_c = sum_p T_p z_{p,c}.  W acts on spin only and T_p on colour and position, so
+    W[p, c, c'] T_p = T_p W[p, c, c'] and this equals layer() in exact arithmetic; it needs
+    9 n_out transports instead of 9 n_in.  With bf16_inputs each input field x_{c'} is rounded to
+    BF16 before the contraction (the form the library uses for a last layer with one output
+    channel); z and the transports stay exact."""
+    n_out, n_in = W.shape[1], W.shape[2]
+    assert len(xs) == n_in
+    xr = [round_bf16(x) for x in xs] if bf16_inputs else xs
+    ys = [np.zeros_like(xs[0]) for _ in range(n_out)]
+    for c in range(n_out):
+        for p in range(NPATH):
+            z = np.zeros_like(xs[0])
+            for cp in range(n_in):
+                z += np.einsum("st,ntc->nsc", W[p, c, cp], xr[cp])
+            ys[c] += transport(f, z, p)
+    return ys
+
+
+def forward(f: dirac.Fields, weights, r: np.ndarray, bf16_inputs: bool = False, last_contract_first: bool = False):
+    """N(r) and the activations of every layer (inputs of layer l are acts[l]).  With
+    last_contract_first the last layer is summed as in layer_contract_first (the library does so
+    when the network has more than one layer and one output channel)."""
     acts = [[r]]
-    for W in weights:
-        acts.append(layer(f, W, acts[-1], bf16_inputs))
+    for l, W in enumerate(weights):
+        if last_contract_first and l == len(weights) - 1:
+            acts.append(layer_contract_first(f, W, acts[-1], bf16_inputs))
+        else:
+            acts.append(layer(f, W, acts[-1], bf16_inputs))
     return acts[-1][0], acts
 
 
@@ -129,13 +154,13 @@ def backward(f: dirac.Fields, weights, acts, g_out: np.ndarray, bf16_inputs: boo
     return g[0], grads
 
 
-def loss_and_grads(f: dirac.Fields, weights, pairs, bf16_inputs: bool = False):
-    """L = mean_i |N(r_i) - e_i|^2 / |e_i|^2 and dL/dW* per layer."""
+def loss_and_grads(f: dirac.Fields, weights, pairs, bf16_inputs: bool = False, last_contract_first: bool = False):
+    """L = mean_i |N(r_i) - e_i|^2 / |e_i|^2 and dL/dW* per layer (forward as in forward())."""
     total = 0.0
     gsum = [np.zeros_like(W) for W in weights]
     n = len(pairs)
     for r, e in pairs:
-        y, acts = forward(f, weights, r, bf16_inputs)
+        y, acts = forward(f, weights, r, bf16_inputs, last_contract_first)
         ne2 = np.vdot(e, e).real
         d = y - e
         total += np.vdot(d, d).real / ne2 / n

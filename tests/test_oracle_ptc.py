@@ -157,3 +157,50 @@ def test_bf16_inputs_error_is_bounded_by_the_unit_roundoff():
     gxr, _ = ptc.backward(f, ws, acts, g, bf16_inputs=True)
     d = np.linalg.norm(gxr - gx) / np.linalg.norm(gx)
     assert 1e-5 < d < 2.0 ** -7
+
+
+def test_contract_first_equals_transport_first():
+    """Spin weights commute with the transports: summing the layer as sum_p T_p (sum_c' W x_c')
+    gives the transport-first layer up to FP64 rounding, for several channel counts and with the
+    boundary phases and U(1) angles on."""
+    f = fields(csw=1.0, cq=1.0)
+    for n_in, n_out in ((8, 1), (2, 3), (1, 2)):
+        W = ptc.init_weights((n_in, n_out), seed=10 + n_in, scale=1.0)[0]
+        xs = [gen.gaussian_spinor(f.p.dims, 20 + k) for k in range(n_in)]
+        a = ptc.layer(f, W, xs)
+        b = ptc.layer_contract_first(f, W, xs)
+        for u, v in zip(a, b):
+            assert np.abs(u - v).max() < 1e-13 * np.abs(u).max()
+        # a slip (the weights of path p applied after the transport of another path) is caught
+        Wp = W[[0, 2, 1, 3, 4, 5, 6, 7, 8]]
+        bad = ptc.layer_contract_first(f, Wp, xs)
+        assert np.abs(bad[0] - a[0]).max() > 1e-2 * np.abs(a[0]).max()
+
+
+def test_contract_first_rounds_the_untransported_inputs():
+    """On fields whose transports are signed permutations (unit links, phases 0 / pi), rounding
+    commutes with transport, so the contract-first layer with BF16 inputs equals the
+    transport-first one with BF16 inputs; rounding z instead of x would not.  On a random field
+    the rounded forms stay within the BF16 unit roundoff of the exact one."""
+    f = _exact_fields()
+    rng = np.random.default_rng(9)
+    xs = [rng.standard_normal((f.V, 4, 3)) + 1j * rng.standard_normal((f.V, 4, 3)) for _ in range(2)]
+    W = ptc.init_weights((2, 1), seed=4, scale=1.0)[0]
+    a = ptc.layer(f, W, xs, bf16_inputs=True)[0]
+    b = ptc.layer_contract_first(f, W, xs, bf16_inputs=True)[0]
+    assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+    exact = ptc.layer(f, W, xs)[0]
+    assert np.abs(b - exact).max() > 1e-4 * np.abs(exact).max()  # the rounding happened
+    z_rounded = sum(ptc.transport(f, ptc.round_bf16(sum(np.einsum("st,ntc->nsc", W[p, 0, cp], xs[cp])
+                                                        for cp in range(2))), p) for p in range(ptc.NPATH))
+    assert np.abs(z_rounded - a).max() > 1e-4 * np.abs(a).max()
+    f2 = fields()
+    xs2 = [gen.gaussian_spinor(f2.p.dims, 30 + k) for k in range(2)]
+    e = ptc.layer(f2, W, xs2)[0]
+    r = ptc.layer_contract_first(f2, W, xs2, bf16_inputs=True)[0]
+    d = np.linalg.norm(r - e) / np.linalg.norm(e)
+    assert 1e-5 < d < 2.0 ** -7
+    ws = ptc.init_weights((1, 2, 1), seed=3, scale=1.0)
+    y, _ = ptc.forward(f2, ws, xs2[0])
+    yc, _ = ptc.forward(f2, ws, xs2[0], last_contract_first=True)
+    assert np.abs(y - yc).max() < 1e-13 * np.abs(y).max()
