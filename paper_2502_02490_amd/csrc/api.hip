@@ -421,7 +421,7 @@ dirac_status ptc_destroy(dirac_ptc *n) {
     API_BEGIN
     if (!n) return DIRAC_OK;
     (void)hipDeviceSynchronize();
-    for (dl::DevBuf *b : {&n->w, &n->wbf, &n->wt, &n->grad, &n->m, &n->v, &n->acts, &n->gbuf, &n->part, &n->afw, &n->afb})
+    for (dl::DevBuf *b : {&n->w, &n->wbf, &n->wt, &n->grad, &n->m, &n->v, &n->acts, &n->gbuf, &n->part, &n->afw, &n->afb, &n->afz, &n->zbuf})
         b->release();
     delete n;
     API_END
@@ -504,7 +504,7 @@ dirac_status ptc_forward(dirac_ctx *c, dirac_ptc *n, void *out, const void *in, 
     check_no_alias(out, nb, in, nb);
     dl::ptc_ensure_acts(c, n);
     HIP_CHECK(hipMemcpyAsync(dl::ptc_act(c, n, 0), in, nb, hipMemcpyDeviceToDevice, s));
-    dl::ptc_forward_acts(c, n, s);
+    dl::ptc_forward_acts(c, n, s, false);
     HIP_CHECK(hipMemcpyAsync(out, dl::ptc_act(c, n, n->nlayers), nb, hipMemcpyDeviceToDevice, s));
     API_END
 }

@@ -168,7 +168,9 @@ DEV void transport_site(const PtcGeom &a, const float4 *xc, int p, uint32_t i, c
 //   columns n = (site, colour)                  (16 sites of a wavefront per tile, one colour per tile)
 //   depth   k = 8 pair + 2 tau + ri_in,  pair = path * n_in + c' (path major: the four pairs of
 //           a K step share one link, which the four lane groups load in one instruction; the
-//           input-channel-major order was measured 1.5x slower)
+//           input-channel-major order was measured 1.5x slower, and channel groups outermost
+//           with the paths into one neighbouring block consecutive fetched 5 % fewer bytes in
+//           the same time)
 // with the real embedding of the complex weights: (re, re) = (im, im) = Re W, (re, im) = -Im W,
 // (im, re) = Im W.  A K step of 32 holds four (path, c') pairs; the lanes with k group g = lane / 16
 // compute the transport T_path x_c' of pair 4 q + g at their site, and its 4 spins of colour a
@@ -176,6 +178,8 @@ DEV void transport_site(const PtcGeom &a, const float4 *xc, int p, uint32_t i, c
 // The A operand (weights) is prepared once per weight update in the lane order of the
 // instruction (row lane % 16, depth 8 (lane / 16) + j) and staged in LDS per work-group.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+typedef short s16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // A fragments of one layer: Af[(q * nm + t) * 64 + lane] = 8 BF16 values (uint4), q < nk, t < nm.
@@ -202,13 +206,45 @@ __global__ void k_ptc_afrag(int nin, int nout, int nk, int nm, const uint32_t *_
     Af[e] = make_uint4(v[0], v[1], v[2], v[3]);
 }
 
+// A fragments of the contraction z = W x of a contract-first last layer (one output channel) on
+// the 16x16x16 BF16 matrix cores: rows m = 8 p + 2 sigma + ri_out (path, spin, re/im; 5 tiles,
+// the last half empty), depth k = 8 c' + 2 tau + ri_in (the previous layer's output rows, NM tiles
+// of 16).  Az[(tz * nm + t) * 64 + lane] = 4 BF16 values (uint2): row 16 tz + lane % 16, depth
+// 16 t + 4 (lane / 16) + j.  W holds BF16 (re, im) pairs [9][1][nin][4][4].
+constexpr int kZTiles = 5;
+__global__ void k_ptc_zfrag(int nin, int nm, const uint32_t *__restrict__ W, uint2 *__restrict__ Az) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kZTiles * nm * 64) return;
+    const int lane = e & 63, t = (e >> 6) % nm, tz = (e >> 6) / nm;
+    const int m = 16 * tz + (lane & 15);
+    const int path = m >> 3, sg = (m >> 1) & 3, rio = m & 1;
+    uint32_t h[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = 16 * t + 4 * (lane >> 4) + j;
+        const int cp = k >> 3, tau = (k >> 1) & 3, rii = k & 1;
+        if (path < kPaths && cp < nin) {
+            const uint32_t w = W[((size_t)path * nin + cp) * 16 + sg * 4 + tau];
+            const uint32_t re = w & 0xffffu, im = w >> 16;
+            // (re, re) = (im, im) = Re W, (re, im) = -Im W, (im, re) = Im W
+            h[j] = rio == rii ? re : (rio ? im : (im ^ 0x8000u));
+        }
+    }
+    Az[e] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+}
+
 // One layer on the matrix cores.  Persistent: the grid's work-groups (4 wavefronts, 16 sites
 // each) sweep the 64-site blocks of both parities; the A fragments are staged once per
 // work-group.  NIN input channels, NM = ceil(8 NOUT / 16) row tiles.
-template <int NIN, int NM>
-__global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, const uint4 *__restrict__ Af,
-                                                        const float4 *__restrict__ xin,
-                                                        float4 *__restrict__ yout) {
+// ZOUT: the next layer is a contract-first last layer; its contractions z_p = sum_c' W[p][c'] y_c'
+// (p < 9) are formed from this layer's accumulators in registers -- the 16x16 accumulator tile t
+// of a lane is, rounded to BF16, its B operand of depth step t on the 16x16x16 instruction -- and
+// written to zout as 9 channels; y itself is written only when store_y is set.
+template <int NIN, int NM, bool ZOUT>
+__global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, const uint4 *__restrict__ Af,
+                                                        const float4 *__restrict__ xin, float4 *__restrict__ yout,
+                                                        const uint2 *__restrict__ Az, float4 *__restrict__ zout,
+                                                        int store_y) {
     constexpr int NPAIR = kPaths * NIN, NK = (NPAIR + 3) / 4;
     __shared__ uint4 af[NK * NM * 64];
     for (int e = threadIdx.x; e < NK * NM * 64; e += 256) af[e] = Af[e];
@@ -220,35 +256,33 @@ __global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, con
 #pragma nounroll
     for (int blk = blockIdx.x; blk < 2 * nbp; blk += gridDim.x) {
         const int p = blk >= nbp;
-        const int i = (blk - p * nbp) * 64 + wave * 16 + sl;
+        const int b = blk - p * nbp;
+        const int i = b * 64 + wave * 16 + sl;
         const bool on = i < a.g.vh;
-        int x[4] = {0, 0, 0, 0};
-        if (on) site_coords(a.g, i, p, x);
+        // A lane past the end of the lattice computes the transports of the last site: the
+        // matrix-core output column of a site depends on that site's B column alone, and its
+        // results are not stored.  Depth slots past the last (path, c') pair load pair NPAIR - 1;
+        // their A fragments are zero, and the loaded values are finite.
+        const uint32_t ic = on ? (uint32_t)i : (uint32_t)(a.g.vh - 1);
+        int x[4];
+        site_coords(a.g, (int)ic, p, x);
         f32x4_t acc[NM][3];
 #pragma unroll
         for (int t = 0; t < NM; ++t)
 #pragma unroll
             for (int col = 0; col < 3; ++col) acc[t][col] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-        // software pipeline: the loads of K step q + 1 are issued before the transport and the
-        // matrix-core work of step q
-        TRaw cur, nxt;
-        auto load = [&](int q, TRaw &r) {
-            const int pair = 4 * q + g;
-            if (on && pair < NPAIR)
-                transport_load(a, xin + (size_t)(pair % NIN) * chan4, p, (uint32_t)i, x, pair / NIN, r);
+        auto pair_of = [&](int q) {
+            const int pr = 4 * q + g;
+            if constexpr (NPAIR % 4 != 0) return pr < NPAIR ? pr : NPAIR - 1;
+            return pr;
         };
-        load(0, cur);
-#pragma nounroll
-        for (int q = 0; q < NK; ++q) {
-            if (q + 1 < NK) load(q + 1, nxt);
-            const int pair = 4 * q + g;
+        auto load = [&](int q, TRaw &r) {
+            const int pair = pair_of(q);
+            transport_load(a, xin + (size_t)(pair % NIN) * chan4, p, ic, x, pair / NIN, r);
+        };
+        auto step = [&](int q, const TRaw &r) {
             C<float> tr[12];
-            if (on && pair < NPAIR) {
-                transport_compute(cur, pair / NIN, tr);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) tr[k] = mk(0.f, 0.f);
-            }
+            transport_compute(r, pair_of(q) / NIN, tr);
             bf16x8_t b[3];
 #pragma unroll
             for (int col = 0; col < 3; ++col) {
@@ -265,99 +299,195 @@ __global__ __launch_bounds__(256) void k_ptc_layer_mfma(PtcGeom a, int nout, con
                 for (int col = 0; col < 3; ++col)
                     acc[t][col] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, b[col], acc[t][col], 0, 0, 0);
             }
-            cur = nxt;
+        };
+        // software pipeline over two register sets: the loads of K step q + 1 are issued before
+        // the transport and the matrix-core work of step q
+        TRaw ra, rb;
+        load(0, ra);
+#pragma nounroll
+        for (int q = 0; q < NK; q += 2) {
+            if (q + 1 < NK) load(q + 1, rb);
+            step(q, ra);
+            if (q + 1 < NK) {
+                if (q + 2 < NK) load(q + 2, ra);
+                step(q + 1, rb);
+            }
         }
-        if (!on) continue;
         // lane (g, site) holds rows m = 16 t + 4 g + r, r < 4: channel 2 t + g / 2, spins
         // 2 (g & 1) + r / 2, re/im r & 1 -- twelve consecutive reals (three planes) of one spinor
-#pragma unroll
-        for (int t = 0; t < NM; ++t) {
-            const int c = 2 * t + (g >> 1);
-            if (c >= nout) continue;
+        auto store_tile = [&](const f32x4_t (&v)[3], float4 *base, int c) {
             float r[12];
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-                for (int col = 0; col < 3; ++col) r[6 * (rr >> 1) + 2 * col + (rr & 1)] = acc[t][col][rr];
-            float4 *dst = site_ptr(yout + (size_t)c * chan4 + p * hv, (uint32_t)i, 6) + 3 * (g & 1) * kSB;
+                for (int col = 0; col < 3; ++col) r[6 * (rr >> 1) + 2 * col + (rr & 1)] = v[col][rr];
+            float4 *dst = site_ptr(base + (size_t)c * chan4 + p * hv, (uint32_t)i, 6) + 3 * (g & 1) * kSB;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
                 st_stream(dst + k * kSB, make_float4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]));
+        };
+        if (!ZOUT || store_y) {
+            if (on) {
+#pragma unroll
+                for (int t = 0; t < NM; ++t)
+                    if (2 * t + (g >> 1) < nout) store_tile(acc[t], yout, 2 * t + (g >> 1));
+            }
+        }
+        if constexpr (ZOUT) {
+            // every lane takes part in the matrix-core steps; only the stores are masked.  One
+            // output tile at a time keeps the extra accumulators at 12 registers.
+#pragma nounroll
+            for (int tz = 0; tz < kZTiles; ++tz) {
+                f32x4_t zacc[3];
+#pragma unroll
+                for (int col = 0; col < 3; ++col) zacc[col] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int t = 0; t < NM; ++t) {
+                    const s16x4_t A = __builtin_bit_cast(s16x4_t, Az[(tz * NM + t) * 64 + lane]);
+#pragma unroll
+                    for (int col = 0; col < 3; ++col) {
+                        bf16x4_t b;
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr) b[rr] = (__bf16)acc[t][col][rr];
+                        zacc[col] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, __builtin_bit_cast(s16x4_t, b),
+                                                                              zacc[col], 0, 0, 0);
+                    }
+                }
+                if (on && 2 * tz + (g >> 1) < kPaths) store_tile(zacc, zout, 2 * tz + (g >> 1));
+            }
         }
     }
 }
 
-// Partial weight gradient of one 64-site tile: part[tile][path][c][c'][s][t] (complex float).
-// Four wavefronts per work-group: the gradient of the tile (all output channels) is staged in
-// LDS once; then each wavefront takes one (path, c') pair at a time, computes its transport at
-// the 64 sites into its own LDS slot and reduces the 16 NOUT outputs of that pair over the tile
-// (sites, then colours, in index order: deterministic).
+// y(x) = sum_p (T_p z_p)(x): the transports of a contract-first last layer (one output channel),
+// one thread per site of either parity, the nine terms added in path order in FP32.
+__global__ __launch_bounds__(256) void k_ptc_tsum(PtcGeom a, const float4 *__restrict__ z, float4 *__restrict__ y) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= 2 * a.g.vh) return;
+    const int p = s >= a.g.vh;
+    const uint32_t i = (uint32_t)(s - p * a.g.vh);
+    int x[4];
+    site_coords(a.g, (int)i, p, x);
+    const size_t chan4 = a.chan / 4, hv = (size_t)6 * a.g.vhp;
+    C<float> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = mk(0.f, 0.f);
+#pragma nounroll
+    for (int path = 0; path < kPaths; ++path) {
+        C<float> t[12];
+        transport_site(a, z + (size_t)path * chan4, p, i, x, path, t);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            acc[k].r += t[k].r;
+            acc[k].i += t[k].i;
+        }
+    }
+    float4 *dst = site_ptr(y + p * hv, i, 6);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        st_stream(dst + k * kSB, make_float4(acc[2 * k].r, acc[2 * k].i, acc[2 * k + 1].r, acc[2 * k + 1].i));
+}
+
+// Partial weight gradients: part[wg][path][c][c'][s][t] (complex float), one slice per work-group.
+// Persistent: work-group wg takes the 64-site tiles wg, wg + G, wg + 2G, ... (G = grid size) and
+// sums their contributions into its slice in that order.  Per tile, four wavefronts: the gradient
+// of the tile (all output channels) is staged in LDS once; then each wavefront takes one (path, c')
+// pair at a time, computes its transport at the 64 sites into its own LDS slot and reduces the
+// 16 NOUT outputs of that pair over the tile (sites, then colours, in index order).  Every entry
+// of the slice belongs to one lane, so the running sums need no atomics and are deterministic.
 template <int NOUT>
 __global__ __launch_bounds__(256) void k_ptc_wgrad(PtcGeom a, int nin, const float4 *__restrict__ xin,
                                                    const float4 *__restrict__ g, float2 *__restrict__ part) {
     __shared__ C<float> gs[NOUT][kTile][12];
     __shared__ C<float> ts[4][kTile][12];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
-    const int s = blockIdx.x * kTile + lane;
-    const bool on = s < 2 * a.g.vh;
-    const int p = on && s >= a.g.vh;
-    const uint32_t i = on ? (uint32_t)(s - p * a.g.vh) : 0u;
-    int x[4] = {0, 0, 0, 0};
-    if (on) site_coords(a.g, (int)i, p, x);
+    const int ntile = (2 * a.g.vh + kTile - 1) / kTile;
     const size_t chan4 = a.chan / 4, hv = (size_t)6 * a.g.vhp;
-    for (int c = wave; c < NOUT; c += 4) {
-        float r[24];
-        if (on) load_field<float, 24>(g + c * chan4 + p * hv, i, r);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) gs[c][lane][k] = on ? mk(r[2 * k], r[2 * k + 1]) : mk(0.f, 0.f);
-    }
     const int npair = kPaths * nin;
+    float2 *slice = part + (size_t)blockIdx.x * npair * NOUT * 16;
 #pragma nounroll
-    for (int base = 0; base < npair; base += 4) {
-        const int pr = base + wave;
-        const int path = pr / nin, cp = pr % nin;
-        C<float> t[12];
-        if (on && pr < npair) {
-            transport_site(a, xin + cp * chan4, p, i, x, path, t);
-        } else {
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const bool first = tile == (int)blockIdx.x;
+        const int s = tile * kTile + lane;
+        const bool on = s < 2 * a.g.vh;
+        const int p = on && s >= a.g.vh;
+        const uint32_t i = on ? (uint32_t)(s - p * a.g.vh) : 0u;
+        int x[4] = {0, 0, 0, 0};
+        if (on) site_coords(a.g, (int)i, p, x);
+        __syncthreads();  // the previous tile's reads of gs and ts are done
+        for (int c = wave; c < NOUT; c += 4) {
+            float r[24];
+            if (on) load_field<float, 24>(g + c * chan4 + p * hv, i, r);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) t[k] = mk(0.f, 0.f);
+            for (int k = 0; k < 12; ++k) gs[c][lane][k] = on ? mk(r[2 * k], r[2 * k + 1]) : mk(0.f, 0.f);
         }
-        __syncthreads();  // the previous pairs' reads of ts (and the staging of gs) are done
+#pragma nounroll
+        for (int base = 0; base < npair; base += 4) {
+            const int pr = base + wave;
+            const int path = pr / nin, cp = pr % nin;
+            C<float> t[12];
+            if (on && pr < npair) {
+                transport_site(a, xin + cp * chan4, p, i, x, path, t);
+            } else {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) ts[wave][lane][k] = t[k];
-        __syncthreads();
-        if (pr < npair) {
-            for (int o = lane; o < NOUT * 16; o += kTile) {
-                const int c = o >> 4, ss = (o >> 2) & 3, tt = o & 3;
-                C<float> acc = mk(0.f, 0.f);
-                for (int xs = 0; xs < kTile; ++xs)
+                for (int k = 0; k < 12; ++k) t[k] = mk(0.f, 0.f);
+            }
+            __syncthreads();  // the previous pairs' reads of ts (and the staging of gs) are done
 #pragma unroll
-                    for (int col = 0; col < 3; ++col) {
-                        // g_c[s, col] conj(t[t, col])
-                        const C<float> gv = gs[c][xs][3 * ss + col], tv = ts[wave][xs][3 * tt + col];
-                        acc.r += gv.r * tv.r + gv.i * tv.i;
-                        acc.i += gv.i * tv.r - gv.r * tv.i;
+            for (int k = 0; k < 12; ++k) ts[wave][lane][k] = t[k];
+            __syncthreads();
+            if (pr < npair) {
+                for (int o = lane; o < NOUT * 16; o += kTile) {
+                    const int c = o >> 4, ss = (o >> 2) & 3, tt = o & 3;
+                    C<float> acc = mk(0.f, 0.f);
+                    for (int xs = 0; xs < kTile; ++xs)
+#pragma unroll
+                        for (int col = 0; col < 3; ++col) {
+                            // g_c[s, col] conj(t[t, col])
+                            const C<float> gv = gs[c][xs][3 * ss + col], tv = ts[wave][xs][3 * tt + col];
+                            acc.r += gv.r * tv.r + gv.i * tv.i;
+                            acc.i += gv.i * tv.r - gv.r * tv.i;
+                        }
+                    float2 &dst = slice[((size_t)path * NOUT * nin + (size_t)c * nin + cp) * 16 + ss * 4 + tt];
+                    if (first) {
+                        dst = make_float2(acc.r, acc.i);
+                    } else {
+                        const float2 old = dst;
+                        dst = make_float2(old.x + acc.r, old.y + acc.i);
                     }
-                part[(((size_t)blockIdx.x * kPaths + path) * NOUT * nin + (size_t)c * nin + cp) * 16 + ss * 4 + tt] =
-                    make_float2(acc.r, acc.i);
+                }
             }
         }
     }
 }
 
-// out[k] += sum_b part[b][k] (b ascending), k < n complex entries
-__global__ void k_ptc_reduce(int nblk, int n, const float2 *__restrict__ part, float2 *__restrict__ out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+// out[k] += sum_b part[b][k] (b ascending), k < n complex entries.  A work-group of 256 threads
+// takes 64 entries; wavefront w sums the partials b = w, w + 4, ... in FP64 and the four sums
+// are added in the order w = 0..3 (deterministic).
+constexpr int kRedK = 64;
+__global__ __launch_bounds__(256) void k_ptc_reduce(int nblk, int n, const float2 *__restrict__ part,
+                                                    float2 *__restrict__ out) {
+    __shared__ double2 sum[4][kRedK];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int k = blockIdx.x * kRedK + l;
     double re = 0.0, im = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-        const float2 v = part[(size_t)b * n + k];
-        re += v.x;
-        im += v.y;
+    if (k < n) {
+        for (int b = w; b < nblk; b += 4) {
+            const float2 v = part[(size_t)b * n + k];
+            re += v.x;
+            im += v.y;
+        }
     }
-    out[k].x += (float)re;
-    out[k].y += (float)im;
+    sum[w][l] = make_double2(re, im);
+    __syncthreads();
+    if (w == 0 && k < n) {
+        for (int j = 1; j < 4; ++j) {
+            re += sum[j][l].x;
+            im += sum[j][l].y;
+        }
+        out[k].x += (float)re;
+        out[k].y += (float)im;
+    }
 }
 
 // Adam on n real parameters (interleaved re, im); writes the BF16 working copy
@@ -410,6 +540,13 @@ int compute_units() {
 int row_tiles(int nout) { return (8 * nout + 15) / 16; }
 int k_steps(int nin) { return (kPaths * nin + 3) / 4; }
 size_t afrag_count(int nin, int nout) { return (size_t)k_steps(nin) * row_tiles(nout) * 64; }
+size_t zfrag_count(int nin) { return (size_t)kZTiles * row_tiles(nin) * 64; }
+
+void build_zfrags(int nin, const uint32_t *W, uint2 *Az, hipStream_t s) {
+    const int n = (int)zfrag_count(nin);
+    k_ptc_zfrag<<<(n + 255) / 256, 256, 0, s>>>(nin, row_tiles(nin), W, Az);
+    HIP_CHECK(hipGetLastError());
+}
 
 void build_afrags(int nin, int nout, const uint32_t *W, uint4 *Af, hipStream_t s) {
     const int n = (int)afrag_count(nin, nout);
@@ -417,35 +554,55 @@ void build_afrags(int nin, int nout, const uint32_t *W, uint4 *Af, hipStream_t s
     HIP_CHECK(hipGetLastError());
 }
 
+// The optional ZOUT arguments (Az, z, store_y) select the variant that also forms the
+// contractions of a contract-first last layer.
+struct ZArgs {
+    const uint2 *Az = nullptr;
+    void *z = nullptr;
+    bool store_y = true;
+};
 template <int NIN, int NM>
-void launch_layer(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, hipStream_t s) {
+void launch_layer(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, const ZArgs &zo,
+                  hipStream_t s) {
     const int nblk = 2 * (int)((a.g.vh + 63) / 64);
     const int grid = std::min(nblk, 2 * compute_units());
-    k_ptc_layer_mfma<NIN, NM><<<grid, 256, 0, s>>>(a, nout, Af, (const float4 *)x, (float4 *)y);
+    if (zo.z)
+        k_ptc_layer_mfma<NIN, NM, true><<<grid, 256, 0, s>>>(a, nout, Af, (const float4 *)x, (float4 *)y, zo.Az,
+                                                             (float4 *)zo.z, zo.store_y ? 1 : 0);
+    else
+        k_ptc_layer_mfma<NIN, NM, false><<<grid, 256, 0, s>>>(a, nout, Af, (const float4 *)x, (float4 *)y, nullptr,
+                                                              nullptr, 1);
 }
 template <int NIN>
-void launch_layer_nm(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, hipStream_t s) {
+void launch_layer_nm(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, const ZArgs &zo,
+                     hipStream_t s) {
     switch (row_tiles(nout)) {
-        case 1: launch_layer<NIN, 1>(a, nout, Af, x, y, s); break;
-        case 2: launch_layer<NIN, 2>(a, nout, Af, x, y, s); break;
-        default: launch_layer<NIN, 4>(a, nout, Af, x, y, s); break;
+        case 1: launch_layer<NIN, 1>(a, nout, Af, x, y, zo, s); break;
+        case 2: launch_layer<NIN, 2>(a, nout, Af, x, y, zo, s); break;
+        default: launch_layer<NIN, 4>(a, nout, Af, x, y, zo, s); break;
     }
 }
 // y = layer(x) with the A fragments Af of a (nin -> nout) layer
-void layer_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const uint4 *Af, void *y, hipStream_t s) {
+void layer_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const uint4 *Af, void *y, hipStream_t s,
+                    const ZArgs &zo = ZArgs()) {
     switch (nin) {
-        case 1: launch_layer_nm<1>(a, nout, Af, x, y, s); break;
-        case 2: launch_layer_nm<2>(a, nout, Af, x, y, s); break;
-        case 4: launch_layer_nm<4>(a, nout, Af, x, y, s); break;
-        case 8: launch_layer_nm<8>(a, nout, Af, x, y, s); break;
+        case 1: launch_layer_nm<1>(a, nout, Af, x, y, zo, s); break;
+        case 2: launch_layer_nm<2>(a, nout, Af, x, y, zo, s); break;
+        case 4: launch_layer_nm<4>(a, nout, Af, x, y, zo, s); break;
+        case 8: launch_layer_nm<8>(a, nout, Af, x, y, zo, s); break;
         default: throw Error(DIRAC_EUNSUPPORTED, "PTC channel counts must be 1, 2, 4 or 8");
     }
     HIP_CHECK(hipGetLastError());
 }
+// work-groups of the weight-gradient kernel (two per compute unit, at most one per tile)
+int wgrad_grid(size_t vh) {
+    const size_t ntile = (2 * vh + kTile - 1) / kTile;
+    return (int)std::min(ntile, (size_t)2 * compute_units());
+}
 template <int NOUT>
 void launch_wgrad(const PtcGeom &a, int nin, const void *x, const void *g, void *part, hipStream_t s) {
-    k_ptc_wgrad<NOUT><<<(2 * a.g.vh + kTile - 1) / kTile, 256, 0, s>>>(a, nin, (const float4 *)x,
-                                                                       (const float4 *)g, (float2 *)part);
+    k_ptc_wgrad<NOUT><<<wgrad_grid(a.g.vh), 256, 0, s>>>(a, nin, (const float4 *)x, (const float4 *)g,
+                                                         (float2 *)part);
 }
 void wgrad_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const void *g, void *part, hipStream_t s) {
     switch (nout) {
@@ -498,6 +655,7 @@ void ptc_alloc(dirac_ptc *n) {
     }
     n->afw.alloc(fw * sizeof(uint4));
     n->afb.alloc(fb * sizeof(uint4));
+    if (n->contract_last()) n->afz.alloc(zfrag_count(n->ch[n->nlayers - 1]) * sizeof(uint2));
     n->w.alloc(tot * 8);
     n->wbf.alloc(tot * 4);
     n->wt.alloc(tot * 4);
@@ -517,6 +675,10 @@ static void refresh_afrags(dirac_ptc *n, hipStream_t s) {
     for (int l = 0; l < n->nlayers; ++l)
         build_afrags(n->ch[l], n->ch[l + 1], (const uint32_t *)n->wbf.p + n->off[l], (uint4 *)n->afw.p + n->afw_off[l],
                      s);
+    if (n->contract_last()) {
+        const int l = n->nlayers - 1;
+        build_zfrags(n->ch[l], (const uint32_t *)n->wbf.p + n->off[l], (uint2 *)n->afz.p, s);
+    }
 }
 
 void ptc_refresh_bf16(dirac_ptc *n, hipStream_t s) {
@@ -534,10 +696,10 @@ void ptc_ensure_acts(dirac_ctx *c, dirac_ptc *n) {
     int maxc = 0;
     for (int l = 0; l <= n->nlayers; ++l) maxc = std::max(maxc, n->ch[l]);
     n->gbuf.alloc(2 * (size_t)maxc * chanb);
-    const size_t ntile = (2 * (size_t)c->vh + kTile - 1) / kTile;
+    if (n->contract_last()) n->zbuf.alloc((size_t)kPaths * chanb);
     size_t maxw = 0;
     for (int l = 0; l < n->nlayers; ++l) maxw = std::max(maxw, ptc_nweights(n, l));
-    n->part.alloc(ntile * maxw * 8);
+    n->part.alloc((size_t)wgrad_grid(c->vh) * maxw * 8);
 }
 
 float *ptc_act(dirac_ctx *c, dirac_ptc *n, int l) {
@@ -547,12 +709,27 @@ float *ptc_act(dirac_ctx *c, dirac_ptc *n, int l) {
     return (float *)n->acts.p + off;
 }
 
-// forward: acts[0] must hold the input; leaves every layer's output in acts[l + 1]
-void ptc_forward_acts(dirac_ctx *c, dirac_ptc *n, hipStream_t s) {
+// forward: acts[0] must hold the input; leaves the output in acts[nlayers] and, with keep_all,
+// every layer's output in acts[l + 1] (the backward pass needs them)
+void ptc_forward_acts(dirac_ctx *c, dirac_ptc *n, hipStream_t s, bool keep_all) {
     PtcGeom a = geom_of(c, s);
-    for (int l = 0; l < n->nlayers; ++l)
+    const int L = n->nlayers;
+    const bool cf = n->contract_last();
+    for (int l = 0; l < (cf ? L - 1 : L); ++l) {
+        ZArgs zo;
+        if (cf && l == L - 2) {
+            zo.Az = (const uint2 *)n->afz.p;
+            zo.z = n->zbuf.p;
+            zo.store_y = keep_all;
+        }
         layer_dispatch(a, n->ch[l], n->ch[l + 1], ptc_act(c, n, l), (const uint4 *)n->afw.p + n->afw_off[l],
-                       ptc_act(c, n, l + 1), s);
+                       ptc_act(c, n, l + 1), s, zo);
+    }
+    if (cf) {
+        k_ptc_tsum<<<(int)((2 * c->vh + 255) / 256), 256, 0, s>>>(a, (const float4 *)n->zbuf.p,
+                                                                  (float4 *)ptc_act(c, n, L));
+        HIP_CHECK(hipGetLastError());
+    }
 }
 
 // backward from g (dL/dy*, FP32 NATIVE full, 1 channel) at the output: accumulates dL/dW* into
@@ -564,12 +741,12 @@ void ptc_backward_acts(dirac_ctx *c, dirac_ptc *n, const void *g_out, void *gin,
     for (int l = 0; l <= n->nlayers; ++l) maxc = std::max(maxc, n->ch[l]);
     char *gA = (char *)n->gbuf.p, *gB = gA + (size_t)maxc * chanb;
     HIP_CHECK(hipMemcpyAsync(gA, g_out, (size_t)n->ch[n->nlayers] * chanb, hipMemcpyDeviceToDevice, s));
-    const int ntile = (int)((2 * c->vh + kTile - 1) / kTile);
+    const int nslice = wgrad_grid(c->vh);
     for (int l = n->nlayers - 1; l >= 0; --l) {
         const int nin = n->ch[l], nout = n->ch[l + 1];
         const int nw = (int)ptc_nweights(n, l);
         wgrad_dispatch(a, nin, nout, ptc_act(c, n, l), gA, n->part.p, s);
-        k_ptc_reduce<<<(nw + 255) / 256, 256, 0, s>>>(ntile, nw, (const float2 *)n->part.p,
+        k_ptc_reduce<<<(nw + kRedK - 1) / kRedK, 256, 0, s>>>(nslice, nw, (const float2 *)n->part.p,
                                                       (float2 *)n->grad.p + n->off[l]);
         HIP_CHECK(hipGetLastError());
         if (l == 0 && !gin) break;

@@ -249,7 +249,7 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
         // p = N(r): FP64 -> FP32 activations -> network -> FP64 (the network is linear: no scaling needed)
         const Precond M = [&](void *pv, const void *rv) {
             B.lincomb(DIRAC_F32, DIRAC_F64, DIRAC_F64, 2, a_in, nullptr, 1.0, rv, 0.0, nullptr, nullptr, 1.0, s);
-            ptc_forward_acts(c, net, s);
+            ptc_forward_acts(c, net, s, false);
             B.lincomb(DIRAC_F64, DIRAC_F32, DIRAC_F64, 2, pv, nullptr, 1.0, a_out, 0.0, nullptr, nullptr, 1.0, s);
         };
         GcrOut g = gcr(c, w, DIRAC_F64, xf, bf, x0, target, p->restart, p->max_iter, s, true, &M, 2.0);
@@ -284,7 +284,7 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
             const Precond M = [&](void *pv, const void *rv) {
                 B.lincomb(DIRAC_F32, DIRAC_F64, DIRAC_F64, 1, a_in, nullptr, 1.0, rv, 0.0, nullptr, nullptr, 1.0, s);
                 HIP_CHECK(hipMemsetAsync(a_in + half32, 0, half32 * sizeof(float), s));
-                ptc_forward_acts(c, net, s);
+                ptc_forward_acts(c, net, s, false);
                 B.lincomb(DIRAC_F64, DIRAC_F32, DIRAC_F64, 1, pv, nullptr, 1.0, a_out, 0.0, nullptr, nullptr, 1.0, s);
             };
             GcrOut g = gcr(c, w, DIRAC_F64, xe, eta, x0, target, p->restart, p->max_iter, s, false, &M, 2.0);
