@@ -202,6 +202,45 @@ PTC_TRAIN_DIMS = (32, 16, 16, 16)
 # entries x 3 colours complex multiply-adds (8 real flops each)
 PTC_FLOP_PER_SITE = 8 * 9 * 16 * 3 * (1 * 8 + 8 * 8 + 8 * 1)
 PTC_KAPPA = 0.1245
+# algorithmic bytes of one network application per site, layer by layer (each activation read
+# once and written once in FP32, links as 13 FP32 reals per direction): 1 -> 8: 96 + 768 + 416,
+# 8 -> 8: 768 + 768 + 416, 8 -> 1: 768 + 96 + 416
+PTC_BYTES_PER_SITE = 1280 + 1952 + 1280
+
+
+def ptc_kernels(reps: int):
+    """The network's kernels alone on 32^3 x 64 (seed 505 field, seed-7 initial weights): one
+    forward application and one backward pass (forward with every activation kept, weight and
+    input gradients), timed with HIP events; one JSON line."""
+    import torch
+
+    import gen
+    import paper_2502_02490_amd as P
+    from paper_2502_02490_amd import ptc_train as T
+
+    d = DIMS
+    D = P.Dirac(torch.from_numpy(gen.su3_field(d, EPS, 505)).cuda(), torch.from_numpy(gen.u1_field(d, 0.3, 505)).cuda(),
+                d, PTC_KAPPA, CSW, CSW_QED, QHAT)
+    net = P.PTC((1, 8, 8, 1))
+    net.set_weights(T.init_weights((1, 8, 8, 1), seed=7))
+    vin = D.to_native(torch.from_numpy(gen.gaussian_spinor(d, 505)).cuda().to(torch.complex64), "f32", "lex")
+    g = D.to_native(torch.from_numpy(gen.gaussian_spinor(d, 506)).cuda().to(torch.complex64), "f32", "lex")
+    vout, gin = torch.empty_like(vin), torch.empty_like(vin)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        net.forward(D, vout, vin)
+        net.backward(D, gin, vin, g)
+    t_f = timed(lambda: net.forward(D, vout, vin), reps, stream) / reps
+    t_b = timed(lambda: net.backward(D, gin, vin, g), max(1, reps // 4), stream) / max(1, reps // 4)
+    V = math.prod(d)
+    out = {"lattice": "x".join(map(str, d)), "channels": [1, 8, 8, 1],
+           "forward_ms": round(t_f * 1e3, 3), "backward_ms": round(t_b * 1e3, 3),
+           "forward_algorithmic_GBps": round(PTC_BYTES_PER_SITE * V / t_f / 1e9, 1),
+           "forward_frac_of_8TBps": round(PTC_BYTES_PER_SITE * V / t_f / 8e12, 3),
+           "forward_contraction_TFLOPs": round(PTC_FLOP_PER_SITE * V / t_f / 1e12, 1)}
+    D.close()
+    net.close()
+    return out
 
 
 def ptc_suite(pairs_per_field: int, epochs: int, checkpoint: str | None):
@@ -292,6 +331,8 @@ def main():
     ap.add_argument("--ptc-pairs", type=int, default=500, help="training pairs per 16^3x32 field")
     ap.add_argument("--ptc-epochs", type=int, default=8)
     ap.add_argument("--ptc-checkpoint", default=None, help="write the trained weights and Adam state here")
+    ap.add_argument("--ptc-kernels", action="store_true",
+                    help="only time the PTC network's forward and backward kernels on 32^3x64 (one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 5 plain device copies of 768 MiB (a known-size kernel for HBM counter calibration)")
     args = ap.parse_args()
@@ -299,6 +340,13 @@ def main():
         print("bench.py measures one GPU: the operator runs on a single MI355X (multi-GPU halo exchange is "
               "designed, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.ptc_kernels:
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"ptc_kernels": ptc_kernels(max(1, args.steps // 10))}), flush=True)
+        return
 
     # the launch-shape tuner records its choices here, so the line can name the kernel it timed
     tune_cache = os.path.join("/tmp", f"dirac_tune_{os.getpid()}.json")
