@@ -103,16 +103,23 @@ def layer_contract_first(f: dirac.Fields, W: np.ndarray, xs, bf16_inputs: bool =
     return ys
 
 
-def forward(f: dirac.Fields, weights, r: np.ndarray, bf16_inputs: bool = False, last_contract_first: bool = False):
+def forward(f: dirac.Fields, weights, r: np.ndarray, bf16_inputs: bool = False, last_contract_first: bool = False,
+            bf16_storage: bool = False):
     """N(r) and the activations of every layer (inputs of layer l are acts[l]).  With
     last_contract_first the last layer is summed as in layer_contract_first (the library does so
-    when the network has more than one layer and one output channel)."""
+    when the network has more than one layer and one output channel).  With bf16_storage the
+    output of every layer but the last is rounded to BF16 before the next layer reads it (the
+    library stores those activations in BF16); the input and the output stay unrounded."""
     acts = [[r]]
     for l, W in enumerate(weights):
-        if last_contract_first and l == len(weights) - 1:
-            acts.append(layer_contract_first(f, W, acts[-1], bf16_inputs))
+        last = l == len(weights) - 1
+        if last_contract_first and last:
+            y = layer_contract_first(f, W, acts[-1], bf16_inputs)
         else:
-            acts.append(layer(f, W, acts[-1], bf16_inputs))
+            y = layer(f, W, acts[-1], bf16_inputs)
+        if bf16_storage and not last:
+            y = [round_bf16(v) for v in y]
+        acts.append(y)
     return acts[-1][0], acts
 
 
@@ -154,13 +161,15 @@ def backward(f: dirac.Fields, weights, acts, g_out: np.ndarray, bf16_inputs: boo
     return g[0], grads
 
 
-def loss_and_grads(f: dirac.Fields, weights, pairs, bf16_inputs: bool = False, last_contract_first: bool = False):
-    """L = mean_i |N(r_i) - e_i|^2 / |e_i|^2 and dL/dW* per layer (forward as in forward())."""
+def loss_and_grads(f: dirac.Fields, weights, pairs, bf16_inputs: bool = False, last_contract_first: bool = False,
+                   bf16_storage: bool = False):
+    """L = mean_i |N(r_i) - e_i|^2 / |e_i|^2 and dL/dW* per layer (forward as in forward(); the
+    gradients treat each rounding as the identity, with the rounded activations)."""
     total = 0.0
     gsum = [np.zeros_like(W) for W in weights]
     n = len(pairs)
     for r, e in pairs:
-        y, acts = forward(f, weights, r, bf16_inputs, last_contract_first)
+        y, acts = forward(f, weights, r, bf16_inputs, last_contract_first, bf16_storage)
         ne2 = np.vdot(e, e).real
         d = y - e
         total += np.vdot(d, d).real / ne2 / n

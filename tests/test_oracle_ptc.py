@@ -204,3 +204,33 @@ def test_contract_first_rounds_the_untransported_inputs():
     y, _ = ptc.forward(f2, ws, xs2[0])
     yc, _ = ptc.forward(f2, ws, xs2[0], last_contract_first=True)
     assert np.abs(y - yc).max() < 1e-13 * np.abs(y).max()
+
+
+def test_bf16_storage_rounds_the_hidden_activations_only():
+    """With BF16 storage every hidden activation is a BF16 value (rounding it again changes
+    nothing) while input and output are untouched; on signed-permutation transports with an
+    integer input, the transported values of BF16 activations are BF16 values themselves, so the
+    extra input rounding changes nothing; on a random field the stored form stays within the
+    BF16 unit roundoff of the exact network."""
+    f = _exact_fields()
+    rng = np.random.default_rng(11)
+    r = (rng.integers(-8, 8, size=(f.V, 4, 3)) + 1j * rng.integers(-8, 8, size=(f.V, 4, 3))).astype(np.complex128)
+    ws = ptc.init_weights((1, 3, 2, 1), seed=5, scale=1.0)
+    y_s, acts = ptc.forward(f, ws, r, bf16_storage=True)
+    for a in acts[1:-1]:
+        for v in a:
+            assert np.array_equal(ptc.round_bf16(v), v)
+    assert acts[0][0] is r
+    y_plain, acts_plain = ptc.forward(f, ws, r)
+    assert not np.array_equal(acts_plain[1][0], acts[1][0])  # the hidden layer was rounded
+    assert np.abs(y_s - y_plain).max() > 1e-4 * np.abs(y_plain).max()
+    y_both, _ = ptc.forward(f, ws, r, bf16_inputs=True, last_contract_first=True, bf16_storage=True)
+    y_cf, _ = ptc.forward(f, ws, r, last_contract_first=True, bf16_storage=True)
+    assert np.abs(y_both - y_cf).max() < 1e-12 * np.abs(y_cf).max()
+    f2 = fields()
+    r2 = gen.gaussian_spinor(f2.p.dims, 12)
+    ws2 = ptc.init_weights((1, 2, 2, 1), seed=6, scale=1.0)
+    e, _ = ptc.forward(f2, ws2, r2)
+    m, _ = ptc.forward(f2, ws2, r2, bf16_inputs=True, last_contract_first=True, bf16_storage=True)
+    d = np.linalg.norm(m - e) / np.linalg.norm(e)
+    assert 1e-5 < d < 2.0 ** -6
