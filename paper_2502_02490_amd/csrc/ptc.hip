@@ -28,7 +28,6 @@ constexpr int kTile = 64;  // sites per work-group of the weight-gradient kernel
 struct PtcGeom {
     Geom g;
     const float4 *flinks[2];  // per parity: full FP32 links F = e^{i omega} U, [8 dir][5 planes] blocked
-    size_t chan;              // floats per channel (a full NATIVE FP32 vector)
 };
 
 // The network's transports use the links with the U(1) and boundary phase folded in and the
@@ -76,17 +75,37 @@ __global__ void k_full_links(Geom g, int p, const float4 *__restrict__ links, co
     }
 }
 
+// Storage of an activation channel: a full NATIVE field (both parities), FP32 (six 16-byte
+// planes of 4 reals per site) or BF16 (three planes of 8 reals).  The network's input and
+// output and every gradient are FP32; its hidden activations are BF16, the precision in which
+// the matrix cores read them anyway.
+template <typename A> struct Act;
+template <> struct Act<float> {
+    using vec = float4;
+    static constexpr int planes = 6;
+};
+template <> struct Act<__hip_bfloat16> {
+    using vec = uint4;
+    static constexpr int planes = 3;
+};
+using bf16s = __hip_bfloat16;
+template <typename A> HD size_t chan_vecs(int vhp) { return (size_t)2 * Act<A>::planes * vhp; }  // per channel
+template <typename A> HD size_t half_vecs(int vhp) { return (size_t)Act<A>::planes * vhp; }      // per parity
+
 // Raw data of one transport: the (neighbour's) spinor and, for a hop, the full link.
-struct TRaw {
-    float4 sp[6];
+template <typename A> struct TRaw {
+    typename Act<A>::vec sp[Act<A>::planes];
     float4 lk[kFullPlanes];
 };
 
 // Load what T_path x_c needs at site (p, i) with coordinates x.  Every field of r is written on
 // every path (the link is zero for the unshifted path), so the compiler keeps r in registers.
-DEV void transport_load(const PtcGeom &a, const float4 *xc, int p, uint32_t i, const int x[4], int path, TRaw &r) {
-    const size_t hv = (size_t)6 * a.g.vhp;  // float4 per half vector
-    const int n = path - 1;                 // direction index 2 mu + back (path > 0)
+template <typename A>
+DEV void transport_load(const PtcGeom &a, const typename Act<A>::vec *xc, int p, uint32_t i, const int x[4], int path,
+                        TRaw<A> &r) {
+    constexpr int NP = Act<A>::planes;
+    const size_t hv = half_vecs<A>(a.g.vhp);
+    const int n = path - 1;  // direction index 2 mu + back (path > 0)
     const int mu = n >> 1, back = n & 1;
     int y[4] = {x[0], x[1], x[2], x[3]};
     if (path > 0) {
@@ -97,9 +116,9 @@ DEV void transport_load(const PtcGeom &a, const float4 *xc, int p, uint32_t i, c
     }
     const uint32_t j = path > 0 ? (uint32_t)half_index(a.g, y) : i;
     const int q = path > 0 ? 1 - p : p;
-    const float4 *b = site_ptr(xc + q * hv, j, 6);
+    const typename Act<A>::vec *b = site_ptr(xc + q * hv, j, NP);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.sp[k] = b[k * kSB];
+    for (int k = 0; k < NP; ++k) r.sp[k] = b[k * kSB];
     if (path > 0) {
         const float4 *lb = site_ptr(a.flinks[p] + (size_t)n * kFullPlanes * a.g.vhp, i, kFullPlanes);
 #pragma unroll
@@ -119,10 +138,16 @@ DEV void unpack4(const float4 *v, int nv, float *o) {
         o[4 * k + 3] = v[k].w;
     }
 }
+DEV void unpack_sp(const float4 *v, float *o) { unpack4(v, 6, o); }
+DEV void unpack_sp(const uint4 *v, float *o) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) St<__hip_bfloat16>::unpack(v[k], o + 8 * k);
+}
 
-DEV void transport_compute(const TRaw &r, int path, C<float> t[12]) {
+template <typename A>
+DEV void transport_compute(const TRaw<A> &r, int path, C<float> t[12]) {
     float sp[24];
-    unpack4(r.sp, 6, sp);
+    unpack_sp(r.sp, sp);
     if (path == 0) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) t[k] = mk(sp[2 * k], sp[2 * k + 1]);
@@ -155,11 +180,31 @@ DEV void transport_compute(const TRaw &r, int path, C<float> t[12]) {
 }
 
 // t = T_path x_c at site (p, i)
-DEV void transport_site(const PtcGeom &a, const float4 *xc, int p, uint32_t i, const int x[4], int path,
-                        C<float> t[12]) {
-    TRaw r;
-    transport_load(a, xc, p, i, x, path, r);
-    transport_compute(r, path, t);
+template <typename A>
+DEV void transport_site(const PtcGeom &a, const typename Act<A>::vec *xc, int p, uint32_t i, const int x[4],
+                        int path, C<float> t[12]) {
+    TRaw<A> r;
+    transport_load<A>(a, xc, p, i, x, path, r);
+    transport_compute<A>(r, path, t);
+}
+
+// Store 12 consecutive reals (reals 12 h .. 12 h + 11 of the 24, half h of the spinor) of site
+// i of parity p of channel c.
+DEV void store_half(float4 *base, int vhp, int c, int p, uint32_t i, int h, const float r[12]) {
+    float4 *dst = site_ptr(base + c * chan_vecs<float>(vhp) + p * half_vecs<float>(vhp), i, 6) + 3 * h * kSB;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) st_stream(dst + k * kSB, make_float4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]));
+}
+DEV void store_half(uint4 *base, int vhp, int c, int p, uint32_t i, int h, const float r[12]) {
+    uint4 *site = site_ptr(base + c * chan_vecs<bf16s>(vhp) + p * half_vecs<bf16s>(vhp), i, 3);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int r0 = 12 * h + 4 * k;  // plane r0 / 8, half (r0 % 8) / 4 of it
+        uint2 *dst = reinterpret_cast<uint2 *>(site + (r0 >> 3) * kSB) + ((r0 >> 2) & 1);
+        const uint32_t lo = St<bf16s>::rne(r[4 * k]) | (St<bf16s>::rne(r[4 * k + 1]) << 16);
+        const uint32_t hi = St<bf16s>::rne(r[4 * k + 2]) | (St<bf16s>::rne(r[4 * k + 3]) << 16);
+        st_stream(dst, make_uint2(lo, hi));
+    }
 }
 
 // ------------------------------------------------------------------ matrix-core layer
@@ -240,9 +285,10 @@ __global__ void k_ptc_zfrag(int nin, int nm, const uint32_t *__restrict__ W, uin
 // (p < 9) are formed from this layer's accumulators in registers -- the 16x16 accumulator tile t
 // of a lane is, rounded to BF16, its B operand of depth step t on the 16x16x16 instruction -- and
 // written to zout as 9 channels; y itself is written only when store_y is set.
-template <int NIN, int NM, bool ZOUT>
+template <int NIN, int NM, bool ZOUT, typename AI, typename AO>
 __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, const uint4 *__restrict__ Af,
-                                                        const float4 *__restrict__ xin, float4 *__restrict__ yout,
+                                                        const typename Act<AI>::vec *__restrict__ xin,
+                                                        typename Act<AO>::vec *__restrict__ yout,
                                                         const uint2 *__restrict__ Az, float4 *__restrict__ zout,
                                                         int store_y) {
     constexpr int NPAIR = kPaths * NIN, NK = (NPAIR + 3) / 4;
@@ -252,7 +298,7 @@ __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, sl = lane & 15;
     const int nbp = (a.g.vh + 63) / 64;
-    const size_t chan4 = a.chan / 4, hv = (size_t)6 * a.g.vhp;
+    const size_t chin = chan_vecs<AI>(a.g.vhp);
 #pragma nounroll
     for (int blk = blockIdx.x; blk < 2 * nbp; blk += gridDim.x) {
         const int p = blk >= nbp;
@@ -276,13 +322,13 @@ __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, 
             if constexpr (NPAIR % 4 != 0) return pr < NPAIR ? pr : NPAIR - 1;
             return pr;
         };
-        auto load = [&](int q, TRaw &r) {
+        auto load = [&](int q, TRaw<AI> &r) {
             const int pair = pair_of(q);
-            transport_load(a, xin + (size_t)(pair % NIN) * chan4, p, ic, x, pair / NIN, r);
+            transport_load<AI>(a, xin + (size_t)(pair % NIN) * chin, p, ic, x, pair / NIN, r);
         };
-        auto step = [&](int q, const TRaw &r) {
+        auto step = [&](int q, const TRaw<AI> &r) {
             C<float> tr[12];
-            transport_compute(r, pair_of(q) / NIN, tr);
+            transport_compute<AI>(r, pair_of(q) / NIN, tr);
             bf16x8_t b[3];
 #pragma unroll
             for (int col = 0; col < 3; ++col) {
@@ -302,7 +348,7 @@ __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, 
         };
         // software pipeline over two register sets: the loads of K step q + 1 are issued before
         // the transport and the matrix-core work of step q
-        TRaw ra, rb;
+        TRaw<AI> ra, rb;
         load(0, ra);
 #pragma nounroll
         for (int q = 0; q < NK; q += 2) {
@@ -315,16 +361,13 @@ __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, 
         }
         // lane (g, site) holds rows m = 16 t + 4 g + r, r < 4: channel 2 t + g / 2, spins
         // 2 (g & 1) + r / 2, re/im r & 1 -- twelve consecutive reals (three planes) of one spinor
-        auto store_tile = [&](const f32x4_t (&v)[3], float4 *base, int c) {
+        auto store_tile = [&](const f32x4_t (&v)[3], auto *base, int c) {
             float r[12];
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
                 for (int col = 0; col < 3; ++col) r[6 * (rr >> 1) + 2 * col + (rr & 1)] = v[col][rr];
-            float4 *dst = site_ptr(base + (size_t)c * chan4 + p * hv, (uint32_t)i, 6) + 3 * (g & 1) * kSB;
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                st_stream(dst + k * kSB, make_float4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]));
+            store_half(base, a.g.vhp, c, p, (uint32_t)i, g & 1, r);
         };
         if (!ZOUT || store_y) {
             if (on) {
@@ -368,21 +411,21 @@ __global__ __launch_bounds__(256) void k_ptc_tsum(PtcGeom a, const float4 *__res
     const uint32_t i = (uint32_t)(s - p * a.g.vh);
     int x[4];
     site_coords(a.g, (int)i, p, x);
-    const size_t chan4 = a.chan / 4, hv = (size_t)6 * a.g.vhp;
+    const size_t chz = chan_vecs<float>(a.g.vhp);
     C<float> acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = mk(0.f, 0.f);
 #pragma nounroll
     for (int path = 0; path < kPaths; ++path) {
         C<float> t[12];
-        transport_site(a, z + (size_t)path * chan4, p, i, x, path, t);
+        transport_site<float>(a, z + (size_t)path * chz, p, i, x, path, t);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             acc[k].r += t[k].r;
             acc[k].i += t[k].i;
         }
     }
-    float4 *dst = site_ptr(y + p * hv, i, 6);
+    float4 *dst = site_ptr(y + p * half_vecs<float>(a.g.vhp), i, 6);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
         st_stream(dst + k * kSB, make_float4(acc[2 * k].r, acc[2 * k].i, acc[2 * k + 1].r, acc[2 * k + 1].i));
@@ -395,14 +438,14 @@ __global__ __launch_bounds__(256) void k_ptc_tsum(PtcGeom a, const float4 *__res
 // pair at a time, computes its transport at the 64 sites into its own LDS slot and reduces the
 // 16 NOUT outputs of that pair over the tile (sites, then colours, in index order).  Every entry
 // of the slice belongs to one lane, so the running sums need no atomics and are deterministic.
-template <int NOUT>
-__global__ __launch_bounds__(256) void k_ptc_wgrad(PtcGeom a, int nin, const float4 *__restrict__ xin,
+template <int NOUT, typename AI>
+__global__ __launch_bounds__(256) void k_ptc_wgrad(PtcGeom a, int nin, const typename Act<AI>::vec *__restrict__ xin,
                                                    const float4 *__restrict__ g, float2 *__restrict__ part) {
     __shared__ C<float> gs[NOUT][kTile][12];
     __shared__ C<float> ts[4][kTile][12];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
     const int ntile = (2 * a.g.vh + kTile - 1) / kTile;
-    const size_t chan4 = a.chan / 4, hv = (size_t)6 * a.g.vhp;
+    const size_t chg = chan_vecs<float>(a.g.vhp), hg = half_vecs<float>(a.g.vhp), chin = chan_vecs<AI>(a.g.vhp);
     const int npair = kPaths * nin;
     float2 *slice = part + (size_t)blockIdx.x * npair * NOUT * 16;
 #pragma nounroll
@@ -417,7 +460,7 @@ __global__ __launch_bounds__(256) void k_ptc_wgrad(PtcGeom a, int nin, const flo
         __syncthreads();  // the previous tile's reads of gs and ts are done
         for (int c = wave; c < NOUT; c += 4) {
             float r[24];
-            if (on) load_field<float, 24>(g + c * chan4 + p * hv, i, r);
+            if (on) load_field<float, 24>(g + c * chg + p * hg, i, r);
 #pragma unroll
             for (int k = 0; k < 12; ++k) gs[c][lane][k] = on ? mk(r[2 * k], r[2 * k + 1]) : mk(0.f, 0.f);
         }
@@ -427,7 +470,7 @@ __global__ __launch_bounds__(256) void k_ptc_wgrad(PtcGeom a, int nin, const flo
             const int path = pr / nin, cp = pr % nin;
             C<float> t[12];
             if (on && pr < npair) {
-                transport_site(a, xin + cp * chan4, p, i, x, path, t);
+                transport_site<AI>(a, xin + cp * chin, p, i, x, path, t);
             } else {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) t[k] = mk(0.f, 0.f);
@@ -554,6 +597,9 @@ void build_afrags(int nin, int nout, const uint32_t *W, uint4 *Af, hipStream_t s
     HIP_CHECK(hipGetLastError());
 }
 
+// Storage of a layer's input and output: FP32 -> FP32 (the input-gradient pass, and a network of
+// one layer), FP32 -> BF16 (the first layer), BF16 -> BF16 (the hidden layers).
+enum class Io { F32, In, Mid };
 // The optional ZOUT arguments (Az, z, store_y) select the variant that also forms the
 // contractions of a contract-first last layer.
 struct ZArgs {
@@ -561,35 +607,45 @@ struct ZArgs {
     void *z = nullptr;
     bool store_y = true;
 };
+template <int NIN, int NM, bool ZOUT, typename AI, typename AO>
+void launch_io(int grid, const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, const ZArgs &zo,
+               hipStream_t s) {
+    k_ptc_layer_mfma<NIN, NM, ZOUT, AI, AO><<<grid, 256, 0, s>>>(
+        a, nout, Af, (const typename Act<AI>::vec *)x, (typename Act<AO>::vec *)y, zo.Az, (float4 *)zo.z,
+        zo.store_y ? 1 : 0);
+}
 template <int NIN, int NM>
-void launch_layer(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, const ZArgs &zo,
+void launch_layer(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, const ZArgs &zo, Io io,
                   hipStream_t s) {
     const int nblk = 2 * (int)((a.g.vh + 63) / 64);
     const int grid = std::min(nblk, 2 * compute_units());
-    if (zo.z)
-        k_ptc_layer_mfma<NIN, NM, true><<<grid, 256, 0, s>>>(a, nout, Af, (const float4 *)x, (float4 *)y, zo.Az,
-                                                             (float4 *)zo.z, zo.store_y ? 1 : 0);
-    else
-        k_ptc_layer_mfma<NIN, NM, false><<<grid, 256, 0, s>>>(a, nout, Af, (const float4 *)x, (float4 *)y, nullptr,
-                                                              nullptr, 1);
+    if (zo.z) {
+        if (io == Io::In) launch_io<NIN, NM, true, float, bf16s>(grid, a, nout, Af, x, y, zo, s);
+        else if (io == Io::Mid) launch_io<NIN, NM, true, bf16s, bf16s>(grid, a, nout, Af, x, y, zo, s);
+        else throw Error(DIRAC_EUNSUPPORTED, "contract-first epilogue needs a BF16 layer output");
+    } else {
+        if (io == Io::In) launch_io<NIN, NM, false, float, bf16s>(grid, a, nout, Af, x, y, zo, s);
+        else if (io == Io::Mid) launch_io<NIN, NM, false, bf16s, bf16s>(grid, a, nout, Af, x, y, zo, s);
+        else launch_io<NIN, NM, false, float, float>(grid, a, nout, Af, x, y, zo, s);
+    }
 }
 template <int NIN>
-void launch_layer_nm(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, const ZArgs &zo,
+void launch_layer_nm(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, const ZArgs &zo, Io io,
                      hipStream_t s) {
     switch (row_tiles(nout)) {
-        case 1: launch_layer<NIN, 1>(a, nout, Af, x, y, zo, s); break;
-        case 2: launch_layer<NIN, 2>(a, nout, Af, x, y, zo, s); break;
-        default: launch_layer<NIN, 4>(a, nout, Af, x, y, zo, s); break;
+        case 1: launch_layer<NIN, 1>(a, nout, Af, x, y, zo, io, s); break;
+        case 2: launch_layer<NIN, 2>(a, nout, Af, x, y, zo, io, s); break;
+        default: launch_layer<NIN, 4>(a, nout, Af, x, y, zo, io, s); break;
     }
 }
 // y = layer(x) with the A fragments Af of a (nin -> nout) layer
-void layer_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const uint4 *Af, void *y, hipStream_t s,
+void layer_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const uint4 *Af, void *y, Io io, hipStream_t s,
                     const ZArgs &zo = ZArgs()) {
     switch (nin) {
-        case 1: launch_layer_nm<1>(a, nout, Af, x, y, zo, s); break;
-        case 2: launch_layer_nm<2>(a, nout, Af, x, y, zo, s); break;
-        case 4: launch_layer_nm<4>(a, nout, Af, x, y, zo, s); break;
-        case 8: launch_layer_nm<8>(a, nout, Af, x, y, zo, s); break;
+        case 1: launch_layer_nm<1>(a, nout, Af, x, y, zo, io, s); break;
+        case 2: launch_layer_nm<2>(a, nout, Af, x, y, zo, io, s); break;
+        case 4: launch_layer_nm<4>(a, nout, Af, x, y, zo, io, s); break;
+        case 8: launch_layer_nm<8>(a, nout, Af, x, y, zo, io, s); break;
         default: throw Error(DIRAC_EUNSUPPORTED, "PTC channel counts must be 1, 2, 4 or 8");
     }
     HIP_CHECK(hipGetLastError());
@@ -600,16 +656,21 @@ int wgrad_grid(size_t vh) {
     return (int)std::min(ntile, (size_t)2 * compute_units());
 }
 template <int NOUT>
-void launch_wgrad(const PtcGeom &a, int nin, const void *x, const void *g, void *part, hipStream_t s) {
-    k_ptc_wgrad<NOUT><<<wgrad_grid(a.g.vh), 256, 0, s>>>(a, nin, (const float4 *)x, (const float4 *)g,
-                                                         (float2 *)part);
+void launch_wgrad(const PtcGeom &a, int nin, const void *x, bool x_bf16, const void *g, void *part, hipStream_t s) {
+    if (x_bf16)
+        k_ptc_wgrad<NOUT, bf16s><<<wgrad_grid(a.g.vh), 256, 0, s>>>(a, nin, (const uint4 *)x, (const float4 *)g,
+                                                                    (float2 *)part);
+    else
+        k_ptc_wgrad<NOUT, float><<<wgrad_grid(a.g.vh), 256, 0, s>>>(a, nin, (const float4 *)x, (const float4 *)g,
+                                                                    (float2 *)part);
 }
-void wgrad_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const void *g, void *part, hipStream_t s) {
+void wgrad_dispatch(const PtcGeom &a, int nin, int nout, const void *x, bool x_bf16, const void *g, void *part,
+                    hipStream_t s) {
     switch (nout) {
-        case 1: launch_wgrad<1>(a, nin, x, g, part, s); break;
-        case 2: launch_wgrad<2>(a, nin, x, g, part, s); break;
-        case 4: launch_wgrad<4>(a, nin, x, g, part, s); break;
-        case 8: launch_wgrad<8>(a, nin, x, g, part, s); break;
+        case 1: launch_wgrad<1>(a, nin, x, x_bf16, g, part, s); break;
+        case 2: launch_wgrad<2>(a, nin, x, x_bf16, g, part, s); break;
+        case 4: launch_wgrad<4>(a, nin, x, x_bf16, g, part, s); break;
+        case 8: launch_wgrad<8>(a, nin, x, x_bf16, g, part, s); break;
         default: throw Error(DIRAC_EUNSUPPORTED, "PTC output channels must be 1, 2, 4 or 8");
     }
     HIP_CHECK(hipGetLastError());
@@ -631,7 +692,6 @@ PtcGeom geom_of(dirac_ctx *c, hipStream_t s) {
     PtcGeom a;
     a.g = c->g;
     for (int p = 0; p < 2; ++p) a.flinks[p] = (const float4 *)c->ptc_links[p].p;
-    a.chan = (size_t)48 * c->g.vhp;
     return a;
 }
 
@@ -688,10 +748,16 @@ void ptc_refresh_bf16(dirac_ptc *n, hipStream_t s) {
     refresh_afrags(n, s);
 }
 
+// Activation l is stored in BF16 when it is a hidden layer's (0 < l < nlayers), else in FP32.
+static bool act_bf16(const dirac_ptc *n, int l) { return l > 0 && l < n->nlayers; }
+static size_t act_chan_bytes(const dirac_ctx *c, const dirac_ptc *n, int l) {
+    return act_bf16(n, l) ? chan_vecs<bf16s>(c->g.vhp) * sizeof(uint4) : chan_vecs<float>(c->g.vhp) * sizeof(float4);
+}
+
 void ptc_ensure_acts(dirac_ctx *c, dirac_ptc *n) {
-    const size_t chanb = (size_t)48 * c->g.vhp * sizeof(float);
+    const size_t chanb = chan_vecs<float>(c->g.vhp) * sizeof(float4);
     size_t need = 0;
-    for (int l = 0; l <= n->nlayers; ++l) need += (size_t)n->ch[l] * chanb;
+    for (int l = 0; l <= n->nlayers; ++l) need += (size_t)n->ch[l] * act_chan_bytes(c, n, l);
     n->acts.alloc(need);
     int maxc = 0;
     for (int l = 0; l <= n->nlayers; ++l) maxc = std::max(maxc, n->ch[l]);
@@ -703,10 +769,9 @@ void ptc_ensure_acts(dirac_ctx *c, dirac_ptc *n) {
 }
 
 float *ptc_act(dirac_ctx *c, dirac_ptc *n, int l) {
-    const size_t chan = (size_t)48 * c->g.vhp;
     size_t off = 0;
-    for (int k = 0; k < l; ++k) off += (size_t)n->ch[k] * chan;
-    return (float *)n->acts.p + off;
+    for (int k = 0; k < l; ++k) off += (size_t)n->ch[k] * act_chan_bytes(c, n, k);
+    return (float *)((char *)n->acts.p + off);
 }
 
 // forward: acts[0] must hold the input; leaves the output in acts[nlayers] and, with keep_all,
@@ -722,8 +787,9 @@ void ptc_forward_acts(dirac_ctx *c, dirac_ptc *n, hipStream_t s, bool keep_all) 
             zo.z = n->zbuf.p;
             zo.store_y = keep_all;
         }
+        const Io io = act_bf16(n, l + 1) ? (act_bf16(n, l) ? Io::Mid : Io::In) : Io::F32;
         layer_dispatch(a, n->ch[l], n->ch[l + 1], ptc_act(c, n, l), (const uint4 *)n->afw.p + n->afw_off[l],
-                       ptc_act(c, n, l + 1), s, zo);
+                       ptc_act(c, n, l + 1), io, s, zo);
     }
     if (cf) {
         k_ptc_tsum<<<(int)((2 * c->vh + 255) / 256), 256, 0, s>>>(a, (const float4 *)n->zbuf.p,
@@ -736,7 +802,7 @@ void ptc_forward_acts(dirac_ctx *c, dirac_ptc *n, hipStream_t s, bool keep_all) 
 // n->grad and, when gin is given, writes dL/dx* of the input.
 void ptc_backward_acts(dirac_ctx *c, dirac_ptc *n, const void *g_out, void *gin, hipStream_t s) {
     PtcGeom a = geom_of(c, s);
-    const size_t chanb = (size_t)48 * c->g.vhp * sizeof(float);
+    const size_t chanb = chan_vecs<float>(c->g.vhp) * sizeof(float4);
     int maxc = 0;
     for (int l = 0; l <= n->nlayers; ++l) maxc = std::max(maxc, n->ch[l]);
     char *gA = (char *)n->gbuf.p, *gB = gA + (size_t)maxc * chanb;
@@ -745,7 +811,7 @@ void ptc_backward_acts(dirac_ctx *c, dirac_ptc *n, const void *g_out, void *gin,
     for (int l = n->nlayers - 1; l >= 0; --l) {
         const int nin = n->ch[l], nout = n->ch[l + 1];
         const int nw = (int)ptc_nweights(n, l);
-        wgrad_dispatch(a, nin, nout, ptc_act(c, n, l), gA, n->part.p, s);
+        wgrad_dispatch(a, nin, nout, ptc_act(c, n, l), act_bf16(n, l), gA, n->part.p, s);
         k_ptc_reduce<<<(nw + kRedK - 1) / kRedK, 256, 0, s>>>(nslice, nw, (const float2 *)n->part.p,
                                                       (float2 *)n->grad.p + n->off[l]);
         HIP_CHECK(hipGetLastError());
@@ -756,7 +822,7 @@ void ptc_backward_acts(dirac_ctx *c, dirac_ptc *n, const void *g_out, void *gin,
         uint4 *afb = (uint4 *)n->afb.p + n->afb_off[l];
         build_afrags(nout, nin, (const uint32_t *)n->wt.p + n->off[l], afb, s);
         void *dst = l == 0 ? gin : (void *)gB;
-        layer_dispatch(a, nout, nin, gA, afb, dst, s);
+        layer_dispatch(a, nout, nin, gA, afb, dst, Io::F32, s);
         std::swap(gA, gB);
     }
 }

@@ -5,7 +5,8 @@ The GPU layer runs on the BF16 matrix cores: BF16 working weights, each transpor
 rounded to BF16 from its FP32 value, FP32 accumulation.  The oracle is given the same
 BF16-rounded weights and rounds its transported inputs the same way (bf16_inputs=True); a last
 layer with one output channel is summed contract-first, sum_p T_p (sum_c' W x_c'), with its
-untransported inputs rounded (last_contract_first=True).  What
+untransported inputs rounded (last_contract_first=True); hidden activations are stored in BF16
+(bf16_storage=True).  What
 remains is FP32 arithmetic, and the rare element whose BF16 rounding goes the other way because
 the FP32 transport and the FP64 one straddle a rounding boundary (about 5e-5 of the elements,
 each off by one BF16 step, 2^-8 relative): a few 1e-5 in norm.  The bar, 3e-4, is ten times
@@ -25,6 +26,9 @@ from oracle import ptc as optc
 from oracle import solvers as osolvers
 
 pytestmark = pytest.mark.gpu
+
+# the library's rounding model of the network (see the oracle's forward())
+MODEL = dict(bf16_inputs=True, last_contract_first=True, bf16_storage=True)
 
 
 def bf16(a):
@@ -60,7 +64,7 @@ def test_forward_matches_oracle(case):
     net.set_weights(ws)
     wq = [bf16(w) for w in ws]
     r = c.spinor(7).astype(np.complex64).astype(np.complex128)
-    y, _ = optc.forward(c.f, wq, r, bf16_inputs=True, last_contract_first=True)
+    y, _ = optc.forward(c.f, wq, r, **MODEL)
     out = c.D.native_empty("f32")
     net.forward(c.D, out, to_f32_native(c.D, r))
     err = rel(from_f32_native(c.D, out), y)
@@ -75,7 +79,7 @@ def test_backward_matches_oracle(case):
     wq = [bf16(w) for w in ws]
     r = c.spinor(8).astype(np.complex64).astype(np.complex128)
     g = c.spinor(9).astype(np.complex64).astype(np.complex128)
-    _, acts = optc.forward(c.f, wq, r, bf16_inputs=True)
+    _, acts = optc.forward(c.f, wq, r, **MODEL)
     gx, gW = optc.backward(c.f, wq, acts, g, bf16_inputs=True)
     net.zero_grad()
     gin = c.D.native_empty("f32")
@@ -100,7 +104,7 @@ def test_other_networks_forward(case, channels):
         net.set_weights(ws)
         wq = [bf16(w) for w in ws]
         r = c.spinor(13).astype(np.complex64).astype(np.complex128)
-        y, _ = optc.forward(c.f, wq, r, bf16_inputs=True, last_contract_first=True)
+        y, _ = optc.forward(c.f, wq, r, **MODEL)
         y_exact, _ = optc.forward(c.f, wq, r)
         out = c.D.native_empty("f32")
         net.forward(c.D, out, to_f32_native(c.D, r))
@@ -130,7 +134,7 @@ def test_gradients_over_many_tiles():
         wq = [bf16(w) for w in ws]
         r = c.spinor(8).astype(np.complex64).astype(np.complex128)
         g = c.spinor(9).astype(np.complex64).astype(np.complex128)
-        y, acts = optc.forward(c.f, wq, r, bf16_inputs=True, last_contract_first=True)
+        y, acts = optc.forward(c.f, wq, r, **MODEL)
         gx, gW = optc.backward(c.f, wq, acts, g, bf16_inputs=True)
         out = c.D.native_empty("f32")
         net.forward(c.D, out, to_f32_native(c.D, r))
@@ -175,7 +179,7 @@ def test_train_step_loss_and_update(case):
     wq = [bf16(w) for w in ws]
     pairs = [(c.spinor(20 + k).astype(np.complex64).astype(np.complex128),
               c.spinor(30 + k).astype(np.complex64).astype(np.complex128)) for k in range(2)]
-    L, g = optc.loss_and_grads(c.f, wq, pairs, bf16_inputs=True, last_contract_first=True)
+    L, g = optc.loss_and_grads(c.f, wq, pairs, **MODEL)
     rs = [to_f32_native(c.D, r) for r, _ in pairs]
     es = [to_f32_native(c.D, e) for _, e in pairs]
     lr = 1e-3
