@@ -346,17 +346,22 @@ __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, 
                     acc[t][col] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, b[col], acc[t][col], 0, 0, 0);
             }
         };
-        // software pipeline over two register sets: the loads of K step q + 1 are issued before
-        // the transport and the matrix-core work of step q
-        TRaw<AI> ra, rb;
+        // software pipeline over three register sets in turn: the loads of K step q + 2 are
+        // issued before the transport and the matrix-core work of step q
+        TRaw<AI> ra, rb, rc;
         load(0, ra);
+        if (1 < NK) load(1, rb);
 #pragma nounroll
-        for (int q = 0; q < NK; q += 2) {
-            if (q + 1 < NK) load(q + 1, rb);
+        for (int q = 0; q < NK; q += 3) {
+            if (q + 2 < NK) load(q + 2, rc);
             step(q, ra);
             if (q + 1 < NK) {
-                if (q + 2 < NK) load(q + 2, ra);
+                if (q + 3 < NK) load(q + 3, ra);
                 step(q + 1, rb);
+            }
+            if (q + 2 < NK) {
+                if (q + 4 < NK) load(q + 4, rb);
+                step(q + 2, rc);
             }
         }
         // lane (g, site) holds rows m = 16 t + 4 g + r, r < 4: channel 2 t + g / 2, spins
