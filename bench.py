@@ -210,8 +210,9 @@ PTC_BYTES_PER_SITE = 1280 + 1952 + 1280
 
 def ptc_kernels(reps: int):
     """The network's kernels alone on 32^3 x 64 (seed 505 field, seed-7 initial weights): one
-    forward application and one backward pass (forward with every activation kept, weight and
-    input gradients), timed with HIP events; one JSON line."""
+    forward application, one even-odd application (the Schur-system preconditioner: even half in,
+    even half out) and one backward pass (forward with every activation kept, weight and input
+    gradients), timed with HIP events; one JSON line."""
     import torch
 
     import gen
@@ -231,10 +232,15 @@ def ptc_kernels(reps: int):
         net.forward(D, vout, vin)
         net.backward(D, gin, vin, g)
     t_f = timed(lambda: net.forward(D, vout, vin), reps, stream) / reps
+    half = vin.numel() // 2
+    vin_e, vout_e = vin[:half].clone(), torch.empty_like(vin[:half])
+    net.forward_eo(D, vout_e, vin_e)
+    t_eo = timed(lambda: net.forward_eo(D, vout_e, vin_e), reps, stream) / reps
     t_b = timed(lambda: net.backward(D, gin, vin, g), max(1, reps // 4), stream) / max(1, reps // 4)
     V = math.prod(d)
     out = {"lattice": "x".join(map(str, d)), "channels": [1, 8, 8, 1],
-           "forward_ms": round(t_f * 1e3, 3), "backward_ms": round(t_b * 1e3, 3),
+           "forward_ms": round(t_f * 1e3, 3), "forward_eo_ms": round(t_eo * 1e3, 3),
+           "backward_ms": round(t_b * 1e3, 3),
            "forward_algorithmic_GBps": round(PTC_BYTES_PER_SITE * V / t_f / 1e9, 1),
            "forward_frac_of_8TBps": round(PTC_BYTES_PER_SITE * V / t_f / 8e12, 3),
            "forward_contraction_TFLOPs": round(PTC_FLOP_PER_SITE * V / t_f / 1e12, 1)}

@@ -234,8 +234,11 @@ dirac_status dirac_solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x
  *   T_{+mu} psi(x) = V_mu(x) b+_mu(x) psi(x + mu),  T_{-mu} psi(x) = V_mu(x - mu)^dag b-_mu(x) psi(x - mu),
  * W[p][c][c'] a complex 4x4 spin matrix; no nonlinearity, no bias.  Weights of layer l
  * are [9][c_{l+1}][c_l][4][4] complex, stored as interleaved (re, im) float, layer after
- * layer.  FP32 master weights, BF16 working weights, FP32 activations and accumulation.
- * Activations and gradients are NATIVE F32 full-lattice vectors (one channel in and out).
+ * layer.  FP32 master weights, BF16 working weights; each transported input is rounded to
+ * BF16 for the matrix cores, products accumulate in FP32; hidden activations are stored in
+ * BF16; a last layer (one output channel) is summed as sum_p T_p (sum_c' W x_c') with its
+ * inputs rounded to BF16.  The network's input and output and all gradients are NATIVE F32
+ * full-lattice vectors (one channel in and out).
  * Training: loss L = mean_i |N(r_i) - e_i|^2 / |e_i|^2, gradients dL/dW* (Wirtinger),
  * Adam (lr given, beta = 0.9, 0.999, eps = 1e-8) on (Re W, Im W). */
 dirac_status ptc_create(const int *channels, int nlayers, dirac_ptc **out);  /* channels[0] = channels[nlayers] = 1 */
@@ -247,6 +250,11 @@ dirac_status ptc_get_grad(const dirac_ptc *net, float *host_g, size_t n);   /* a
 dirac_status ptc_zero_grad(dirac_ptc *net, void *stream);
 /* out = N(in) */
 dirac_status ptc_forward(dirac_ctx *ctx, dirac_ptc *net, void *out, const void *in, void *stream);
+/* out_e = [N((in_e, 0))]_e: the network as a preconditioner of the even-odd Schur system.
+ * in_e and out_e are NATIVE F32 even halves (native_bytes of one parity); bitwise equal to the
+ * even half of ptc_forward on (in_e, 0), with the work that only reads the zero odd half or only
+ * feeds the odd half of the output left out.  EINVAL on NULL, undersized or aliasing buffers. */
+dirac_status ptc_forward_eo(dirac_ctx *ctx, dirac_ptc *net, void *out_e, const void *in_e, void *stream);
 /* Given grad_out = dL/dN(in)*, accumulate dL/dW* into the network and, if grad_in is not
  * NULL, write dL/d(in)*.  Recomputes the forward activations of `in`. */
 dirac_status ptc_backward(dirac_ctx *ctx, dirac_ptc *net, void *grad_in, const void *in, const void *grad_out,

@@ -282,6 +282,12 @@ class PTC:
         _lib.check(self.lib.ptc_forward(D._ctx, self._net, _ptr(out, nb), _ptr(inp, nb), _stream(stream)))
         return out
 
+    def forward_eo(self, D: Dirac, out_e, inp_e, stream=None):
+        """out_e = [N((inp_e, 0))]_e on NATIVE F32 even halves (the Schur-system preconditioner)."""
+        nb = D.native_bytes("f32", 1)
+        _lib.check(self.lib.ptc_forward_eo(D._ctx, self._net, _ptr(out_e, nb), _ptr(inp_e, nb), _stream(stream)))
+        return out_e
+
     def backward(self, D: Dirac, grad_in, inp, grad_out, stream=None):
         nb = D.native_bytes("f32", 0)
         _lib.check(self.lib.ptc_backward(D._ctx, self._net, _ptr(grad_in, nb) if grad_in is not None else None,

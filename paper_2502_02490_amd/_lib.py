@@ -19,7 +19,7 @@ EXPORTS = ["dirac_create", "dirac_destroy", "dirac_load_clover", "dirac_get_clov
            "dirac_native_bytes", "dirac_import", "dirac_export", "dirac_apply", "dirac_apply_eo", "dirac_apply_eo_multi",
            "dirac_apply_hop", "dirac_apply_clover", "dirac_solve", "dirac_solve_batched", "dirac_last_error",
            "ptc_create", "ptc_destroy", "ptc_num_weights", "ptc_set_weights", "ptc_get_weights", "ptc_get_grad",
-           "ptc_zero_grad", "ptc_forward", "ptc_backward", "ptc_adam_step", "ptc_get_adam_state", "ptc_set_adam_state",
+           "ptc_zero_grad", "ptc_forward", "ptc_forward_eo", "ptc_backward", "ptc_adam_step", "ptc_get_adam_state", "ptc_set_adam_state",
            "ptc_train_step"]
 
 
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
     lib.ptc_get_grad.argtypes = [vp, vp, ctypes.c_size_t]
     lib.ptc_zero_grad.argtypes = [vp, vp]
     lib.ptc_forward.argtypes = [vp, vp, vp, vp, vp]
+    lib.ptc_forward_eo.argtypes = [vp, vp, vp, vp, vp]
     lib.ptc_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.ptc_adam_step.argtypes = [vp, ctypes.c_double, vp]
     lib.ptc_get_adam_state.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int)]

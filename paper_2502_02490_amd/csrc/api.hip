@@ -509,6 +509,24 @@ dirac_status ptc_forward(dirac_ctx *c, dirac_ptc *n, void *out, const void *in, 
     API_END
 }
 
+dirac_status ptc_forward_eo(dirac_ctx *c, dirac_ptc *n, void *out, const void *in, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    require(n != nullptr, "network is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = native_bytes(c, DIRAC_F32, 1);
+    check_dev(in, nb, "in_e");
+    check_dev(out, nb, "out_e");
+    check_no_alias(out, nb, in, nb);
+    dl::ptc_ensure_acts(c, n);
+    char *a0 = (char *)dl::ptc_act(c, n, 0);
+    HIP_CHECK(hipMemcpyAsync(a0, in, nb, hipMemcpyDeviceToDevice, s));
+    dl::ptc_zero(a0 + nb, nb, s);
+    dl::ptc_forward_acts(c, n, s, false, true);
+    HIP_CHECK(hipMemcpyAsync(out, dl::ptc_act(c, n, n->nlayers), nb, hipMemcpyDeviceToDevice, s));
+    API_END
+}
+
 dirac_status ptc_backward(dirac_ctx *c, dirac_ptc *n, void *grad_in, const void *in, const void *grad_out,
                           void *stream) {
     API_BEGIN

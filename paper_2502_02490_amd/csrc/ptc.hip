@@ -278,6 +278,8 @@ __global__ void k_ptc_zfrag(int nin, int nm, const uint32_t *__restrict__ W, uin
     Az[e] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
 }
 
+constexpr int kEoIn = 1, kEoOut = 2;  // even-odd deployment flags of the layer kernel
+
 // One layer on the matrix cores.  Persistent: the grid's work-groups (4 wavefronts, 16 sites
 // each) sweep the 64-site blocks of both parities; the A fragments are staged once per
 // work-group.  NIN input channels, NM = ceil(8 NOUT / 16) row tiles.
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, 
                                                         const typename Act<AI>::vec *__restrict__ xin,
                                                         typename Act<AO>::vec *__restrict__ yout,
                                                         const uint2 *__restrict__ Az, float4 *__restrict__ zout,
-                                                        int store_y) {
+                                                        int store_y, int eo) {
     constexpr int NPAIR = kPaths * NIN, NK = (NPAIR + 3) / 4;
     __shared__ uint4 af[NK * NM * 64];
     for (int e = threadIdx.x; e < NK * NM * 64; e += 256) af[e] = Af[e];
@@ -348,19 +350,22 @@ __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, 
         };
         // software pipeline over three register sets in turn: the loads of K step q + 2 are
         // issued before the transport and the matrix-core work of step q
+        // kEoIn: the input's odd half is zero, so at an even site every path but the unshifted
+        // one transports zeros; its K steps after those of path 0 add exact zeros and are skipped
+        const int nk = ((eo & kEoIn) && p == 0) ? (NIN + 3) / 4 : NK;
         TRaw<AI> ra, rb, rc;
         load(0, ra);
-        if (1 < NK) load(1, rb);
+        if (1 < nk) load(1, rb);
 #pragma nounroll
-        for (int q = 0; q < NK; q += 3) {
-            if (q + 2 < NK) load(q + 2, rc);
+        for (int q = 0; q < nk; q += 3) {
+            if (q + 2 < nk) load(q + 2, rc);
             step(q, ra);
-            if (q + 1 < NK) {
-                if (q + 3 < NK) load(q + 3, ra);
+            if (q + 1 < nk) {
+                if (q + 3 < nk) load(q + 3, ra);
                 step(q + 1, rb);
             }
-            if (q + 2 < NK) {
-                if (q + 4 < NK) load(q + 4, rb);
+            if (q + 2 < nk) {
+                if (q + 4 < nk) load(q + 4, rb);
                 step(q + 2, rc);
             }
         }
@@ -384,8 +389,12 @@ __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, 
         if constexpr (ZOUT) {
             // every lane takes part in the matrix-core steps; only the stores are masked.  One
             // output tile at a time keeps the extra accumulators at 12 registers.
+            // kEoOut: only the even half of the network's output is wanted, which reads z_0 at even
+            // sites and z_1 .. z_8 at odd ones
+            const bool eo_out = (eo & kEoOut) != 0;
+            const int ntz = eo_out && p == 0 ? 1 : kZTiles;
 #pragma nounroll
-            for (int tz = 0; tz < kZTiles; ++tz) {
+            for (int tz = 0; tz < ntz; ++tz) {
                 f32x4_t zacc[3];
 #pragma unroll
                 for (int col = 0; col < 3; ++col) zacc[col] = f32x4_t{0.f, 0.f, 0.f, 0.f};
@@ -401,7 +410,9 @@ __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, 
                                                                               zacc[col], 0, 0, 0);
                     }
                 }
-                if (on && 2 * tz + (g >> 1) < kPaths) store_tile(zacc, zout, 2 * tz + (g >> 1));
+                const int pz = 2 * tz + (g >> 1);
+                const bool want = !eo_out || (p == 0 ? pz == 0 : pz > 0);
+                if (on && pz < kPaths && want) store_tile(zacc, zout, pz);
             }
         }
     }
@@ -409,9 +420,10 @@ __global__ __launch_bounds__(256, 2) void k_ptc_layer_mfma(PtcGeom a, int nout, 
 
 // y(x) = sum_p (T_p z_p)(x): the transports of a contract-first last layer (one output channel),
 // one thread per site of either parity, the nine terms added in path order in FP32.
-__global__ __launch_bounds__(256) void k_ptc_tsum(PtcGeom a, const float4 *__restrict__ z, float4 *__restrict__ y) {
+__global__ __launch_bounds__(256) void k_ptc_tsum(PtcGeom a, int nparity, const float4 *__restrict__ z,
+                                                  float4 *__restrict__ y) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= 2 * a.g.vh) return;
+    if (s >= nparity * a.g.vh) return;
     const int p = s >= a.g.vh;
     const uint32_t i = (uint32_t)(s - p * a.g.vh);
     int x[4];
@@ -611,13 +623,14 @@ struct ZArgs {
     const uint2 *Az = nullptr;
     void *z = nullptr;
     bool store_y = true;
+    int eo = 0;  // kEoIn, kEoOut
 };
 template <int NIN, int NM, bool ZOUT, typename AI, typename AO>
 void launch_io(int grid, const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, const ZArgs &zo,
                hipStream_t s) {
     k_ptc_layer_mfma<NIN, NM, ZOUT, AI, AO><<<grid, 256, 0, s>>>(
         a, nout, Af, (const typename Act<AI>::vec *)x, (typename Act<AO>::vec *)y, zo.Az, (float4 *)zo.z,
-        zo.store_y ? 1 : 0);
+        zo.store_y ? 1 : 0, zo.eo);
 }
 template <int NIN, int NM>
 void launch_layer(const PtcGeom &a, int nout, const uint4 *Af, const void *x, void *y, const ZArgs &zo, Io io,
@@ -779,9 +792,22 @@ float *ptc_act(dirac_ctx *c, dirac_ptc *n, int l) {
     return (float *)((char *)n->acts.p + off);
 }
 
+__global__ void k_zero16(size_t n, uint4 *__restrict__ p) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = make_uint4(0u, 0u, 0u, 0u);
+}
+// zero `bytes` (a multiple of 16) at p with a kernel, so that a captured graph holds no memset node
+void ptc_zero(void *p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    k_zero16<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, (uint4 *)p);
+    HIP_CHECK(hipGetLastError());
+}
+
 // forward: acts[0] must hold the input; leaves the output in acts[nlayers] and, with keep_all,
-// every layer's output in acts[l + 1] (the backward pass needs them)
-void ptc_forward_acts(dirac_ctx *c, dirac_ptc *n, hipStream_t s, bool keep_all) {
+// every layer's output in acts[l + 1] (the backward pass needs them).  With eo the input's odd
+// half must be zero, and only the even half of the output is formed (a network of one layer
+// forms both).
+void ptc_forward_acts(dirac_ctx *c, dirac_ptc *n, hipStream_t s, bool keep_all, bool eo) {
     PtcGeom a = geom_of(c, s);
     const int L = n->nlayers;
     const bool cf = n->contract_last();
@@ -791,14 +817,17 @@ void ptc_forward_acts(dirac_ctx *c, dirac_ptc *n, hipStream_t s, bool keep_all) 
             zo.Az = (const uint2 *)n->afz.p;
             zo.z = n->zbuf.p;
             zo.store_y = keep_all;
+            if (eo) zo.eo |= kEoOut;
         }
+        if (eo && l == 0) zo.eo |= kEoIn;
         const Io io = act_bf16(n, l + 1) ? (act_bf16(n, l) ? Io::Mid : Io::In) : Io::F32;
         layer_dispatch(a, n->ch[l], n->ch[l + 1], ptc_act(c, n, l), (const uint4 *)n->afw.p + n->afw_off[l],
                        ptc_act(c, n, l + 1), io, s, zo);
     }
     if (cf) {
-        k_ptc_tsum<<<(int)((2 * c->vh + 255) / 256), 256, 0, s>>>(a, (const float4 *)n->zbuf.p,
-                                                                  (float4 *)ptc_act(c, n, L));
+        const int npar = eo ? 1 : 2;
+        k_ptc_tsum<<<(int)((npar * c->vh + 255) / 256), 256, 0, s>>>(a, npar, (const float4 *)n->zbuf.p,
+                                                                     (float4 *)ptc_act(c, n, L));
         HIP_CHECK(hipGetLastError());
     }
 }

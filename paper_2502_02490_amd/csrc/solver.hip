@@ -283,8 +283,8 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
             // p_e = [N(r_e, 0)]_e
             const Precond M = [&](void *pv, const void *rv) {
                 B.lincomb(DIRAC_F32, DIRAC_F64, DIRAC_F64, 1, a_in, nullptr, 1.0, rv, 0.0, nullptr, nullptr, 1.0, s);
-                HIP_CHECK(hipMemsetAsync(a_in + half32, 0, half32 * sizeof(float), s));
-                ptc_forward_acts(c, net, s, false);
+                ptc_zero(a_in + half32, half32 * sizeof(float), s);
+                ptc_forward_acts(c, net, s, false, true);  // the even half of the output only
                 B.lincomb(DIRAC_F64, DIRAC_F32, DIRAC_F64, 1, pv, nullptr, 1.0, a_out, 0.0, nullptr, nullptr, 1.0, s);
             };
             GcrOut g = gcr(c, w, DIRAC_F64, xe, eta, x0, target, p->restart, p->max_iter, s, false, &M, 2.0);

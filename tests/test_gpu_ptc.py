@@ -121,6 +121,37 @@ def test_other_networks_forward(case, channels):
         net.close()
 
 
+@pytest.mark.parametrize("channels", [(1, 8, 8, 1), (1, 4, 1), (1, 1)], ids=str)
+def test_forward_eo_is_the_even_half(case, channels):
+    """ptc_forward_eo(r_e) is bitwise the even half of ptc_forward((r_e, 0)) -- the skipped work
+    only adds exact zeros or feeds the odd half -- and matches the oracle's model."""
+    c, _ = case
+    net = P.PTC(channels)
+    try:
+        ws = optc.init_weights(channels, seed=21, scale=1.0)
+        net.set_weights(ws)
+        wq = [bf16(w) for w in ws]
+        r = c.spinor(22).astype(np.complex64).astype(np.complex128)
+        r[c.odd] = 0.0
+        full_in = to_f32_native(c.D, r)
+        half = full_in.numel() // 2
+        out_full = c.D.native_empty("f32")
+        net.forward(c.D, out_full, full_in)
+        in_e = full_in[:half].clone()
+        out_e = torch.zeros_like(in_e)
+        net.forward_eo(c.D, out_e, in_e)
+        # compare at the lattice sites (the padding of the NATIVE layout is never written)
+        got = from_f32_native(c.D, torch.cat([out_e, torch.zeros_like(out_e)]))[c.even]
+        y_gpu = from_f32_native(c.D, out_full)
+        assert np.array_equal(got, y_gpu[c.even])
+        y, _ = optc.forward(c.f, wq, r, **MODEL)
+        err = rel(y_gpu[c.even], y[c.even])
+        flush(f"[gpu] ptc {channels} even-odd forward vs oracle {err:.2e}")
+        assert err < 3e-4
+    finally:
+        net.close()
+
+
 def test_gradients_over_many_tiles():
     """16^4: more 64-site tiles than weight-gradient work-groups, so each work-group sums several
     tiles into its slice; forward, input and weight gradients against the oracle."""
