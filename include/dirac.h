@@ -49,7 +49,13 @@
  *                      vector is the even half then the odd half; dirac_native_bytes gives
  *                      the size.  Padding sites are never read or written.  Use this layout
  *                      when timing.
- * User-layout (LEX/EO) buffers are complex128 for DIRAC_F64 and complex64 for
+ * DIRAC_LAYOUT_OPENQXD the same per-site layout, sites in openQxD's order, eq. (ipt) with
+ *                      the context's cache block B (Sec. 4.1.1):
+ *                        xhat = floor((V_B Lambda(n, N_B) + Lambda(b, B)) / 2) + P(x) V / 2,
+ *                      b = x mod B, n = floor(x / B), N_B = L / B, V_B = B0 B1 B2 B3;
+ *                      dirac_set_cache_block sets B (default B = L, the EO order).  A half
+ *                      (even-site) vector is the first V/2 sites.
+ * User-layout (LEX/EO/OPENQXD) buffers are complex128 for DIRAC_F64 and complex64 for
  * DIRAC_F32; F16 and BF16 exist in the NATIVE layout only.
  *
  * Gauge input (Sec. 4.1.4): su3_links [V][mu = 0..3][a][b] complex128, row-major
@@ -95,7 +101,7 @@ typedef enum {
 } dirac_status;
 
 typedef enum { DIRAC_F64 = 0, DIRAC_F32 = 1, DIRAC_F16 = 2, DIRAC_BF16 = 3 } dirac_prec;
-typedef enum { DIRAC_LAYOUT_LEX = 0, DIRAC_LAYOUT_EO = 1, DIRAC_LAYOUT_NATIVE = 2 } dirac_layout;
+typedef enum { DIRAC_LAYOUT_LEX = 0, DIRAC_LAYOUT_EO = 1, DIRAC_LAYOUT_NATIVE = 2, DIRAC_LAYOUT_OPENQXD = 3 } dirac_layout;
 
 typedef struct {
     int dims[4];        /* L0 (time), L1, L2, L3; each even and >= 2 */
@@ -114,14 +120,28 @@ dirac_status dirac_create(const dirac_params *params, const void *su3_links, con
                           void *stream, dirac_ctx **out);
 dirac_status dirac_destroy(dirac_ctx *ctx);
 
+/* Create a context from openQxD's storage of the gauge field (Sec. 4.1.4, Fig. gauge): the 8
+ * links attached to every odd point, the odd points in eq. (ipt) order with cache block
+ * `block` (which also becomes the context's cache block), odd point V/2 + k at position k:
+ *   u_odd [V/2][8][3][3] complex128, slot 2 mu = U_mu(x), slot 2 mu + 1 = U_mu(x - mu);
+ *   a_odd [V/2][8] float64 U(1) angles theta in the same slots, or NULL for theta = 0.
+ * Every link of the lattice is one of these exactly once.  Device pointers; otherwise as
+ * dirac_create.  EINVAL when a block extent does not divide the lattice extent or B3 is odd. */
+dirac_status dirac_create_openqxd(const dirac_params *params, const int block[4], const void *u_odd,
+                                  const double *a_odd, void *stream, dirac_ctx **out);
+
+/* Set the cache block B of the DIRAC_LAYOUT_OPENQXD user layout (default B = L).  Every B_mu
+ * must divide L_mu and B3 must be even (then eq. (ipt) is one-to-one); EINVAL otherwise. */
+dirac_status dirac_set_cache_block(dirac_ctx *ctx, const int block[4]);
+
 /* Replace the clover field A = (4 + m0) + C by a user field (Sec. 4.1.3: the
  * application may compute the QCD+QED clover term itself and upload it).
- * `clover` is [V][2][36] float64 in LEX or EO site order.  Inverses and
+ * `clover` is [V][2][36] float64 in LEX, EO or OPENQXD site order.  Inverses and
  * lower-precision copies are invalidated; call clover_invert next. */
 dirac_status dirac_load_clover(dirac_ctx *ctx, const double *clover, dirac_layout layout, void *stream);
 
 /* Copy the clover field (inverse = 0) or its inverse (inverse = 1) out, [V][2][36]
- * float64 in LEX or EO order.  Sites whose inverse was not computed read 0. */
+ * float64 in LEX, EO or OPENQXD order.  Sites whose inverse was not computed read 0. */
 dirac_status dirac_get_clover(dirac_ctx *ctx, double *out, int inverse, dirac_layout layout, void *stream);
 
 /* Invert the 6x6 chirality blocks of A in FP64: parity_mask bit 0 = even sites,
@@ -134,9 +154,9 @@ dirac_status clover_invert(dirac_ctx *ctx, int parity_mask, void *stream);
 /* Size in bytes of a NATIVE vector: sites = 0 full lattice, 1 one parity. */
 size_t dirac_native_bytes(const dirac_ctx *ctx, dirac_prec prec, int sites);
 
-/* Layout conversion of a spinor field.  sites = 0: full vector (LEX or EO user
- * layout); sites = 1: even half (EO user layout only); sites = 2: odd half (EO
- * user layout only, the second V/2 sites of an EO vector).  `user` is complex128
+/* Layout conversion of a spinor field.  sites = 0: full vector (LEX, EO or OPENQXD
+ * user layout); sites = 1: even half (EO or OPENQXD user layout); sites = 2: odd half
+ * (EO or OPENQXD, the second V/2 sites of such a vector).  `user` is complex128
  * for F64 and F16/BF16 targets, complex64 for F32. */
 dirac_status dirac_import(dirac_ctx *ctx, void *native, const void *user, int sites, dirac_prec prec,
                           dirac_layout user_layout, void *stream);
@@ -147,7 +167,7 @@ dirac_status dirac_export(dirac_ctx *ctx, void *user, const void *native, int si
 dirac_status dirac_apply(dirac_ctx *ctx, void *out, const void *in, dirac_prec prec, dirac_layout layout,
                          int dagger, void *stream);
 
-/* out_e = D-hat in_e (dagger = 0) or D-hat^dag in_e, even half-vectors (EO or NATIVE layout). */
+/* out_e = D-hat in_e (dagger = 0) or D-hat^dag in_e, even half-vectors (EO, OPENQXD or NATIVE layout). */
 dirac_status dirac_apply_eo(dirac_ctx *ctx, void *out_e, const void *in_e, dirac_prec prec, dirac_layout layout,
                             int dagger, void *stream);
 

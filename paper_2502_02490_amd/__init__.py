@@ -13,12 +13,12 @@ import torch
 
 from . import _lib
 from ._lib import (BF16, CGLS, EO, F16, F32, F64, FGCR_PTC, FGCR_PTC_EO, GCR, LEX, MIXED_GCR, NATIVE,  # noqa: F401
-                   DiracError, SolveInfo, SolverParams)
+                   OPENQXD, DiracError, SolveInfo, SolverParams)
 
 _TORCH_REAL = {F64: torch.float64, F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
 _TORCH_USER = {F64: torch.complex128, F32: torch.complex64, F16: torch.complex128, BF16: torch.complex128}
 _PREC = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
-_LAYOUT = {"lex": LEX, "eo": EO, "native": NATIVE}
+_LAYOUT = {"lex": LEX, "eo": EO, "native": NATIVE, "openqxd": OPENQXD}
 
 
 def _prec(p):
@@ -51,10 +51,13 @@ class Dirac:
 
     U:     complex128 [V, 4, 3, 3] SU(3) links on the GPU, LEX order (x0 = time slowest).
     theta: float64 [V, 4] U(1) angles, or None.
+    With openqxd_block = (B0, B1, B2, B3) the gauge field is given in openQxD's storage instead:
+    U complex128 [V/2, 8, 3, 3] and theta float64 [V/2, 8] (or None), the 8 links attached to each
+    odd point in eq. (ipt) order with that cache block (see dirac_create_openqxd).
     """
 
     def __init__(self, U: torch.Tensor, theta, dims, kappa: float, csw: float, csw_qed: float, qhat: int,
-                 bc_phase=(math.pi, 0.0, 0.0, 0.0), stream=None, allow_singular: bool = False):
+                 bc_phase=(math.pi, 0.0, 0.0, 0.0), stream=None, allow_singular: bool = False, openqxd_block=None):
         self.lib = _lib.load()
         self.dims = tuple(int(d) for d in dims)
         self.V = int(math.prod(self.dims))
@@ -66,15 +69,26 @@ class Dirac:
         p.kappa, p.csw, p.csw_qed, p.qhat = float(kappa), float(csw), float(csw_qed), int(qhat)
         self.params = p
         self._ctx = ctypes.c_void_p()
-        st = self.lib.dirac_create(ctypes.byref(p), _ptr(U, self.V * 576),
-                                   _ptr(theta, self.V * 32) if theta is not None else None,
-                                   _stream(stream), ctypes.byref(self._ctx))
+        if openqxd_block is None:
+            st = self.lib.dirac_create(ctypes.byref(p), _ptr(U, self.V * 576),
+                                       _ptr(theta, self.V * 32) if theta is not None else None,
+                                       _stream(stream), ctypes.byref(self._ctx))
+        else:
+            blk = (ctypes.c_int * 4)(*[int(b) for b in openqxd_block])
+            st = self.lib.dirac_create_openqxd(ctypes.byref(p), blk, _ptr(U, self.V * 576),
+                                               _ptr(theta, self.V * 32) if theta is not None else None,
+                                               _stream(stream), ctypes.byref(self._ctx))
         self.singular = st == _lib.ESINGULAR
         if st != _lib.OK and not (self.singular and allow_singular and self._ctx.value):
             if self._ctx.value:
                 self.lib.dirac_destroy(self._ctx)
                 self._ctx = ctypes.c_void_p()
             _lib.check(st)
+
+    def set_cache_block(self, block):
+        """Cache block B of the "openqxd" user layout (eq. (ipt)); default B = dims."""
+        blk = (ctypes.c_int * 4)(*[int(b) for b in block])
+        _lib.check(self.lib.dirac_set_cache_block(self._ctx, blk))
 
     # -------------------------------------------------------------- lifetime
     def close(self):

@@ -11,11 +11,11 @@ OK, EINVAL, ENOMEM, EHIP, ESINGULAR, ENOCONV, ENONFINITE, EUNSUPPORTED = range(8
 STATUS_NAMES = ["DIRAC_OK", "DIRAC_EINVAL", "DIRAC_ENOMEM", "DIRAC_EHIP", "DIRAC_ESINGULAR", "DIRAC_ENOCONV",
                 "DIRAC_ENONFINITE", "DIRAC_EUNSUPPORTED"]
 F64, F32, F16, BF16 = 0, 1, 2, 3
-LEX, EO, NATIVE = 0, 1, 2
+LEX, EO, NATIVE, OPENQXD = 0, 1, 2, 3
 CGLS, GCR, MIXED_GCR, FGCR_PTC, FGCR_PTC_EO = 0, 1, 2, 3, 4
 
 # every symbol declared in include/dirac.h
-EXPORTS = ["dirac_create", "dirac_destroy", "dirac_load_clover", "dirac_get_clover", "clover_invert",
+EXPORTS = ["dirac_create", "dirac_create_openqxd", "dirac_set_cache_block", "dirac_destroy", "dirac_load_clover", "dirac_get_clover", "clover_invert",
            "dirac_native_bytes", "dirac_import", "dirac_export", "dirac_apply", "dirac_apply_eo", "dirac_apply_eo_multi",
            "dirac_apply_hop", "dirac_apply_clover", "dirac_solve", "dirac_solve_batched", "dirac_last_error",
            "ptc_create", "ptc_destroy", "ptc_num_weights", "ptc_set_weights", "ptc_get_weights", "ptc_get_grad",
@@ -61,6 +61,8 @@ def load(path: str = LIB_PATH):
     vp, i, st = ctypes.c_void_p, ctypes.c_int, ctypes.c_int
     lib.dirac_create.argtypes = [ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(vp)]
     lib.dirac_destroy.argtypes = [vp]
+    lib.dirac_create_openqxd.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.dirac_set_cache_block.argtypes = [vp, vp]
     lib.dirac_load_clover.argtypes = [vp, vp, i, vp]
     lib.dirac_get_clover.argtypes = [vp, vp, i, i, vp]
     lib.clover_invert.argtypes = [vp, i, vp]

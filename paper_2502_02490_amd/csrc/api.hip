@@ -80,8 +80,20 @@ size_t native_bytes(const dirac_ctx *c, dirac_prec pr, int sites) {
     return n * 24 * dl::real_size(pr);
 }
 
+// eq. (ipt) is one-to-one on each parity when the blocks tile the lattice and B3 is even: the
+// two sites of each pair (2j, 2j + 1) of block order then differ in x3 alone
+void check_cache_block(const int *dims, const int *block) {
+    for (int m = 0; m < 4; ++m)
+        require(block[m] >= 1 && dims[m] % block[m] == 0,
+                "cache-block extent block[" + std::to_string(m) + "] = " + std::to_string(block[m]) +
+                    " does not divide the lattice extent " + std::to_string(dims[m]));
+    require(block[3] % 2 == 0, "the cache-block extent block[3] must be even");
+}
+
 void check_user_layout(dirac_prec pr, dirac_layout lay) {
-    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_NATIVE, "unknown layout");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_NATIVE ||
+                lay == DIRAC_LAYOUT_OPENQXD,
+            "unknown layout");
     if (lay != DIRAC_LAYOUT_NATIVE && (pr == DIRAC_F16 || pr == DIRAC_BF16))
         throw dl::Error(DIRAC_EUNSUPPORTED, "F16 and BF16 fields exist in the NATIVE layout only");
 }
@@ -121,6 +133,7 @@ dirac_status dirac_create(const dirac_params *prm, const void *su3_links, const 
         c->g.h3 = prm->dims[3] / 2;
         c->g.vh = (int)c->vh;
         c->g.vhp = (int)padded_sites(c->vh);
+        for (int m = 0; m < 4; ++m) c->g.B[m] = prm->dims[m];
         c->U_lex.alloc((size_t)V * 4 * 9 * 16);
         HIP_CHECK(hipMemcpyAsync(c->U_lex.p, su3_links, (size_t)V * 4 * 9 * 16, hipMemcpyDeviceToDevice, s));
         if (u1_angles) {
@@ -150,6 +163,59 @@ dirac_status dirac_create(const dirac_params *prm, const void *su3_links, const 
 }
 
 
+
+dirac_status dirac_set_cache_block(dirac_ctx *c, const int *block) {
+    API_BEGIN
+    check_ctx(c);
+    require(block != nullptr, "block is NULL");
+    check_cache_block(c->p.dims, block);
+    for (int m = 0; m < 4; ++m) c->g.B[m] = block[m];
+    API_END
+}
+
+dirac_status dirac_create_openqxd(const dirac_params *prm, const int *block, const void *u_odd, const double *a_odd,
+                                  void *stream, dirac_ctx **out) {
+    dl::DevBuf U, th;
+    g_err.clear();
+    try {
+        require(prm != nullptr && out != nullptr && block != nullptr, "params, block and out must not be NULL");
+        *out = nullptr;
+        int64_t V = 1;
+        for (int m = 0; m < 4; ++m) {
+            require(prm->dims[m] >= 2 && prm->dims[m] % 2 == 0, "every lattice extent must be even and >= 2");
+            V *= prm->dims[m];
+        }
+        require(V < (int64_t)1 << 30, "lattice too large for 32-bit site indices");
+        check_cache_block(prm->dims, block);
+        check_dev(u_odd, (size_t)V / 2 * 8 * 9 * 16, "u_odd");
+        if (a_odd) check_dev(a_odd, (size_t)V / 2 * 8 * 8, "a_odd");
+        hipStream_t s = (hipStream_t)stream;
+        Geom g{};
+        for (int m = 0; m < 4; ++m) {
+            g.L[m] = prm->dims[m];
+            g.B[m] = block[m];
+        }
+        g.h3 = prm->dims[3] / 2;
+        g.vh = (int)(V / 2);
+        g.vhp = (int)padded_sites(V / 2);
+        U.alloc((size_t)V * 4 * 9 * 16);
+        if (a_odd) th.alloc((size_t)V * 4 * 8);
+        dl::openqxd_links_to_lex(g, (const double *)u_odd, a_odd, (double *)U.p, a_odd ? (double *)th.p : nullptr, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+    } catch (const dl::Error &e) {
+        return fail(e.status, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(DIRAC_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(DIRAC_EHIP, std::string("internal error: ") + e.what());
+    }
+    // the rest is dirac_create on the LEX copy, which is released on return
+    const dirac_status st = dirac_create(prm, U.p, a_odd ? (const double *)th.p : nullptr, stream, out);
+    if (*out) {
+        for (int m = 0; m < 4; ++m) (*out)->g.B[m] = block[m];
+    }
+    return st;
+}
 
 dirac_status dirac_destroy(dirac_ctx *c) {
     API_BEGIN
@@ -215,7 +281,8 @@ dirac_status dirac_import(dirac_ctx *c, void *native, const void *user, int site
     check_ctx(c);
     check_prec(pr);
     require(sites >= 0 && sites <= 2, "sites must be 0, 1 or 2");
-    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO, "user layout must be LEX or EO");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_OPENQXD,
+            "user layout must be LEX, EO or OPENQXD");
     const size_t ub = sites == 0 ? (size_t)c->V * 24 * (pr == DIRAC_F32 ? 4 : 8) : (size_t)c->vh * 24 * (pr == DIRAC_F32 ? 4 : 8);
     check_dev(user, ub, "user");
     check_dev(native, native_bytes(c, pr, sites), "native");
@@ -230,7 +297,8 @@ dirac_status dirac_export(dirac_ctx *c, void *user, const void *native, int site
     check_ctx(c);
     check_prec(pr);
     require(sites >= 0 && sites <= 2, "sites must be 0, 1 or 2");
-    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO, "user layout must be LEX or EO");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_OPENQXD,
+            "user layout must be LEX, EO or OPENQXD");
     const size_t ub = sites == 0 ? (size_t)c->V * 24 * (pr == DIRAC_F32 ? 4 : 8) : (size_t)c->vh * 24 * (pr == DIRAC_F32 ? 4 : 8);
     check_dev(user, ub, "user");
     check_dev(native, native_bytes(c, pr, sites), "native");
@@ -269,7 +337,7 @@ dirac_status dirac_apply_eo(dirac_ctx *c, void *out, const void *in, dirac_prec 
     check_ctx(c);
     check_prec(pr);
     check_user_layout(pr, lay);
-    require(lay != DIRAC_LAYOUT_LEX, "an even half-vector is defined in the EO or NATIVE layout, not LEX");
+    require(lay != DIRAC_LAYOUT_LEX, "an even half-vector is defined in the EO, OPENQXD or NATIVE layout, not LEX");
     hipStream_t s = (hipStream_t)stream;
     const size_t nb = lay == DIRAC_LAYOUT_NATIVE ? native_bytes(c, pr, 1) : user_bytes(c, pr, 1);
     check_dev(in, nb, "in_e");
@@ -336,7 +404,9 @@ dirac_status dirac_solve(dirac_ctx *c, void *x, const void *b, dirac_layout lay,
     require(info != nullptr, "info is NULL");
     *info = dirac_solve_info{};
     dl::check_solver_params(p);
-    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_NATIVE, "unknown layout");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_NATIVE ||
+                lay == DIRAC_LAYOUT_OPENQXD,
+            "unknown layout");
     hipStream_t s = (hipStream_t)stream;
     const size_t nb = lay == DIRAC_LAYOUT_NATIVE ? native_bytes(c, DIRAC_F64, 0) : user_bytes(c, DIRAC_F64, 0);
     check_dev(b, nb, "b");
@@ -379,7 +449,9 @@ dirac_status dirac_solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x
     dl::check_solver_params(p);
     require(p->method == DIRAC_SOLVER_GCR || p->method == DIRAC_SOLVER_MIXED_GCR,
             "batched solves run GCR or MIXED_GCR");
-    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_NATIVE, "unknown layout");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_NATIVE ||
+                lay == DIRAC_LAYOUT_OPENQXD,
+            "unknown layout");
     for (int l = 0; l < nlat; ++l) {
         check_ctx(ctx[l]);
         for (int k = 0; k < l; ++k) require(ctx[k] != ctx[l], "each lattice needs its own context");

@@ -184,9 +184,10 @@ DEV void store_field(typename St<S>::vec *__restrict__ base, uint32_t s, const t
 // which is floor(Lambda / 2) (eq. (lexi) with x3 fastest).
 struct Geom {
     int L[4];
-    int h3;   // L3 / 2
-    int vh;   // V / 2
-    int vhp;  // V / 2 padded to a multiple of 64 (site blocks)
+    int h3;    // L3 / 2
+    int vh;    // V / 2
+    int vhp;   // V / 2 padded to a multiple of 64 (site blocks)
+    int B[4];  // cache block of the OPENQXD user layout (B = L: the EO order)
 };
 
 DEV void site_coords(const Geom &g, int i, int p, int x[4]) {
@@ -203,6 +204,22 @@ DEV int half_index(const Geom &g, const int x[4]) {
 }
 DEV int lex_index(const Geom &g, const int x[4]) {
     return ((x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
+}
+// eq. (ipt): openQxD's site index with cache block B, floor((V_B Lambda(n, N_B) + Lambda(b, B)) / 2)
+// + P(x) V / 2 with b = x mod B, n = floor(x / B), N_B = L / B
+DEV int64_t ipt_index(const Geom &g, const int x[4]) {
+    int b[4], n[4], nb[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        b[m] = x[m] % g.B[m];
+        n[m] = x[m] / g.B[m];
+        nb[m] = g.L[m] / g.B[m];
+    }
+    const int64_t vb = (int64_t)g.B[0] * g.B[1] * g.B[2] * g.B[3];
+    const int64_t lb = ((b[0] * g.B[1] + b[1]) * g.B[2] + b[2]) * g.B[3] + b[3];
+    const int64_t ln = ((n[0] * nb[1] + n[1]) * nb[2] + n[2]) * nb[3] + n[3];
+    const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+    return (vb * ln + lb) / 2 + (int64_t)par * g.vh;
 }
 DEV void lex_coords(const Geom &g, int lam, int x[4]) {
     x[3] = lam % g.L[3];

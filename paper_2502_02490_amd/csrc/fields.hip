@@ -110,12 +110,15 @@ __global__ __launch_bounds__(kBlock) void k_convert_clover(int vh, const double2
     store_field<S, 72>(dst, i, a);
 }
 
-// user index of the site (p, i): LEX -> Lambda, EO -> xhat (relative to `base_parity` for half vectors)
+// user index of the site (p, i): LEX -> Lambda, EO -> xhat, OPENQXD -> eq. (ipt) with the cache
+// block (relative to the first site of the parity for half vectors)
 DEV int64_t user_site(const Geom &g, int p, int i, int lay, int half) {
-    if (lay == DIRAC_LAYOUT_LEX) {
+    if (lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_OPENQXD) {
         int x[4];
         site_coords(g, i, p, x);
-        return lex_index(g, x);
+        if (lay == DIRAC_LAYOUT_LEX) return lex_index(g, x);
+        const int64_t k = ipt_index(g, x);
+        return half ? k - (int64_t)p * g.vh : k;
     }
     return half ? (int64_t)i : (int64_t)i + (int64_t)p * g.vh;
 }
@@ -240,9 +243,10 @@ void spinor_io_user(dirac_ctx *c, void *native, const void *user, bool in, int s
 
 void spinor_dispatch(dirac_ctx *c, void *native, const void *user, bool in, int sites, dirac_prec pr,
                      dirac_layout lay, hipStream_t s) {
-    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO, "user layout must be LEX or EO");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_OPENQXD,
+            "user layout must be LEX, EO or OPENQXD");
     require(sites >= 0 && sites <= 2, "sites must be 0 (full), 1 (even half) or 2 (odd half)");
-    require(sites == 0 || lay == DIRAC_LAYOUT_EO, "half vectors exist in the EO layout only");
+    require(sites == 0 || lay != DIRAC_LAYOUT_LEX, "half vectors exist in the EO and OPENQXD layouts only");
     switch (pr) {
         case DIRAC_F64: spinor_io_user<double>(c, native, user, in, sites, pr, lay, s); break;
         case DIRAC_F32: spinor_io_user<float>(c, native, user, in, sites, pr, lay, s); break;
@@ -252,7 +256,41 @@ void spinor_dispatch(dirac_ctx *c, void *native, const void *user, bool in, int 
     }
 }
 
+// openQxD's gauge storage -> LEX: the thread of odd site (1, i) with ipt position V/2 + k reads the
+// 8 links attached to it, slot 2 mu = U_mu(x) and slot 2 mu + 1 = U_mu(x - mu); every LEX link is
+// written by exactly one thread (the forward link of an even site y ends at the odd site y + mu)
+__global__ __launch_bounds__(kBlock) void k_openqxd_links(Geom g, const double *__restrict__ u_odd,
+                                                           const double *__restrict__ a_odd,
+                                                           double *__restrict__ U, double *__restrict__ th) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.vh) return;
+    int x[4];
+    site_coords(g, i, 1, x);
+    const int64_t k = ipt_index(g, x) - g.vh;
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll 1
+        for (int back = 0; back < 2; ++back) {
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            if (back) y[mu] = wrap_dn(y[mu], g.L[mu]);
+            const int64_t lam = lex_index(g, y);
+            const int64_t slot = k * 8 + 2 * mu + back;
+            const double2 *src = reinterpret_cast<const double2 *>(u_odd) + slot * 9;
+            double2 *dst = reinterpret_cast<double2 *>(U) + (lam * 4 + mu) * 9;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) dst[e] = src[e];
+            if (th) th[lam * 4 + mu] = a_odd[slot];
+        }
+    }
+}
+
 }  // namespace
+
+void openqxd_links_to_lex(const Geom &g, const double *u_odd, const double *a_odd, double *U, double *th,
+                          hipStream_t s) {
+    k_openqxd_links<<<grid_for(g.vh), kBlock, 0, s>>>(g, u_odd, a_odd, U, th);
+    HIP_CHECK(hipGetLastError());
+}
 
 size_t link_plane_bytes(dirac_prec pr) { return pr == DIRAC_F64 ? 96 : pr == DIRAC_F32 ? 48 : 24; }
 
@@ -301,7 +339,8 @@ void spinor_export(dirac_ctx *c, void *user, const void *native, int sites, dira
 }
 
 void clover_import(dirac_ctx *c, const double *user, dirac_layout lay, hipStream_t s) {
-    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO, "clover layout must be LEX or EO");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_OPENQXD,
+            "clover layout must be LEX, EO or OPENQXD");
     PrecFields &f = c->f[DIRAC_F64];
     for (int p = 0; p < 2; ++p) {
         f.clov[p].alloc((size_t)72 * sizeof(double) * c->g.vhp);
@@ -315,7 +354,8 @@ void clover_import(dirac_ctx *c, const double *user, dirac_layout lay, hipStream
 }
 
 void clover_export(dirac_ctx *c, double *user, int inverse, dirac_layout lay, hipStream_t s) {
-    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO, "clover layout must be LEX or EO");
+    require(lay == DIRAC_LAYOUT_LEX || lay == DIRAC_LAYOUT_EO || lay == DIRAC_LAYOUT_OPENQXD,
+            "clover layout must be LEX, EO or OPENQXD");
     PrecFields &f = c->f[DIRAC_F64];
     for (int p = 0; p < 2; ++p) {
         const double2 *src = inverse ? (f.inv_ready[p] ? (const double2 *)f.clinv[p].p : nullptr)

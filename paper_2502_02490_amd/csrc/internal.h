@@ -99,6 +99,9 @@ size_t link_plane_bytes(dirac_prec pr);  // bytes of one 12-real link plane set,
 
 // fields.hip
 void import_links(dirac_ctx *c, hipStream_t s);
+// openQxD odd-point gauge storage (u_odd [V/2][8][3][3], a_odd [V/2][8] or NULL) to LEX [V][4] arrays
+void openqxd_links_to_lex(const Geom &g, const double *u_odd, const double *a_odd, double *U, double *th,
+                          hipStream_t s);
 void ensure_prec(dirac_ctx *c, dirac_prec pr, hipStream_t s);
 void spinor_import(dirac_ctx *c, void *native, const void *user, int sites, dirac_prec pr, dirac_layout lay,
                    hipStream_t s);
