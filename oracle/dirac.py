@@ -74,6 +74,7 @@ class Params:
     csw_qed: float
     qhat: int
     bc_phase: tuple = (np.pi, 0.0, 0.0, 0.0)
+    cstar: int = 0  # C* boundary conditions in directions 1 .. cstar (geometry.shift)
 
     @property
     def m0(self) -> float:
@@ -90,7 +91,7 @@ class Fields:
     _clover: dict = field(default_factory=dict, repr=False)
 
     def __post_init__(self):
-        geo.check_dims(self.p.dims)
+        geo.check_dims(self.p.dims, self.p.cstar)
         V = geo.volume(self.p.dims)
         assert self.U.shape == (V, 4, 3, 3) and self.theta.shape == (V, 4)
         # R3 / Sec. 4.3: the U(3) link exp(i qhat theta) U
@@ -136,8 +137,8 @@ def hop(f: Fields, psi: np.ndarray, sites=None) -> np.ndarray:
     x = geo.coords(sites, L)
     out = np.zeros((len(sites), 4, 3), dtype=np.complex128)
     for mu in range(4):
-        fwd = geo.shift(sites, L, mu, +1)
-        bwd = geo.shift(sites, L, mu, -1)
+        fwd = geo.shift(sites, L, mu, +1, f.p.cstar)
+        bwd = geo.shift(sites, L, mu, -1, f.p.cstar)
         phi = f.p.bc_phase[mu]
         bplus = np.where(x[:, mu] == L[mu] - 1, np.exp(1j * phi), 1.0)
         bminus = np.where(x[:, mu] == 0, np.exp(-1j * phi), 1.0)
@@ -154,10 +155,10 @@ def _dag(m):
     return np.conj(np.swapaxes(m, -1, -2))
 
 
-def leaves(W: np.ndarray, L, sites: np.ndarray, mu: int, nu: int) -> np.ndarray:
+def leaves(W: np.ndarray, L, sites: np.ndarray, mu: int, nu: int, cstar: int = 0) -> np.ndarray:
     """Q_{mu nu}(x): sum of the four plaquettes in the (mu, nu) plane that start and end at x.
     W[site, mu] are N x N link matrices (N = 3 for SU(3), N = 1 for U(1))."""
-    s = lambda lam, d, k: geo.shift(lam, L, d, k)  # noqa: E731
+    s = lambda lam, d, k: geo.shift(lam, L, d, k, cstar)  # noqa: E731
     x = sites
     xpm, xpn = s(x, mu, +1), s(x, nu, +1)
     xmm, xmn = s(x, mu, -1), s(x, nu, -1)
@@ -172,9 +173,9 @@ def leaves(W: np.ndarray, L, sites: np.ndarray, mu: int, nu: int) -> np.ndarray:
     return q
 
 
-def field_strength(W: np.ndarray, L, sites, mu: int, nu: int) -> np.ndarray:
+def field_strength(W: np.ndarray, L, sites, mu: int, nu: int, cstar: int = 0) -> np.ndarray:
     """F_{mu nu}(x) = (Q_{mu nu} - Q_{mu nu}^dag) / 8 (no traceless projection, reading R4)."""
-    q = leaves(W, L, np.asarray(sites, dtype=np.int64), mu, nu)
+    q = leaves(W, L, np.asarray(sites, dtype=np.int64), mu, nu, cstar)
     return (q - _dag(q)) / 8.0
 
 
@@ -191,9 +192,9 @@ def clover_matrix(f: Fields, sites) -> np.ndarray:
         for nu in range(4):
             if mu == nu:
                 continue
-            F = field_strength(f.U, L, sites, mu, nu)  # [n, 3, 3]
+            F = field_strength(f.U, L, sites, mu, nu, f.p.cstar)  # [n, 3, 3]
             A += f.p.csw * 0.25j * np.einsum("st,nab->nsatb", SIGMA[mu][nu], F).reshape(n, 12, 12)
-            Fq = field_strength(z, L, sites, mu, nu)[:, 0, 0]  # [n]
+            Fq = field_strength(z, L, sites, mu, nu, f.p.cstar)[:, 0, 0]  # [n]
             A += (f.p.csw_qed * f.p.qhat * 0.25j) * np.einsum(
                 "st,n,ab->nsatb", SIGMA[mu][nu], Fq, one3).reshape(n, 12, 12)
     return A
@@ -216,8 +217,8 @@ def apply_Ddag(f: Fields, psi: np.ndarray) -> np.ndarray:
     x = geo.coords(sites, L)
     out = np.zeros_like(psi)
     for mu in range(4):
-        fwd = geo.shift(sites, L, mu, +1)
-        bwd = geo.shift(sites, L, mu, -1)
+        fwd = geo.shift(sites, L, mu, +1, f.p.cstar)
+        bwd = geo.shift(sites, L, mu, -1, f.p.cstar)
         phi = f.p.bc_phase[mu]
         bplus = np.where(x[:, mu] == L[mu] - 1, np.exp(1j * phi), 1.0)
         bminus = np.where(x[:, mu] == 0, np.exp(-1j * phi), 1.0)
@@ -282,7 +283,7 @@ def schur_at(f: Fields, psi_e: np.ndarray, out_sites) -> np.ndarray:
     ev, _ = even_odd(f)
     out_sites = np.asarray(out_sites, dtype=np.int64)
     full_e = _embed(f, ev, psi_e)
-    nb = np.unique(np.concatenate([geo.shift(out_sites, L, mu, s) for mu in range(4) for s in (1, -1)]))
+    nb = np.unique(np.concatenate([geo.shift(out_sites, L, mu, s, f.p.cstar) for mu in range(4) for s in (1, -1)]))
     t = -0.5 * hop(f, full_e, nb)
     t = np.einsum("nij,nj->ni", f.clover_inv(nb), t.reshape(-1, 12)).reshape(-1, 4, 3)
     full_t = np.zeros((f.V, 4, 3), dtype=np.complex128)

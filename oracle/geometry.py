@@ -63,10 +63,19 @@ def eo_index(x, L) -> np.ndarray:
     return lex(x, L) // 2 + parity(x) * (volume(L) // 2)
 
 
-def shift(lam, L, mu: int, step: int) -> np.ndarray:
-    """Lambda(x + step * mu-hat) with periodic wrap of the coordinate x_mu."""
+def shift(lam, L, mu: int, step: int, cstar: int = 0) -> np.ndarray:
+    """Lambda(x + step * mu-hat) with periodic wrap of the coordinate x_mu (step = +1 or -1).
+
+    C* boundary conditions (Sec. 4.2: the lattice doubled in direction 1, shifted boundaries):
+    cstar = number of C* directions, 1 .. cstar.  L[1] is then the doubled extent and direction 1
+    is plainly periodic; crossing the boundary of a further C* direction mu (2 <= mu <= cstar)
+    also moves x1 by L[1] / 2, into the mirror copy."""
     x = coords(lam, L)
-    x[..., mu] = (x[..., mu] + step) % int(L[mu])
+    y = x[..., mu] + step
+    cross = (y < 0) | (y >= int(L[mu]))
+    x[..., mu] = y % int(L[mu])
+    if 2 <= mu <= cstar:
+        x[..., 1] = np.where(cross, (x[..., 1] + int(L[1]) // 2) % int(L[1]), x[..., 1])
     return lex(x, L)
 
 
@@ -84,6 +93,11 @@ def lex_to_eo_perm(L) -> np.ndarray:
     return perm
 
 
-def check_dims(L) -> None:
+def check_dims(L, cstar: int = 0) -> None:
     if len(L) != 4 or any(int(v) < 2 or int(v) % 2 for v in L):
         raise ValueError(f"lattice extents must be four even numbers >= 2, got {tuple(L)}")
+    if not 0 <= cstar <= 3:
+        raise ValueError("cstar must be 0 .. 3")
+    if cstar >= 2 and int(L[1]) % 4:
+        # the mirror shift L1 / 2 must be even, or it would join sites of equal parity
+        raise ValueError("with C* boundaries in more than one direction the doubled extent L1 must be a multiple of 4")

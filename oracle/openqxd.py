@@ -44,7 +44,7 @@ def site_order(L, B) -> np.ndarray:
     return perm
 
 
-def links_to_openqxd(U: np.ndarray, theta, L, B):
+def links_to_openqxd(U: np.ndarray, theta, L, B, cstar: int = 0):
     """LEX links U [V][4][3][3] (and angles theta [V][4] or None) -> openQxD's odd-point storage
     u [V/2][8][3][3], a [V/2][8] (None without angles)."""
     check_block(L, B)
@@ -54,7 +54,7 @@ def links_to_openqxd(U: np.ndarray, theta, L, B):
     u = np.empty((V // 2, 8, 3, 3), dtype=np.complex128)
     a = None if theta is None else np.empty((V // 2, 8))
     for mu in range(4):
-        back = geo.shift(odd, L, mu, -1)    # Lambda(x - mu)
+        back = geo.shift(odd, L, mu, -1, cstar)    # Lambda(x - mu)
         u[:, 2 * mu] = U[odd, mu]
         u[:, 2 * mu + 1] = U[back, mu]
         if a is not None:
@@ -63,7 +63,7 @@ def links_to_openqxd(U: np.ndarray, theta, L, B):
     return u, a
 
 
-def links_from_openqxd(u: np.ndarray, a, L, B):
+def links_from_openqxd(u: np.ndarray, a, L, B, cstar: int = 0):
     """The inverse of links_to_openqxd: LEX U [V][4][3][3], theta [V][4] (None without angles)."""
     check_block(L, B)
     V = geo.volume(L)
@@ -72,7 +72,7 @@ def links_from_openqxd(u: np.ndarray, a, L, B):
     U = np.full((V, 4, 3, 3), np.nan, dtype=np.complex128)
     th = None if a is None else np.full((V, 4), np.nan)
     for mu in range(4):
-        back = geo.shift(odd, L, mu, -1)
+        back = geo.shift(odd, L, mu, -1, cstar)
         U[odd, mu] = u[:, 2 * mu]
         U[back, mu] = u[:, 2 * mu + 1]
         if th is not None:

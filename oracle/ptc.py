@@ -43,10 +43,10 @@ def transport(f: dirac.Fields, psi: np.ndarray, p: int) -> np.ndarray:
     x = geo.coords(sites, L)
     phi = f.p.bc_phase[mu]
     if d > 0:
-        nb = geo.shift(sites, L, mu, 1)
+        nb = geo.shift(sites, L, mu, 1, f.p.cstar)
         b = np.where(x[:, mu] == L[mu] - 1, np.exp(1j * phi), 1.0)
         return b[:, None, None] * np.einsum("nab,nsb->nsa", f.Vlink[:, mu], psi[nb])
-    nb = geo.shift(sites, L, mu, -1)
+    nb = geo.shift(sites, L, mu, -1, f.p.cstar)
     b = np.where(x[:, mu] == 0, np.exp(-1j * phi), 1.0)
     Vd = np.conj(np.swapaxes(f.Vlink[nb, mu], -1, -2))
     return b[:, None, None] * np.einsum("nab,nsb->nsa", Vd, psi[nb])
