@@ -110,6 +110,13 @@ typedef struct {
     double csw_qed;     /* U(1) SW coefficient c_sw^U(1) (Sec. 4.3) */
     int qhat;           /* integer charge multiplying theta in the link and the U(1) SW term */
     double bc_phase[4]; /* phi_mu in radians: {pi, 0, 0, 0} = antiperiodic time, periodic space */
+    int cstar;          /* C* boundary conditions (Sec. 4.2) in directions 1 .. cstar, 0 = none:
+                         * dims[1] is then the doubled extent (the physical lattice and its mirror
+                         * copy), direction 1 is periodic with it, and crossing the boundary of a
+                         * further C* direction mu >= 2 also moves x1 by dims[1] / 2; with cstar >= 2
+                         * dims[1] must be a multiple of 4.  The caller supplies the links of the
+                         * whole doubled lattice (for C* fields, the mirror copy holds the complex
+                         * conjugate links and the negated U(1) angles). */
 } dirac_params;
 
 /* Create a context: copies the gauge field, compresses the links (two rows of

@@ -51,13 +51,15 @@ class Dirac:
 
     U:     complex128 [V, 4, 3, 3] SU(3) links on the GPU, LEX order (x0 = time slowest).
     theta: float64 [V, 4] U(1) angles, or None.
+    cstar: C* boundary conditions in directions 1 .. cstar (dims[1] the doubled extent).
     With openqxd_block = (B0, B1, B2, B3) the gauge field is given in openQxD's storage instead:
     U complex128 [V/2, 8, 3, 3] and theta float64 [V/2, 8] (or None), the 8 links attached to each
     odd point in eq. (ipt) order with that cache block (see dirac_create_openqxd).
     """
 
     def __init__(self, U: torch.Tensor, theta, dims, kappa: float, csw: float, csw_qed: float, qhat: int,
-                 bc_phase=(math.pi, 0.0, 0.0, 0.0), stream=None, allow_singular: bool = False, openqxd_block=None):
+                 bc_phase=(math.pi, 0.0, 0.0, 0.0), stream=None, allow_singular: bool = False, openqxd_block=None,
+                 cstar: int = 0):
         self.lib = _lib.load()
         self.dims = tuple(int(d) for d in dims)
         self.V = int(math.prod(self.dims))
@@ -67,6 +69,7 @@ class Dirac:
             p.dims[m] = self.dims[m]
             p.bc_phase[m] = float(bc_phase[m])
         p.kappa, p.csw, p.csw_qed, p.qhat = float(kappa), float(csw), float(csw_qed), int(qhat)
+        p.cstar = int(cstar)
         self.params = p
         self._ctx = ctypes.c_void_p()
         if openqxd_block is None:

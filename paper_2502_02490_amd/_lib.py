@@ -25,7 +25,8 @@ EXPORTS = ["dirac_create", "dirac_create_openqxd", "dirac_set_cache_block", "dir
 
 class Params(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("kappa", ctypes.c_double), ("csw", ctypes.c_double),
-                ("csw_qed", ctypes.c_double), ("qhat", ctypes.c_int), ("bc_phase", ctypes.c_double * 4)]
+                ("csw_qed", ctypes.c_double), ("qhat", ctypes.c_int), ("bc_phase", ctypes.c_double * 4),
+                ("cstar", ctypes.c_int)]
 
 
 class SolverParams(ctypes.Structure):

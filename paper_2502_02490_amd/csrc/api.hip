@@ -80,6 +80,14 @@ size_t native_bytes(const dirac_ctx *c, dirac_prec pr, int sites) {
     return n * 24 * dl::real_size(pr);
 }
 
+// C* boundaries: directions 1 .. cstar; the mirror shift dims[1] / 2 must be even with cstar >= 2
+// (it would otherwise join sites of equal parity)
+void check_cstar(const dirac_params *prm) {
+    require(prm->cstar >= 0 && prm->cstar <= 3, "cstar must be 0 .. 3");
+    require(prm->cstar < 2 || prm->dims[1] % 4 == 0,
+            "with C* boundaries in more than one direction dims[1] (the doubled extent) must be a multiple of 4");
+}
+
 // eq. (ipt) is one-to-one on each parity when the blocks tile the lattice and B3 is even: the
 // two sites of each pair (2j, 2j + 1) of block order then differ in x3 alone
 void check_cache_block(const int *dims, const int *block) {
@@ -122,6 +130,7 @@ dirac_status dirac_create(const dirac_params *prm, const void *su3_links, const 
         require(std::isfinite(prm->kappa) && prm->kappa != 0.0, "kappa must be finite and non-zero");
         require(std::isfinite(prm->csw) && std::isfinite(prm->csw_qed), "c_sw and c_sw^QED must be finite");
         for (int m = 0; m < 4; ++m) require(std::isfinite(prm->bc_phase[m]), "boundary phases must be finite");
+        check_cstar(prm);
         check_dev(su3_links, (size_t)V * 4 * 9 * 16, "su3_links");
         if (u1_angles) check_dev(u1_angles, (size_t)V * 4 * 8, "u1_angles");
         hipStream_t s = (hipStream_t)stream;
@@ -134,6 +143,8 @@ dirac_status dirac_create(const dirac_params *prm, const void *su3_links, const 
         c->g.vh = (int)c->vh;
         c->g.vhp = (int)padded_sites(c->vh);
         for (int m = 0; m < 4; ++m) c->g.B[m] = prm->dims[m];
+        c->g.cs = prm->cstar;
+        c->g.h1 = prm->dims[1] / 2;
         c->U_lex.alloc((size_t)V * 4 * 9 * 16);
         HIP_CHECK(hipMemcpyAsync(c->U_lex.p, su3_links, (size_t)V * 4 * 9 * 16, hipMemcpyDeviceToDevice, s));
         if (u1_angles) {
@@ -187,6 +198,7 @@ dirac_status dirac_create_openqxd(const dirac_params *prm, const int *block, con
         }
         require(V < (int64_t)1 << 30, "lattice too large for 32-bit site indices");
         check_cache_block(prm->dims, block);
+        check_cstar(prm);
         check_dev(u_odd, (size_t)V / 2 * 8 * 9 * 16, "u_odd");
         if (a_odd) check_dev(a_odd, (size_t)V / 2 * 8 * 8, "a_odd");
         hipStream_t s = (hipStream_t)stream;
@@ -196,6 +208,8 @@ dirac_status dirac_create_openqxd(const dirac_params *prm, const int *block, con
             g.B[m] = block[m];
         }
         g.h3 = prm->dims[3] / 2;
+        g.cs = prm->cstar;
+        g.h1 = prm->dims[1] / 2;
         g.vh = (int)(V / 2);
         g.vhp = (int)padded_sites(V / 2);
         U.alloc((size_t)V * 4 * 9 * 16);

@@ -68,10 +68,15 @@ DEV void plane_field(const Geom &g, const double *__restrict__ U, const double *
     int y[4];
     auto at = [&](int dm, int dn) {
         y[0] = x[0]; y[1] = x[1]; y[2] = x[2]; y[3] = x[3];
-        if (dm > 0) y[mu] = wrap_up(y[mu], g.L[mu]);
-        if (dm < 0) y[mu] = wrap_dn(y[mu], g.L[mu]);
-        if (dn > 0) y[nu] = wrap_up(y[nu], g.L[nu]);
-        if (dn < 0) y[nu] = wrap_dn(y[nu], g.L[nu]);
+        // each step that crosses the boundary of a C* direction also moves x1 (the shifts commute)
+        auto step = [&](int d, int k) {
+            if (k == 0) return;
+            const bool cross = k > 0 ? y[d] == g.L[d] - 1 : y[d] == 0;
+            y[d] = k > 0 ? wrap_up(y[d], g.L[d]) : wrap_dn(y[d], g.L[d]);
+            y[1] = cstar_x1(g, d, cross, y[1]);
+        };
+        step(mu, dm);
+        step(nu, dn);
         return lex_index(g, y);
     };
     const int x0 = at(0, 0), xpm = at(1, 0), xpn = at(0, 1), xmm = at(-1, 0), xmn = at(0, -1);

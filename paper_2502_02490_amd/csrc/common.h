@@ -188,7 +188,19 @@ struct Geom {
     int vh;    // V / 2
     int vhp;   // V / 2 padded to a multiple of 64 (site blocks)
     int B[4];  // cache block of the OPENQXD user layout (B = L: the EO order)
+    int cs;    // C* boundary conditions in directions 1 .. cs (0: none)
+    int h1;    // L1 / 2: the shift of x1 on crossing the boundary of a C* direction mu >= 2
 };
+
+// Crossing the boundary of a C* direction mu >= 2 moves x1 into the mirror copy (C* boundary
+// conditions on the lattice doubled in direction 1).
+DEV int cstar_x1(const Geom &g, int mu, bool cross, int x1) {
+    if (cross && mu >= 2 && mu <= g.cs) {
+        x1 += g.h1;
+        if (x1 >= 2 * g.h1) x1 -= 2 * g.h1;
+    }
+    return x1;
+}
 
 DEV void site_coords(const Geom &g, int i, int p, int x[4]) {
     int h = i % g.h3;

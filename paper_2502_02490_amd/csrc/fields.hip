@@ -31,7 +31,11 @@ __global__ __launch_bounds__(kBlock) void k_import_links(Geom g, int p, const do
 #pragma unroll
         for (int back = 0; back < 2; ++back) {
             int y[4] = {x[0], x[1], x[2], x[3]};
-            if (back) y[mu] = wrap_dn(y[mu], g.L[mu]);
+            if (back) {
+                const bool cross = y[mu] == 0;
+                y[mu] = wrap_dn(y[mu], g.L[mu]);
+                y[1] = cstar_x1(g, mu, cross, y[1]);  // C*: the link behind x may sit in the mirror copy
+            }
             const int lam = lex_index(g, y);
             const double *u = U + ((size_t)lam * 4 + mu) * 18;
             const int dir = 2 * mu + back;
@@ -272,7 +276,11 @@ __global__ __launch_bounds__(kBlock) void k_openqxd_links(Geom g, const double *
 #pragma unroll 1
         for (int back = 0; back < 2; ++back) {
             int y[4] = {x[0], x[1], x[2], x[3]};
-            if (back) y[mu] = wrap_dn(y[mu], g.L[mu]);
+            if (back) {
+                const bool cross = y[mu] == 0;
+                y[mu] = wrap_dn(y[mu], g.L[mu]);
+                y[1] = cstar_x1(g, mu, cross, y[1]);  // C*: the link behind x may sit in the mirror copy
+            }
             const int64_t lam = lex_index(g, y);
             const int64_t slot = k * 8 + 2 * mu + back;
             const double2 *src = reinterpret_cast<const double2 *>(u_odd) + slot * 9;

@@ -78,9 +78,11 @@ DEV uint32_t neighbour(const HopArgs<S> &a, const int x[4], int row, int n) {
     const int mu = n >> 1, back = n & 1;
     const int xm = mu == 0 ? x[0] : mu == 1 ? x[1] : mu == 2 ? x[2] : x[3];
     const int Lm = mu == 0 ? a.g.L[0] : mu == 1 ? a.g.L[1] : mu == 2 ? a.g.L[2] : a.g.L[3];
+    const bool cross = back ? xm == 0 : xm + 1 == Lm;
     const int xn = back ? (xm == 0 ? Lm - 1 : xm - 1) : (xm + 1 == Lm ? 0 : xm + 1);
     const int rs = mu == 0 ? a.g.L[1] * a.g.L[2] : mu == 1 ? a.g.L[2] : 1;
-    return mu == 3 ? (uint32_t)(row * a.g.h3 + (xn >> 1)) : (uint32_t)((row + (xn - xm) * rs) * a.g.h3 + (x[3] >> 1));
+    const int rw = row + (cstar_x1(a.g, mu, cross, x[1]) - x[1]) * a.g.L[2];  // C*: into the mirror copy
+    return mu == 3 ? (uint32_t)(rw * a.g.h3 + (xn >> 1)) : (uint32_t)((rw + (xn - xm) * rs) * a.g.h3 + (x[3] >> 1));
 }
 
 // acc += the direction-n term for the neighbour spinor psi and the link (u, co, si): project to

@@ -112,7 +112,9 @@ DEV void transport_load(const PtcGeom &a, const typename Act<A>::vec *xc, int p,
         const int xm = mu == 0 ? x[0] : mu == 1 ? x[1] : mu == 2 ? x[2] : x[3];
         const int Lm = mu == 0 ? a.g.L[0] : mu == 1 ? a.g.L[1] : mu == 2 ? a.g.L[2] : a.g.L[3];
         const int xn = back ? (xm == 0 ? Lm - 1 : xm - 1) : (xm + 1 == Lm ? 0 : xm + 1);
+        const bool cross = back ? xm == 0 : xm + 1 == Lm;
         if (mu == 0) y[0] = xn; else if (mu == 1) y[1] = xn; else if (mu == 2) y[2] = xn; else y[3] = xn;
+        y[1] = cstar_x1(a.g, mu, cross, y[1]);  // C*: into the mirror copy
     }
     const uint32_t j = path > 0 ? (uint32_t)half_index(a.g, y) : i;
     const int q = path > 0 ? 1 - p : p;

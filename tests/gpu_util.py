@@ -24,18 +24,18 @@ class Case:
     """A lattice with seeded SU(3) x U(1) fields, the oracle's view of it and the GPU operator."""
 
     def __init__(self, dims, eps=0.5, kappa=0.1245, csw=1.6, csw_qed=1.0, qhat=-1, seed=201,
-                 bc_phase=(math.pi, 0.0, 0.0, 0.0), theta_max=0.3):
+                 bc_phase=(math.pi, 0.0, 0.0, 0.0), theta_max=0.3, cstar=0):
         import paper_2502_02490_amd as P
 
         self.dims = tuple(dims)
         self.V = geo.volume(dims)
         self.U = gen.su3_field(dims, eps, seed)
         self.theta = gen.u1_field(dims, theta_max, seed)
-        self.p = odirac.Params(self.dims, kappa, csw, csw_qed, qhat, tuple(bc_phase))
+        self.p = odirac.Params(self.dims, kappa, csw, csw_qed, qhat, tuple(bc_phase), cstar)
         self.f = odirac.Fields(self.U, self.theta, self.p)
         self.Ud = torch.from_numpy(self.U).cuda()
         self.thd = torch.from_numpy(self.theta).cuda()
-        self.D = P.Dirac(self.Ud, self.thd, self.dims, kappa, csw, csw_qed, qhat, bc_phase)
+        self.D = P.Dirac(self.Ud, self.thd, self.dims, kappa, csw, csw_qed, qhat, bc_phase, cstar=cstar)
         self.even, self.odd = odirac.even_odd(self.f)
 
     def spinor(self, seed, index=0):
