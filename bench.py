@@ -487,6 +487,18 @@ def main():
         cl()
     tc = timed(cl, args.steps, stream)
     extra["clover_f64_GBps"] = round(120 * 8 * vh * args.steps / tc / 1e9, 1)
+    # C* boundaries in directions 1..3 on the same field, read as the doubled lattice (dims[1] = 32
+    # holds the physical x extent 16 and its mirror copy): the shifted neighbours cost nothing
+    Dc = P.Dirac(torch.from_numpy(U).cuda(), torch.from_numpy(th).cuda(), DIMS, KAPPA, CSW, CSW_QED, QHAT,
+                 (math.pi, 0.0, 0.0, 0.0), cstar=3)
+    yc = torch.empty_like(xe)
+    schur_c = lambda: Dc.apply_eo(yc, xe, "f64", "native")  # noqa: E731
+    for _ in range(5):
+        schur_c()
+    tcs = timed(schur_c, args.steps, stream)
+    extra["schur_f64_cstar3_GBps"] = round(SCHUR_REALS * 8 * vh * args.steps / tcs / 1e9, 1)
+    Dc.close()
+    del yc
     log(f"[bench] extra {extra}")
 
     solves = {}
