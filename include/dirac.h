@@ -202,7 +202,8 @@ typedef enum {
     DIRAC_SOLVER_GCR = 1,       /* even-odd GCR(restart), FP64 */
     DIRAC_SOLVER_MIXED_GCR = 2, /* FP64 defect correction around an inner_prec even-odd GCR */
     DIRAC_SOLVER_FGCR_PTC = 3,  /* flexible GCR on the full D with a PTC network as preconditioner */
-    DIRAC_SOLVER_FGCR_PTC_EO = 4 /* flexible GCR on D-hat, preconditioner r_e -> even half of N(r_e, 0) */
+    DIRAC_SOLVER_FGCR_PTC_EO = 4, /* flexible GCR on D-hat, preconditioner r_e -> even half of N(r_e, 0) */
+    DIRAC_SOLVER_FGCR_SAP = 5   /* flexible GCR on the full D, Schwarz (SAP) preconditioner (dirac_sap) */
 } dirac_solver;
 
 typedef struct dirac_ptc dirac_ptc;  /* parallel-transport convolution network (see below) */
@@ -217,6 +218,8 @@ typedef struct {
     int x0_given;        /* 1: x holds the initial guess */
     int precision;       /* GCR / CGLS: dirac_prec of the whole solve (F64 only) */
     const dirac_ptc *ptc; /* FGCR_PTC(_EO): the preconditioner network (trained weights) */
+    int sap_ncy;         /* FGCR_SAP: Schwarz cycles per preconditioner application (0: 4) */
+    int sap_nmr;         /* FGCR_SAP: minimal-residual steps per block solve (0: 4) */
 } dirac_solver_params;
 
 typedef struct {
@@ -253,6 +256,18 @@ dirac_status dirac_solve(dirac_ctx *ctx, void *x, const void *b, dirac_layout la
 dirac_status dirac_solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x, const void *const *b, int nrhs,
                                  dirac_layout layout, const dirac_solver_params *params, dirac_solve_info *info,
                                  void *stream);
+
+/* psi = M r, the Schwarz alternating procedure (SAP) of openQxD's solver (named in the
+ * paper's outlook; the method is Luscher's multiplicative Schwarz preconditioner): the lattice
+ * is tiled by 4^4 blocks coloured as a checkerboard of blocks; psi = 0, rho = r, and ncy times,
+ * for colour 0 then colour 1, on every block of that colour nmr minimal-residual steps
+ *   v = D_blk r_b, w = <v, r_b> / <v, v>, delta += w r_b, r_b -= w v   (from delta = 0, r_b = rho)
+ * on the block operator D_blk (hops that leave the block dropped), psi += delta, rho = r - D psi.
+ * in, out: NATIVE F32 full vectors; FP32 arithmetic on the F32 copies of the fields.  Every
+ * lattice extent must be a multiple of 8, and with C* boundaries in two or more directions
+ * dims[1] a multiple of 16 (the mirror shift an even number of blocks, so that blocks of one
+ * colour never meet); EINVAL otherwise; ncy, nmr in 1..64.  Asynchronous. */
+dirac_status dirac_sap(dirac_ctx *ctx, void *out, const void *in, int ncy, int nmr, void *stream);
 
 /* ---------------------------------------------------------------- learned preconditioner
  * A gauge-covariant parallel-transport convolution (PTC) network N (a reading of the

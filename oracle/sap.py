@@ -23,15 +23,19 @@ from . import dirac
 from . import geometry as geo
 
 
-def check_blocks(L, bs) -> None:
+def check_blocks(L, bs, cstar: int = 0) -> None:
     for m in range(4):
         if bs[m] < 1 or L[m] % bs[m] != 0 or (L[m] // bs[m]) % 2 != 0:
             raise ValueError("block extents must divide the lattice into an even number of blocks per direction")
+    if cstar >= 2 and (L[1] // 2) % (2 * bs[1]) != 0:
+        # crossing a shifted boundary moves x1 by L1/2: an odd number of blocks would join two
+        # blocks of one colour across that face
+        raise ValueError("with C* boundaries the mirror shift L1/2 must be an even number of blocks")
 
 
-def block_index(L, bs):
+def block_index(L, bs, cstar: int = 0):
     """(block id [V], colour [V]) of every LEX site; ids lexicographic in the block coordinates."""
-    check_blocks(L, bs)
+    check_blocks(L, bs, cstar)
     x = geo.coords(np.arange(geo.volume(L)), L)
     n = x // np.asarray(bs)
     nb = [L[m] // bs[m] for m in range(4)]
@@ -48,7 +52,7 @@ def restricted_apply(f: dirac.Fields, psi: np.ndarray, mask: np.ndarray) -> np.n
 def mr_blocks(f: dirac.Fields, rho: np.ndarray, colour: int, bs, nmr: int, history=None) -> np.ndarray:
     """nmr minimal-residual steps on every block of the given colour (one step length per block:
     the inner products are sums over the sites of each block)."""
-    ids, col = block_index(f.p.dims, bs)
+    ids, col = block_index(f.p.dims, bs, f.p.cstar)
     mask = col == colour
     nblk = int(ids.max()) + 1
     r = np.where(mask[:, None, None], rho, 0.0)

@@ -12,8 +12,8 @@ import math
 import torch
 
 from . import _lib
-from ._lib import (BF16, CGLS, EO, F16, F32, F64, FGCR_PTC, FGCR_PTC_EO, GCR, LEX, MIXED_GCR, NATIVE,  # noqa: F401
-                   OPENQXD, DiracError, SolveInfo, SolverParams)
+from ._lib import (BF16, CGLS, EO, F16, F32, F64, FGCR_PTC, FGCR_PTC_EO, FGCR_SAP, GCR, LEX, MIXED_GCR,  # noqa: F401
+                   NATIVE, OPENQXD, DiracError, SolveInfo, SolverParams)
 
 _TORCH_REAL = {F64: torch.float64, F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
 _TORCH_USER = {F64: torch.complex128, F32: torch.complex64, F16: torch.complex128, BF16: torch.complex128}
@@ -197,9 +197,16 @@ class Dirac:
     def clover_invert(self, parity_mask: int = 2, stream=None):
         _lib.check(self.lib.clover_invert(self._ctx, int(parity_mask), _stream(stream)))
 
+    def sap(self, out, inp, ncy=4, nmr=4, stream=None):
+        """out = M_SAP inp (Schwarz preconditioner) on NATIVE F32 full vectors."""
+        nb = self.native_bytes("f32", 0)
+        _lib.check(self.lib.dirac_sap(self._ctx, _ptr(out, nb), _ptr(inp, nb), int(ncy), int(nmr), _stream(stream)))
+        return out
+
     # -------------------------------------------------------------- solvers
     def solve(self, x, b, method=GCR, tol=1e-10, restart=32, max_iter=10000, layout="lex", precision="f64",
-              inner_prec="f32", inner_tol=None, x0_given=False, ptc=None, stream=None, raise_on_noconv=True):
+              inner_prec="f32", inner_tol=None, x0_given=False, ptc=None, stream=None, raise_on_noconv=True,
+              sap_ncy=0, sap_nmr=0):
         """Solve D x = b (full-lattice FP64 vectors in `layout`); returns the SolveInfo."""
         sp = SolverParams()
         sp.method, sp.restart, sp.max_iter, sp.tol = int(method), int(restart), int(max_iter), float(tol)
@@ -207,6 +214,7 @@ class Dirac:
         sp.inner_tol = float(inner_tol) if inner_tol is not None else 0.0
         sp.x0_given, sp.precision = int(x0_given), _prec(precision)
         sp.ptc = ptc._net if ptc is not None else None
+        sp.sap_ncy, sp.sap_nmr = int(sap_ncy), int(sap_nmr)
         info = SolveInfo()
         nb = self._vec_bytes("f64", layout, 0)
         st = self.lib.dirac_solve(self._ctx, _ptr(x, nb), _ptr(b, nb), _layout(layout), ctypes.byref(sp),

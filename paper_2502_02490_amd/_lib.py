@@ -12,12 +12,12 @@ STATUS_NAMES = ["DIRAC_OK", "DIRAC_EINVAL", "DIRAC_ENOMEM", "DIRAC_EHIP", "DIRAC
                 "DIRAC_ENONFINITE", "DIRAC_EUNSUPPORTED"]
 F64, F32, F16, BF16 = 0, 1, 2, 3
 LEX, EO, NATIVE, OPENQXD = 0, 1, 2, 3
-CGLS, GCR, MIXED_GCR, FGCR_PTC, FGCR_PTC_EO = 0, 1, 2, 3, 4
+CGLS, GCR, MIXED_GCR, FGCR_PTC, FGCR_PTC_EO, FGCR_SAP = 0, 1, 2, 3, 4, 5
 
 # every symbol declared in include/dirac.h
 EXPORTS = ["dirac_create", "dirac_create_openqxd", "dirac_set_cache_block", "dirac_destroy", "dirac_load_clover", "dirac_get_clover", "clover_invert",
            "dirac_native_bytes", "dirac_import", "dirac_export", "dirac_apply", "dirac_apply_eo", "dirac_apply_eo_multi",
-           "dirac_apply_hop", "dirac_apply_clover", "dirac_solve", "dirac_solve_batched", "dirac_last_error",
+           "dirac_apply_hop", "dirac_apply_clover", "dirac_sap", "dirac_solve", "dirac_solve_batched", "dirac_last_error",
            "ptc_create", "ptc_destroy", "ptc_num_weights", "ptc_set_weights", "ptc_get_weights", "ptc_get_grad",
            "ptc_zero_grad", "ptc_forward", "ptc_forward_eo", "ptc_backward", "ptc_adam_step", "ptc_get_adam_state", "ptc_set_adam_state",
            "ptc_train_step"]
@@ -32,7 +32,8 @@ class Params(ctypes.Structure):
 class SolverParams(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("x0_given", ctypes.c_int), ("precision", ctypes.c_int), ("ptc", ctypes.c_void_p)]
+                ("x0_given", ctypes.c_int), ("precision", ctypes.c_int), ("ptc", ctypes.c_void_p),
+                ("sap_ncy", ctypes.c_int), ("sap_nmr", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -76,6 +77,7 @@ def load(path: str = LIB_PATH):
     lib.dirac_apply_eo_multi.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_apply_hop.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_apply_clover.argtypes = [vp, vp, vp, i, i, i, vp]
+    lib.dirac_sap.argtypes = [vp, vp, vp, i, i, vp]
     lib.dirac_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(SolverParams), ctypes.POINTER(SolveInfo), vp]
     lib.dirac_solve_batched.argtypes = [vp, i, vp, vp, i, i, ctypes.POINTER(SolverParams), vp, vp]
     lib.dirac_last_error.restype = ctypes.c_char_p

@@ -246,6 +246,7 @@ dirac_status dirac_destroy(dirac_ctx *c) {
         f.tmp_half.release(); f.user_in.release(); f.user_out.release();
     }
     for (auto &b : c->ptc_links) b.release();
+    for (dl::DevBuf *b : {&c->sap_rho, &c->sap_dlt, &c->sap_in, &c->sap_out}) b->release();
     c->flags.release();
     c->red.release();
     delete c;
@@ -481,6 +482,17 @@ dirac_status dirac_solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x
     API_END
 }
 
+dirac_status dirac_sap(dirac_ctx *c, void *out, const void *in, int ncy, int nmr, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    const size_t nb = native_bytes(c, DIRAC_F32, 0);
+    check_dev(in, nb, "in");
+    check_dev(out, nb, "out");
+    check_no_alias(out, nb, in, nb);
+    dl::sap_apply(c, out, in, ncy, nmr, (hipStream_t)stream);
+    API_END
+}
+
 // ---------------------------------------------------------------- learned preconditioner
 dirac_status ptc_create(const int *channels, int nlayers, dirac_ptc **out) {
     API_BEGIN
@@ -607,7 +619,7 @@ dirac_status ptc_forward_eo(dirac_ctx *c, dirac_ptc *n, void *out, const void *i
     dl::ptc_ensure_acts(c, n);
     char *a0 = (char *)dl::ptc_act(c, n, 0);
     HIP_CHECK(hipMemcpyAsync(a0, in, nb, hipMemcpyDeviceToDevice, s));
-    dl::ptc_zero(a0 + nb, nb, s);
+    dl::zero_fill(a0 + nb, nb, s);
     dl::ptc_forward_acts(c, n, s, false, true);
     HIP_CHECK(hipMemcpyAsync(out, dl::ptc_act(c, n, n->nlayers), nb, hipMemcpyDeviceToDevice, s));
     API_END

@@ -292,7 +292,18 @@ __global__ __launch_bounds__(kBlock) void k_openqxd_links(Geom g, const double *
     }
 }
 
+__global__ void k_zero16(size_t n, uint4 *__restrict__ p) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 }  // namespace
+
+void zero_fill(void *p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    k_zero16<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, (uint4 *)p);
+    HIP_CHECK(hipGetLastError());
+}
 
 void openqxd_links_to_lex(const Geom &g, const double *u_odd, const double *a_odd, double *U, double *th,
                           hipStream_t s) {

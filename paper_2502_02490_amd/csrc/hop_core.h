@@ -1,0 +1,115 @@
+// Device pieces of the hopping term shared by the hop kernels (hop.hip) and the Schwarz block
+// solver (sap.hip): kernel arguments, spinor and link loads, the neighbour index and the
+// projected accumulation of one direction.
+#pragma once
+
+#include "dirac_ops.h"
+#include "internal.h"
+
+namespace dl {
+namespace {
+
+template <typename S>
+struct HopArgs {
+    Geom g;
+    int p;           // output parity
+    int nb8;         // work-groups launched (a multiple of 8 with the XCD-contiguous order)
+    int xcd;         // 1: XCD-contiguous work-group order
+    int nrhs;        // right-hand sides: vector r of in / out / chi is r * vs vectors after the base
+    size_t vs;       // 16-byte vectors per half-lattice spinor
+    const int *active;  // per right-hand side, NULL = all
+    const typename St<S>::vec *in;     // parity 1 - p, 24 reals per site
+    const typename Lk<S>::vec *links;  // parity p, [8 dir][12 / W][vh]
+    const typename Lk<S>::om *omega;   // parity p, [8 dir][vh]
+    const typename St<S>::vec *clov;   // parity p, 72 reals: A (HOP_CLOV) or A^-1 (HOP_INV)
+    const typename St<S>::vec *chi;    // parity p (HOP_CLOV)
+    typename St<S>::vec *out;          // parity p
+    typename St<S>::acc coef;
+};
+
+template <typename S>
+DEV void load_spinor(const typename St<S>::vec *__restrict__ base, uint32_t s, C<typename St<S>::acc> psi[12]) {
+    using T = typename St<S>::acc;
+    T r[24];
+    load_field<S, 24>(base, s, r);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = mk(r[2 * k], r[2 * k + 1]);
+}
+
+template <typename S, bool NT>
+DEV void load_link(const HopArgs<S> &a, int dir, uint32_t i, C<typename St<S>::acc> u[6], typename St<S>::acc &co,
+                   typename St<S>::acc &si) {
+    using T = typename St<S>::acc;
+    using LV = typename Lk<S>::vec;
+    using OM = typename Lk<S>::om;
+    constexpr int W = Lk<S>::W;
+    const size_t vhp = (size_t)a.g.vhp;
+    const LV *b = site_ptr(a.links + (size_t)dir * (12 / W) * vhp, i, 12 / W);
+    T r[12];
+#pragma unroll
+    for (int k = 0; k < 12 / W; ++k) Lk<S>::unpack(NT ? ld_stream(b + k * kSB) : b[k * kSB], r + k * W);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) u[k] = mk(r[2 * k], r[2 * k + 1]);
+    const OM *om = a.omega + (size_t)dir * vhp + i;
+    const OM w = NT ? ld_stream(om) : *om;
+    if constexpr (Lk<S>::phase_pair) Lk<S>::phase(w, co, si);
+    else sc((T)w, si, co);
+}
+
+// Spin structure of gamma_mu = [[0, e_mu], [e_mu^dag, 0]]: e_mu is monomial, row k has its
+// one entry c_k in column p_k, with p_1 = 1 - p_0.  Per mu: (p_0, c_0, c_1), c in {+-1, +-i}:
+//   e_0 = -1: (0, -1, -1)   e_1 = -i sigma_1: (1, -i, -i)
+//   e_2 = -i sigma_2: (1, -1, +1)   e_3 = -i sigma_3: (0, -i, +i)
+// so (e l)_k = c_k l_{p_k} and (e^dag w)_{p_k} = conj(c_k) w_k.
+template <typename T>
+DEV C<T> cmul_unit(T cr, T ci, C<T> z) { return mk(cr * z.r - ci * z.i, cr * z.i + ci * z.r); }
+
+// Index of the neighbour of site (x, row) in direction n = 2 mu + back, in the other parity.
+template <typename S>
+DEV uint32_t neighbour(const HopArgs<S> &a, const int x[4], int row, int n) {
+    const int mu = n >> 1, back = n & 1;
+    const int xm = mu == 0 ? x[0] : mu == 1 ? x[1] : mu == 2 ? x[2] : x[3];
+    const int Lm = mu == 0 ? a.g.L[0] : mu == 1 ? a.g.L[1] : mu == 2 ? a.g.L[2] : a.g.L[3];
+    const bool cross = back ? xm == 0 : xm + 1 == Lm;
+    const int xn = back ? (xm == 0 ? Lm - 1 : xm - 1) : (xm + 1 == Lm ? 0 : xm + 1);
+    const int rs = mu == 0 ? a.g.L[1] * a.g.L[2] : mu == 1 ? a.g.L[2] : 1;
+    const int rw = row + (cstar_x1(a.g, mu, cross, x[1]) - x[1]) * a.g.L[2];  // C*: into the mirror copy
+    return mu == 3 ? (uint32_t)(rw * a.g.h3 + (xn >> 1)) : (uint32_t)((rw + (xn - xm) * rs) * a.g.h3 + (x[3] >> 1));
+}
+
+// acc += the direction-n term for the neighbour spinor psi and the link (u, co, si): project to
+// a half-spinor, multiply by the link (or its adjoint), reconstruct.
+template <typename T, int DAG>
+DEV void accumulate_dir(int n, const C<T> psi[12], const C<T> u[6], T co, T si, C<T> acc[12]) {
+    const int mu = n >> 1, back = n & 1;
+    // projector sign: forward (1 + SF gamma), backward (1 - SF gamma); SF = -1 for D, +1 for D^dag
+    const T sg = (DAG ? T(1) : T(-1)) * (back ? T(-1) : T(1));
+    const int sw = (mu == 1 || mu == 2);
+    const T c0r = (mu == 0 || mu == 2) ? T(-1) : T(0), c0i = (mu == 1 || mu == 3) ? T(-1) : T(0);
+    const T c1r = mu == 0 ? T(-1) : mu == 2 ? T(1) : T(0), c1i = mu == 1 ? T(-1) : mu == 3 ? T(1) : T(0);
+    C<T> h[6], w[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const C<T> l0 = psi[6 + c], l1 = psi[9 + c];
+        const C<T> e0 = cmul_unit(c0r, c0i, sw ? l1 : l0);
+        const C<T> e1 = cmul_unit(c1r, c1i, sw ? l0 : l1);
+        h[c] = mk(fma(sg, e0.r, psi[c].r), fma(sg, e0.i, psi[c].i));
+        h[3 + c] = mk(fma(sg, e1.r, psi[3 + c].r), fma(sg, e1.i, psi[3 + c].i));
+    }
+    if (back) link_adj_mul(u, co, si, h, w);
+    else link_mul(u, co, si, h, w);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[c] = acc[c] + w[c];
+        acc[3 + c] = acc[3 + c] + w[3 + c];
+        const C<T> t0 = cmul_unit(c0r, -c0i, w[c]);      // conj(c_0) w_0 -> lower spin p_0
+        const C<T> t1 = cmul_unit(c1r, -c1i, w[3 + c]);  // conj(c_1) w_1 -> lower spin p_1
+        const C<T> l0 = sw ? t1 : t0, l1 = sw ? t0 : t1;
+        acc[6 + c] = mk(fma(sg, l0.r, acc[6 + c].r), fma(sg, l0.i, acc[6 + c].i));
+        acc[9 + c] = mk(fma(sg, l1.r, acc[9 + c].r), fma(sg, l1.i, acc[9 + c].i));
+    }
+}
+
+
+}  // namespace
+}  // namespace dl

@@ -82,6 +82,8 @@ struct dirac_ctx {
     dl::DevBuf U_lex, theta_lex;   // FP64 copies of the gauge input (clover rebuild, precision copies)
     dl::PrecFields f[4];           // indexed by dirac_prec
     dl::DevBuf ptc_links[2];       // full FP32 links with phases for the PTC network (built on first use)
+    dl::DevBuf sap_rho, sap_dlt;   // Schwarz preconditioner: residual and block corrections (F32 full)
+    dl::DevBuf sap_in, sap_out;    // FGCR_SAP: the preconditioner's F32 input and output
     bool ptc_links_ready = false;
     dl::DevBuf flags;              // small device scratch: flags, maxima
     dl::DevBuf red;                // reduction partials
@@ -103,6 +105,11 @@ void import_links(dirac_ctx *c, hipStream_t s);
 void openqxd_links_to_lex(const Geom &g, const double *u_odd, const double *a_odd, double *U, double *th,
                           hipStream_t s);
 void ensure_prec(dirac_ctx *c, dirac_prec pr, hipStream_t s);
+// zero `bytes` (a multiple of 16) with a kernel, so that a captured graph holds no memset node
+void zero_fill(void *p, size_t bytes, hipStream_t s);
+// Schwarz (SAP) preconditioner, psi = M r on NATIVE F32 full vectors (sap.hip)
+bool sap_supported(const dirac_ctx *c);
+void sap_apply(dirac_ctx *c, void *psi, const void *r, int ncy, int nmr, hipStream_t s);
 void spinor_import(dirac_ctx *c, void *native, const void *user, int sites, dirac_prec pr, dirac_layout lay,
                    hipStream_t s);
 void spinor_export(dirac_ctx *c, void *user, const void *native, int sites, dirac_prec pr, dirac_layout lay,

@@ -31,7 +31,6 @@ void ptc_alloc(dirac_ptc *n);
 void ptc_refresh_bf16(dirac_ptc *n, hipStream_t s);
 void ptc_ensure_acts(dirac_ctx *c, dirac_ptc *n);
 float *ptc_act(dirac_ctx *c, dirac_ptc *n, int layer);
-void ptc_zero(void *p, size_t bytes, hipStream_t s);
 void ptc_forward_acts(dirac_ctx *c, dirac_ptc *n, hipStream_t s, bool keep_all = true, bool eo = false);
 void ptc_backward_acts(dirac_ctx *c, dirac_ptc *n, const void *g_out, void *gin, hipStream_t s);
 void ptc_adam(dirac_ptc *n, double lr, hipStream_t s);

@@ -794,17 +794,6 @@ float *ptc_act(dirac_ctx *c, dirac_ptc *n, int l) {
     return (float *)((char *)n->acts.p + off);
 }
 
-__global__ void k_zero16(size_t n, uint4 *__restrict__ p) {
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) p[k] = make_uint4(0u, 0u, 0u, 0u);
-}
-// zero `bytes` (a multiple of 16) at p with a kernel, so that a captured graph holds no memset node
-void ptc_zero(void *p, size_t bytes, hipStream_t s) {
-    const size_t n = bytes / 16;
-    k_zero16<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, (uint4 *)p);
-    HIP_CHECK(hipGetLastError());
-}
-
 // forward: acts[0] must hold the input; leaves the output in acts[nlayers] and, with keep_all,
 // every layer's output in acts[l + 1] (the backward pass needs them).  With eo the input's odd
 // half must be zero, and only the even half of the output is formed (a network of one layer

@@ -176,7 +176,10 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
 
 void check_solver_params(const dirac_solver_params *p) {
     require(p != nullptr, "solver params are NULL");
-    require(p->method >= DIRAC_SOLVER_CGLS && p->method <= DIRAC_SOLVER_FGCR_PTC_EO, "unknown solver method");
+    require(p->method >= DIRAC_SOLVER_CGLS && p->method <= DIRAC_SOLVER_FGCR_SAP, "unknown solver method");
+    require(p->method != DIRAC_SOLVER_FGCR_SAP ||
+                (p->sap_ncy >= 0 && p->sap_ncy <= 64 && p->sap_nmr >= 0 && p->sap_nmr <= 64),
+            "sap_ncy and sap_nmr must be 0 (default) .. 64");
     require((p->method != DIRAC_SOLVER_FGCR_PTC && p->method != DIRAC_SOLVER_FGCR_PTC_EO) || p->ptc != nullptr,
             "FGCR_PTC needs a network (ptc)");
     require(std::isfinite(p->tol) && p->tol > 0.0 && p->tol < 1.0, "tol must be in (0, 1)");
@@ -240,6 +243,33 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
     int iters = 0;
     bool done = false;
 
+    if (p->method == DIRAC_SOLVER_FGCR_SAP) {
+        require(sap_supported(c), "FGCR_SAP needs every lattice extent to be a multiple of 8");
+        ensure_work(c, p->restart, DIRAC_F64, 2);
+        const size_t b32 = (size_t)48 * c->g.vhp * sizeof(float);
+        c->sap_in.alloc(b32);
+        c->sap_out.alloc(b32);
+        const int ncy = p->sap_ncy > 0 ? p->sap_ncy : 4, nmr = p->sap_nmr > 0 ? p->sap_nmr : 4;
+        // p = M_SAP r: FP64 -> FP32 -> Schwarz cycles -> FP64
+        const Precond M = [&](void *pv, const void *rv) {
+            B.lincomb(DIRAC_F32, DIRAC_F64, DIRAC_F64, 2, c->sap_in.p, nullptr, 1.0, rv, 0.0, nullptr, nullptr, 1.0, s);
+            sap_apply(c, c->sap_out.p, c->sap_in.p, ncy, nmr, s);
+            B.lincomb(DIRAC_F64, DIRAC_F32, DIRAC_F64, 2, pv, nullptr, 1.0, c->sap_out.p, 0.0, nullptr, nullptr, 1.0, s);
+        };
+        GcrOut g = gcr(c, w, DIRAC_F64, xf, bf, x0, target, p->restart, p->max_iter, s, true, &M, 2.0);
+        iters = g.iters;
+        info->restarts = g.restarts;
+        if (g.converged) {
+            done = true;
+        } else if (iters >= p->max_iter) {
+            st = DIRAC_ENOCONV;
+            done = true;
+        } else {
+            info->fell_back = 1;
+            x0 = !g.nonfinite;
+        }
+    }
+
     if (p->method == DIRAC_SOLVER_FGCR_PTC) {
         dirac_ptc *net = const_cast<dirac_ptc *>(p->ptc);
         require(net->ch[0] == 1 && net->ch[net->nlayers] == 1, "the PTC network must map 1 channel to 1 channel");
@@ -283,7 +313,7 @@ dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, d
             // p_e = [N(r_e, 0)]_e
             const Precond M = [&](void *pv, const void *rv) {
                 B.lincomb(DIRAC_F32, DIRAC_F64, DIRAC_F64, 1, a_in, nullptr, 1.0, rv, 0.0, nullptr, nullptr, 1.0, s);
-                ptc_zero(a_in + half32, half32 * sizeof(float), s);
+                zero_fill(a_in + half32, half32 * sizeof(float), s);
                 ptc_forward_acts(c, net, s, false, true);  // the even half of the output only
                 B.lincomb(DIRAC_F64, DIRAC_F32, DIRAC_F64, 1, pv, nullptr, 1.0, a_out, 0.0, nullptr, nullptr, 1.0, s);
             };

@@ -1,0 +1,80 @@
+"""Schwarz (SAP) preconditioner on the GPU against the oracle (oracle/sap.py): the FP32 block
+solves against the FP64 reference, repeatability, and flexible GCR with SAP against the oracle's
+operator."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import paper_2502_02490_amd as P
+from gpu_util import Case, flush, need_gpu, rel, to_dev
+from oracle import dirac as odirac
+from oracle import sap as osap
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", params=[((8, 8, 8, 8), 0), ((8, 16, 8, 8), 3)],
+                ids=lambda c: "L" + "x".join(map(str, c[0])) + f"_cstar{c[1]}")
+def case(request):
+    need_gpu()
+    dims, cs = request.param
+    flush(f"[gpu] sap case {dims} cstar {cs}")
+    c = Case(dims, seed=33, bc_phase=(math.pi, 0.3, 0.0, -0.2), cstar=cs)
+    yield c
+    c.D.close()
+
+
+def test_sap_matches_oracle(case):
+    """FP32 Schwarz cycles against the FP64 reference: each minimal-residual step length comes
+    from FP32 block sums, so the two drift apart by a few FP32 ulps per operator application
+    (2 cycles x 2 colours x 3 steps); 1e-5 leaves room for that and fails a dropped face term,
+    a wrong colour order or a misplaced hop by orders of magnitude."""
+    r = case.spinor(1).astype(np.complex64).astype(np.complex128)
+    exp = osap.sap(case.f, r, (4, 4, 4, 4), ncy=2, nmr=3)
+    inp = case.D.to_native(to_dev(r.astype(np.complex64)), "f32", "lex")
+    out = torch.empty_like(inp)
+    case.D.sap(out, inp, ncy=2, nmr=3)
+    got = case.D.from_native(out, "f32", "lex").cpu().numpy().astype(np.complex128)
+    err = rel(got, exp)
+    flush(f"[gpu] SAP vs oracle {err:.2e}")
+    assert err < 1e-5
+    # one colour step of one cycle (no face update) is the block solve alone
+    exp1 = osap.sap(case.f, r, (4, 4, 4, 4), ncy=1, nmr=5)
+    case.D.sap(out, inp, ncy=1, nmr=5)
+    assert rel(case.D.from_native(out, "f32", "lex").cpu().numpy(), exp1) < 1e-5
+    # repeatable bit for bit
+    o2 = torch.empty_like(inp)
+    case.D.sap(o2, inp, ncy=1, nmr=5)
+    assert torch.equal(out, o2)
+
+
+def test_fgcr_sap_solve(case):
+    b = case.spinor(2)
+    x = torch.zeros_like(to_dev(b))
+    info = case.D.solve(x, to_dev(b), method=P.FGCR_SAP, tol=1e-10, sap_ncy=3, sap_nmr=4)
+    res = b - odirac.apply_D(case.f, x.cpu().numpy())
+    assert np.linalg.norm(res) / np.linalg.norm(b) < 1.5e-10
+    x0 = torch.zeros_like(x)
+    plain = case.D.solve(x0, to_dev(b), method=P.GCR, tol=1e-10)
+    flush(f"[gpu] FGCR-SAP {info.iters} iterations, plain even-odd GCR {plain.iters}")
+    assert not info.fell_back
+    assert info.iters * 2 < plain.iters
+
+
+@pytest.mark.parametrize("dims,cs", [((4, 8, 8, 8), 0), ((8, 8, 8, 8), 3)])
+def test_sap_needs_blocks_that_tile(dims, cs):
+    """4^4 blocks must tile each direction an even number of times, and a C* mirror shift must
+    move an even number of blocks (L1 = 8 with C* would join blocks of one colour)."""
+    need_gpu()
+    D = P.Dirac(to_dev(gen.su3_field(dims, 0.5, 3)), to_dev(gen.u1_field(dims, 0.3, 3)), dims, 0.12, 1.0, 1.0, -1,
+                cstar=cs)
+    try:
+        v = D.native_empty("f32")
+        with pytest.raises(P.DiracError) as e:
+            D.sap(torch.empty_like(v), v)
+        assert e.value.status == P._lib.EINVAL
+    finally:
+        D.close()

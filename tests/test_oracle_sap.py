@@ -17,18 +17,20 @@ def fields(L=(4, 4, 4, 8), seed=7):
 BS = (2, 2, 2, 2)
 
 
-def test_colouring_is_a_block_checkerboard():
-    L = (4, 4, 4, 8)
-    ids, col = sap.block_index(L, BS)
-    assert len(np.unique(ids)) == 2 * 2 * 2 * 4
+@pytest.mark.parametrize("L,cs", [((4, 4, 4, 8), 0), ((4, 8, 4, 4), 3)])
+def test_colouring_is_a_block_checkerboard(L, cs):
+    ids, col = sap.block_index(L, BS, cs)
+    assert len(np.unique(ids)) == geo.volume(L) // 16
     lam = np.arange(geo.volume(L))
     for mu in range(4):
-        nb = geo.shift(lam, L, mu, 1)
+        nb = geo.shift(lam, L, mu, 1, cs)
         cross = ids[nb] != ids
         assert np.all(col[nb][cross] != col[cross])   # a face always joins the two colours
         assert np.all(col[nb][~cross] == col[~cross])
     with pytest.raises(ValueError):
         sap.block_index((4, 4, 4, 6), (2, 2, 2, 2))   # three blocks in direction 3
+    with pytest.raises(ValueError):
+        sap.block_index((4, 4, 4, 4), (2, 2, 2, 2), 3)  # C* shift of one block: same colours meet
 
 
 def test_many_mr_steps_reach_the_exact_block_solve():
