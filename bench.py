@@ -133,6 +133,44 @@ def solve_suite(D, b, inner_precs):
     return res
 
 
+# algorithmic bytes per site and Schwarz step of one colour (FP32): the residual, the solution and
+# the correction (read / written once: 5 x 96), the corrections of the face neighbours and their
+# links (on average 2 of the 8 directions cross a face of a 4^4 block: 2 x (96 + 52)), and per
+# minimal-residual step the links inside the block (on average 6 directions: 6 x 52) and the
+# clover field (288); a site takes one step per cycle
+def sap_bytes_per_site(ncy, nmr):
+    return ncy * (5 * 96 + 2 * (96 + 52) + nmr * (6 * 52 + 288))
+
+
+SAP_SETTINGS = ((2, 4), (4, 4), (4, 6))
+
+
+def sap_suite(D, b, plain_seconds, plain_iters):
+    """SAP-preconditioned flexible GCR(32) on the full D to 1e-10 (FP32 Schwarz cycles on 4^4
+    blocks) against plain FP64 even-odd GCR(32); and one preconditioner application alone."""
+    import torch
+
+    import paper_2502_02490_amd as P
+
+    res = {}
+    stream = torch.cuda.current_stream()
+    V = math.prod(DIMS)
+    r32 = D.to_native(b.to(torch.complex64), "f32", "lex")
+    o32 = torch.empty_like(r32)
+    for ncy, nmr in SAP_SETTINGS:
+        D.sap(o32, r32, ncy, nmr)
+        t = timed(lambda: D.sap(o32, r32, ncy, nmr), 10, stream) / 10
+        D.solve(torch.zeros_like(b), b, method=P.FGCR_SAP, tol=1e-4, sap_ncy=ncy, sap_nmr=nmr)  # warm-up
+        x = torch.zeros_like(b)
+        info = D.solve(x, b, method=P.FGCR_SAP, tol=1e-10, sap_ncy=ncy, sap_nmr=nmr, max_iter=100000)
+        res[f"ncy{ncy}_nmr{nmr}"] = {
+            "seconds": round(info.seconds, 4), "iters": info.iters, "fell_back": info.fell_back,
+            "true_rel_res": info.true_rel_res, "speedup_vs_fp64_eo_gcr": round(plain_seconds / info.seconds, 3),
+            "iters_plain": plain_iters, "precond_ms": round(t * 1e3, 3),
+            "precond_algorithmic_GBps": round(sap_bytes_per_site(ncy, nmr) * V / t / 1e9, 1)}
+    return res
+
+
 BATCH_DIMS = [(8, 8, 8, 8), (12, 12, 12, 12)] + [(32, 16, 16, 16)] * 3 + [(48, 24, 24, 24)] * 3
 
 
@@ -505,6 +543,9 @@ def main():
     if not args.no_solve:
         solves["32^3x64"] = solve_suite(D, torch.from_numpy(psi).cuda(), ("f32", "f16", "bf16"))
         log(f"[bench] solves 32^3x64 {solves['32^3x64']}")
+        plain = solves["32^3x64"]["fp64_gcr"]
+        solves["32^3x64_fgcr_sap"] = sap_suite(D, torch.from_numpy(psi).cuda(), plain["seconds"], plain["iters"])
+        log(f"[bench] SAP 32^3x64 {solves['32^3x64_fgcr_sap']}")
     D.close()
     del x, xe, ye, y, x32, xe32, ye32
     torch.cuda.empty_cache()

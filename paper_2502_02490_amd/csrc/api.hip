@@ -246,7 +246,7 @@ dirac_status dirac_destroy(dirac_ctx *c) {
         f.tmp_half.release(); f.user_in.release(); f.user_out.release();
     }
     for (auto &b : c->ptc_links) b.release();
-    for (dl::DevBuf *b : {&c->sap_rho, &c->sap_dlt, &c->sap_in, &c->sap_out}) b->release();
+    for (dl::DevBuf *b : {&c->sap_rho, &c->sap_in, &c->sap_out, &c->sap_links, &c->sap_clov}) b->release();
     c->flags.release();
     c->red.release();
     delete c;

@@ -327,6 +327,7 @@ void clover_build(dirac_ctx *c, hipStream_t s) {
                                                           c->p.csw_qed * c->p.qhat, diag, (double2 *)f.clov[p].p);
     }
     HIP_CHECK(hipGetLastError());
+    c->sap_ready = false;
     for (int q = 0; q < 4; ++q) {
         c->f[q].clover_ready = (q == DIRAC_F64);
         c->f[q].inv_ready[0] = c->f[q].inv_ready[1] = false;

@@ -366,6 +366,7 @@ void clover_import(dirac_ctx *c, const double *user, dirac_layout lay, hipStream
         k_clover_in<<<grid_for(c->vh), kBlock, 0, s>>>(c->g, p, lay, user, (double2 *)f.clov[p].p);
     }
     HIP_CHECK(hipGetLastError());
+    c->sap_ready = false;
     for (int q = 0; q < 4; ++q) {
         c->f[q].clover_ready = (q == DIRAC_F64);
         c->f[q].inv_ready[0] = c->f[q].inv_ready[1] = false;

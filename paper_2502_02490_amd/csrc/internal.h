@@ -82,8 +82,10 @@ struct dirac_ctx {
     dl::DevBuf U_lex, theta_lex;   // FP64 copies of the gauge input (clover rebuild, precision copies)
     dl::PrecFields f[4];           // indexed by dirac_prec
     dl::DevBuf ptc_links[2];       // full FP32 links with phases for the PTC network (built on first use)
-    dl::DevBuf sap_rho, sap_dlt;   // Schwarz preconditioner: residual and block corrections (F32 full)
+    dl::DevBuf sap_rho;            // Schwarz preconditioner: residual, solution, corrections (block order)
     dl::DevBuf sap_in, sap_out;    // FGCR_SAP: the preconditioner's F32 input and output
+    dl::DevBuf sap_links, sap_clov;  // Schwarz blocks: F32 links and clover field in block order
+    bool sap_ready = false;        // sap_links / sap_clov match the current fields
     bool ptc_links_ready = false;
     dl::DevBuf flags;              // small device scratch: flags, maxima
     dl::DevBuf red;                // reduction partials

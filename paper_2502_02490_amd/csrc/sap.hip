@@ -9,7 +9,7 @@
 // update after a colour's solves changes rho only on the faces of the other colour's blocks
 // (D delta = -1/2 H delta there); it is done by the next step's work-groups on entry, from the
 // corrections delta of the previous step, so a step is one launch.  FP32 throughout (the
-// arithmetic of a preconditioner), on the F32 copies of the links and the clover field.
+// arithmetic of a preconditioner), on block-ordered copies of the F32 links and clover field.
 #include "dirac_ops.h"
 #include "hop_core.h"
 #include "internal.h"
@@ -17,18 +17,27 @@
 namespace dl {
 namespace {
 
-constexpr int kSapB = 4;                           // block extent in every direction
+constexpr int kSapB = 4;                                  // block extent in every direction
 constexpr int kSapSites = kSapB * kSapB * kSapB * kSapB;  // 256: one work-group
+constexpr int kSapLinkPlanes = 4;  // a link in block order: 12 reals of rows 0, 1, then cos, sin of its phase
 
+// Block order: the fields of the Schwarz blocks are kept block by block (block k lexicographic in
+// the block coordinates, site t = 64 b0 + 16 b1 + 4 b2 + b3 inside it), plane-major within a
+// block, so that a work-group reads one contiguous chunk and every wavefront load is 1 KB of
+// consecutive 16-byte vectors:  spinor [k][6][256], clover [k][18][256], links [k][8][4][256].
+// (The sites of a 4^4 block lie in 2-site pieces of the x3-fastest NATIVE order: read from there,
+// every wavefront load touches 32 cache lines for 32 bytes each.)
 struct SapArgs {
     Geom g;
-    const float4 *links[2];  // F32 compressed links per parity, [8 dir][3 planes] blocked
-    const float *omega[2];   // per parity, [8 dir][vhp]
-    const float4 *clov[2];   // F32 clover field A per parity, 72 reals = 18 planes
-    float4 *rho, *psi, *dlt;  // F32 NATIVE full vectors (even half, then odd half)
-    int nb[4];               // blocks per direction
+    const float4 *links;  // block order
+    const float4 *clov;   // block order
+    float4 *rho, *psi, *dlt;  // block order, all blocks
+    int nb[4];            // blocks per direction
     int colour, nmr, update;
 };
+
+DEV int block_of(const SapArgs &a, const int n[4]) { return ((n[0] * a.nb[1] + n[1]) * a.nb[2] + n[2]) * a.nb[3] + n[3]; }
+DEV size_t spinor_at(int k, int t) { return (size_t)k * 6 * kSapSites + t; }  // plane 0; plane j at + j * 256
 
 // Block coordinates of the k-th block of colour c: blocks are lexicographic in (n0, n1, n2, n3),
 // and every row of n3 (an even number of blocks) holds half of each colour.
@@ -47,6 +56,29 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+DEV void load_sp(const float4 *base, C<float> r[12]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const float4 q = base[k * kSapSites];
+        r[2 * k] = mk(q.x, q.y);
+        r[2 * k + 1] = mk(q.z, q.w);
+    }
+}
+DEV void store_sp(float4 *base, const C<float> r[12]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) base[k * kSapSites] = make_float4(r[2 * k].r, r[2 * k].i, r[2 * k + 1].r, r[2 * k + 1].i);
+}
+// link of direction d at site t of block k (block order)
+DEV void load_blink(const SapArgs &a, int k, int d, int t, C<float> u[6], float &co, float &si) {
+    const float4 *q = a.links + ((size_t)(k * 8 + d) * kSapLinkPlanes) * kSapSites + t;
+    const float4 l0 = q[0], l1 = q[kSapSites], l2 = q[2 * kSapSites], l3 = q[3 * kSapSites];
+    u[0] = mk(l0.x, l0.y); u[1] = mk(l0.z, l0.w);
+    u[2] = mk(l1.x, l1.y); u[3] = mk(l1.z, l1.w);
+    u[4] = mk(l2.x, l2.y); u[5] = mk(l2.z, l2.w);
+    co = l3.x;
+    si = l3.y;
+}
+
 __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
     __shared__ float4 rs[6][kSapSites];  // the block's residual, plane-major
     __shared__ float red[3][4];
@@ -54,55 +86,59 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
     const int b[4] = {t >> 6, (t >> 4) & 3, (t >> 2) & 3, t & 3};
     int n[4];
     sap_block(a, blockIdx.x, n);
-    int x[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) x[m] = kSapB * n[m] + b[m];
-    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
-    const uint32_t i = (uint32_t)half_index(a.g, x);
-    const size_t hv = (size_t)6 * a.g.vhp;
-    HopArgs<float> h{};
-    h.g = a.g;
-    h.links = a.links[p];
-    h.omega = a.omega[p];
+    const int k = block_of(a, n);
 
     C<float> r[12];
-    load_spinor<float>(a.rho + p * hv, i, r);
+    load_sp(a.rho + spinor_at(k, t), r);
     if (a.update) {
         // rho += 1/2 H delta over the faces of the block: the previous step's corrections live on
         // the neighbouring blocks (the other colour)
         C<float> acc[12];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = mk(0.f, 0.f);
-        h.in = a.dlt + (1 - p) * hv;
-        const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
+        for (int q = 0; q < 12; ++q) acc[q] = mk(0.f, 0.f);
+        int x[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) x[m] = kSapB * n[m] + b[m];
 #pragma nounroll
         for (int d = 0; d < 8; ++d) {
             const int mu = d >> 1, back = d & 1;
             const int bm = mu == 0 ? b[0] : mu == 1 ? b[1] : mu == 2 ? b[2] : b[3];
             if (back ? bm != 0 : bm != kSapB - 1) continue;  // the neighbour is inside the block
+            // the neighbour across the face, with the lattice wrap and the C* mirror shift
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            const int Lm = a.g.L[mu];
+            const int ym = mu == 0 ? y[0] : mu == 1 ? y[1] : mu == 2 ? y[2] : y[3];
+            const bool cross = back ? ym == 0 : ym == Lm - 1;
+            const int yn = back ? (ym == 0 ? Lm - 1 : ym - 1) : (ym == Lm - 1 ? 0 : ym + 1);
+            if (mu == 0) y[0] = yn; else if (mu == 1) y[1] = yn; else if (mu == 2) y[2] = yn; else y[3] = yn;
+            y[1] = cstar_x1(a.g, mu, cross, y[1]);
+            int nn[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) nn[m] = y[m] / kSapB;
+            const int tn = ((y[0] % kSapB) * kSapB + (y[1] % kSapB)) * kSapB * kSapB + (y[2] % kSapB) * kSapB + (y[3] % kSapB);
             C<float> nb[12], u[6];
             float co, si;
-            load_spinor<float>(h.in, neighbour(h, x, row, d), nb);
-            load_link<float, false>(h, d, i, u, co, si);
+            load_sp(a.dlt + spinor_at(block_of(a, nn), tn), nb);
+            load_blink(a, k, d, t, u, co, si);
             accumulate_dir<float, 0>(d, nb, u, co, si, acc);
         }
 #pragma unroll
-        for (int k = 0; k < 12; ++k) r[k] = mk(fmaf(0.5f, acc[k].r, r[k].r), fmaf(0.5f, acc[k].i, r[k].i));
+        for (int q = 0; q < 12; ++q) r[q] = mk(fmaf(0.5f, acc[q].r, r[q].r), fmaf(0.5f, acc[q].i, r[q].i));
     }
     C<float> dl_[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) dl_[k] = mk(0.f, 0.f);
+    for (int q = 0; q < 12; ++q) dl_[q] = mk(0.f, 0.f);
 
 #pragma nounroll
     for (int it = 0; it < a.nmr; ++it) {
         __syncthreads();  // the previous step's reads of rs are done
 #pragma unroll
-        for (int k = 0; k < 6; ++k) rs[k][t] = make_float4(r[2 * k].r, r[2 * k].i, r[2 * k + 1].r, r[2 * k + 1].i);
+        for (int q = 0; q < 6; ++q) rs[q][t] = make_float4(r[2 * q].r, r[2 * q].i, r[2 * q + 1].r, r[2 * q + 1].i);
         __syncthreads();
         // v = D_blk r = A r - 1/2 sum over the neighbours inside the block
         C<float> v[12], hs[12];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) hs[k] = mk(0.f, 0.f);
+        for (int q = 0; q < 12; ++q) hs[q] = mk(0.f, 0.f);
 #pragma nounroll
         for (int d = 0; d < 8; ++d) {
             const int mu = d >> 1, back = d & 1;
@@ -113,29 +149,37 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
             C<float> nb[12], u[6];
             float co, si;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const float4 q = rs[k][tn];
-                nb[2 * k] = mk(q.x, q.y);
-                nb[2 * k + 1] = mk(q.z, q.w);
+            for (int q = 0; q < 6; ++q) {
+                const float4 f = rs[q][tn];
+                nb[2 * q] = mk(f.x, f.y);
+                nb[2 * q + 1] = mk(f.z, f.w);
             }
-            load_link<float, false>(h, d, i, u, co, si);
+            load_blink(a, k, d, t, u, co, si);
             accumulate_dir<float, 0>(d, nb, u, co, si, hs);
         }
         {
+            const float4 *cq = a.clov + (size_t)k * 18 * kSapSites + t;
             float pk[72];
-            load_field<float, 72>(a.clov[p], i, pk);
+#pragma unroll
+            for (int q = 0; q < 18; ++q) {
+                const float4 f = cq[q * kSapSites];
+                pk[4 * q] = f.x;
+                pk[4 * q + 1] = f.y;
+                pk[4 * q + 2] = f.z;
+                pk[4 * q + 3] = f.w;
+            }
 #pragma unroll
             for (int blk = 0; blk < 2; ++blk) block_mul(pk + 36 * blk, r + 6 * blk, v + 6 * blk);
         }
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v[k] = mk(fmaf(-0.5f, hs[k].r, v[k].r), fmaf(-0.5f, hs[k].i, v[k].i));
+        for (int q = 0; q < 12; ++q) v[q] = mk(fmaf(-0.5f, hs[q].r, v[q].r), fmaf(-0.5f, hs[q].i, v[q].i));
         // w = <v, r> / <v, v> over the block
         float vr = 0.f, vi = 0.f, vv = 0.f;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            vr = fmaf(v[k].r, r[k].r, fmaf(v[k].i, r[k].i, vr));
-            vi = fmaf(v[k].r, r[k].i, fmaf(-v[k].i, r[k].r, vi));
-            vv = fmaf(v[k].r, v[k].r, fmaf(v[k].i, v[k].i, vv));
+        for (int q = 0; q < 12; ++q) {
+            vr = fmaf(v[q].r, r[q].r, fmaf(v[q].i, r[q].i, vr));
+            vi = fmaf(v[q].r, r[q].i, fmaf(-v[q].i, r[q].r, vi));
+            vv = fmaf(v[q].r, v[q].r, fmaf(v[q].i, v[q].i, vv));
         }
         vr = wave_sum(vr);
         vi = wave_sum(vi);
@@ -152,23 +196,76 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
         const float inv = sv > 0.f ? 1.0f / sv : 0.f;
         const C<float> w = mk(sr * inv, si * inv);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            madd(dl_[k], w, r[k]);
-            const C<float> wv = w * v[k];
-            r[k] = mk(r[k].r - wv.r, r[k].i - wv.i);
+        for (int q = 0; q < 12; ++q) {
+            madd(dl_[q], w, r[q]);
+            const C<float> wv = w * v[q];
+            r[q] = mk(r[q].r - wv.r, r[q].i - wv.i);
         }
         __syncthreads();  // red is read by every thread before the next step overwrites it
     }
     // psi += delta, rho = the block residual, delta kept for the next step's face update
-    float4 *ps = site_ptr(a.psi + p * hv, i, 6);
-    float4 *rh = site_ptr(a.rho + p * hv, i, 6);
-    float4 *dd = site_ptr(a.dlt + p * hv, i, 6);
+    float4 *ps = a.psi + spinor_at(k, t);
+    C<float> o[12];
+    load_sp(ps, o);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const float4 o = ps[k * kSB];
-        ps[k * kSB] = make_float4(o.x + dl_[2 * k].r, o.y + dl_[2 * k].i, o.z + dl_[2 * k + 1].r, o.w + dl_[2 * k + 1].i);
-        rh[k * kSB] = make_float4(r[2 * k].r, r[2 * k].i, r[2 * k + 1].r, r[2 * k + 1].i);
-        dd[k * kSB] = make_float4(dl_[2 * k].r, dl_[2 * k].i, dl_[2 * k + 1].r, dl_[2 * k + 1].i);
+    for (int q = 0; q < 12; ++q) o[q] = mk(o[q].r + dl_[q].r, o[q].i + dl_[q].i);
+    store_sp(ps, o);
+    store_sp(a.rho + spinor_at(k, t), r);
+    store_sp(a.dlt + spinor_at(k, t), dl_);
+}
+
+// Block order of the fields (once per field): site (p, i) -> block k, site t
+DEV void block_pos(const Geom &g, const int nb[4], const int x[4], int &k, int &t) {
+    int n[4], b[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        n[m] = x[m] / kSapB;
+        b[m] = x[m] % kSapB;
+    }
+    k = ((n[0] * nb[1] + n[1]) * nb[2] + n[2]) * nb[3] + n[3];
+    t = ((b[0] * kSapB + b[1]) * kSapB + b[2]) * kSapB + b[3];
+}
+
+__global__ void k_sap_fields(Geom g, int p, int4 nb4, const float4 *__restrict__ links, const float *__restrict__ omega,
+                             const float4 *__restrict__ clov, float4 *__restrict__ blinks, float4 *__restrict__ bclov) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.vh) return;
+    const int nb[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
+    int x[4], k, t;
+    site_coords(g, i, p, x);
+    block_pos(g, nb, x, k, t);
+    const size_t vhp = (size_t)g.vhp;
+#pragma unroll 1
+    for (int d = 0; d < 8; ++d) {
+        const float4 *src = site_ptr(links + (size_t)d * 3 * vhp, (uint32_t)i, 3);
+        float4 *dst = blinks + ((size_t)(k * 8 + d) * kSapLinkPlanes) * kSapSites + t;
+        dst[0] = src[0];
+        dst[kSapSites] = src[kSB];
+        dst[2 * kSapSites] = src[2 * kSB];
+        float sn, cs;
+        sc(omega[(size_t)d * vhp + i], sn, cs);
+        dst[3 * kSapSites] = make_float4(cs, sn, 0.f, 0.f);
+    }
+    const float4 *cs = site_ptr(clov, (uint32_t)i, 18);
+    float4 *cd = bclov + (size_t)k * 18 * kSapSites + t;
+#pragma unroll
+    for (int q = 0; q < 18; ++q) cd[q * kSapSites] = cs[q * kSB];
+}
+
+// NATIVE F32 full vector <-> block order (to_block = 1: NATIVE -> block)
+__global__ void k_sap_order(Geom g, int p, int4 nb4, int to_block, float4 *__restrict__ nat, float4 *__restrict__ blk) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.vh) return;
+    const int nb[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
+    int x[4], k, t;
+    site_coords(g, i, p, x);
+    block_pos(g, nb, x, k, t);
+    float4 *q = site_ptr(nat + (size_t)p * 6 * g.vhp, (uint32_t)i, 6);
+    float4 *bq = blk + spinor_at(k, t);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        if (to_block) bq[j * kSapSites] = q[j * kSB];
+        else q[j * kSB] = bq[j * kSapSites];
     }
 }
 
@@ -190,26 +287,40 @@ void sap_apply(dirac_ctx *c, void *psi, const void *r, int ncy, int nmr, hipStre
                               "multiple of 16");
     require(ncy >= 1 && ncy <= 64 && nmr >= 1 && nmr <= 64, "SAP cycles and block steps must be 1..64");
     ensure_prec(c, DIRAC_F32, s);
-    const size_t bytes = (size_t)48 * c->g.vhp * sizeof(float);
-    c->sap_rho.alloc(bytes);
-    c->sap_dlt.alloc(bytes);
-    HIP_CHECK(hipMemcpyAsync(c->sap_rho.p, r, bytes, hipMemcpyDeviceToDevice, s));
-    zero_fill(psi, bytes, s);
+    int nblk = 1;
+    int nb[4];
+    for (int m = 0; m < 4; ++m) {
+        nb[m] = c->g.L[m] / kSapB;
+        nblk *= nb[m];
+    }
+    const int4 nb4 = make_int4(nb[0], nb[1], nb[2], nb[3]);
+    const int vh = (int)c->vh;
+    if (!c->sap_ready) {
+        c->sap_links.alloc((size_t)nblk * 8 * kSapLinkPlanes * kSapSites * sizeof(float4));
+        c->sap_clov.alloc((size_t)nblk * 18 * kSapSites * sizeof(float4));
+        for (int p = 0; p < 2; ++p)
+            k_sap_fields<<<grid_for(vh), kBlock, 0, s>>>(c->g, p, nb4, (const float4 *)c->f[DIRAC_F32].links[p].p,
+                                                         (const float *)c->f[DIRAC_F32].omega[p].p,
+                                                         (const float4 *)c->f[DIRAC_F32].clov[p].p,
+                                                         (float4 *)c->sap_links.p, (float4 *)c->sap_clov.p);
+        HIP_CHECK(hipGetLastError());
+        c->sap_ready = true;
+    }
+    const size_t vbytes = (size_t)nblk * 6 * kSapSites * sizeof(float4);
+    c->sap_rho.alloc(3 * vbytes);  // rho, psi, delta in block order
+    float4 *rho = (float4 *)c->sap_rho.p, *pb = rho + vbytes / sizeof(float4), *dlt = pb + vbytes / sizeof(float4);
+    for (int p = 0; p < 2; ++p)
+        k_sap_order<<<grid_for(vh), kBlock, 0, s>>>(c->g, p, nb4, 1, (float4 *)const_cast<void *>(r), rho);
+    HIP_CHECK(hipGetLastError());
+    zero_fill(pb, vbytes, s);
     SapArgs a{};
     a.g = c->g;
-    for (int p = 0; p < 2; ++p) {
-        a.links[p] = (const float4 *)c->f[DIRAC_F32].links[p].p;
-        a.omega[p] = (const float *)c->f[DIRAC_F32].omega[p].p;
-        a.clov[p] = (const float4 *)c->f[DIRAC_F32].clov[p].p;
-    }
-    a.rho = (float4 *)c->sap_rho.p;
-    a.psi = (float4 *)psi;
-    a.dlt = (float4 *)c->sap_dlt.p;
-    int nblk = 1;
-    for (int m = 0; m < 4; ++m) {
-        a.nb[m] = c->g.L[m] / kSapB;
-        nblk *= a.nb[m];
-    }
+    a.links = (const float4 *)c->sap_links.p;
+    a.clov = (const float4 *)c->sap_clov.p;
+    a.rho = rho;
+    a.psi = pb;
+    a.dlt = dlt;
+    for (int m = 0; m < 4; ++m) a.nb[m] = nb[m];
     a.nmr = nmr;
     for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
@@ -218,6 +329,9 @@ void sap_apply(dirac_ctx *c, void *psi, const void *r, int ncy, int nmr, hipStre
             k_sap_step<<<nblk / 2, kSapSites, 0, s>>>(a);
             HIP_CHECK(hipGetLastError());
         }
+    for (int p = 0; p < 2; ++p)
+        k_sap_order<<<grid_for(vh), kBlock, 0, s>>>(c->g, p, nb4, 0, (float4 *)psi, pb);
+    HIP_CHECK(hipGetLastError());
 }
 
 }  // namespace dl
