@@ -171,6 +171,31 @@ def sap_suite(D, b, plain_seconds, plain_iters):
     return res
 
 
+def sap_kernels(reps: int):
+    """The Schwarz preconditioner alone on 32^3 x 64 (the benchmark field): one application with
+    4 cycles of 4 minimal-residual steps, timed with HIP events; one JSON line."""
+    import torch
+
+    import gen
+    import paper_2502_02490_amd as P
+
+    D = P.Dirac(torch.from_numpy(gen.su3_field(DIMS, EPS, SEED)).cuda(), torch.from_numpy(gen.u1_field(DIMS, 0.3, SEED)).cuda(),
+                DIMS, KAPPA, CSW, CSW_QED, QHAT)
+    r32 = D.to_native(torch.from_numpy(gen.gaussian_spinor(DIMS, SEED)).cuda().to(torch.complex64), "f32", "lex")
+    o32 = torch.empty_like(r32)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        D.sap(o32, r32, 4, 4)
+    t = timed(lambda: D.sap(o32, r32, 4, 4), reps, stream) / reps
+    V = math.prod(DIMS)
+    out = {"lattice": "x".join(map(str, DIMS)), "ncy": 4, "nmr": 4, "precond_ms": round(t * 1e3, 3),
+           "bytes_per_site": sap_bytes_per_site(4, 4),
+           "algorithmic_GBps": round(sap_bytes_per_site(4, 4) * V / t / 1e9, 1),
+           "frac_of_8TBps": round(sap_bytes_per_site(4, 4) * V / t / 8e12, 3)}
+    D.close()
+    return out
+
+
 BATCH_DIMS = [(8, 8, 8, 8), (12, 12, 12, 12)] + [(32, 16, 16, 16)] * 3 + [(48, 24, 24, 24)] * 3
 
 
@@ -375,6 +400,8 @@ def main():
     ap.add_argument("--ptc-pairs", type=int, default=500, help="training pairs per 16^3x32 field")
     ap.add_argument("--ptc-epochs", type=int, default=8)
     ap.add_argument("--ptc-checkpoint", default=None, help="write the trained weights and Adam state here")
+    ap.add_argument("--sap-kernels", action="store_true",
+                    help="only time the Schwarz preconditioner (4 cycles x 4 block steps) on 32^3x64 (one JSON line)")
     ap.add_argument("--ptc-kernels", action="store_true",
                     help="only time the PTC network's forward and backward kernels on 32^3x64 (one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -385,6 +412,12 @@ def main():
               "designed, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.sap_kernels:
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"sap_kernels": sap_kernels(max(1, args.steps // 10))}), flush=True)
+        return
     if args.ptc_kernels:
         import torch
 
