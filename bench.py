@@ -47,7 +47,7 @@ HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persis
 # profiles/hop_fp64_32c64_hbm_traffic.txt), by launch shape.  A shape missing here, or a kernel
 # changed since the counters were taken, reports null.
 HOP_CLOV_TRAFFIC_32C64 = {
-    "k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persistent)": 2.479e9 + 0.201e9,
+    "k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persistent)": 2.476e9 + 0.201e9,
     "k_hop_p bs256 1/CU streaming hints (persistent)": 2.477e9 + 0.201e9,
     "k_hop_p bs256 2/CU streaming hints (persistent)": 2.620e9 + 0.201e9,
     "k_hop_p bs256 1/CU (persistent)": 2.606e9 + 0.201e9,
