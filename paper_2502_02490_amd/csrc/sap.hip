@@ -128,6 +128,19 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
     C<float> dl_[12];
 #pragma unroll
     for (int q = 0; q < 12; ++q) dl_[q] = mk(0.f, 0.f);
+    // the site's clover block, read once for all minimal-residual steps
+    float pk[72];
+    {
+        const float4 *cq = a.clov + (size_t)k * 18 * kSapSites + t;
+#pragma unroll
+        for (int q = 0; q < 18; ++q) {
+            const float4 f = cq[q * kSapSites];
+            pk[4 * q] = f.x;
+            pk[4 * q + 1] = f.y;
+            pk[4 * q + 2] = f.z;
+            pk[4 * q + 3] = f.w;
+        }
+    }
 
 #pragma nounroll
     for (int it = 0; it < a.nmr; ++it) {
@@ -157,20 +170,8 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
             load_blink(a, k, d, t, u, co, si);
             accumulate_dir<float, 0>(d, nb, u, co, si, hs);
         }
-        {
-            const float4 *cq = a.clov + (size_t)k * 18 * kSapSites + t;
-            float pk[72];
 #pragma unroll
-            for (int q = 0; q < 18; ++q) {
-                const float4 f = cq[q * kSapSites];
-                pk[4 * q] = f.x;
-                pk[4 * q + 1] = f.y;
-                pk[4 * q + 2] = f.z;
-                pk[4 * q + 3] = f.w;
-            }
-#pragma unroll
-            for (int blk = 0; blk < 2; ++blk) block_mul(pk + 36 * blk, r + 6 * blk, v + 6 * blk);
-        }
+        for (int blk = 0; blk < 2; ++blk) block_mul(pk + 36 * blk, r + 6 * blk, v + 6 * blk);
 #pragma unroll
         for (int q = 0; q < 12; ++q) v[q] = mk(fmaf(-0.5f, hs[q].r, v[q].r), fmaf(-0.5f, hs[q].i, v[q].i));
         // w = <v, r> / <v, v> over the block
