@@ -136,11 +136,11 @@ def solve_suite(D, b, inner_precs):
 # algorithmic bytes per site and Schwarz step of one colour (FP32): the residual, the solution and
 # the correction (read / written once: 5 x 96), the corrections of the face neighbours and their
 # links (on average 2 of the 8 directions cross a face of a 4^4 block: 2 x (96 + 52)), the clover
-# field once (288, held in registers over the block solve), and per minimal-residual step the
-# links inside the block (on average 6 directions: 6 x 52; the kernel reads them again in every
-# step); a site takes one step per cycle
+# field (288) and the forward links of the hops inside the block (3 of 4 directions: 3 x 52), both
+# once per block solve (held in registers and LDS over its minimal-residual steps, whatever their
+# number); a site takes one step per cycle
 def sap_bytes_per_site(ncy, nmr):
-    return ncy * (5 * 96 + 2 * (96 + 52) + 288 + nmr * 6 * 52)
+    return ncy * (5 * 96 + 2 * (96 + 52) + 288 + 3 * 52)
 
 
 SAP_SETTINGS = ((2, 4), (4, 4), (4, 6))

@@ -453,20 +453,32 @@ __global__ __launch_bounds__(256) void k_ptc_tsum(PtcGeom a, int nparity, const 
 // Partial weight gradients: part[wg][path][c][c'][s][t] (complex float), one slice per work-group.
 // Persistent: work-group wg takes the 64-site tiles wg, wg + G, wg + 2G, ... (G = grid size) and
 // sums their contributions into its slice in that order.  Per tile, four wavefronts: the gradient
-// of the tile (all output channels) is staged in LDS once; then each wavefront takes one (path, c')
-// pair at a time, computes its transport at the 64 sites into its own LDS slot and reduces the
-// 16 NOUT outputs of that pair over the tile (sites, then colours, in index order).  Every entry
-// of the slice belongs to one lane, so the running sums need no atomics and are deterministic.
+// of the tile (all output channels) is staged in LDS once, as [site][colour][row] with the
+// R = 4 NOUT rows (c, s) innermost; then each wavefront takes one (path, c') pair at a time and
+// computes its transport at the 64 sites into its own LDS slot, as [site][colour][t].  The pair's
+// 4 NOUT x 4 block of outputs is formed by the wavefront's 64 lanes as R rows x S = 64 / R site
+// classes: lane (class k, row) sums g_row conj(t_t) for all four t over the sites k, k + S, ...
+// (site, then colour, in index order; one read of g feeds four products and the transport reads
+// are shared by the R lanes of a class), then the S class sums of a row are combined by a
+// butterfly over the lanes, which gives every lane the same bits.  The running sums of a slice
+// belong to one lane each: no atomics, deterministic.
 template <int NOUT, typename AI>
 __global__ __launch_bounds__(256) void k_ptc_wgrad(PtcGeom a, int nin, const typename Act<AI>::vec *__restrict__ xin,
                                                    const float4 *__restrict__ g, float2 *__restrict__ part) {
-    __shared__ C<float> gs[NOUT][kTile][12];
-    __shared__ C<float> ts[4][kTile][12];
+    constexpr int R = 4 * NOUT, S = kTile / R;
+    static_assert(kTile % R == 0, "the rows of a pair must divide the tile");
+    constexpr int GX = 3 * R + 1;  // complex per site in gs (one of padding: the staging writes of
+                                   // the 64 sites then fall in distinct banks)
+    constexpr int TX = 14;         // complex per site in ts (12 + 2: 16-byte rows, staggered banks)
+    __shared__ float2 gs[kTile * GX];
+    __shared__ float4 ts[4][kTile * TX / 2];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
+    const int row = lane % R, cls = lane / R;  // this lane's output row (c, s) and site class
     const int ntile = (2 * a.g.vh + kTile - 1) / kTile;
     const size_t chg = chan_vecs<float>(a.g.vhp), hg = half_vecs<float>(a.g.vhp), chin = chan_vecs<AI>(a.g.vhp);
     const int npair = kPaths * nin;
     float2 *slice = part + (size_t)blockIdx.x * npair * NOUT * 16;
+    float4 *tw = ts[wave];
 #pragma nounroll
     for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
         const bool first = tile == (int)blockIdx.x;
@@ -481,41 +493,71 @@ __global__ __launch_bounds__(256) void k_ptc_wgrad(PtcGeom a, int nin, const typ
             float r[24];
             if (on) load_field<float, 24>(g + c * chg + p * hg, i, r);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) gs[c][lane][k] = on ? mk(r[2 * k], r[2 * k + 1]) : mk(0.f, 0.f);
+            for (int ss = 0; ss < 4; ++ss)
+#pragma unroll
+                for (int col = 0; col < 3; ++col)
+                    gs[lane * GX + col * R + 4 * c + ss] =
+                        on ? make_float2(r[2 * (3 * ss + col)], r[2 * (3 * ss + col) + 1]) : make_float2(0.f, 0.f);
         }
+        // the gathers of a wavefront's next pair are issued before the reduction of the current one
+        TRaw<AI> raw;
+        if (on && wave < npair) transport_load<AI>(a, xin + (wave % nin) * chin, p, i, x, wave / nin, raw);
 #pragma nounroll
         for (int base = 0; base < npair; base += 4) {
             const int pr = base + wave;
             const int path = pr / nin, cp = pr % nin;
             C<float> t[12];
             if (on && pr < npair) {
-                transport_site<AI>(a, xin + cp * chin, p, i, x, path, t);
+                transport_compute<AI>(raw, path, t);
             } else {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) t[k] = mk(0.f, 0.f);
             }
+            const int nx = pr + 4;
+            if (on && nx < npair) transport_load<AI>(a, xin + (nx % nin) * chin, p, i, x, nx / nin, raw);
             __syncthreads();  // the previous pairs' reads of ts (and the staging of gs) are done
 #pragma unroll
-            for (int k = 0; k < 12; ++k) ts[wave][lane][k] = t[k];
+            for (int col = 0; col < 3; ++col)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    tw[lane * (TX / 2) + 2 * col + h] = make_float4(t[3 * (2 * h) + col].r, t[3 * (2 * h) + col].i,
+                                                                    t[3 * (2 * h + 1) + col].r, t[3 * (2 * h + 1) + col].i);
             __syncthreads();
             if (pr < npair) {
-                for (int o = lane; o < NOUT * 16; o += kTile) {
-                    const int c = o >> 4, ss = (o >> 2) & 3, tt = o & 3;
-                    C<float> acc = mk(0.f, 0.f);
-                    for (int xs = 0; xs < kTile; ++xs)
+                float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+                for (int j = 0; j < R; ++j) {
+                    const int xs = j * S + cls;
 #pragma unroll
-                        for (int col = 0; col < 3; ++col) {
-                            // g_c[s, col] conj(t[t, col])
-                            const C<float> gv = gs[c][xs][3 * ss + col], tv = ts[wave][xs][3 * tt + col];
-                            acc.r += gv.r * tv.r + gv.i * tv.i;
-                            acc.i += gv.i * tv.r - gv.r * tv.i;
+                    for (int col = 0; col < 3; ++col) {
+                        // g_row[col] conj(t_t[col]), t = 0..3
+                        const float2 gv = gs[xs * GX + col * R + row];
+                        const float4 t01 = tw[xs * (TX / 2) + 2 * col], t23 = tw[xs * (TX / 2) + 2 * col + 1];
+                        const float tr[4] = {t01.x, t01.z, t23.x, t23.z}, ti[4] = {t01.y, t01.w, t23.y, t23.w};
+#pragma unroll
+                        for (int tt = 0; tt < 4; ++tt) {
+                            ar[tt] += gv.x * tr[tt] + gv.y * ti[tt];
+                            ai[tt] += gv.y * tr[tt] - gv.x * ti[tt];
                         }
-                    float2 &dst = slice[((size_t)path * NOUT * nin + (size_t)c * nin + cp) * 16 + ss * 4 + tt];
+                    }
+                }
+#pragma unroll
+                for (int o = R; o < kTile; o <<= 1)
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) {
+                        ar[tt] += __shfl_xor(ar[tt], o, 64);
+                        ai[tt] += __shfl_xor(ai[tt], o, 64);
+                    }
+                if (cls == 0) {
+                    const int c = row >> 2, ss = row & 3;
+                    float4 *dst = (float4 *)(slice + ((size_t)path * NOUT * nin + (size_t)c * nin + cp) * 16 + ss * 4);
                     if (first) {
-                        dst = make_float2(acc.r, acc.i);
+                        dst[0] = make_float4(ar[0], ai[0], ar[1], ai[1]);
+                        dst[1] = make_float4(ar[2], ai[2], ar[3], ai[3]);
                     } else {
-                        const float2 old = dst;
-                        dst = make_float2(old.x + acc.r, old.y + acc.i);
+                        const float4 o0 = dst[0], o1 = dst[1];
+                        dst[0] = make_float4(o0.x + ar[0], o0.y + ai[0], o0.z + ar[1], o0.w + ai[1]);
+                        dst[1] = make_float4(o1.x + ar[2], o1.y + ai[2], o1.z + ar[3], o1.w + ai[3]);
                     }
                 }
             }
@@ -670,18 +712,20 @@ void layer_dispatch(const PtcGeom &a, int nin, int nout, const void *x, const ui
     }
     HIP_CHECK(hipGetLastError());
 }
-// work-groups of the weight-gradient kernel (two per compute unit, at most one per tile)
-int wgrad_grid(size_t vh) {
+// work-groups of the weight-gradient kernel: as many per compute unit as its LDS tiles and
+// registers let run at once (three for one or two output channels, two for four or eight), at
+// most one per tile
+int wgrad_grid(size_t vh, int nout) {
     const size_t ntile = (2 * vh + kTile - 1) / kTile;
-    return (int)std::min(ntile, (size_t)2 * compute_units());
+    return (int)std::min(ntile, (size_t)(nout <= 2 ? 3 : 2) * compute_units());
 }
 template <int NOUT>
 void launch_wgrad(const PtcGeom &a, int nin, const void *x, bool x_bf16, const void *g, void *part, hipStream_t s) {
     if (x_bf16)
-        k_ptc_wgrad<NOUT, bf16s><<<wgrad_grid(a.g.vh), 256, 0, s>>>(a, nin, (const uint4 *)x, (const float4 *)g,
+        k_ptc_wgrad<NOUT, bf16s><<<wgrad_grid(a.g.vh, NOUT), 256, 0, s>>>(a, nin, (const uint4 *)x, (const float4 *)g,
                                                                     (float2 *)part);
     else
-        k_ptc_wgrad<NOUT, float><<<wgrad_grid(a.g.vh), 256, 0, s>>>(a, nin, (const float4 *)x, (const float4 *)g,
+        k_ptc_wgrad<NOUT, float><<<wgrad_grid(a.g.vh, NOUT), 256, 0, s>>>(a, nin, (const float4 *)x, (const float4 *)g,
                                                                     (float2 *)part);
 }
 void wgrad_dispatch(const PtcGeom &a, int nin, int nout, const void *x, bool x_bf16, const void *g, void *part,
@@ -783,9 +827,10 @@ void ptc_ensure_acts(dirac_ctx *c, dirac_ptc *n) {
     for (int l = 0; l <= n->nlayers; ++l) maxc = std::max(maxc, n->ch[l]);
     n->gbuf.alloc(2 * (size_t)maxc * chanb);
     if (n->contract_last()) n->zbuf.alloc((size_t)kPaths * chanb);
-    size_t maxw = 0;
-    for (int l = 0; l < n->nlayers; ++l) maxw = std::max(maxw, ptc_nweights(n, l));
-    n->part.alloc((size_t)wgrad_grid(c->vh) * maxw * 8);
+    size_t maxpart = 0;  // complex entries of the weight-gradient slices of the largest layer
+    for (int l = 0; l < n->nlayers; ++l)
+        maxpart = std::max(maxpart, (size_t)wgrad_grid(c->vh, n->ch[l + 1]) * ptc_nweights(n, l));
+    n->part.alloc(maxpart * 8);
 }
 
 float *ptc_act(dirac_ctx *c, dirac_ptc *n, int l) {
@@ -832,12 +877,11 @@ void ptc_backward_acts(dirac_ctx *c, dirac_ptc *n, const void *g_out, void *gin,
     for (int l = 0; l <= n->nlayers; ++l) maxc = std::max(maxc, n->ch[l]);
     char *gA = (char *)n->gbuf.p, *gB = gA + (size_t)maxc * chanb;
     HIP_CHECK(hipMemcpyAsync(gA, g_out, (size_t)n->ch[n->nlayers] * chanb, hipMemcpyDeviceToDevice, s));
-    const int nslice = wgrad_grid(c->vh);
     for (int l = n->nlayers - 1; l >= 0; --l) {
         const int nin = n->ch[l], nout = n->ch[l + 1];
         const int nw = (int)ptc_nweights(n, l);
         wgrad_dispatch(a, nin, nout, ptc_act(c, n, l), act_bf16(n, l), gA, n->part.p, s);
-        k_ptc_reduce<<<(nw + kRedK - 1) / kRedK, 256, 0, s>>>(nslice, nw, (const float2 *)n->part.p,
+        k_ptc_reduce<<<(nw + kRedK - 1) / kRedK, 256, 0, s>>>(wgrad_grid(c->vh, nout), nw, (const float2 *)n->part.p,
                                                       (float2 *)n->grad.p + n->off[l]);
         HIP_CHECK(hipGetLastError());
         if (l == 0 && !gin) break;

@@ -4,7 +4,9 @@
 //   delta = nmr minimal-residual steps on the block operator D_blk (hops that leave the block
 //   dropped) for the residual on the block; psi += delta; rho = r - D psi.
 // One work-group per block, one thread per site.  The residual of the block is staged in LDS
-// (the neighbour reads of D_blk); the block reductions of the minimal-residual steps are
+// (the neighbour reads of D_blk), and so are the block's links of in-block hops and, in
+// registers, each site's clover block: they are read from memory once per block solve, not once
+// per minimal-residual step.  The block reductions of the minimal-residual steps are
 // shuffle trees and a fixed-order sum over the four wavefronts (deterministic).  The residual
 // update after a colour's solves changes rho only on the faces of the other colour's blocks
 // (D delta = -1/2 H delta there); it is done by the next step's work-groups on entry, from the
@@ -20,6 +22,7 @@ namespace {
 constexpr int kSapB = 4;                                  // block extent in every direction
 constexpr int kSapSites = kSapB * kSapB * kSapB * kSapB;  // 256: one work-group
 constexpr int kSapLinkPlanes = 4;  // a link in block order: 12 reals of rows 0, 1, then cos, sin of its phase
+constexpr int kSapInner = kSapSites / kSapB * (kSapB - 1);  // 192 sites of a block with a neighbour inside it in +mu
 
 // Block order: the fields of the Schwarz blocks are kept block by block (block k lexicographic in
 // the block coordinates, site t = 64 b0 + 16 b1 + 4 b2 + b3 inside it), plane-major within a
@@ -79,9 +82,20 @@ DEV void load_blink(const SapArgs &a, int k, int d, int t, C<float> u[6], float 
     si = l3.y;
 }
 
+// Forward link of direction mu at block site t (b_mu < 3, the links of the hops inside the block),
+// in the LDS tile of the block: the 192 such sites of a direction, in site order.
+DEV int inner_link(int mu, int t) {
+    const int sh = 6 - 2 * mu;  // log2 of the site stride of direction mu
+    return t - ((t >> (sh + 2)) << sh);
+}
+
 __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
     __shared__ float4 rs[6][kSapSites];  // the block's residual, plane-major
     __shared__ float red[3][4];
+    // the block's forward links of in-block hops (a backward hop from t takes the forward link of
+    // t - stride): rows 0, 1 of the SU(3) matrix in three planes, (cos, sin) of the phase
+    __shared__ float4 lq[4][3][kSapInner];
+    __shared__ float2 lp[4][kSapInner];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int b[4] = {t >> 6, (t >> 4) & 3, (t >> 2) & 3, t & 3};
     int n[4];
@@ -128,6 +142,19 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
     C<float> dl_[12];
 #pragma unroll
     for (int q = 0; q < 12; ++q) dl_[q] = mk(0.f, 0.f);
+    // the block's inner links, read once for all minimal-residual steps (the first step's barrier
+    // orders these writes before any read)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        if (b[mu] == kSapB - 1) continue;
+        const int ci = inner_link(mu, t);
+        const float4 *q = a.links + ((size_t)(k * 8 + 2 * mu) * kSapLinkPlanes) * kSapSites + t;
+        lq[mu][0][ci] = q[0];
+        lq[mu][1][ci] = q[kSapSites];
+        lq[mu][2][ci] = q[2 * kSapSites];
+        const float4 ph = q[3 * kSapSites];
+        lp[mu][ci] = make_float2(ph.x, ph.y);
+    }
     // the site's clover block, read once for all minimal-residual steps
     float pk[72];
     {
@@ -160,15 +187,19 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
             const int stride = mu == 0 ? 64 : mu == 1 ? 16 : mu == 2 ? 4 : 1;
             const int tn = back ? t - stride : t + stride;
             C<float> nb[12], u[6];
-            float co, si;
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 const float4 f = rs[q][tn];
                 nb[2 * q] = mk(f.x, f.y);
                 nb[2 * q + 1] = mk(f.z, f.w);
             }
-            load_blink(a, k, d, t, u, co, si);
-            accumulate_dir<float, 0>(d, nb, u, co, si, hs);
+            const int ci = inner_link(mu, back ? tn : t);
+            const float4 l0 = lq[mu][0][ci], l1 = lq[mu][1][ci], l2 = lq[mu][2][ci];
+            const float2 ph = lp[mu][ci];
+            u[0] = mk(l0.x, l0.y); u[1] = mk(l0.z, l0.w);
+            u[2] = mk(l1.x, l1.y); u[3] = mk(l1.z, l1.w);
+            u[4] = mk(l2.x, l2.y); u[5] = mk(l2.z, l2.w);
+            accumulate_dir<float, 0>(d, nb, u, ph.x, ph.y, hs);
         }
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) block_mul(pk + 36 * blk, r + 6 * blk, v + 6 * blk);
