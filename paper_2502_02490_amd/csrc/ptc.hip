@@ -536,8 +536,8 @@ __global__ __launch_bounds__(256) void k_ptc_wgrad(PtcGeom a, int nin, const typ
                         const float tr[4] = {t01.x, t01.z, t23.x, t23.z}, ti[4] = {t01.y, t01.w, t23.y, t23.w};
 #pragma unroll
                         for (int tt = 0; tt < 4; ++tt) {
-                            ar[tt] += gv.x * tr[tt] + gv.y * ti[tt];
-                            ai[tt] += gv.y * tr[tt] - gv.x * ti[tt];
+                            ar[tt] = fmaf(gv.y, ti[tt], fmaf(gv.x, tr[tt], ar[tt]));
+                            ai[tt] = fmaf(-gv.x, ti[tt], fmaf(gv.y, tr[tt], ai[tt]));
                         }
                     }
                 }
