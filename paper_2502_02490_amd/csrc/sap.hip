@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
         C<float> v[12], hs[12];
 #pragma unroll
         for (int q = 0; q < 12; ++q) hs[q] = mk(0.f, 0.f);
-#pragma nounroll
+#pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int mu = d >> 1, back = d & 1;
             const int bm = mu == 0 ? b[0] : mu == 1 ? b[1] : mu == 2 ? b[2] : b[3];
