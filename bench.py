@@ -9,6 +9,8 @@ Algorithmic bytes (each field read once, output written once, links as 12 reals 
   Schur D-hat   472 reals per even site  (3776 B in FP64, 1888 B in FP32)
   hop + A_ee chi (second Schur kernel)  248 reals per site (1984 B FP64)
   hop + A_oo^-1  (first Schur kernel)   224 reals per site (1792 B FP64)
+Also reported: FP32/FP16/BF16 and C* Schur applies, 12 right-hand sides in one call, the Schur
+apply at 48^3 x 12 (one GPU's share of 48^3 x 96 cut along t over 8 GPUs), and the solves.
 """
 from __future__ import annotations
 
@@ -570,6 +572,27 @@ def main():
     tcs = timed(schur_c, args.steps, stream)
     extra["schur_f64_cstar3_GBps"] = round(SCHUR_REALS * 8 * vh * args.steps / tcs / 1e9, 1)
     Dc.close()
+    del Dc
+    # one GPU's share of 48^3 x 96 cut along t over 8 GPUs: the Schur apply at 48^3 x 12 (same
+    # parameters, periodic in every direction here; the halo exchange itself is not built)
+    local = (12, 48, 48, 48)
+    vhl = math.prod(local) // 2
+    Dl = P.Dirac(torch.from_numpy(gen.su3_field(local, EPS, SEED)).cuda(),
+                 torch.from_numpy(gen.u1_field(local, 0.3, SEED)).cuda(), local, KAPPA, CSW, CSW_QED, QHAT)
+    psi_l = gen.gaussian_spinor(local, SEED)
+    for pr in ("f64", "f32"):
+        src = psi_l if pr == "f64" else psi_l.astype(np.complex64)
+        xe_l = Dl.to_native(torch.from_numpy(src).cuda(), pr, "lex")
+        xe_l = xe_l[: xe_l.numel() // 2].clone()
+        ye_l = torch.empty_like(xe_l)
+        sl = lambda: Dl.apply_eo(ye_l, xe_l, pr, "native")  # noqa: E731
+        for _ in range(5):
+            sl()
+        tl = timed(sl, args.steps, stream)
+        extra[f"schur_{pr}_local_48c12_GBps"] = round(SCHUR_REALS * (8 if pr == "f64" else 4) * vhl * args.steps / tl / 1e9, 1)
+        extra[f"schur_{pr}_local_48c12_us"] = round(tl / args.steps * 1e6, 1)
+    Dl.close()
+    del Dl, xe_l, ye_l
     del yc
     log(f"[bench] extra {extra}")
 
