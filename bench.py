@@ -274,6 +274,26 @@ PTC_KAPPA = 0.1245
 PTC_BYTES_PER_SITE = 1280 + 1952 + 1280
 
 
+def gcr_solves(n: int):
+    """n plain FP64 even-odd GCR(32) solves to 1e-10 on the bench's 32^3x64 field and source (the
+    first one also tunes the launch shapes)."""
+    import torch
+
+    import gen
+    import paper_2502_02490_amd as P
+
+    D = P.Dirac(torch.from_numpy(gen.su3_field(DIMS, EPS, SEED)).cuda(), torch.from_numpy(gen.u1_field(DIMS, 0.3, SEED)).cuda(),
+                DIMS, KAPPA, CSW, CSW_QED, QHAT)
+    b = torch.from_numpy(gen.gaussian_spinor(DIMS, SEED)).cuda()
+    out = []
+    for _ in range(n):
+        x = torch.zeros_like(b)
+        info = D.solve(x, b, method=P.GCR, tol=1e-10, restart=32, max_iter=100000)
+        out.append({"iters": info.iters, "seconds": round(info.seconds, 4), "true_rel_res": info.true_rel_res})
+    D.close()
+    return {"lattice": "x".join(map(str, DIMS)), "solves": out}
+
+
 def ptc_kernels(reps: int):
     """The network's kernels alone on 32^3 x 64 (seed 505 field, seed-7 initial weights): one
     forward application, one even-odd application (the Schur-system preconditioner: even half in,
@@ -407,6 +427,9 @@ def main():
                     help="only time the Schwarz preconditioner (4 cycles x 4 block steps) on 32^3x64 (one JSON line)")
     ap.add_argument("--ptc-kernels", action="store_true",
                     help="only time the PTC network's forward and backward kernels on 32^3x64 (one JSON line)")
+    ap.add_argument("--gcr-solves", action="store_true",
+                    help="only run three plain FP64 even-odd GCR(32) solves on 32^3x64 (one JSON line), for a "
+                         "kernel trace of the Krylov BLAS")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 5 plain device copies of 768 MiB (a known-size kernel for HBM counter calibration)")
     args = ap.parse_args()
@@ -426,6 +449,12 @@ def main():
 
         torch.cuda.set_device(0)
         print(json.dumps({"ptc_kernels": ptc_kernels(max(1, args.steps // 10))}), flush=True)
+        return
+    if args.gcr_solves:
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"gcr_solves": gcr_solves(3)}), flush=True)
         return
 
     # the launch-shape tuner records its choices here, so the line can name the kernel it timed
