@@ -50,17 +50,17 @@ HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persis
 # changed since the counters were taken, reports null.
 HOP_CLOV_TRAFFIC_32C64 = {
     "k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persistent)": 2.476e9 + 0.201e9,
-    "k_hop_p bs256 1/CU streaming hints (persistent)": 2.477e9 + 0.201e9,
+    "k_hop_p bs256 1/CU streaming hints (persistent)": 2.480e9 + 0.201e9,
     "k_hop_p bs256 2/CU streaming hints (persistent)": 2.620e9 + 0.201e9,
-    "k_hop_p bs256 1/CU (persistent)": 2.606e9 + 0.201e9,
-    "k_hop_p bs256 1/CU 2 neighbours/iteration (persistent)": 2.624e9 + 0.201e9,
-    "k_hop_p bs512 1/CU (persistent)": 2.938e9 + 0.201e9,
-    "k_hop_p bs256 1/CU xcd-regions (persistent)": 2.376e9 + 0.201e9,
-    "k_hop_ps bs256 1/CU (XCD slab sweep)": 2.348e9 + 0.201e9,
-    "k_hop_ps bs128 2/CU (XCD slab sweep)": 2.423e9 + 0.201e9,
-    "k_hop_tp tt4 1/CU (persistent time-tiled)": 2.320e9 + 0.201e9,
-    "k_hop_t tt4 (time-tiled LDS)": 2.570e9 + 0.201e9,
-    "k_hop_t tt8 (time-tiled LDS)": 2.665e9 + 0.201e9,
+    "k_hop_p bs256 1/CU (persistent)": 2.609e9 + 0.201e9,
+    "k_hop_p bs256 1/CU 2 neighbours/iteration (persistent)": 2.622e9 + 0.201e9,
+    "k_hop_p bs512 1/CU (persistent)": 2.943e9 + 0.201e9,
+    "k_hop_p bs256 1/CU xcd-regions (persistent)": 2.369e9 + 0.201e9,
+    "k_hop_ps bs256 1/CU (XCD slab sweep)": 2.347e9 + 0.201e9,
+    "k_hop_ps bs128 2/CU (XCD slab sweep)": 2.426e9 + 0.201e9,
+    "k_hop_tp tt4 1/CU (persistent time-tiled)": 2.322e9 + 0.201e9,
+    "k_hop_t tt4 (time-tiled LDS)": 2.577e9 + 0.201e9,
+    "k_hop_t tt8 (time-tiled LDS)": 2.674e9 + 0.201e9,
 }
 
 
@@ -274,6 +274,35 @@ PTC_KAPPA = 0.1245
 PTC_BYTES_PER_SITE = 1280 + 1952 + 1280
 
 
+def local_share(extra, steps, stream):
+    """The Schur apply on 48^3 x 12, one GPU's share of 48^3 x 96 cut along t over 8 GPUs (same
+    parameters, periodic in every direction here; the halo exchange itself is not built)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2502_02490_amd as P
+
+    local = (12, 48, 48, 48)
+    vhl = math.prod(local) // 2
+    Dl = P.Dirac(torch.from_numpy(gen.su3_field(local, EPS, SEED)).cuda(),
+                 torch.from_numpy(gen.u1_field(local, 0.3, SEED)).cuda(), local, KAPPA, CSW, CSW_QED, QHAT)
+    psi_l = gen.gaussian_spinor(local, SEED)
+    for pr in ("f64", "f32"):
+        src = psi_l if pr == "f64" else psi_l.astype(np.complex64)
+        xe_l = Dl.to_native(torch.from_numpy(src).cuda(), pr, "lex")
+        xe_l = xe_l[: xe_l.numel() // 2].clone()
+        ye_l = torch.empty_like(xe_l)
+        sl = lambda: Dl.apply_eo(ye_l, xe_l, pr, "native")  # noqa: E731
+        for _ in range(5):
+            sl()
+        tl = timed(sl, steps, stream)
+        extra[f"schur_{pr}_local_48c12_GBps"] = round(SCHUR_REALS * (8 if pr == "f64" else 4) * vhl * steps / tl / 1e9, 1)
+        extra[f"schur_{pr}_local_48c12_us"] = round(tl / steps * 1e6, 1)
+    Dl.close()
+    del Dl, xe_l, ye_l
+
+
 def gcr_solves(n: int):
     """n plain FP64 even-odd GCR(32) solves to 1e-10 on the bench's 32^3x64 field and source (the
     first one also tunes the launch shapes)."""
@@ -427,6 +456,8 @@ def main():
                     help="only time the Schwarz preconditioner (4 cycles x 4 block steps) on 32^3x64 (one JSON line)")
     ap.add_argument("--ptc-kernels", action="store_true",
                     help="only time the PTC network's forward and backward kernels on 32^3x64 (one JSON line)")
+    ap.add_argument("--no-local", action="store_true",
+                    help="skip the Schur apply on 48^3x12 (for counter runs that average per kernel over one lattice)")
     ap.add_argument("--gcr-solves", action="store_true",
                     help="only run three plain FP64 even-odd GCR(32) solves on 32^3x64 (one JSON line), for a "
                          "kernel trace of the Krylov BLAS")
@@ -604,24 +635,8 @@ def main():
     del Dc
     # one GPU's share of 48^3 x 96 cut along t over 8 GPUs: the Schur apply at 48^3 x 12 (same
     # parameters, periodic in every direction here; the halo exchange itself is not built)
-    local = (12, 48, 48, 48)
-    vhl = math.prod(local) // 2
-    Dl = P.Dirac(torch.from_numpy(gen.su3_field(local, EPS, SEED)).cuda(),
-                 torch.from_numpy(gen.u1_field(local, 0.3, SEED)).cuda(), local, KAPPA, CSW, CSW_QED, QHAT)
-    psi_l = gen.gaussian_spinor(local, SEED)
-    for pr in ("f64", "f32"):
-        src = psi_l if pr == "f64" else psi_l.astype(np.complex64)
-        xe_l = Dl.to_native(torch.from_numpy(src).cuda(), pr, "lex")
-        xe_l = xe_l[: xe_l.numel() // 2].clone()
-        ye_l = torch.empty_like(xe_l)
-        sl = lambda: Dl.apply_eo(ye_l, xe_l, pr, "native")  # noqa: E731
-        for _ in range(5):
-            sl()
-        tl = timed(sl, args.steps, stream)
-        extra[f"schur_{pr}_local_48c12_GBps"] = round(SCHUR_REALS * (8 if pr == "f64" else 4) * vhl * args.steps / tl / 1e9, 1)
-        extra[f"schur_{pr}_local_48c12_us"] = round(tl / args.steps * 1e6, 1)
-    Dl.close()
-    del Dl, xe_l, ye_l
+    if not args.no_local:
+        local_share(extra, args.steps, stream)
     del yc
     log(f"[bench] extra {extra}")
 
