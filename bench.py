@@ -323,6 +323,49 @@ def gcr_solves(n: int):
     return {"lattice": "x".join(map(str, DIMS)), "solves": out}
 
 
+def apply_kernels(reps: int):
+    """The Schur applies alone on the 32^3 x 64 workload, in each storage precision, and the FP32
+    apply of 12 right-hand sides in one call; each timed with HIP events after the tuner has
+    picked its launch shapes.  One JSON line (for kernel traces and counter runs)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2502_02490_amd as P
+
+    D = P.Dirac(torch.from_numpy(gen.su3_field(DIMS, EPS, SEED)).cuda(),
+                torch.from_numpy(gen.u1_field(DIMS, 0.3, SEED)).cuda(), DIMS, KAPPA, CSW, CSW_QED, QHAT)
+    psi = torch.from_numpy(gen.gaussian_spinor(DIMS, SEED)).cuda()
+    stream = torch.cuda.current_stream()
+    vh = math.prod(DIMS) // 2
+    out = {"lattice": "x".join(map(str, DIMS))}
+    for pr, rb in (("f64", 8), ("f32", 4), ("f16", 2), ("bf16", 2)):
+        src = psi.to(torch.complex64) if pr == "f32" else psi
+        x = D.to_native(src, pr, "lex")
+        xe = x[: x.numel() // 2].clone()
+        ye = torch.empty_like(xe)
+        fn = lambda: D.apply_eo(ye, xe, pr, "native")  # noqa: E731
+        for _ in range(3):
+            fn()
+        t = timed(fn, reps, stream) / reps
+        out[f"schur_{pr}_us"] = round(t * 1e6, 1)
+        out[f"schur_{pr}_GBps"] = round(SCHUR_REALS * rb * vh / t / 1e9, 1)
+        if pr == "f32":
+            nr = 12
+            x12 = torch.cat([xe] * nr)
+            y12 = torch.empty_like(x12)
+            m12 = lambda: D.apply_eo_multi(y12, x12, nr, "f32")  # noqa: E731
+            for _ in range(3):
+                m12()
+            t12 = timed(m12, reps, stream) / reps
+            out["schur_f32_12rhs_us_per_rhs"] = round(t12 / nr * 1e6, 1)
+            out["schur_f32_12rhs_GBps"] = round((nr * 120 + 352) * 4 * vh / t12 / 1e9, 1)
+            del x12, y12
+        del x, xe, ye
+    D.close()
+    return out
+
+
 def ptc_kernels(reps: int):
     """The network's kernels alone on 32^3 x 64 (seed 505 field, seed-7 initial weights): one
     forward application, one even-odd application (the Schur-system preconditioner: even half in,
@@ -458,6 +501,9 @@ def main():
                     help="only time the PTC network's forward and backward kernels on 32^3x64 (one JSON line)")
     ap.add_argument("--no-local", action="store_true",
                     help="skip the Schur apply on 48^3x12 (for counter runs that average per kernel over one lattice)")
+    ap.add_argument("--apply-kernels", action="store_true",
+                    help="only time the Schur applies on 32^3x64 in FP64 / FP32 / FP16 / BF16 and the FP32 12-RHS apply "
+                         "(one JSON line), for kernel traces and counter runs")
     ap.add_argument("--gcr-solves", action="store_true",
                     help="only run three plain FP64 even-odd GCR(32) solves on 32^3x64 (one JSON line), for a "
                          "kernel trace of the Krylov BLAS")
@@ -480,6 +526,12 @@ def main():
 
         torch.cuda.set_device(0)
         print(json.dumps({"ptc_kernels": ptc_kernels(max(1, args.steps // 10))}), flush=True)
+        return
+    if args.apply_kernels:
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"apply_kernels": apply_kernels(max(1, args.steps))}), flush=True)
         return
     if args.gcr_solves:
         import torch

@@ -151,7 +151,11 @@ dirac_status dirac_load_clover(dirac_ctx *ctx, const double *clover, dirac_layou
  * float64 in LEX, EO or OPENQXD order.  Sites whose inverse was not computed read 0. */
 dirac_status dirac_get_clover(dirac_ctx *ctx, double *out, int inverse, dirac_layout layout, void *stream);
 
-/* Invert the 6x6 chirality blocks of A in FP64: parity_mask bit 0 = even sites,
+/* The clover field of Sec. 4.1.3 is the site-local coupling openQxD precomputes: two Hermitian
+ * 6x6 chirality blocks per site (Sec. 2 places it beside the spinor and gauge fields, Sec. 4.3
+ * adds its U(1) term).  This call inverts those blocks, which the even-odd form needs on the
+ * odd sites (A_oo^-1 in D-hat).
+ * Invert the 6x6 chirality blocks of A in FP64: parity_mask bit 0 = even sites,
  * bit 1 = odd sites.  A block is singular when a pivot of Gauss-Jordan
  * elimination with partial pivoting has modulus below 1e-14 * max|A_block|; the
  * call then returns DIRAC_ESINGULAR and names the first such site (Lambda).
@@ -170,7 +174,9 @@ dirac_status dirac_import(dirac_ctx *ctx, void *native, const void *user, int si
 dirac_status dirac_export(dirac_ctx *ctx, void *user, const void *native, int sites, dirac_prec prec,
                           dirac_layout user_layout, void *stream);
 
-/* out = D in (dagger = 0) or D^dag in (dagger = 1), full lattice. */
+/* The operator D_w of the linear system D_w psi = eta that the paper offloads (Sec. 2), in the
+ * QCD+QED form of Sec. 4.3, on the field layouts of Sec. 4.1.
+ * out = D in (dagger = 0) or D^dag in (dagger = 1), full lattice; in and out must not overlap. */
 dirac_status dirac_apply(dirac_ctx *ctx, void *out, const void *in, dirac_prec prec, dirac_layout layout,
                          int dagger, void *stream);
 
@@ -231,7 +237,10 @@ typedef struct {
     double seconds;       /* wall time of the call */
 } dirac_solve_info;
 
-/* Solve D psi = eta.  x (solution) and b (right-hand side) are full-lattice FP64
+/* The solve the paper offloads through invertQuda(h_x, h_b, param) (Sec. 4.1), stopped, as in
+ * its runs, on the relative residual of the FP64 system (Sec. 5.1) and checked a posteriori as
+ * Sec. 2 describes; here x and b are device pointers.
+ * Solve D psi = eta.  x (solution) and b (right-hand side) are full-lattice FP64
  * vectors in `layout`.  GCR and MIXED_GCR run on the even-odd Schur system and
  * reconstruct the odd half; CGLS runs on the full D; FGCR_PTC runs flexible GCR
  * on the full D with p_k = N(r_k); FGCR_PTC_EO runs it on the Schur system with
@@ -268,6 +277,28 @@ dirac_status dirac_solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x
  * dims[1] a multiple of 16 (the mirror shift an even number of blocks, so that blocks of one
  * colour never meet); EINVAL otherwise; ncy, nmr in 1..64.  Asynchronous. */
 dirac_status dirac_sap(dirac_ctx *ctx, void *out, const void *in, int ncy, int nmr, void *stream);
+
+/* ---------------------------------------------------------------- vector arithmetic
+ * NATIVE vectors of the context's lattice: sites = 0 full vectors, 1 one parity.  Sums are
+ * formed in FP64 whatever the storage precision.  Calls that return a number (rel_res, norm2,
+ * dot not NULL) synchronise `stream`; the others are asynchronous. */
+
+/* r = b - D x for full NATIVE vectors of `prec` (F64 or F32): the residual by which Sec. 2 checks
+ * a solution a posteriori.  With rel_res != NULL, *rel_res = |r| / |b| (0 when b = 0);
+ * DIRAC_ENONFINITE when r or b holds NaN or Inf.  r must not overlap b or x. */
+dirac_status dirac_residual(dirac_ctx *ctx, void *r, const void *b, const void *x, dirac_prec prec, double *rel_res,
+                            void *stream);
+
+/* out = alpha a + beta b (element-wise; b is not read when beta = 0 and may then be NULL).  a and b
+ * are in in_prec, out in out_prec: in_prec must equal out_prec, or be F64 (the values are then
+ * rounded once to out_prec).  With norm2 != NULL, *norm2 = |out|^2 of the stored values;
+ * DIRAC_ENONFINITE when out holds NaN or Inf.  out must not overlap a or b. */
+dirac_status dirac_lincomb(dirac_ctx *ctx, void *out, dirac_prec out_prec, double alpha, const void *a, double beta,
+                           const void *b, dirac_prec in_prec, int sites, double *norm2, void *stream);
+
+/* dot[0] + i dot[1] = <a, b> = sum_i conj(a_i) b_i over NATIVE vectors of `prec`.  Blocking. */
+dirac_status dirac_dot(dirac_ctx *ctx, const void *a, const void *b, dirac_prec prec, int sites, double *dot,
+                       void *stream);
 
 /* ---------------------------------------------------------------- learned preconditioner
  * A gauge-covariant parallel-transport convolution (PTC) network N (a reading of the
@@ -307,9 +338,14 @@ dirac_status ptc_adam_step(dirac_ptc *net, double lr, void *stream);
 dirac_status ptc_get_adam_state(const dirac_ptc *net, float *host_m, float *host_v, size_t n, int *step);
 dirac_status ptc_set_adam_state(dirac_ptc *net, const float *host_m, const float *host_v, size_t n, int step);
 /* One minibatch step: zero the gradient, accumulate over the nbatch pairs (r[i], e[i])
- * (NATIVE F32 full vectors), take one Adam step; *loss = L before the step.  Blocking. */
+ * (NATIVE F32 full vectors), take one Adam step; *loss = L before the step.  When the loss or
+ * an entry of the gradient is not finite the call returns DIRAC_ENONFINITE and leaves the
+ * weights and the Adam state unchanged.  Blocking. */
 dirac_status ptc_train_step(dirac_ctx *ctx, dirac_ptc *net, const void *const *r, const void *const *e, int nbatch,
                             double lr, double *loss, void *stream);
+/* *loss = L over the nbatch pairs without any update (held-out evaluation).  Blocking. */
+dirac_status ptc_loss(dirac_ctx *ctx, dirac_ptc *net, const void *const *r, const void *const *e, int nbatch,
+                      double *loss, void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *dirac_last_error(void);

@@ -183,6 +183,35 @@ class Dirac:
                                                _prec(prec), _stream(stream)))
         return out
 
+    # -------------------------------------------------------------- vector arithmetic (NATIVE)
+    def residual(self, r, b, x, prec="f64", rel=False, stream=None):
+        """r = b - D x on full NATIVE vectors; returns |r| / |b| when rel (blocking), else None."""
+        pr = _prec(prec)
+        nb = self.native_bytes(pr, 0)
+        out = ctypes.c_double() if rel else None
+        _lib.check(self.lib.dirac_residual(self._ctx, _ptr(r, nb), _ptr(b, nb), _ptr(x, nb), pr,
+                                           ctypes.byref(out) if rel else None, _stream(stream)))
+        return out.value if rel else None
+
+    def lincomb(self, out, alpha, a, beta=0.0, b=None, out_prec="f64", in_prec="f64", sites=0, norm=False,
+                stream=None):
+        """out = alpha a + beta b on NATIVE vectors (in_prec in, out_prec out); returns |out|^2 when norm."""
+        po, pi = _prec(out_prec), _prec(in_prec)
+        nbo, nbi = self.native_bytes(po, sites), self.native_bytes(pi, sites)
+        n2 = ctypes.c_double() if norm else None
+        _lib.check(self.lib.dirac_lincomb(self._ctx, _ptr(out, nbo), po, float(alpha), _ptr(a, nbi), float(beta),
+                                          _ptr(b, nbi) if b is not None else None, pi, int(sites),
+                                          ctypes.byref(n2) if norm else None, _stream(stream)))
+        return n2.value if norm else None
+
+    def dot(self, a, b, prec="f64", sites=0, stream=None) -> complex:
+        """<a, b> = sum conj(a) b over NATIVE vectors (FP64 sums, blocking)."""
+        pr = _prec(prec)
+        nb = self.native_bytes(pr, sites)
+        d = (ctypes.c_double * 2)()
+        _lib.check(self.lib.dirac_dot(self._ctx, _ptr(a, nb), _ptr(b, nb), pr, int(sites), d, _stream(stream)))
+        return complex(d[0], d[1])
+
     # -------------------------------------------------------------- clover field
     def clover(self, inverse=False, layout="lex", stream=None) -> torch.Tensor:
         """Packed clover field (or inverse) [V, 2, 36] float64 (Sec. 4.1.3 packing)."""
@@ -351,6 +380,16 @@ class PTC:
         _lib.check(self.lib.ptc_train_step(D._ctx, self._net, ra, ea, n, float(lr), ctypes.byref(loss),
                                            _stream(stream)))
         return loss.value
+
+    def loss(self, D: Dirac, rs, es, stream=None) -> float:
+        """Mean |N(r_i) - e_i|^2 / |e_i|^2 over the pairs, without an update (blocking)."""
+        nb = D.native_bytes("f32", 0)
+        n = len(rs)
+        ra = (ctypes.c_void_p * n)(*[_ptr(r, nb).value for r in rs])
+        ea = (ctypes.c_void_p * n)(*[_ptr(e, nb).value for e in es])
+        out = ctypes.c_double()
+        _lib.check(self.lib.ptc_loss(D._ctx, self._net, ra, ea, n, ctypes.byref(out), _stream(stream)))
+        return out.value
 
     def close(self):
         if getattr(self, "_net", None) is not None and self._net.value:

@@ -20,7 +20,7 @@ EXPORTS = ["dirac_create", "dirac_create_openqxd", "dirac_set_cache_block", "dir
            "dirac_apply_hop", "dirac_apply_clover", "dirac_sap", "dirac_solve", "dirac_solve_batched", "dirac_last_error",
            "ptc_create", "ptc_destroy", "ptc_num_weights", "ptc_set_weights", "ptc_get_weights", "ptc_get_grad",
            "ptc_zero_grad", "ptc_forward", "ptc_forward_eo", "ptc_backward", "ptc_adam_step", "ptc_get_adam_state", "ptc_set_adam_state",
-           "ptc_train_step"]
+           "ptc_train_step", "ptc_loss", "dirac_residual", "dirac_lincomb", "dirac_dot"]
 
 
 class Params(ctypes.Structure):
@@ -96,6 +96,11 @@ def load(path: str = LIB_PATH):
     lib.ptc_get_adam_state.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int)]
     lib.ptc_set_adam_state.argtypes = [vp, vp, vp, ctypes.c_size_t, i]
     lib.ptc_train_step.argtypes = [vp, vp, vp, vp, i, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+    lib.ptc_loss.argtypes = [vp, vp, vp, vp, i, ctypes.POINTER(ctypes.c_double), vp]
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.dirac_residual.argtypes = [vp, vp, vp, vp, i, dp, vp]
+    lib.dirac_lincomb.argtypes = [vp, vp, i, ctypes.c_double, vp, ctypes.c_double, vp, i, i, dp, vp]
+    lib.dirac_dot.argtypes = [vp, vp, vp, i, i, dp, vp]
     for name in EXPORTS:
         if name not in ("dirac_native_bytes", "dirac_last_error", "ptc_num_weights"):
             getattr(lib, name).restype = st

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "blas.h"
 #include "internal.h"
@@ -107,6 +108,13 @@ void check_user_layout(dirac_prec pr, dirac_layout lay) {
 }
 
 }  // namespace
+
+namespace dl {
+// The status and message of a failed call, for entry points defined in other files.
+dirac_status api_fail(dirac_status s, const std::string &m) { return fail(s, m); }
+void api_clear_error() { g_err.clear(); }
+void api_check_dev(const void *ptr, size_t bytes, const char *name) { check_dev(ptr, bytes, name); }
+}  // namespace dl
 
 extern "C" {
 
@@ -493,6 +501,95 @@ dirac_status dirac_sap(dirac_ctx *c, void *out, const void *in, int ncy, int nmr
     API_END
 }
 
+// ---------------------------------------------------------------- vector arithmetic
+// Device scalars of these calls: free slots near the end of the context's scalar block.
+static double *vec_slots(dirac_ctx *c) { return (double *)c->work->blas.scal.p + dl::kSysScal - 32; }
+
+static void read_slots(double *host, const double *dev, int n, hipStream_t s) {
+    HIP_CHECK(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+}
+
+dirac_status dirac_residual(dirac_ctx *c, void *r, const void *b, const void *x, dirac_prec pr, double *rel_res,
+                            void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    require(pr == DIRAC_F64 || pr == DIRAC_F32, "the residual is formed in F64 or F32");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = native_bytes(c, pr, 0);
+    check_dev(r, nb, "r");
+    check_dev(b, nb, "b");
+    check_dev(x, nb, "x");
+    check_no_alias(r, nb, b, nb);
+    check_no_alias(r, nb, x, nb);
+    dl::ensure_blas(c);
+    dl::Blas &B = c->work->blas;
+    double *sl = vec_slots(c);
+    dl::full_apply(c, r, x, 0, pr, s);
+    // r = b - D x in place (element-wise), with |r|^2 and the non-finite flag
+    B.lincomb(pr, pr, pr, 2, r, nullptr, 1.0, b, -1.0, r, rel_res ? sl : nullptr, 1.0, s);
+    if (rel_res) {
+        B.mdot(pr, 2, b, 1, b, sl + 2, 1.0, s);
+        double h[4];
+        read_slots(h, sl, 4, s);
+        require(h[1] == 0.0 && std::isfinite(h[0]) && std::isfinite(h[2]), "non-finite value in the residual",
+                DIRAC_ENONFINITE);
+        *rel_res = h[2] > 0.0 ? std::sqrt(h[0] / h[2]) : 0.0;
+    }
+    API_END
+}
+
+dirac_status dirac_lincomb(dirac_ctx *c, void *out, dirac_prec out_prec, double alpha, const void *a, double beta,
+                           const void *b, dirac_prec in_prec, int sites, double *norm2, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_prec(out_prec);
+    check_prec(in_prec);
+    require(sites == 0 || sites == 1, "sites must be 0 (full vectors) or 1 (one parity)");
+    require(std::isfinite(alpha) && std::isfinite(beta), "coefficients must be finite");
+    require(out_prec == in_prec || in_prec == DIRAC_F64,
+            "inputs in the output precision, or F64 inputs converted to any output precision");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nbo = native_bytes(c, out_prec, sites), nbi = native_bytes(c, in_prec, sites);
+    check_dev(a, nbi, "a");
+    check_dev(out, nbo, "out");
+    if (beta != 0.0) {
+        check_dev(b, nbi, "b");
+        check_no_alias(out, nbo, b, nbi);
+    }
+    check_no_alias(out, nbo, a, nbi);
+    dl::ensure_blas(c);
+    dl::Blas &B = c->work->blas;
+    double *sl = vec_slots(c);
+    B.lincomb(out_prec, in_prec, in_prec, sites == 0 ? 2 : 1, out, nullptr, alpha, a, beta, beta != 0.0 ? b : nullptr,
+              norm2 ? sl : nullptr, 1.0, s);
+    if (norm2) {
+        double h[2];
+        read_slots(h, sl, 2, s);
+        require(h[1] == 0.0 && std::isfinite(h[0]), "non-finite value in the result", DIRAC_ENONFINITE);
+        *norm2 = h[0];
+    }
+    API_END
+}
+
+dirac_status dirac_dot(dirac_ctx *c, const void *a, const void *b, dirac_prec pr, int sites, double *dot,
+                       void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_prec(pr);
+    require(dot != nullptr, "dot is NULL");
+    require(sites == 0 || sites == 1, "sites must be 0 (full vectors) or 1 (one parity)");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = native_bytes(c, pr, sites);
+    check_dev(a, nb, "a");
+    check_dev(b, nb, "b");
+    dl::ensure_blas(c);
+    double *sl = vec_slots(c);
+    c->work->blas.mdot(pr, sites == 0 ? 2 : 1, a, 1, b, sl + 4, 1.0, s);
+    read_slots(dot, sl + 4, 2, s);
+    API_END
+}
+
 // ---------------------------------------------------------------- learned preconditioner
 dirac_status ptc_create(const int *channels, int nlayers, dirac_ptc **out) {
     API_BEGIN
@@ -693,8 +790,50 @@ dirac_status ptc_train_step(dirac_ctx *c, dirac_ptc *n, const void *const *r, co
         total += gn / (f * f) / (ne2 / scale) / nbatch;  // |y - e|^2 / |e|^2 / nbatch
         dl::ptc_backward_acts(c, n, g, nullptr, s);
     }
+    *loss = total;
+    // the weights and Adam moments change only when the loss and every gradient entry are finite
+    require(std::isfinite(total), "non-finite loss; weights and Adam state left unchanged", DIRAC_ENONFINITE);
+    std::vector<float> hg(2 * n->total);
+    HIP_CHECK(hipMemcpyAsync(hg.data(), n->grad.p, hg.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    for (float v : hg)
+        require(std::isfinite(v), "non-finite weight gradient; weights and Adam state left unchanged",
+                DIRAC_ENONFINITE);
     dl::ptc_adam(n, lr, s);
     HIP_CHECK(hipStreamSynchronize(s));
+    API_END
+}
+
+dirac_status ptc_loss(dirac_ctx *c, dirac_ptc *n, const void *const *r, const void *const *e, int nbatch,
+                      double *loss, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    require(n != nullptr && r != nullptr && e != nullptr && loss != nullptr, "NULL argument");
+    require(nbatch >= 1, "nbatch must be positive");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = native_bytes(c, DIRAC_F32, 0);
+    for (int i = 0; i < nbatch; ++i) {
+        check_dev(r[i], nb, "r[i]");
+        check_dev(e[i], nb, "e[i]");
+    }
+    dl::ptc_ensure_acts(c, n);
+    dl::ensure_work(c, 1, DIRAC_F32, 2);
+    dl::Blas &B = c->work->blas;
+    double *sc = (double *)B.scal.p + dl::kSysScal - 16;
+    void *d = c->work->P.p;  // N(r_i) - e_i
+    double total = 0.0;
+    for (int i = 0; i < nbatch; ++i) {
+        HIP_CHECK(hipMemcpyAsync(dl::ptc_act(c, n, 0), r[i], nb, hipMemcpyDeviceToDevice, s));
+        dl::ptc_forward_acts(c, n, s, false);
+        B.mdot(DIRAC_F32, 2, e[i], 1, e[i], sc, 1.0, s);
+        B.lincomb(DIRAC_F32, DIRAC_F32, DIRAC_F32, 2, d, nullptr, 1.0, dl::ptc_act(c, n, n->nlayers), -1.0, e[i],
+                  sc + 2, 1.0, s);
+        double h[4];
+        HIP_CHECK(hipMemcpyAsync(h, sc, sizeof h, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        require(std::isfinite(h[0]) && h[0] > 0.0, "target e is zero or not finite", DIRAC_ENONFINITE);
+        total += h[2] / h[0] / nbatch;
+    }
     *loss = total;
     require(std::isfinite(total), "non-finite loss", DIRAC_ENONFINITE);
     API_END

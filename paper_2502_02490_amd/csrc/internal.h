@@ -139,6 +139,7 @@ void full_apply(dirac_ctx *c, void *out, const void *in, int dagger, dirac_prec 
 // solver.hip
 void free_solver_work(dirac_ctx *c);
 void ensure_work(dirac_ctx *c, int restart, dirac_prec inner, int nh);
+void ensure_blas(dirac_ctx *c);  // the reduction buffers alone (no Krylov vectors)
 void *solver_full64(dirac_ctx *c, int k);  // NATIVE FP64 full vectors: 0 = b, 1 = x, 2 = scratch
 dirac_status solve_native(dirac_ctx *c, const dirac_solver_params *p, bool x0, dirac_solve_info *info,
                           hipStream_t s);
@@ -149,6 +150,11 @@ void check_solver_params(const dirac_solver_params *p);
 const char *prec_name(dirac_prec pr);
 int tuned_choice(const char *key, int nshapes, const std::function<void(int)> &launch, hipStream_t s);
 int tuned_lookup(const char *key);  // -1 when the key has not been tuned
+
+// api.hip: status and thread-local message of a failed call, for entry points in other files
+dirac_status api_fail(dirac_status s, const std::string &m);
+void api_clear_error();
+void api_check_dev(const void *ptr, size_t bytes, const char *name);  // device memory of at least `bytes`
 
 // batched.hip
 void free_bwork(dirac_ctx *c);

@@ -50,6 +50,14 @@ double read_scalar(SolverWork &w, int slot, hipStream_t s) {
 
 // Solver buffers; they only grow, so a later call with a wider precision or a longer
 // restart reallocates (contents are not kept across calls).
+void ensure_blas(dirac_ctx *c) {
+    if (!c->work) {
+        c->work = new SolverWork();
+        c->work->blas.c = c;
+    }
+    c->work->blas.reserve(c->V, kMaxRestart);
+}
+
 void ensure_work(dirac_ctx *c, int m, dirac_prec inner, int nh) {
     if (!c->work) {
         c->work = new SolverWork();

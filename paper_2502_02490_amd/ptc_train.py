@@ -30,29 +30,41 @@ CHECKPOINT_VERSION = 1
 DEFAULT_SNAPSHOTS = (0, 2, 4, 8, 16, 32)
 
 
+def _scaled_pair_f32(D: Dirac, r64, e64):
+    """(r, e) scaled so that |e| = 1 and rounded once to NATIVE F32 (library calls)."""
+    ne = math.sqrt(D.dot(e64, e64, "f64").real)
+    r32, e32 = D.native_empty("f32"), D.native_empty("f32")
+    D.lincomb(r32, 1.0 / ne, r64, out_prec="f32", in_prec="f64")
+    D.lincomb(e32, 1.0 / ne, e64, out_prec="f32", in_prec="f64")
+    return r32, e32
+
+
 def generate_pairs(D: Dirac, n_pairs: int, seed: int, snapshots=DEFAULT_SNAPSHOTS, restart: int = 32, log=None):
-    """n_pairs (r, e) pairs on the lattice of D as NATIVE F32 full vectors (two lists)."""
+    """n_pairs (r, e) pairs on the lattice of D as NATIVE F32 full vectors (two lists).  The
+    solves, residuals r_k = b - D x_k, errors e_k = x* - x_k and the scaling run in the library
+    on NATIVE FP64 vectors; only the Gaussian right-hand sides are drawn here."""
     g = torch.Generator(device="cpu").manual_seed(seed)
     rs, es = [], []
     t0 = time.perf_counter()
     while len(rs) < n_pairs:
-        b = torch.randn((D.V, 4, 3), dtype=torch.complex128, generator=g).cuda()
-        xs = torch.zeros_like(b)
-        D.solve(xs, b, method=GCR, tol=1e-12, restart=restart)
+        b = D.to_native(torch.randn((D.V, 4, 3), dtype=torch.complex128, generator=g).cuda(), "f64", "lex")
+        xs = D.native_empty("f64")
+        D.solve(xs, b, method=GCR, tol=1e-12, restart=restart, layout="native")
         for k in snapshots:
             if len(rs) == n_pairs:
                 break
             if k == 0:
                 r, e = b, xs
             else:
-                xk = torch.zeros_like(b)
-                D.solve(xk, b, method=GCR, tol=1e-12, max_iter=k, restart=restart, raise_on_noconv=False)
-                dx = torch.empty_like(b)
-                D.apply(dx, xk)
-                r, e = b - dx, xs - xk
-            s = 1.0 / torch.linalg.vector_norm(e).item()
-            rs.append(D.to_native((r * s).to(torch.complex64), "f32", "lex"))
-            es.append(D.to_native((e * s).to(torch.complex64), "f32", "lex"))
+                xk = D.native_empty("f64")
+                D.solve(xk, b, method=GCR, tol=1e-12, max_iter=k, restart=restart, layout="native",
+                        raise_on_noconv=False)
+                r, e = D.native_empty("f64"), D.native_empty("f64")
+                D.residual(r, b, xk)
+                D.lincomb(e, 1.0, xs, -1.0, xk)
+            r32, e32 = _scaled_pair_f32(D, r, e)
+            rs.append(r32)
+            es.append(e32)
         if log and len(rs) % (10 * len(snapshots)) < len(snapshots):
             log(f"pairs {len(rs)}/{n_pairs} ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
@@ -65,12 +77,12 @@ def generate_apply_pairs(D: Dirac, n_pairs: int, seed: int):
     g = torch.Generator(device="cpu").manual_seed(seed)
     rs, es = [], []
     for _ in range(n_pairs):
-        e = torch.randn((D.V, 4, 3), dtype=torch.complex128, generator=g).cuda()
-        r = torch.empty_like(e)
-        D.apply(r, e)
-        s = 1.0 / torch.linalg.vector_norm(e).item()
-        rs.append(D.to_native((r * s).to(torch.complex64), "f32", "lex"))
-        es.append(D.to_native((e * s).to(torch.complex64), "f32", "lex"))
+        e = D.to_native(torch.randn((D.V, 4, 3), dtype=torch.complex128, generator=g).cuda(), "f64", "lex")
+        r = D.native_empty("f64")
+        D.apply(r, e, "f64", "native")
+        r32, e32 = _scaled_pair_f32(D, r, e)
+        rs.append(r32)
+        es.append(e32)
     torch.cuda.synchronize()
     return rs, es
 
@@ -94,13 +106,9 @@ def evaluate(ops_pairs, net: PTC):
     """Mean loss |N(r) - e|^2 / |e|^2 over all pairs, without an update (held-out pairs)."""
     tot, n = 0.0, 0
     for D, rs, es in ops_pairs:
-        y = D.native_empty("f32")
-        for r, e in zip(rs, es):
-            net.forward(D, y, r)
-            yl = D.from_native(y, "f32", "lex").to(torch.complex128)
-            el = D.from_native(e, "f32", "lex").to(torch.complex128)
-            tot += (torch.linalg.vector_norm(yl - el) ** 2 / torch.linalg.vector_norm(el) ** 2).item()
-            n += 1
+        if rs:
+            tot += net.loss(D, rs, es) * len(rs)
+            n += len(rs)
     return tot / max(n, 1)
 
 

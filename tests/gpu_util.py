@@ -47,6 +47,16 @@ def to_dev(a: np.ndarray) -> torch.Tensor:
 
 
 def rel(a, b) -> float:
+    """The larger of the norm-wise error |a - b| / |b| and the element-wise one
+    max_i |a_i - b_i| / max_i |b_i|: one wrong site, which a norm dilutes by the square root of
+    the number of sites, shows in full in the second."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return max(float(np.linalg.norm(a - b) / np.linalg.norm(b)), float(np.abs(a - b).max() / np.abs(b).max()))
+
+
+def rel_norm(a, b) -> float:
+    """|a - b| / |b| alone (for diagnostics where isolated entries are expected to differ)."""
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))

@@ -10,7 +10,8 @@ import torch
 
 import gen
 import paper_2502_02490_amd as P
-from gpu_util import Case, flush, need_gpu, rel, to_dev
+from gpu_util import Case, flush, need_gpu, rel, rel_norm, to_dev
+from ptc_envelope import envelope
 from oracle import dirac as odirac
 from oracle import openqxd as oq
 from oracle import ptc as optc
@@ -66,13 +67,15 @@ def test_network_transports(case):
         out = case.D.native_empty("f32")
         net.forward(case.D, out, case.D.to_native(to_dev(r.astype(np.complex64)), "f32", "lex"))
         got = case.D.from_native(out, "f32", "lex").cpu().numpy().astype(np.complex128)
-        y, _ = optc.forward(case.f, ws, r)  # unrounded network: the BF16 model is checked elsewhere
-        assert rel(got, y) < 2.0 ** -7
+        wq = [optc.round_bf16(np.asarray(w, dtype=np.complex64).astype(np.complex128)) for w in ws]
+        y, _ = optc.forward(case.f, wq, r)  # the plain network with the BF16 weights
+        env, _, _ = envelope(case.f, wq, r)
+        env.check(got, y, "C* network forward")
         # the same network with the plain neighbours is far off (the transports take the shift)
         f0 = odirac.Fields(case.U, case.theta, odirac.Params(case.dims, case.p.kappa, case.p.csw, case.p.csw_qed,
                                                            case.p.qhat, case.p.bc_phase, 0))
         y0, _ = optc.forward(f0, ws, r)
-        assert rel(y0, y) > 0.05
+        assert rel_norm(y0, y) > 0.05
     finally:
         net.close()
 

@@ -234,3 +234,71 @@ def test_bf16_storage_rounds_the_hidden_activations_only():
     m, _ = ptc.forward(f2, ws2, r2, bf16_inputs=True, last_contract_first=True, bf16_storage=True)
     d = np.linalg.norm(m - e) / np.linalg.norm(e)
     assert 1e-5 < d < 2.0 ** -6
+
+
+def test_adam_bias_correction_closed_forms():
+    """Adam beyond its first step.  A constant gradient g keeps m_hat = g and v_hat = g^2 exactly
+    (the bias corrections cancel the zero start), so every step moves each real part by
+    lr g / (|g| + eps).  A single gradient g at step 1 followed by zeros gives
+    m_t = (1 - b1) b1^(t-1) g, v_t = (1 - b2) b2^(t-1) g^2, hence the step at t is
+    lr (1 - b1) b1^(t-1) / (1 - b1^t) g / (sqrt((1 - b2) b2^(t-1) / (1 - b2^t)) |g| + eps)."""
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    w0 = [np.array([[1.0 + 2.0j, -0.5j, 0.25]])]
+    g = [np.array([[0.3 - 0.1j, 2.0 + 0.0j, -0.7 + 0.2j]])]
+    # the real gradient of (Re W, Im W) is 2 (Re, Im) of dL/dW*
+    gr, gi = 2 * g[0].real, 2 * g[0].imag
+    opt = ptc.Adam(w0, lr=lr)
+    w = w0
+    for t in range(1, 7):
+        prev = w[0]
+        w = opt.step(w, g)
+        d = w[0] - prev
+        exp = -lr * (gr / (np.abs(gr) + eps) + 1j * gi / (np.abs(gi) + eps))
+        assert np.abs(d - exp).max() < 1e-12, t
+    opt = ptc.Adam(w0, lr=lr)
+    w = opt.step(w0, g)
+    zero = [np.zeros_like(g[0])]
+    for t in range(2, 8):
+        prev = w[0]
+        w = opt.step(w, zero)
+        mh = (1 - b1) * b1 ** (t - 1) / (1 - b1 ** t)
+        vh = np.sqrt((1 - b2) * b2 ** (t - 1) / (1 - b2 ** t))
+        exp = -lr * mh * (gr / (vh * np.abs(gr) + eps) + 1j * gi / (vh * np.abs(gi) + eps))
+        assert np.abs((w[0] - prev) - exp).max() < 1e-12, t
+        assert np.abs(opt.m[0][..., 0] - (1 - b1) * b1 ** (t - 1) * gr).max() < 1e-15
+        assert np.abs(opt.v[0][..., 1] - (1 - b2) * b2 ** (t - 1) * gi ** 2).max() < 1e-15
+
+
+def test_rounding_envelope_separates_rounding_from_mistakes():
+    """The envelope the GPU network is held to (tests/ptc_envelope.py) is neither vacuous nor too
+    tight: an evaluation that rounds every layer input and hidden activation to BF16 (the
+    oracle's rounding model) lies well inside it -- forward, input gradient and every weight
+    gradient, element-wise and in norm -- while a network with one path's transport direction
+    reversed, or one boundary phase dropped, lies far outside."""
+    import math
+
+    from ptc_envelope import envelope, max_rel
+
+    L = (4, 4, 2, 4)
+    f = dirac.Fields(gen.su3_field(L, 0.5, 41), gen.u1_field(L, 0.3, 41),
+                     dirac.Params(L, 0.1245, 1.6, 1.0, -1, (math.pi, 0.2, 0.0, -0.4)))
+    for chans in [(1, 4, 1), (1, 2, 4, 1)]:
+        ws = [ptc.round_bf16(w) for w in ptc.init_weights(chans, seed=3, scale=1.0)]
+        r = ptc.round_bf16(gen.gaussian_spinor(L, 7))
+        g = ptc.round_bf16(gen.gaussian_spinor(L, 9))
+        env, env_gin, env_gw = envelope(f, ws, r, g)
+        y, acts = ptc.forward(f, ws, r)
+        gx, gW = ptc.backward(f, ws, acts, g)
+        ym, am = ptc.forward(f, ws, r, bf16_inputs=True, last_contract_first=True, bf16_storage=True)
+        gxm, gWm = ptc.backward(f, ws, am, g, bf16_inputs=True)
+        for e, a, b in [(env, ym, y), (env_gin, gxm, gx)] + list(zip(env_gw, gWm, gW)):
+            assert np.linalg.norm(a - b) / np.linalg.norm(b) < 0.6 * e.norm
+            assert max_rel(a, b) < 0.7 * e.max
+        # planted mistakes: path +1 replaced by -1 in the first layer; boundary phase of mu = 1 dropped
+        bad = [w.copy() for w in ws]
+        bad[0][3], bad[0][4] = ws[0][4], ws[0][3]
+        yb, _ = ptc.forward(f, bad, r)
+        assert np.linalg.norm(yb - y) / np.linalg.norm(y) > 20 * env.norm
+        f0 = dirac.Fields(f.U, f.theta, dirac.Params(L, 0.1245, 1.6, 1.0, -1, (math.pi, 0.0, 0.0, -0.4)))
+        y0, _ = ptc.forward(f0, ws, r)
+        assert np.linalg.norm(y0 - y) / np.linalg.norm(y) > 5 * env.norm
