@@ -44,24 +44,53 @@ HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persis
               "k_hop_mr 2 RHS/work-item 1/CU streaming hints", "k_hop_mr 4 RHS/work-item 1/CU streaming hints",
               "k_hop_mr 2 RHS/work-item 2/CU streaming hints"]
 
-# HBM bytes per launch of the FP64 hop + A chi kernel on 32^3 x 64 (calibrated FETCH_SIZE +
-# WRITE_SIZE from rocprofv3 counter runs; summary and commands in
-# profiles/hop_fp64_32c64_hbm_traffic.txt), by launch shape.  A shape missing here, or a kernel
-# changed since the counters were taken, reports null.
-HOP_CLOV_TRAFFIC_32C64 = {
-    "k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persistent)": 2.476e9 + 0.201e9,
-    "k_hop_p bs256 1/CU streaming hints (persistent)": 2.480e9 + 0.201e9,
-    "k_hop_p bs256 2/CU streaming hints (persistent)": 2.620e9 + 0.201e9,
-    "k_hop_p bs256 1/CU (persistent)": 2.609e9 + 0.201e9,
-    "k_hop_p bs256 1/CU 2 neighbours/iteration (persistent)": 2.622e9 + 0.201e9,
-    "k_hop_p bs512 1/CU (persistent)": 2.943e9 + 0.201e9,
-    "k_hop_p bs256 1/CU xcd-regions (persistent)": 2.369e9 + 0.201e9,
-    "k_hop_ps bs256 1/CU (XCD slab sweep)": 2.347e9 + 0.201e9,
-    "k_hop_ps bs128 2/CU (XCD slab sweep)": 2.426e9 + 0.201e9,
-    "k_hop_tp tt4 1/CU (persistent time-tiled)": 2.322e9 + 0.201e9,
-    "k_hop_t tt4 (time-tiled LDS)": 2.577e9 + 0.201e9,
-    "k_hop_t tt8 (time-tiled LDS)": 2.674e9 + 0.201e9,
+# The FP64 hop + A chi kernel of each launch shape, as rocprofv3 names it, and its grid in
+# work-items on 32^3 x 64 (V/2 = 1,048,576 output sites, 256 compute units): the key of its row in
+# the committed counter summary, from which the roofline's HBM traffic is read.
+HOP_CLOV_KERNEL_32C64 = {
+    0: ("k_hop_p<double, 0, 2, 256, 0, 2, true>", 65536), 1: ("k_hop_p<double, 0, 2, 256, 0, 1, true>", 65536),
+    2: ("k_hop_p<double, 0, 2, 256, 0, 1, true>", 131072), 3: ("k_hop_p<double, 0, 2, 256, 0, 1, false>", 65536),
+    4: ("k_hop_p<double, 0, 2, 256, 0, 2, false>", 65536), 11: ("k_hop_p<double, 0, 2, 512, 0, 1, false>", 131072),
+    12: ("k_hop_p<double, 0, 2, 256, 0, 1, false>", 131072), 13: ("k_hop_p<double, 0, 2, 256, 1, 1, false>", 65536),
+    14: ("k_hop_tp<double, 0, 2, 4>", 65536), 15: ("k_hop_tp<double, 0, 2, 8>", 131072),
+    16: ("k_hop_ps<double, 0, 2, 256>", 65536), 17: ("k_hop_ps<double, 0, 2, 256>", 131072),
+    18: ("k_hop_ps<double, 0, 2, 128>", 65536), 19: ("k_hop_p<double, 0, 2, 256, 0, 2, false>", 131072),
 }
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hop_fp64_32c64_hbm_traffic.txt")
+# the sources the hop kernels are compiled from: the counter summary records their hash, and a
+# summary taken from other sources is not used
+HOP_SOURCES = ["hop.hip", "hop_core.h", "dirac_ops.h", "common.h"]
+
+
+def hop_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in HOP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2502_02490_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel: str, grid: int):
+    """HBM bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE) of `kernel` with `grid`
+    work-items from the committed counter summary, or None when the summary is missing, was
+    taken from other kernel sources, or has no such row."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    src = [l for l in lines if l.startswith("# kernel sources sha256:")]
+    if not src or src[0].split(":", 1)[1].split()[0] != hop_source_hash():
+        return None
+    for l in lines:
+        if l.startswith("#") or "|" not in l:
+            continue
+        cols = [c.strip() for c in l.split("|")]
+        if len(cols) >= 8 and cols[0] == kernel and cols[1] == str(grid):
+            return (float(cols[6]) + float(cols[7])) * 1e9
+    return None
 
 
 def log(*a):
@@ -80,12 +109,11 @@ def timed(fn, n, stream):
     return start.elapsed_time(stop) / 1e3  # seconds
 
 
-def cpu_baseline(reps: int = 30):
+def _oracle_schur_rate(reps: int):
     """The oracle's D-hat (FP64, numpy, one thread) on a 16^4 lattice with the same parameters and
     field recipe: the same per-site work as the 32^3 x 64 workload on 1/32 of its volume.  As for
-    the GPU, the clover field and its inverse are set-up work outside the timed applies."""
-    import numpy as np
-
+    the GPU, the clover field and its inverse are set-up work outside the timed applies.
+    Returns (GB/s of algorithmic bytes, seconds per apply)."""
     import gen
     from oracle import dirac as odirac
 
@@ -98,14 +126,51 @@ def cpu_baseline(reps: int = 30):
     psi_e = gen.gaussian_spinor(dims, SEED)[ev]
     from threadpoolctl import threadpool_limits
 
-    with threadpool_limits(limits=1):  # one core: the figure is per thread of the host
+    with threadpool_limits(limits=1):
+        odirac.apply_schur(f, psi_e)
         t0 = time.perf_counter()
         for _ in range(reps):
             odirac.apply_schur(f, psi_e)
         dt = (time.perf_counter() - t0) / reps
-    return {"value": round(len(ev) * SCHUR_REALS * 8 / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle D-hat (FP64) on a 16^4 lattice with the 32^3x64 parameters (same per-site work, "
-                      f"1/32 of the volume), mean of {reps} applies, {dt:.2f} s each, clover set-up excluded"}
+    return len(ev) * SCHUR_REALS * 8 / dt / 1e9, dt
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(reps: int = 20):
+    """The oracle's Schur apply timed on this host's cores: one thread, then one single-threaded
+    worker process per usable core (at most 16, each on its own copy of the problem, all started
+    together), whose summed rate is the all-core figure."""
+    import subprocess
+
+    one, dt = _oracle_schur_rate(reps)
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count() or 1
+    workers = max(1, min(16, ncpu))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1", HIP_VISIBLE_DEVICES="")
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(max(4, reps // 2))],
+                              stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, env=env, text=True)
+             for _ in range(workers)]
+    rates = []
+    for pr in procs:
+        out, _ = pr.communicate(timeout=600)
+        if pr.returncode == 0 and out.strip():
+            rates.append(json.loads(out.strip().splitlines()[-1])["GBps"])
+    allc = sum(rates)
+    return {"value": round(allc, 4), "unit": "GB/s", "cores": len(rates), "kind": "oracle",
+            "sample": f"oracle D-hat (FP64, numpy) on a 16^4 lattice with the 32^3x64 parameters (same per-site "
+                      f"work, 1/32 of the volume), clover set-up excluded: {len(rates)} single-threaded processes "
+                      f"at once, {max(4, reps // 2)} applies each (summed rate); one thread alone {one:.4f} GB/s "
+                      f"({dt:.2f} s per apply, mean of {reps})",
+            "single_thread_GBps": round(one, 4), "nproc": ncpu, "cpu_model": _cpu_model()}
 
 
 def solve_suite(D, b, inner_precs):
@@ -443,7 +508,7 @@ def ptc_suite(pairs_per_field: int, epochs: int, checkpoint: str | None):
     res["held_out_loss_init"] = T.evaluate(held, net)
     t1 = time.perf_counter()
     hist = T.train(ops_pairs, net, epochs=epochs, batch=16, lr=2e-3, seed=11, lr_decay=0.8,
-                   log=lambda m: log("[ptc] " + m), time_budget=240.0)
+                   log=lambda m: log("[ptc] " + m), time_budget=60.0)
     res["training_seconds"] = round(time.perf_counter() - t1, 2)
     res["train_loss_by_epoch"] = [round(h, 5) for h in hist]
     res["held_out_loss"] = T.evaluate(held, net)
@@ -490,8 +555,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the solve timings")
     ap.add_argument("--no-48", action="store_true", help="skip the 48^3x96 mixed-precision solves")
     ap.add_argument("--no-batched", action="store_true", help="skip the 8-lattice x 12-RHS batched solve")
-    ap.add_argument("--ptc", action="store_true",
-                    help="also train the PTC preconditioner (2000 pairs on 16^3x32) and deploy it on 32^3x64")
+    ap.add_argument("--no-ptc", action="store_true",
+                    help="skip the learned preconditioner (trained on 16^3x32 pairs, deployed on 32^3x64)")
     ap.add_argument("--ptc-pairs", type=int, default=500, help="training pairs per 16^3x32 field")
     ap.add_argument("--ptc-epochs", type=int, default=8)
     ap.add_argument("--ptc-checkpoint", default=None, help="write the trained weights and Adam state here")
@@ -509,7 +574,13 @@ def main():
                          "kernel trace of the Krylov BLAS")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 5 plain device copies of 768 MiB (a known-size kernel for HBM counter calibration)")
+    ap.add_argument("--cpu-worker", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        # one single-threaded worker of the all-core CPU baseline (started by cpu_baseline)
+        gbs, dt = _oracle_schur_rate(args.cpu_worker)
+        print(json.dumps({"GBps": gbs, "seconds_per_apply": dt}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the operator runs on a single MI355X (multi-GPU halo exchange is "
               "designed, not built); run with --gpus 1", file=sys.stderr)
@@ -719,12 +790,12 @@ def main():
         solves["batched_8lat_12rhs"] = batched_suite()
         log(f"[bench] batched {solves['batched_8lat_12rhs']}")
 
-    if args.ptc:
+    if not args.no_solve and not args.no_ptc:
         solves["ptc_learned_preconditioner"] = ptc_suite(args.ptc_pairs, args.ptc_epochs, args.ptc_checkpoint)
 
     traffic = None
-    if chosen is not None and DIMS == (64, 32, 32, 32):
-        traffic = HOP_CLOV_TRAFFIC_32C64.get(HOP_SHAPES[chosen])
+    if chosen is not None and DIMS == (64, 32, 32, 32) and chosen in HOP_CLOV_KERNEL_32C64:
+        traffic = profiled_traffic(*HOP_CLOV_KERNEL_32C64[chosen])
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline()
