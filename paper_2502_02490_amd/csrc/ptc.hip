@@ -595,14 +595,16 @@ __global__ __launch_bounds__(256) void k_ptc_reduce(int nblk, int n, const float
 }
 
 // Adam on n real parameters (interleaved re, im); writes the BF16 working copy
+// omb1 = 1 - b1 and omb2 = 1 - b2 come rounded once from their exact values: 1 - b2 formed in FP32
+// from the rounded b2 = 0.999f would be 1.3e-5 off in relative terms.
 __global__ void k_adam(int n, float *__restrict__ w, const float *__restrict__ grad_conj, float *__restrict__ m,
-                       float *__restrict__ v, uint16_t *__restrict__ wbf, float lr, float b1, float b2, float eps,
-                       float c1, float c2) {
+                       float *__restrict__ v, uint16_t *__restrict__ wbf, float lr, float b1, float omb1, float b2,
+                       float omb2, float eps, float c1, float c2) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const float g = 2.0f * grad_conj[k];  // dL/d(Re W) = 2 Re dL/dW*, dL/d(Im W) = 2 Im dL/dW*
-    const float mk_ = b1 * m[k] + (1.0f - b1) * g;
-    const float vk = b2 * v[k] + (1.0f - b2) * g * g;
+    const float mk_ = b1 * m[k] + omb1 * g;
+    const float vk = b2 * v[k] + omb2 * g * g;
     m[k] = mk_;
     v[k] = vk;
     const float nw = w[k] - lr * (mk_ / c1) / (sqrtf(vk / c2) + eps);
@@ -898,11 +900,14 @@ void ptc_backward_acts(dirac_ctx *c, dirac_ptc *n, const void *g_out, void *gin,
 
 void ptc_adam(dirac_ptc *n, double lr, hipStream_t s) {
     n->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.0f - std::pow(b1, (float)n->step), c2 = 1.0f - std::pow(b2, (float)n->step);
+    // the decay rates and the bias corrections 1 - b^t in FP64, each rounded to FP32 once
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    const double c1 = 1.0 - std::pow(b1, (double)n->step), c2 = 1.0 - std::pow(b2, (double)n->step);
     const int nr = (int)(2 * n->total);
     k_adam<<<(nr + 255) / 256, 256, 0, s>>>(nr, (float *)n->w.p, (const float *)n->grad.p, (float *)n->m.p,
-                                           (float *)n->v.p, (uint16_t *)n->wbf.p, (float)lr, b1, b2, eps, c1, c2);
+                                           (float *)n->v.p, (uint16_t *)n->wbf.p, (float)lr, (float)b1,
+                                           (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps, (float)c1,
+                                           (float)c2);
     HIP_CHECK(hipGetLastError());
     refresh_afrags(n, s);
 }
