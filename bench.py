@@ -42,7 +42,12 @@ HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persis
               "k_hop_ps bs256 1/CU (XCD slab sweep)", "k_hop_ps bs256 2/CU (XCD slab sweep)",
               "k_hop_ps bs128 2/CU (XCD slab sweep)", "k_hop_p bs256 2/CU 2 neighbours/iteration (persistent)",
               "k_hop_mr 2 RHS/work-item 1/CU streaming hints", "k_hop_mr 4 RHS/work-item 1/CU streaming hints",
-              "k_hop_mr 2 RHS/work-item 2/CU streaming hints"]
+              "k_hop_mr 2 RHS/work-item 2/CU streaming hints",
+              "k_hop_rb 4 waves (right-hand sides blocked, links and clover in LDS)",
+              "k_hop_rb 8 waves (right-hand sides blocked, links and clover in LDS)",
+              "k_hop_rb 12 waves (right-hand sides blocked, links and clover in LDS)",
+              "k_hop_rb 4 waves xcd-order (right-hand sides blocked, links and clover in LDS)",
+              "k_hop_rb 8 waves xcd-order (right-hand sides blocked, links and clover in LDS)"]
 
 # The FP64 hop + A chi kernel of each launch shape, as rocprofv3 names it, and its grid in
 # work-items on 32^3 x 64 (V/2 = 1,048,576 output sites, 256 compute units): the key of its row in

@@ -22,9 +22,33 @@ namespace {
 // index of its (x0, x1, x2) row), accumulated into acc.  With `tile` the time-direction neighbour
 // comes from LDS: slot `tslot` - 1 / + 1 of the tile holds the input block of the previous / next
 // time slice at the same spatial block, and the neighbour sits at the same lane.
-template <typename S, int DAG, bool NT>
+// Links, phases and clover block of one 64-site block staged in LDS (the right-hand-side blocked
+// kernel): the same planes as in HBM, [direction][plane][64 sites] and [plane][64 sites].
+template <typename S>
+struct LdsBlock {
+    const typename Lk<S>::vec *lk;
+    const typename Lk<S>::om *om;
+    const typename St<S>::vec *cl;
+};
+
+template <typename S>
+DEV void load_link_lds(const LdsBlock<S> &L, int dir, int lane, C<typename St<S>::acc> u[6],
+                       typename St<S>::acc &co, typename St<S>::acc &si) {
+    using T = typename St<S>::acc;
+    constexpr int W = Lk<S>::W;
+    T r[12];
+#pragma unroll
+    for (int k = 0; k < 12 / W; ++k) Lk<S>::unpack(L.lk[(dir * (12 / W) + k) * kSB + lane], r + k * W);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) u[k] = mk(r[2 * k], r[2 * k + 1]);
+    const typename Lk<S>::om w = L.om[dir * kSB + lane];
+    if constexpr (Lk<S>::phase_pair) Lk<S>::phase(w, co, si);
+    else sc((T)w, si, co);
+}
+
+template <typename S, int DAG, bool NT, bool LDSF = false>
 DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n, C<typename St<S>::acc> acc[12],
-                 const typename St<S>::vec *tile, int tslot) {
+                 const typename St<S>::vec *tile, int tslot, const LdsBlock<S> *lds = nullptr) {
     using T = typename St<S>::acc;
     const int mu = n >> 1, back = n & 1;
     C<T> psi[12], u[6];
@@ -32,7 +56,8 @@ DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n
     if (tile && mu == 0) load_spinor<S>(tile + (size_t)(tslot + (back ? -1 : 1)) * (24 / St<S>::W) * kSB,
                                         i & (kSB - 1), psi);
     else load_spinor<S>(a.in, neighbour(a, x, row, n), psi);
-    load_link<S, NT>(a, n, i, u, co, si);
+    if constexpr (LDSF) load_link_lds<S>(*lds, n, (int)(i & (kSB - 1)), u, co, si);
+    else load_link<S, NT>(a, n, i, u, co, si);
     accumulate_dir<T, DAG>(n, psi, u, co, si, acc);
 }
 
@@ -42,18 +67,18 @@ DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n
 // NPI = 1 keeps one neighbour's data live at a time; NPI = 2 takes the forward and backward
 // neighbour of one mu per iteration, so each wave has twice the loads in flight.  The sums are
 // accumulated in the same order either way.
-template <typename S, int DAG, int NPI, bool NT>
+template <typename S, int DAG, int NPI, bool NT, bool LDSF = false>
 DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<S>::acc> acc[12],
-                 const typename St<S>::vec *tile = nullptr, int tslot = 0) {
+                 const typename St<S>::vec *tile = nullptr, int tslot = 0, const LdsBlock<S> *lds = nullptr) {
     const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
     if constexpr (NPI == 1) {
 #pragma nounroll
-        for (int n = 0; n < 8; ++n) hop_dir<S, DAG, NT>(a, x, row, i, n, acc, tile, tslot);
+        for (int n = 0; n < 8; ++n) hop_dir<S, DAG, NT, LDSF>(a, x, row, i, n, acc, tile, tslot, lds);
     } else {
 #pragma nounroll
         for (int mu = 0; mu < 4; ++mu) {
-            hop_dir<S, DAG, NT>(a, x, row, i, 2 * mu, acc, tile, tslot);
-            hop_dir<S, DAG, NT>(a, x, row, i, 2 * mu + 1, acc, tile, tslot);
+            hop_dir<S, DAG, NT, LDSF>(a, x, row, i, 2 * mu, acc, tile, tslot, lds);
+            hop_dir<S, DAG, NT, LDSF>(a, x, row, i, 2 * mu + 1, acc, tile, tslot, lds);
         }
     }
 }
@@ -63,8 +88,9 @@ DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<
 // same code per site, so all shapes give bitwise identical results; the tuner only picks the
 // fastest.  NT: links, clover field, chi and the output, each touched once, carry a streaming
 // hint.
-template <typename S, int DAG, int MODE, int NPI = 1, bool NT = false>
-DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, int tslot) {
+template <typename S, int DAG, int MODE, int NPI = 1, bool NT = false, bool LDSF = false>
+DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, int tslot,
+                  const LdsBlock<S> *lds = nullptr) {
     using T = typename St<S>::acc;
     const uint32_t i = (uint32_t)ii;
     int x[4];
@@ -72,7 +98,7 @@ DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, 
     C<T> acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = mk(T(0), T(0));
-    hop_all<S, DAG, NPI, NT>(a, x, i, acc, tile, tslot);
+    hop_all<S, DAG, NPI, NT, LDSF>(a, x, i, acc, tile, tslot, lds);
     C<T> y[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) y[k] = a.coef * acc[k];
@@ -94,9 +120,22 @@ DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, 
         for (int blk = 0; blk < 2; ++blk) {
             const T *q = pk;
             if constexpr (split) {
-                load_planes_h<S, 36, NT>(a.clov, 72 / W, blk * (36 / W), i, pk);
+                if constexpr (LDSF) {
+#pragma unroll
+                    for (int k = 0; k < 36 / W; ++k)
+                        St<S>::unpack(lds->cl[(blk * (36 / W) + k) * kSB + (i & (kSB - 1))], pk + k * W);
+                } else {
+                    load_planes_h<S, 36, NT>(a.clov, 72 / W, blk * (36 / W), i, pk);
+                }
             } else {
-                if (blk == 0) load_planes_h<S, 72, NT>(a.clov, 72 / W, 0, i, pk);
+                if (blk == 0) {
+                    if constexpr (LDSF) {
+#pragma unroll
+                        for (int k = 0; k < 72 / W; ++k) St<S>::unpack(lds->cl[k * kSB + (i & (kSB - 1))], pk + k * W);
+                    } else {
+                        load_planes_h<S, 72, NT>(a.clov, 72 / W, 0, i, pk);
+                    }
+                }
                 q = pk + 36 * blk;
             }
             if constexpr (MODE == HOP_INV) {
@@ -279,6 +318,57 @@ __global__ __launch_bounds__(BS) void k_hop_mr(HopArgs<S> a, int nlog) {
     }
 }
 
+// Right-hand-side blocked kernel: a work-group of NW wavefronts takes one 64-site block and all
+// right-hand sides.  It stages the block's links (8 directions), phases and clover block in LDS
+// once, and wavefront w then computes right-hand sides w, w + NW, ... of the block from there, so
+// every link and clover entry is read from HBM once per site whatever the number of right-hand
+// sides, and no right-hand side's work-group on another XCD fetches them again.  Each site's sums
+// are those of hop_site with the same values, so the results equal the one-RHS kernel's bit for
+// bit.  Work-group b takes block b (dispatch order: consecutive blocks on consecutive XCDs, so
+// the neighbours one and eight blocks away in x2 and x1, and the time neighbours, come from the
+// blocks in flight beside it) or, with XCD, the XCD-contiguous order.  The stores of the output
+// and the loads of chi carry a streaming hint (NT): each is touched once.
+template <typename S, int DAG, int MODE, int NW, bool XCD>
+__global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
+    using LV = typename Lk<S>::vec;
+    using OM = typename Lk<S>::om;
+    using V = typename St<S>::vec;
+    constexpr int LP = 12 / Lk<S>::W;  // link planes per direction
+    constexpr int CP = 72 / St<S>::W;  // clover planes
+    __shared__ LV s_lk[8 * LP * kSB];
+    __shared__ OM s_om[8 * kSB];
+    __shared__ V s_cl[MODE != HOP_PLAIN ? CP * kSB : 1];
+    const int blk = XCD ? xcd_block(a.nb8) : (int)blockIdx.x;
+    const int nblk = (a.g.vh + kSB - 1) / kSB;
+    if (blk >= nblk) return;  // uniform over the work-group
+    const size_t vhp = (size_t)a.g.vhp;
+    const int t = (int)threadIdx.x;
+    for (int k = t; k < 8 * LP * kSB; k += 64 * NW) {
+        const int dir = k / (LP * kSB), rem = k - dir * (LP * kSB);
+        s_lk[k] = ld_stream(a.links + (size_t)dir * LP * vhp + (size_t)blk * LP * kSB + rem);
+    }
+    for (int k = t; k < 8 * kSB; k += 64 * NW) {
+        const int dir = k / kSB, lane = k - dir * kSB;
+        s_om[k] = ld_stream(a.omega + (size_t)dir * vhp + (size_t)blk * kSB + lane);
+    }
+    if constexpr (MODE != HOP_PLAIN) {
+        for (int k = t; k < CP * kSB; k += 64 * NW) s_cl[k] = ld_stream(a.clov + (size_t)blk * CP * kSB + k);
+    }
+    __syncthreads();
+    const LdsBlock<S> L{s_lk, s_om, s_cl};
+    const int w = t >> 6, ii = blk * kSB + (t & (kSB - 1));
+    if (ii >= a.g.vh) return;  // no barrier follows
+#pragma nounroll
+    for (int r = w; r < a.nrhs; r += NW) {
+        if (a.active && !a.active[r]) continue;
+        HopArgs<S> b = a;
+        b.in += r * a.vs;
+        b.out += r * a.vs;
+        if (b.chi) b.chi += r * a.vs;
+        hop_site<S, DAG, MODE, 1, true, true>(b, ii, nullptr, 0, &L);
+    }
+}
+
 // Slab sweep: XCD k (work-groups b with b % 8 == k) owns the time slices [k L0 / 8, (k + 1) L0 / 8)
 // and walks them with time faster than x1: the work-groups of one XCD in flight together cover a
 // few (t, x1) planes of all its time slices, so the neighbours in every direction but across the
@@ -381,21 +471,24 @@ __global__ __launch_bounds__(64 * TT) void k_hop_tp(HopArgs<S> a, int nwg) {
 }
 
 struct HopShape {
-    int bs, xcd, tt, pers, slab, npi, nt, mr;
+    int bs, xcd, tt, pers, slab, npi, nt, mr, rb;
 };
 // Shape 0 is the default (used when tuning is off, and inside a graph capture before the key
 // was tuned): the persistent sweep, one 256-wide work-group per compute unit, two neighbours per
 // loop iteration, streaming hints.  tt > 0: the time-tiled kernel (bs = 64 tt); pers > 0: a
 // persistent grid of pers work-groups per compute unit (xcd: each XCD sweeps its own eighth);
 // slab: the XCD slab sweep; npi: neighbours per loop iteration; nt: streaming hints; mr: right-hand
-// sides per work-item (the links and clover block read once for all of them).
+// sides per work-item (the links and clover block read once for all of them); rb: the right-hand-
+// side blocked kernel with rb wavefronts per work-group (links and clover block staged in LDS).
 const HopShape kShapes[] = {
     {256, 0, 0, 1, 0, 2, 1, 1}, {256, 0, 0, 1, 0, 1, 1, 1}, {256, 0, 0, 2, 0, 1, 1, 1}, {256, 0, 0, 1, 0, 1, 0, 1},
     {256, 0, 0, 1, 0, 2, 0, 1}, {256, 1, 0, 0, 0, 1, 0, 1}, {256, 0, 0, 0, 0, 1, 0, 1}, {128, 1, 0, 0, 0, 1, 0, 1},
     {64, 1, 0, 0, 0, 1, 0, 1},  {256, 1, 4, 0, 0, 1, 0, 1}, {512, 1, 8, 0, 0, 1, 0, 1}, {512, 0, 0, 1, 0, 1, 0, 1},
     {256, 0, 0, 2, 0, 1, 0, 1}, {256, 1, 0, 1, 0, 1, 0, 1}, {256, 0, 4, 1, 0, 1, 0, 1}, {512, 0, 8, 1, 0, 1, 0, 1},
     {256, 0, 0, 1, 1, 1, 0, 1}, {256, 0, 0, 2, 1, 1, 0, 1}, {128, 0, 0, 2, 1, 1, 0, 1}, {256, 0, 0, 2, 0, 2, 0, 1},
-    {256, 0, 0, 1, 0, 1, 1, 2}, {256, 0, 0, 1, 0, 1, 1, 4}, {256, 0, 0, 2, 0, 1, 1, 2}};
+    {256, 0, 0, 1, 0, 1, 1, 2}, {256, 0, 0, 1, 0, 1, 1, 4}, {256, 0, 0, 2, 0, 1, 1, 2}, {256, 0, 0, 0, 0, 1, 1, 1, 4},
+    {512, 0, 0, 0, 0, 1, 1, 1, 8}, {768, 0, 0, 0, 0, 1, 1, 1, 12}, {256, 1, 0, 0, 0, 1, 1, 1, 4},
+    {512, 1, 0, 0, 0, 1, 1, 1, 8}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 template <typename S> constexpr int num_shapes() { return kNumShapes; }
 
@@ -475,11 +568,30 @@ void launch_tiled(HopArgs<S> a, hipStream_t s) {
     k_hop_t<S, DAG, MODE, TT><<<a.nb8, 64 * TT, 0, s>>>(a);
 }
 
+template <typename S, int DAG, int MODE, int NW>
+void launch_rb_nw(HopArgs<S> a, int xcd, hipStream_t s) {
+    const int nblk = (a.g.vh + kSB - 1) / kSB;
+    a.xcd = xcd;
+    a.nb8 = xcd ? (nblk + 7) & ~7 : nblk;
+    if (xcd) k_hop_rb<S, DAG, MODE, NW, true><<<a.nb8, 64 * NW, 0, s>>>(a);
+    else k_hop_rb<S, DAG, MODE, NW, false><<<a.nb8, 64 * NW, 0, s>>>(a);
+}
+
+template <typename S, int DAG, int MODE>
+void launch_rb(const HopArgs<S> &a, int nw, int xcd, hipStream_t s) {
+    // FP64 needs about 176 registers per lane: at most two wavefronts per SIMD, 8 per work-group
+    if (nw == 4) launch_rb_nw<S, DAG, MODE, 4>(a, xcd, s);
+    else if (nw == 8 || std::is_same<S, double>::value) launch_rb_nw<S, DAG, MODE, 8>(a, xcd, s);
+    else if constexpr (!std::is_same<S, double>::value) launch_rb_nw<S, DAG, MODE, 12>(a, 0, s);
+}
+
 template <typename S, int DAG, int MODE>
 void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
     HopShape h = kShapes[shape];
     if ((h.tt && !tiled_ok(a.g, h.tt)) || (h.slab && !slab_ok(a.g, h.bs))) h = kShapes[0];  // does not fit
-    if (h.mr > 1) {
+    if (h.rb) {
+        launch_rb<S, DAG, MODE>(a, h.rb, h.xcd, s);
+    } else if (h.mr > 1) {
         // two right-hand sides per work-item in FP64 (four would not fit the registers)
         if constexpr (std::is_same<S, double>::value) {
             launch_multi<S, DAG, MODE, 2>(a, h.pers, s);

@@ -221,7 +221,7 @@ def test_multi_rhs_schur_equals_single(case, prec, monkeypatch):
         singles.append(one)
     one_dag = torch.zeros_like(nats[nr - 1])
     D.apply_eo(one_dag, nats[nr - 1], prec, "native", dagger=True)
-    for shape in (None, 20, 21, 22):
+    for shape in (None, 20, 21, 22, 23, 24, 25, 26, 27):
         if shape is not None:
             monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
         out = torch.zeros_like(inp)
