@@ -193,6 +193,23 @@ dirac_status dirac_apply_eo(dirac_ctx *ctx, void *out_e, const void *in_e, dirac
 dirac_status dirac_apply_eo_multi(dirac_ctx *ctx, void *out, const void *in, int nrhs, dirac_prec prec, int dagger,
                                   void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  out_e = D-hat in_e (dagger = 0) or D-hat^dag in_e on
+ * NATIVE even half-vectors of `prec`, computed by the same kernels as dirac_apply_eo and bitwise
+ * equal to it.  The odd-site intermediate A_oo^-1 D_oe in_e (24 reals per padded odd site) is kept
+ * in a static device buffer of DIRAC_NOALLOC_SCRATCH_BYTES (64 MiB) that every GPU the library
+ * runs on holds until the process ends, so this call allocates nothing and runs no launch-shape
+ * timing (it takes the shape tuned earlier for the lattice, else the default shape).  Limits:
+ * the intermediate must fit the buffer (at most 349,504 odd sites in F64, e.g. 24^3x48;
+ * 699,008 in F32; 1,398,080 in F16 / BF16, e.g. 32^3x64), else DIRAC_EINVAL; the fields of
+ * `prec` must exist (F64 always; the
+ * others after any earlier apply or solve in that precision), else DIRAC_EINVAL.  Every call on
+ * one GPU shares that GPU's buffer: calls that overlap in time on one GPU (other streams, other
+ * threads) race.  Asynchronous on `stream`. */
+#define DIRAC_NOALLOC_SCRATCH_BYTES (64u << 20)
+dirac_status dirac_apply_eo_noalloc(dirac_ctx *ctx, void *out_e, const void *in_e, dirac_prec prec, int dagger,
+                                    void *stream);
+
 /* out_p = D_{p,1-p} in_{1-p} = -1/2 H in (the hopping term between parities), NATIVE
  * half-vectors; out_parity selects p.  dagger = 1 gives gamma_5 D_{p,1-p} gamma_5. */
 dirac_status dirac_apply_hop(dirac_ctx *ctx, void *out, const void *in, int out_parity, dirac_prec prec,

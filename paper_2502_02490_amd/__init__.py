@@ -169,6 +169,14 @@ class Dirac:
                                                  int(dagger), _stream(stream)))
         return out
 
+    def apply_eo_noalloc(self, out, inp, prec="f64", dagger=False, stream=None):
+        """out_e = D-hat inp_e on NATIVE half vectors without any device allocation (the odd
+        intermediate sits in the library's static buffer; see dirac_apply_eo_noalloc)."""
+        nb = self.native_bytes(prec, 1)
+        _lib.check(self.lib.dirac_apply_eo_noalloc(self._ctx, _ptr(out, nb), _ptr(inp, nb), _prec(prec), int(dagger),
+                                                   _stream(stream)))
+        return out
+
     def apply_hop(self, out, inp, out_parity: int, prec="f64", dagger=False, stream=None):
         """out_p = D_{p,1-p} inp = -1/2 H inp (NATIVE half-vectors)."""
         nb = self.native_bytes(prec, 1)

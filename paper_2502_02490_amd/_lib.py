@@ -17,6 +17,7 @@ CGLS, GCR, MIXED_GCR, FGCR_PTC, FGCR_PTC_EO, FGCR_SAP = 0, 1, 2, 3, 4, 5
 # every symbol declared in include/dirac.h
 EXPORTS = ["dirac_create", "dirac_create_openqxd", "dirac_set_cache_block", "dirac_destroy", "dirac_load_clover", "dirac_get_clover", "clover_invert",
            "dirac_native_bytes", "dirac_import", "dirac_export", "dirac_apply", "dirac_apply_eo", "dirac_apply_eo_multi",
+           "dirac_apply_eo_noalloc",
            "dirac_apply_hop", "dirac_apply_clover", "dirac_sap", "dirac_solve", "dirac_solve_batched", "dirac_last_error",
            "ptc_create", "ptc_destroy", "ptc_num_weights", "ptc_set_weights", "ptc_get_weights", "ptc_get_grad",
            "ptc_zero_grad", "ptc_forward", "ptc_forward_eo", "ptc_backward", "ptc_adam_step", "ptc_get_adam_state", "ptc_set_adam_state",
@@ -75,6 +76,7 @@ def load(path: str = LIB_PATH):
     lib.dirac_apply.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_apply_eo.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_apply_eo_multi.argtypes = [vp, vp, vp, i, i, i, vp]
+    lib.dirac_apply_eo_noalloc.argtypes = [vp, vp, vp, i, i, vp]
     lib.dirac_apply_hop.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_apply_clover.argtypes = [vp, vp, vp, i, i, i, vp]
     lib.dirac_sap.argtypes = [vp, vp, vp, i, i, vp]

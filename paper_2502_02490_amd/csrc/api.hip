@@ -393,6 +393,18 @@ dirac_status dirac_apply_eo_multi(dirac_ctx *c, void *out, const void *in, int n
     API_END
 }
 
+dirac_status dirac_apply_eo_noalloc(dirac_ctx *c, void *out, const void *in, dirac_prec pr, int dagger, void *stream) {
+    API_BEGIN
+    check_ctx(c);
+    check_prec(pr);
+    const size_t nb = native_bytes(c, pr, 1);
+    check_dev(in, nb, "in_e");
+    check_dev(out, nb, "out_e");
+    check_no_alias(out, nb, in, nb);
+    dl::schur_apply_noalloc(c, out, in, dagger != 0, pr, (hipStream_t)stream);
+    API_END
+}
+
 dirac_status dirac_apply_hop(dirac_ctx *c, void *out, const void *in, int out_parity, dirac_prec pr, int dagger,
                              void *stream) {
     API_BEGIN

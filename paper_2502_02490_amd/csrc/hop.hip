@@ -625,7 +625,7 @@ void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
 
 template <typename S>
 void hop_t(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopMode mode, double coef, int dagger,
-           dirac_prec pr, hipStream_t s, int nrhs, const int *active) {
+           dirac_prec pr, hipStream_t s, int nrhs, const int *active, bool no_tune) {
     PrecFields &f = c->f[pr];
     HopArgs<S> a;
     a.g = c->g;
@@ -657,23 +657,35 @@ void hop_t(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopM
     char key[160];
     snprintf(key, sizeof key, "hop-v2|%s|dag%d|mode%d|%dx%dx%dx%d|nrhs%d", prec_name(pr), dagger, (int)mode,
              c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3], nrhs);
-    launch(tuned_choice(key, num_shapes<S>(), launch, s));
+    if (no_tune) {
+        // no timing runs (they create events): the shape tuned earlier for this key, else shape 0
+        const int v = tuned_lookup(key);
+        launch(v >= 0 && v < num_shapes<S>() ? v : 0);
+    } else {
+        launch(tuned_choice(key, num_shapes<S>(), launch, s));
+    }
 }
 
 }  // namespace
 
 void hop_apply(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopMode mode, double coef, int dagger,
-               dirac_prec pr, hipStream_t s, int nrhs, const int *active) {
+               dirac_prec pr, hipStream_t s, int nrhs, const int *active, bool no_alloc) {
     require(nrhs >= 1, "nrhs must be positive");
     require(p == 0 || p == 1, "parity must be 0 (even) or 1 (odd)");
-    ensure_prec(c, pr, s);
     PrecFields &f = c->f[pr];
+    if (no_alloc)
+        require(f.links_ready && (mode == HOP_PLAIN || f.clover_ready),
+                std::string("the ") + prec_name(pr) + " fields have not been built; any apply in this precision builds them");
+    else
+        ensure_prec(c, pr, s);
     require(mode != HOP_INV || f.inv_ready[p], "clover inverse of this parity not computed; call clover_invert");
     switch (pr) {
-        case DIRAC_F64: hop_t<double>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active); break;
-        case DIRAC_F32: hop_t<float>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active); break;
-        case DIRAC_F16: hop_t<__half>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active); break;
-        case DIRAC_BF16: hop_t<__hip_bfloat16>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active); break;
+        case DIRAC_F64: hop_t<double>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active, no_alloc); break;
+        case DIRAC_F32: hop_t<float>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active, no_alloc); break;
+        case DIRAC_F16: hop_t<__half>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active, no_alloc); break;
+        case DIRAC_BF16:
+            hop_t<__hip_bfloat16>(c, out, in, chi, p, mode, coef, dagger, pr, s, nrhs, active, no_alloc);
+            break;
         default: throw Error(DIRAC_EINVAL, "unknown precision");
     }
 }
@@ -686,8 +698,16 @@ void schur_apply(dirac_ctx *c, void *out_e, const void *in_e, int dagger, dirac_
     PrecFields &f = c->f[pr];
     require(f.inv_ready[1], "odd-site clover inverse not available (clover_invert failed or was not run)");
     f.tmp_half.alloc((size_t)nrhs * 24 * real_size(pr) * c->g.vhp);
-    hop_apply(c, f.tmp_half.p, in_e, nullptr, 1, HOP_INV, -0.5, dagger, pr, s, nrhs, active);
-    hop_apply(c, out_e, f.tmp_half.p, in_e, 0, HOP_CLOV, 0.5, dagger, pr, s, nrhs, active);
+    schur_apply_into(c, out_e, in_e, f.tmp_half.p, dagger, pr, s, nrhs, active, false);
+}
+
+// The two launches of D-hat with the odd intermediate t_o in `tmp` (nrhs odd half vectors of pr);
+// no_alloc: build nothing and time nothing (the fields of pr must exist).
+void schur_apply_into(dirac_ctx *c, void *out_e, const void *in_e, void *tmp, int dagger, dirac_prec pr,
+                      hipStream_t s, int nrhs, const int *active, bool no_alloc) {
+    require(c->f[pr].inv_ready[1], "odd-site clover inverse not available (clover_invert failed or was not run)");
+    hop_apply(c, tmp, in_e, nullptr, 1, HOP_INV, -0.5, dagger, pr, s, nrhs, active, no_alloc);
+    hop_apply(c, out_e, tmp, in_e, 0, HOP_CLOV, 0.5, dagger, pr, s, nrhs, active, no_alloc);
 }
 
 // D in: out_p = A_pp in_p - 1/2 H in_{1-p} for both parities (NATIVE full vectors).

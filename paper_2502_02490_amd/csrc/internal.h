@@ -130,11 +130,19 @@ enum HopMode { HOP_PLAIN = 0, HOP_INV = 1, HOP_CLOV = 2 };
 // out_p = mode(coef * H in_{1-p}); HOP_INV applies A_pp^-1 after, HOP_CLOV adds A_pp chi_p.
 // nrhs right-hand sides: vector r of out / in / chi is r half-lattice vectors after the base;
 // right-hand sides whose active flag is 0 are skipped.
+// no_alloc: neither build the fields of pr (they must exist) nor time launch shapes.
 void hop_apply(dirac_ctx *c, void *out, const void *in, const void *chi, int out_parity, HopMode mode, double coef,
-               int dagger, dirac_prec pr, hipStream_t s, int nrhs = 1, const int *active = nullptr);
+               int dagger, dirac_prec pr, hipStream_t s, int nrhs = 1, const int *active = nullptr,
+               bool no_alloc = false);
 void schur_apply(dirac_ctx *c, void *out_e, const void *in_e, int dagger, dirac_prec pr, hipStream_t s, int nrhs = 1,
                  const int *active = nullptr);
+// D-hat with the odd intermediate in caller-provided device memory `tmp` (nrhs odd half vectors)
+void schur_apply_into(dirac_ctx *c, void *out_e, const void *in_e, void *tmp, int dagger, dirac_prec pr,
+                      hipStream_t s, int nrhs, const int *active, bool no_alloc);
 void full_apply(dirac_ctx *c, void *out, const void *in, int dagger, dirac_prec pr, hipStream_t s);
+
+// noalloc.hip: D-hat with the intermediate in the library's static device buffer (allocates nothing)
+void schur_apply_noalloc(dirac_ctx *c, void *out_e, const void *in_e, int dagger, dirac_prec pr, hipStream_t s);
 
 // solver.hip
 void free_solver_work(dirac_ctx *c);
