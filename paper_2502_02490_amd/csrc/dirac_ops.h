@@ -63,11 +63,9 @@ DEV void third_row(const C<T> u[6], C<T> r2[3]) {
     r2[2] = conj(u[0] * u[4] - u[1] * u[3]);
 }
 
-// w = e^{i om} U h (forward) for both spin rows of the half-spinor.
+// w = e^{i om} U h (forward) for both spin rows of the half-spinor; r2 = third_row(u).
 template <typename T>
-DEV void link_mul(const C<T> u[6], T co, T si, const C<T> h[6], C<T> w[6]) {
-    C<T> r2[3];
-    third_row(u, r2);
+DEV void link_mul_r2(const C<T> u[6], const C<T> r2[3], T co, T si, const C<T> h[6], C<T> w[6]) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const C<T> *hs = h + 3 * s;
@@ -79,11 +77,16 @@ DEV void link_mul(const C<T> u[6], T co, T si, const C<T> h[6], C<T> w[6]) {
     }
 }
 
-// w = e^{-i om} U^dag h (backward).
 template <typename T>
-DEV void link_adj_mul(const C<T> u[6], T co, T si, const C<T> h[6], C<T> w[6]) {
+DEV void link_mul(const C<T> u[6], T co, T si, const C<T> h[6], C<T> w[6]) {
     C<T> r2[3];
     third_row(u, r2);
+    link_mul_r2(u, r2, co, si, h, w);
+}
+
+// w = e^{-i om} U^dag h (backward); r2 = third_row(u).
+template <typename T>
+DEV void link_adj_mul_r2(const C<T> u[6], const C<T> r2[3], T co, T si, const C<T> h[6], C<T> w[6]) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const C<T> *hs = h + 3 * s;
@@ -94,6 +97,13 @@ DEV void link_adj_mul(const C<T> u[6], T co, T si, const C<T> h[6], C<T> w[6]) {
         const C<T> ph = mk(co, -si);
         w[3 * s + 0] = ph * t0; w[3 * s + 1] = ph * t1; w[3 * s + 2] = ph * t2;
     }
+}
+
+template <typename T>
+DEV void link_adj_mul(const C<T> u[6], T co, T si, const C<T> h[6], C<T> w[6]) {
+    C<T> r2[3];
+    third_row(u, r2);
+    link_adj_mul_r2(u, r2, co, si, h, w);
 }
 
 // out = B in for a packed Hermitian 6x6 block: pk[0..5] diagonal, then (re, im) of the

@@ -22,33 +22,20 @@ namespace {
 // index of its (x0, x1, x2) row), accumulated into acc.  With `tile` the time-direction neighbour
 // comes from LDS: slot `tslot` - 1 / + 1 of the tile holds the input block of the previous / next
 // time slice at the same spatial block, and the neighbour sits at the same lane.
-// Links, phases and clover block of one 64-site block staged in LDS (the right-hand-side blocked
-// kernel): the same planes as in HBM, [direction][plane][64 sites] and [plane][64 sites].
+// What the right-hand-side blocked kernel stages in LDS for one 64-site block: per direction n
+// and site, the link's two stored rows, its third row and its phase (cos, sin) in the
+// accumulation precision ([n][20][64]: u[0..5], r2[0..2] as (re, im), then cos, sin), the
+// neighbour's index ([n][64]), and the clover block in its HBM planes ([plane][64]).
 template <typename S>
 struct LdsBlock {
-    const typename Lk<S>::vec *lk;
-    const typename Lk<S>::om *om;
+    const typename St<S>::acc *lk;
+    const uint32_t *nb;
     const typename St<S>::vec *cl;
 };
 
-template <typename S>
-DEV void load_link_lds(const LdsBlock<S> &L, int dir, int lane, C<typename St<S>::acc> u[6],
-                       typename St<S>::acc &co, typename St<S>::acc &si) {
-    using T = typename St<S>::acc;
-    constexpr int W = Lk<S>::W;
-    T r[12];
-#pragma unroll
-    for (int k = 0; k < 12 / W; ++k) Lk<S>::unpack(L.lk[(dir * (12 / W) + k) * kSB + lane], r + k * W);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) u[k] = mk(r[2 * k], r[2 * k + 1]);
-    const typename Lk<S>::om w = L.om[dir * kSB + lane];
-    if constexpr (Lk<S>::phase_pair) Lk<S>::phase(w, co, si);
-    else sc((T)w, si, co);
-}
-
-template <typename S, int DAG, bool NT, bool LDSF = false>
+template <typename S, int DAG, bool NT>
 DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n, C<typename St<S>::acc> acc[12],
-                 const typename St<S>::vec *tile, int tslot, const LdsBlock<S> *lds = nullptr) {
+                 const typename St<S>::vec *tile, int tslot) {
     using T = typename St<S>::acc;
     const int mu = n >> 1, back = n & 1;
     C<T> psi[12], u[6];
@@ -56,8 +43,7 @@ DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n
     if (tile && mu == 0) load_spinor<S>(tile + (size_t)(tslot + (back ? -1 : 1)) * (24 / St<S>::W) * kSB,
                                         i & (kSB - 1), psi);
     else load_spinor<S>(a.in, neighbour(a, x, row, n), psi);
-    if constexpr (LDSF) load_link_lds<S>(*lds, n, (int)(i & (kSB - 1)), u, co, si);
-    else load_link<S, NT>(a, n, i, u, co, si);
+    load_link<S, NT>(a, n, i, u, co, si);
     accumulate_dir<T, DAG>(n, psi, u, co, si, acc);
 }
 
@@ -67,38 +53,29 @@ DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n
 // NPI = 1 keeps one neighbour's data live at a time; NPI = 2 takes the forward and backward
 // neighbour of one mu per iteration, so each wave has twice the loads in flight.  The sums are
 // accumulated in the same order either way.
-template <typename S, int DAG, int NPI, bool NT, bool LDSF = false>
+template <typename S, int DAG, int NPI, bool NT>
 DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<S>::acc> acc[12],
-                 const typename St<S>::vec *tile = nullptr, int tslot = 0, const LdsBlock<S> *lds = nullptr) {
+                 const typename St<S>::vec *tile = nullptr, int tslot = 0) {
     const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
     if constexpr (NPI == 1) {
 #pragma nounroll
-        for (int n = 0; n < 8; ++n) hop_dir<S, DAG, NT, LDSF>(a, x, row, i, n, acc, tile, tslot, lds);
+        for (int n = 0; n < 8; ++n) hop_dir<S, DAG, NT>(a, x, row, i, n, acc, tile, tslot);
     } else {
 #pragma nounroll
         for (int mu = 0; mu < 4; ++mu) {
-            hop_dir<S, DAG, NT, LDSF>(a, x, row, i, 2 * mu, acc, tile, tslot, lds);
-            hop_dir<S, DAG, NT, LDSF>(a, x, row, i, 2 * mu + 1, acc, tile, tslot, lds);
+            hop_dir<S, DAG, NT>(a, x, row, i, 2 * mu, acc, tile, tslot);
+            hop_dir<S, DAG, NT>(a, x, row, i, 2 * mu + 1, acc, tile, tslot);
         }
     }
 }
 
-// Everything of one output site after the work assignment: the 8 neighbours, the scale, the
-// clover epilogue / prologue and the store.  Every kernel below (the launch shapes) runs this
-// same code per site, so all shapes give bitwise identical results; the tuner only picks the
-// fastest.  NT: links, clover field, chi and the output, each touched once, carry a streaming
-// hint.
-template <typename S, int DAG, int MODE, int NPI = 1, bool NT = false, bool LDSF = false>
-DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, int tslot,
-                  const LdsBlock<S> *lds = nullptr) {
+// The scale, the clover epilogue / prologue and the store of output site i, from its hopping sum
+// acc.  NT: the clover field, chi and the output, each touched once, carry a streaming hint.
+// LDSF: the clover block comes from the LDS copy of the right-hand-side blocked kernel.
+template <typename S, int MODE, bool NT, bool LDSF = false>
+DEV void hop_finish(const HopArgs<S> &a, uint32_t i, const C<typename St<S>::acc> acc[12],
+                    const LdsBlock<S> *lds = nullptr) {
     using T = typename St<S>::acc;
-    const uint32_t i = (uint32_t)ii;
-    int x[4];
-    site_coords(a.g, ii, a.p, x);
-    C<T> acc[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = mk(T(0), T(0));
-    hop_all<S, DAG, NPI, NT, LDSF>(a, x, i, acc, tile, tslot, lds);
     C<T> y[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) y[k] = a.coef * acc[k];
@@ -153,6 +130,23 @@ DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, 
 #pragma unroll
     for (int k = 0; k < 12; ++k) { r[2 * k] = y[k].r; r[2 * k + 1] = y[k].i; }
     store_field_h<S, 24, NT>(a.out, i, r);
+}
+
+// Everything of one output site after the work assignment: the 8 neighbours, then hop_finish.
+// Every kernel below (the launch shapes) runs this same arithmetic per site, so all shapes give
+// bitwise identical results; the tuner only picks the fastest.  NT: the links also carry the
+// streaming hint.
+template <typename S, int DAG, int MODE, int NPI = 1, bool NT = false>
+DEV void hop_site(const HopArgs<S> &a, int ii, const typename St<S>::vec *tile, int tslot) {
+    using T = typename St<S>::acc;
+    const uint32_t i = (uint32_t)ii;
+    int x[4];
+    site_coords(a.g, ii, a.p, x);
+    C<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = mk(T(0), T(0));
+    hop_all<S, DAG, NPI, NT>(a, x, i, acc, tile, tslot);
+    hop_finish<S, MODE, NT>(a, i, acc);
 }
 
 template <typename S, int DAG, int MODE, int BS>
@@ -319,44 +313,64 @@ __global__ __launch_bounds__(BS) void k_hop_mr(HopArgs<S> a, int nlog) {
 }
 
 // Right-hand-side blocked kernel: a work-group of NW wavefronts takes one 64-site block and all
-// right-hand sides.  It stages the block's links (8 directions), phases and clover block in LDS
-// once, and wavefront w then computes right-hand sides w, w + NW, ... of the block from there, so
-// every link and clover entry is read from HBM once per site whatever the number of right-hand
-// sides, and no right-hand side's work-group on another XCD fetches them again.  Each site's sums
-// are those of hop_site with the same values, so the results equal the one-RHS kernel's bit for
-// bit.  Work-group b takes block b (dispatch order: consecutive blocks on consecutive XCDs, so
-// the neighbours one and eight blocks away in x2 and x1, and the time neighbours, come from the
-// blocks in flight beside it) or, with XCD, the XCD-contiguous order.  The stores of the output
-// and the loads of chi carry a streaming hint (NT): each is touched once.
+// right-hand sides.  First the work-group prepares, once for the block, everything of a site that
+// does not depend on the right-hand side: per direction the link's stored rows with its third row
+// rebuilt, the phase's cos and sin, and the neighbour's index (LdsBlock), and it copies the
+// clover block.  Wavefront w then computes right-hand sides w, w + NW, ... of the block from LDS:
+// per right-hand side only the neighbour spinors come from memory and only the projections, link
+// products and reconstruction are computed.  So every link and clover entry is read from HBM
+// once per site whatever the number of right-hand sides, and the third rows, phases and indices
+// are computed once instead of once per right-hand side.  The rebuilt rows and phases are the
+// values the one-RHS kernel computes with the same code, and each site's sums run in the same
+// order, so the results equal the one-RHS kernel's bit for bit.  Work-group b takes block b
+// (dispatch order: consecutive blocks on consecutive XCDs, and blocks 8 and 256 apart, the x1
+// and time neighbours at 32^3 x 64, on the same XCD) or, with XCD, the XCD-contiguous order.
+// The stores of the output and the loads of chi carry a streaming hint: each is touched once.
 template <typename S, int DAG, int MODE, int NW, bool XCD>
 __global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
-    using LV = typename Lk<S>::vec;
-    using OM = typename Lk<S>::om;
+    using T = typename St<S>::acc;
     using V = typename St<S>::vec;
-    constexpr int LP = 12 / Lk<S>::W;  // link planes per direction
     constexpr int CP = 72 / St<S>::W;  // clover planes
-    __shared__ LV s_lk[8 * LP * kSB];
-    __shared__ OM s_om[8 * kSB];
+    constexpr int NL = 20;             // reals per link in LDS: u[0..5], r2[0..2], cos, sin
+    __shared__ T s_lk[8 * NL * kSB];
+    __shared__ uint32_t s_nb[8 * kSB];
     __shared__ V s_cl[MODE != HOP_PLAIN ? CP * kSB : 1];
     const int blk = XCD ? xcd_block(a.nb8) : (int)blockIdx.x;
     const int nblk = (a.g.vh + kSB - 1) / kSB;
     if (blk >= nblk) return;  // uniform over the work-group
-    const size_t vhp = (size_t)a.g.vhp;
     const int t = (int)threadIdx.x;
-    for (int k = t; k < 8 * LP * kSB; k += 64 * NW) {
-        const int dir = k / (LP * kSB), rem = k - dir * (LP * kSB);
-        s_lk[k] = ld_stream(a.links + (size_t)dir * LP * vhp + (size_t)blk * LP * kSB + rem);
-    }
     for (int k = t; k < 8 * kSB; k += 64 * NW) {
-        const int dir = k / kSB, lane = k - dir * kSB;
-        s_om[k] = ld_stream(a.omega + (size_t)dir * vhp + (size_t)blk * kSB + lane);
+        const int n = k / kSB, lane = k - n * kSB;
+        const int ii = blk * kSB + lane;
+        if (ii >= a.g.vh) continue;  // padding sites: never read below
+        int x[4];
+        site_coords(a.g, ii, a.p, x);
+        const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
+        s_nb[k] = neighbour(a, x, row, n);
+        C<T> u[6], r2[3];
+        T co, si;
+        load_link<S, true>(a, n, (uint32_t)ii, u, co, si);
+        third_row(u, r2);
+        T *d = s_lk + (size_t)n * NL * kSB + lane;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            d[(2 * q) * kSB] = u[q].r;
+            d[(2 * q + 1) * kSB] = u[q].i;
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            d[(12 + 2 * q) * kSB] = r2[q].r;
+            d[(13 + 2 * q) * kSB] = r2[q].i;
+        }
+        d[18 * kSB] = co;
+        d[19 * kSB] = si;
     }
     if constexpr (MODE != HOP_PLAIN) {
         for (int k = t; k < CP * kSB; k += 64 * NW) s_cl[k] = ld_stream(a.clov + (size_t)blk * CP * kSB + k);
     }
     __syncthreads();
-    const LdsBlock<S> L{s_lk, s_om, s_cl};
-    const int w = t >> 6, ii = blk * kSB + (t & (kSB - 1));
+    const LdsBlock<S> L{s_lk, s_nb, s_cl};
+    const int w = t >> 6, lane = t & (kSB - 1), ii = blk * kSB + lane;
     if (ii >= a.g.vh) return;  // no barrier follows
 #pragma nounroll
     for (int r = w; r < a.nrhs; r += NW) {
@@ -365,7 +379,21 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
         b.in += r * a.vs;
         b.out += r * a.vs;
         if (b.chi) b.chi += r * a.vs;
-        hop_site<S, DAG, MODE, 1, true, true>(b, ii, nullptr, 0, &L);
+        C<T> acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = mk(T(0), T(0));
+#pragma nounroll
+        for (int n = 0; n < 8; ++n) {
+            C<T> psi[12], u[6], r2[3];
+            load_spinor<S>(b.in, L.nb[n * kSB + lane], psi);
+            const T *q = L.lk + (size_t)n * NL * kSB + lane;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) u[k] = mk(q[(2 * k) * kSB], q[(2 * k + 1) * kSB]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) r2[k] = mk(q[(12 + 2 * k) * kSB], q[(13 + 2 * k) * kSB]);
+            accumulate_dir_r2<T, DAG>(n, psi, u, r2, q[18 * kSB], q[19 * kSB], acc);
+        }
+        hop_finish<S, MODE, true, true>(b, (uint32_t)ii, acc, &L);
     }
 }
 

@@ -79,8 +79,10 @@ DEV uint32_t neighbour(const HopArgs<S> &a, const int x[4], int row, int n) {
 
 // acc += the direction-n term for the neighbour spinor psi and the link (u, co, si): project to
 // a half-spinor, multiply by the link (or its adjoint), reconstruct.
+// r2: the link's third row, third_row(u), computed by the caller (once for several right-hand
+// sides); the sums are those of accumulate_dir below, which forms it itself.
 template <typename T, int DAG>
-DEV void accumulate_dir(int n, const C<T> psi[12], const C<T> u[6], T co, T si, C<T> acc[12]) {
+DEV void accumulate_dir_r2(int n, const C<T> psi[12], const C<T> u[6], const C<T> r2[3], T co, T si, C<T> acc[12]) {
     const int mu = n >> 1, back = n & 1;
     // projector sign: forward (1 + SF gamma), backward (1 - SF gamma); SF = -1 for D, +1 for D^dag
     const T sg = (DAG ? T(1) : T(-1)) * (back ? T(-1) : T(1));
@@ -96,8 +98,8 @@ DEV void accumulate_dir(int n, const C<T> psi[12], const C<T> u[6], T co, T si, 
         h[c] = mk(fma(sg, e0.r, psi[c].r), fma(sg, e0.i, psi[c].i));
         h[3 + c] = mk(fma(sg, e1.r, psi[3 + c].r), fma(sg, e1.i, psi[3 + c].i));
     }
-    if (back) link_adj_mul(u, co, si, h, w);
-    else link_mul(u, co, si, h, w);
+    if (back) link_adj_mul_r2(u, r2, co, si, h, w);
+    else link_mul_r2(u, r2, co, si, h, w);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         acc[c] = acc[c] + w[c];
@@ -108,6 +110,13 @@ DEV void accumulate_dir(int n, const C<T> psi[12], const C<T> u[6], T co, T si, 
         acc[6 + c] = mk(fma(sg, l0.r, acc[6 + c].r), fma(sg, l0.i, acc[6 + c].i));
         acc[9 + c] = mk(fma(sg, l1.r, acc[9 + c].r), fma(sg, l1.i, acc[9 + c].i));
     }
+}
+
+template <typename T, int DAG>
+DEV void accumulate_dir(int n, const C<T> psi[12], const C<T> u[6], T co, T si, C<T> acc[12]) {
+    C<T> r2[3];
+    third_row(u, r2);
+    accumulate_dir_r2<T, DAG>(n, psi, u, r2, co, si, acc);
 }
 
 
