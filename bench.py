@@ -330,7 +330,8 @@ def batched_suite():
             "sequential_mixed_f32_seconds": round(t_seq_mixed, 4),
             "speedup_vs_sequential_mixed_f32": round(t_seq_mixed / t_batched, 3), "worst_true_rel_res": worst,
             "max_rel_diff_vs_fp64": err, "fp64_total_iters": iters,
-            "inner_iters_per_lattice": [max(i.iters for i in row) for row in infos]}
+            "inner_iters_per_lattice": [max(i.iters for i in row) for row in infos],
+            "host_syncs": infos[0][0].host_syncs}
 
 
 PTC_TRAIN_DIMS = (32, 16, 16, 16)

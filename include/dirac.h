@@ -252,6 +252,7 @@ typedef struct {
     int fell_back;        /* 1 if MIXED_GCR finished in plain FP64 GCR */
     double true_rel_res;  /* ||eta - D psi|| / ||eta|| recomputed in FP64 at the end */
     double seconds;       /* wall time of the call */
+    int host_syncs;       /* times the call waited on the device for a value (norms, counts) */
 } dirac_solve_info;
 
 /* The solve the paper offloads through invertQuda(h_x, h_b, param) (Sec. 4.1), stopped, as in

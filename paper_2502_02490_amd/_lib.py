@@ -39,7 +39,8 @@ class SolverParams(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("outer", ctypes.c_int),
-                ("fell_back", ctypes.c_int), ("true_rel_res", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("fell_back", ctypes.c_int), ("true_rel_res", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("host_syncs", ctypes.c_int)]
 
 
 class DiracError(RuntimeError):

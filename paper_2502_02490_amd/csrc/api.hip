@@ -450,6 +450,7 @@ dirac_status dirac_solve(dirac_ctx *c, void *x, const void *b, dirac_layout lay,
     const dirac_prec inner = p->method == DIRAC_SOLVER_MIXED_GCR ? (dirac_prec)p->inner_prec : DIRAC_F64;
     dl::ensure_work(c, p->method == DIRAC_SOLVER_CGLS ? 1 : p->restart, inner, 1);
     void *bn = dl::solver_full64(c, 0), *xn = dl::solver_full64(c, 1);
+    c->work->syncs = 0;
     if (lay == DIRAC_LAYOUT_NATIVE) {
         HIP_CHECK(hipMemcpyAsync(bn, b, nb, hipMemcpyDeviceToDevice, s));
         if (p->x0_given) HIP_CHECK(hipMemcpyAsync(xn, x, nb, hipMemcpyDeviceToDevice, s));
@@ -464,6 +465,7 @@ dirac_status dirac_solve(dirac_ctx *c, void *x, const void *b, dirac_layout lay,
     else
         dl::spinor_export(c, x, xn, 0, DIRAC_F64, lay, s);
     HIP_CHECK(hipStreamSynchronize(s));
+    info->host_syncs = (int)(c->work->syncs + 1);
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (st != DIRAC_OK) {
         char msg[160];

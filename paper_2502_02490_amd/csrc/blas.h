@@ -39,9 +39,11 @@ struct Blas {
     // q /= gamma; r -= alpha q; pnext = r; out = scale |r|^2
     void gcr_update(dirac_prec pr, int nh, const double *sc, void *q, void *r, void *pnext, double *out_dev,
                     double scale, hipStream_t s, const BatchSpec &bs = BatchSpec());
-    // x += xscale sum_j coef_j P_j (xscale_r = xscales[r * sstride] when given)
+    // x += xscale sum_j coef_j P_j, j < k (xscale_r = xscales[r * sstride] when given; system r sums
+    // only j < kcount[r] when kcount is given)
     void axpy_multi(dirac_prec px, dirac_prec pp, int nh, void *x, const void *P, int k, const double *coef_dev,
-                    double xscale, hipStream_t s, const BatchSpec &bs = BatchSpec(), const double *xscales = nullptr);
+                    double xscale, hipStream_t s, const BatchSpec &bs = BatchSpec(), const double *xscales = nullptr,
+                    const int *kcount = nullptr);
     // out = alpha a + beta b; copy2 = out; out_dev = scale {|out|^2, nonfinite flag}
     void lincomb(dirac_prec po, dirac_prec pa, dirac_prec pb, int nh, void *out, void *copy2, double alpha,
                  const void *a, double beta, const void *b, double *out_dev, double scale, hipStream_t s,
@@ -63,6 +65,7 @@ struct SolverWork {
     DevBuf f64[3];          // FP64 full vectors: b, x, r
     int m = 0;
     dirac_prec pr = DIRAC_F64;
+    long syncs = 0;  // host waits on the device (value reads) since the current solve began
 };
 
 }  // namespace dl

@@ -232,16 +232,18 @@ __global__ __launch_bounds__(kRed) void k_gcr_update(Bat B, const double *sc, ty
 template <typename SX, typename SP>
 __global__ __launch_bounds__(kRed) void k_axpy_multi(Bat B, typename St<SX>::vec *x, const typename St<SP>::vec *P,
                                                      int k, const double *coef, double xscale,
-                                                     const double *xscales) {
+                                                     const double *xscales, const int *kcount) {
     int r, t;
     if (!sys_of(B, r, t) || t >= B.n) return;
     x += r * vstride<SX>(B);
     const size_t vp = vstride<SP>(B);
     const double2 *cf = reinterpret_cast<const double2 *>(coef + (size_t)r * B.sstride);
     const double xs = xscales ? xscales[(size_t)r * B.sstride] : xscale;
+    // a system's own count of basis vectors: those past it were not written in this cycle
+    const int kr = kcount ? min(k, kcount[r]) : k;
     double a[24], b[24];
     ld<SX>(x, t, B.vh, a);
-    for (int j = 0; j < k; ++j) {
+    for (int j = 0; j < kr; ++j) {
         const double2 cj = cf[j];
         ld_basis<SP>(P + ((size_t)j * B.nrhs + r) * vp, t, B.vh, b);
 #pragma unroll
@@ -449,12 +451,12 @@ void Blas::gcr_update(dirac_prec pr, int nh, const double *sc, void *q, void *r,
 }
 
 void Blas::axpy_multi(dirac_prec px, dirac_prec pp, int nh, void *x, const void *P, int k, const double *coef_dev,
-                      double xscale, hipStream_t s, const BatchSpec &bs, const double *xscales) {
+                      double xscale, hipStream_t s, const BatchSpec &bs, const double *xscales, const int *kcount) {
     const Bat b = make_bat(c, nh, bs);
 #define FN2(SX, SP)                                                                                              \
     k_axpy_multi<SX, SP><<<b.nb * b.nrhs, kRed, 0, s>>>(b, (typename St<SX>::vec *)x,                             \
                                                         (const typename St<SP>::vec *)P, k, coef_dev, xscale,     \
-                                                        xscales);
+                                                        xscales, kcount);
 #define FN(SP)                                                                                     \
     if (px == DIRAC_F64) { FN2(double, SP) } else if (px == DIRAC_F32) { FN2(float, SP) }          \
     else if (px == DIRAC_F16) { FN2(__half, SP) } else { FN2(__hip_bfloat16, SP) }

@@ -43,6 +43,7 @@ double read_scalar(SolverWork &w, int slot, hipStream_t s) {
     double h = 0.0;
     HIP_CHECK(hipMemcpyAsync(&h, sc_ptr(w, slot), sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
+    ++w.syncs;
     return h;
 }
 
@@ -147,6 +148,7 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
             HIP_CHECK(hipMemcpyAsync(beta.data() + 2 * m * k, sc_ptr(w, S_BETA + 2 * kMaxRestart * k),
                                      2 * k * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
+        ++w.syncs;
         for (int j = n - 1; j >= 0; --j) {
             std::complex<double> acc(alp[2 * j], alp[2 * j + 1]);
             for (int k = j + 1; k < n; ++k)

@@ -46,6 +46,13 @@ def test_batched_fp64_matches_oracle(lattices):
             exact, _ = osolvers.solve_eo(c.f, b[r], 1e-13)
             assert rel(xg[r], exact) < 1e-9, (c.dims, r)
         assert all(i.true_rel_res < 1e-12 for i in inf)
+    # convergence is decided on the device: the host waits for a value once per 4 iterations of a
+    # cycle and once per cycle end, plus a few set-up and final reads per lattice
+    iters = max(i.iters for row in infos for i in row)
+    cycles = max(i.restarts for row in infos for i in row) + 1
+    syncs = infos[0][0].host_syncs
+    flush(f"[gpu] batched FP64: {iters} iterations, {cycles} cycles, {syncs} host waits")
+    assert syncs <= iters // 4 + 2 * cycles + 3 * len(lattices) + 4, (syncs, iters)
 
 
 def test_batched_mixed_f32_matches_single(lattices):
