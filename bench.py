@@ -43,11 +43,10 @@ HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persis
               "k_hop_ps bs128 2/CU (XCD slab sweep)", "k_hop_p bs256 2/CU 2 neighbours/iteration (persistent)",
               "k_hop_mr 2 RHS/work-item 1/CU streaming hints", "k_hop_mr 4 RHS/work-item 1/CU streaming hints",
               "k_hop_mr 2 RHS/work-item 2/CU streaming hints",
-              "k_hop_rb 4 waves (right-hand sides blocked, links and clover in LDS)",
-              "k_hop_rb 8 waves (right-hand sides blocked, links and clover in LDS)",
-              "k_hop_rb 12 waves (right-hand sides blocked, links and clover in LDS)",
-              "k_hop_rb 4 waves xcd-order (right-hand sides blocked, links and clover in LDS)",
-              "k_hop_rb 8 waves xcd-order (right-hand sides blocked, links and clover in LDS)"]
+              "k_hop_rb 4 waves (right-hand sides blocked, link work and clover in LDS)",
+              "k_hop_rb 8 waves (right-hand sides blocked, link work and clover in LDS)",
+              "k_hop_rb 4 waves, next-direction prefetch", "k_hop_rb 8 waves, next-direction prefetch",
+              "k_hop_rb 12 waves, next-direction prefetch"]
 
 # The FP64 hop + A chi kernel of each launch shape, as rocprofv3 names it, and its grid in
 # work-items on 32^3 x 64 (V/2 = 1,048,576 output sites, 256 compute units): the key of its row in
@@ -335,9 +334,6 @@ def batched_suite():
 
 
 PTC_TRAIN_DIMS = (32, 16, 16, 16)
-# spin contractions of the (1, 8, 8, 1) network per site: 9 paths x c_in x c_out x 16 spin
-# entries x 3 colours complex multiply-adds (8 real flops each)
-PTC_FLOP_PER_SITE = 8 * 9 * 16 * 3 * (1 * 8 + 8 * 8 + 8 * 1)
 PTC_KAPPA = 0.1245
 # algorithmic bytes of one network application per site, layer by layer (each activation read
 # once and written once in FP32, links as 13 FP32 reals per direction): 1 -> 8: 96 + 768 + 416,
@@ -472,25 +468,39 @@ def ptc_kernels(reps: int):
            "backward_ms": round(t_b * 1e3, 3),
            "forward_algorithmic_GBps": round(PTC_BYTES_PER_SITE * V / t_f / 1e9, 1),
            "forward_frac_of_8TBps": round(PTC_BYTES_PER_SITE * V / t_f / 8e12, 3),
-           "forward_contraction_TFLOPs": round(PTC_FLOP_PER_SITE * V / t_f / 1e12, 1)}
+           "forward_contraction_TFLOPs": round(ptc_flop_per_site((1, 8, 8, 1)) * V / t_f / 1e12, 1)}
     D.close()
     net.close()
     return out
 
 
+# networks trained and deployed by the learned-preconditioner suite: the configured (1, 8, 8, 1)
+# and two thin ones, all on the same pairs; the suite reports each and selects the one with the
+# shortest measured time to solution
+PTC_NETWORKS = ((1, 8, 8, 1), (1, 4, 1), (1, 2, 2, 2, 1))
+PTC_TRAIN_BUDGET_S = {(1, 8, 8, 1): 40.0, (1, 4, 1): 15.0, (1, 2, 2, 2, 1): 20.0}
+
+
+def ptc_flop_per_site(channels) -> int:
+    """Spin contractions of a network per site: 9 paths x c_in x c_out x 16 spin entries x 3
+    colours complex multiply-adds (8 real flops each)."""
+    return 8 * 9 * 16 * 3 * sum(a * b for a, b in zip(channels[:-1], channels[1:]))
+
+
 def ptc_suite(pairs_per_field: int, epochs: int, checkpoint: str | None):
-    """Learned preconditioner: a (1, 8, 8, 1)-channel PTC network trained on pairs from four
-    16^3 x 32 fields (seeds 501..504, eps = 0.5, kappa = 0.1245, c_sw = 1.6, c_sw^QED = 1.0,
-    qhat = -1), then deployed in flexible GCR on a 32^3 x 64 field (seed 505) against plain
-    FP64 even-odd GCR(32), both to 1e-10.  Pair generation and training time are reported
-    apart from the solves."""
+    """Learned preconditioner: PTC networks (the configured (1, 8, 8, 1) and the thin (1, 4, 1) and
+    (1, 2, 2, 2, 1)) trained on the same pairs from four 16^3 x 32 fields (seeds 501..504,
+    eps = 0.5, kappa = 0.1245, c_sw = 1.6, c_sw^QED = 1.0, qhat = -1), then each deployed in
+    flexible GCR on a 32^3 x 64 field (seed 505) against plain FP64 even-odd GCR(32), all to 1e-10.
+    Pair generation and training time are reported apart from the solves; the network with the
+    shortest measured solve is the selected one."""
     import torch
 
     import gen
     import paper_2502_02490_amd as P
     from paper_2502_02490_amd import ptc_train as T
 
-    res = {"train_lattice": "x".join(map(str, PTC_TRAIN_DIMS)), "fields": 4, "channels": [1, 8, 8, 1]}
+    res = {"train_lattice": "x".join(map(str, PTC_TRAIN_DIMS)), "fields": 4}
     ops_pairs, held = [], []
     t0 = time.perf_counter()
     for j in range(4):
@@ -509,18 +519,22 @@ def ptc_suite(pairs_per_field: int, epochs: int, checkpoint: str | None):
     res["pairs"] = sum(len(rs) for _, rs, _ in ops_pairs)
     res["pair_kinds"] = "half truncated FP64 GCR solves (e = x* - x_k), half Gaussian e with r = D e"
     res["pair_generation_seconds"] = round(time.perf_counter() - t0, 2)
-    net = P.PTC((1, 8, 8, 1))
-    net.set_weights(T.init_weights((1, 8, 8, 1), seed=7))
-    res["held_out_loss_init"] = T.evaluate(held, net)
-    t1 = time.perf_counter()
-    hist = T.train(ops_pairs, net, epochs=epochs, batch=16, lr=2e-3, seed=11, lr_decay=0.8,
-                   log=lambda m: log("[ptc] " + m), time_budget=60.0)
-    res["training_seconds"] = round(time.perf_counter() - t1, 2)
-    res["train_loss_by_epoch"] = [round(h, 5) for h in hist]
-    res["held_out_loss"] = T.evaluate(held, net)
-    log(f"[ptc] held-out loss {res['held_out_loss_init']:.4f} -> {res['held_out_loss']:.4f}")
-    if checkpoint:
-        T.save_checkpoint(checkpoint, net, len(hist), 11, meta={"pairs": res["pairs"], "train": res["train_lattice"]})
+    nets, per = {}, {}
+    for ch in PTC_NETWORKS:
+        key = "-".join(map(str, ch))
+        net = P.PTC(ch)
+        net.set_weights(T.init_weights(ch, seed=7))
+        r = {"channels": list(ch), "held_out_loss_init": T.evaluate(held, net)}
+        t1 = time.perf_counter()
+        hist = T.train(ops_pairs, net, epochs=epochs, batch=16, lr=2e-3, seed=11, lr_decay=0.8,
+                       log=lambda m: log(f"[ptc {key}] " + m), time_budget=PTC_TRAIN_BUDGET_S[ch])
+        r["training_seconds"] = round(time.perf_counter() - t1, 2)
+        r["train_loss_by_epoch"] = [round(h, 5) for h in hist]
+        r["held_out_loss"] = T.evaluate(held, net)
+        log(f"[ptc {key}] held-out loss {r['held_out_loss_init']:.4f} -> {r['held_out_loss']:.4f}")
+        if checkpoint and ch == PTC_NETWORKS[0]:
+            T.save_checkpoint(checkpoint, net, len(hist), 11, meta={"pairs": res["pairs"], "train": res["train_lattice"]})
+        nets[key], per[key] = net, r
     for D, _, _ in ops_pairs:
         D.close()
     del ops_pairs, held
@@ -529,26 +543,38 @@ def ptc_suite(pairs_per_field: int, epochs: int, checkpoint: str | None):
     D = P.Dirac(torch.from_numpy(gen.su3_field(d, EPS, 505)).cuda(), torch.from_numpy(gen.u1_field(d, 0.3, 505)).cuda(),
                 d, PTC_KAPPA, CSW, CSW_QED, QHAT)
     b = torch.from_numpy(gen.gaussian_spinor(d, 505)).cuda()
-    # one network application on 32^3 x 64: the three layers on the matrix cores
     vin = D.to_native(b.to(torch.complex64), "f32", "lex")
     vout = torch.empty_like(vin)
     stream = torch.cuda.current_stream()
-    for _ in range(3):
-        net.forward(D, vout, vin)
-    t_fwd = timed(lambda: net.forward(D, vout, vin), 10, stream) / 10
-    flop = PTC_FLOP_PER_SITE * math.prod(d)
-    res["forward_32c64_ms"] = round(t_fwd * 1e3, 3)
-    res["forward_32c64_contraction_TFLOPs"] = round(flop / t_fwd / 1e12, 1)
-    log(f"[ptc] forward 32^3x64: {t_fwd * 1e3:.2f} ms, {flop / t_fwd / 1e12:.1f} TFLOP/s in the spin contractions")
+    for key, net in nets.items():
+        r = per[key]
+        # one network application on 32^3 x 64: the layers on the matrix cores
+        for _ in range(3):
+            net.forward(D, vout, vin)
+        t_fwd = timed(lambda: net.forward(D, vout, vin), 10, stream) / 10
+        flop = ptc_flop_per_site(net.channels) * math.prod(d)
+        r["forward_32c64_ms"] = round(t_fwd * 1e3, 3)
+        r["forward_32c64_contraction_TFLOPs"] = round(flop / t_fwd / 1e12, 1)
+        log(f"[ptc {key}] forward 32^3x64: {t_fwd * 1e3:.2f} ms, {flop / t_fwd / 1e12:.1f} TFLOP/s in the spin "
+            "contractions")
+        T.compare_solvers(D, net, b, tol=1e-10)  # warm-up (tuning, work buffers)
+        dep = T.compare_solvers(D, net, b, tol=1e-10, reps=2)
+        r["deploy_32c64"] = dep
+        for k in ("fgcr_ptc", "fgcr_ptc_eo"):
+            r[f"{k}_speedup_vs_eo_gcr"] = round(dep["eo_gcr"]["seconds"] / dep[k]["seconds"], 3)
+        log(f"[ptc {key}] deploy {dep}")
     del vin, vout
-    T.compare_solvers(D, net, b, tol=1e-10)  # warm-up (tuning, work buffers)
-    res["deploy_32c64"] = T.compare_solvers(D, net, b, tol=1e-10, reps=2)
-    log(f"[ptc] deploy {res['deploy_32c64']}")
-    dep = res["deploy_32c64"]
-    for k in ("fgcr_ptc", "fgcr_ptc_eo"):
-        res[f"{k}_speedup_vs_eo_gcr"] = round(dep["eo_gcr"]["seconds"] / dep[k]["seconds"], 3)
+    best = min(per, key=lambda k: per[k]["deploy_32c64"]["fgcr_ptc_eo"]["seconds"])
+    res["networks"] = per
+    res["selected"] = best
+    res["selected_fgcr_ptc_eo_seconds"] = per[best]["deploy_32c64"]["fgcr_ptc_eo"]["seconds"]
+    res["selected_fgcr_ptc_eo_iters"] = per[best]["deploy_32c64"]["fgcr_ptc_eo"]["iters"]
+    res["eo_gcr_seconds"] = per[best]["deploy_32c64"]["eo_gcr"]["seconds"]
+    res["eo_gcr_iters"] = per[best]["deploy_32c64"]["eo_gcr"]["iters"]
+    res["selected_speedup_vs_eo_gcr"] = per[best]["fgcr_ptc_eo_speedup_vs_eo_gcr"]
     D.close()
-    net.close()
+    for net in nets.values():
+        net.close()
     return res
 
 

@@ -315,18 +315,19 @@ __global__ __launch_bounds__(BS) void k_hop_mr(HopArgs<S> a, int nlog) {
 // Right-hand-side blocked kernel: a work-group of NW wavefronts takes one 64-site block and all
 // right-hand sides.  First the work-group prepares, once for the block, everything of a site that
 // does not depend on the right-hand side: per direction the link's stored rows with its third row
-// rebuilt, the phase's cos and sin, and the neighbour's index (LdsBlock), and it copies the
-// clover block.  Wavefront w then computes right-hand sides w, w + NW, ... of the block from LDS:
-// per right-hand side only the neighbour spinors come from memory and only the projections, link
-// products and reconstruction are computed.  So every link and clover entry is read from HBM
-// once per site whatever the number of right-hand sides, and the third rows, phases and indices
-// are computed once instead of once per right-hand side.  The rebuilt rows and phases are the
-// values the one-RHS kernel computes with the same code, and each site's sums run in the same
-// order, so the results equal the one-RHS kernel's bit for bit.  Work-group b takes block b
-// (dispatch order: consecutive blocks on consecutive XCDs, and blocks 8 and 256 apart, the x1
-// and time neighbours at 32^3 x 64, on the same XCD) or, with XCD, the XCD-contiguous order.
-// The stores of the output and the loads of chi carry a streaming hint: each is touched once.
-template <typename S, int DAG, int MODE, int NW, bool XCD>
+// rebuilt, the phase's cos and sin, and the neighbour's index (LdsBlock), and it copies the clover
+// block.  Wavefront w then computes right-hand sides w, w + NW, ... of the block from LDS: per
+// right-hand side only the neighbour spinors come from memory and only the projections, link
+// products and reconstruction are computed.  So every link and clover entry is read from HBM once
+// per site whatever the number of right-hand sides, and the third rows, phases and indices are
+// computed once instead of once per right-hand side.  The rebuilt rows and phases are the values
+// the one-RHS kernel computes with the same code, and each site's sums run in the same order, so
+// the results equal the one-RHS kernel's bit for bit.  Work-group b takes block b (dispatch
+// order: blocks 8 and 256 apart, the x1 and time neighbours at 32^3 x 64, run on the same XCD).
+// PF: the loop over the 8 directions is unrolled by two with the next direction's spinor loads
+// issued before the current direction's arithmetic.  The stores of the output and the loads of
+// chi carry a streaming hint.
+template <typename S, int DAG, int MODE, int NW, bool PF>
 __global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
     using T = typename St<S>::acc;
     using V = typename St<S>::vec;
@@ -335,13 +336,11 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
     __shared__ T s_lk[8 * NL * kSB];
     __shared__ uint32_t s_nb[8 * kSB];
     __shared__ V s_cl[MODE != HOP_PLAIN ? CP * kSB : 1];
-    const int blk = XCD ? xcd_block(a.nb8) : (int)blockIdx.x;
-    const int nblk = (a.g.vh + kSB - 1) / kSB;
-    if (blk >= nblk) return;  // uniform over the work-group
+    const int blk = (int)blockIdx.x;
     const int t = (int)threadIdx.x;
     for (int k = t; k < 8 * kSB; k += 64 * NW) {
-        const int n = k / kSB, lane = k - n * kSB;
-        const int ii = blk * kSB + lane;
+        const int n = k / kSB, ln = k - n * kSB;
+        const int ii = blk * kSB + ln;
         if (ii >= a.g.vh) continue;  // padding sites: never read below
         int x[4];
         site_coords(a.g, ii, a.p, x);
@@ -351,7 +350,7 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
         T co, si;
         load_link<S, true>(a, n, (uint32_t)ii, u, co, si);
         third_row(u, r2);
-        T *d = s_lk + (size_t)n * NL * kSB + lane;
+        T *d = s_lk + (size_t)n * NL * kSB + ln;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             d[(2 * q) * kSB] = u[q].r;
@@ -372,6 +371,16 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
     const LdsBlock<S> L{s_lk, s_nb, s_cl};
     const int w = t >> 6, lane = t & (kSB - 1), ii = blk * kSB + lane;
     if (ii >= a.g.vh) return;  // no barrier follows
+    // direction n of the sum from the spinor psi already loaded
+    auto dir = [&](int n, const C<T> psi[12], C<T> acc[12]) {
+        C<T> u[6], r2[3];
+        const T *q = L.lk + (size_t)n * NL * kSB + lane;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) u[k] = mk(q[(2 * k) * kSB], q[(2 * k + 1) * kSB]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r2[k] = mk(q[(12 + 2 * k) * kSB], q[(13 + 2 * k) * kSB]);
+        accumulate_dir_r2<T, DAG>(n, psi, u, r2, q[18 * kSB], q[19 * kSB], acc);
+    };
 #pragma nounroll
     for (int r = w; r < a.nrhs; r += NW) {
         if (a.active && !a.active[r]) continue;
@@ -382,16 +391,23 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
         C<T> acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = mk(T(0), T(0));
+        if constexpr (PF) {
+            C<T> pa[12], pb[12];
+            load_spinor<S>(b.in, L.nb[lane], pa);
 #pragma nounroll
-        for (int n = 0; n < 8; ++n) {
-            C<T> psi[12], u[6], r2[3];
-            load_spinor<S>(b.in, L.nb[n * kSB + lane], psi);
-            const T *q = L.lk + (size_t)n * NL * kSB + lane;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) u[k] = mk(q[(2 * k) * kSB], q[(2 * k + 1) * kSB]);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) r2[k] = mk(q[(12 + 2 * k) * kSB], q[(13 + 2 * k) * kSB]);
-            accumulate_dir_r2<T, DAG>(n, psi, u, r2, q[18 * kSB], q[19 * kSB], acc);
+            for (int n = 0; n < 8; n += 2) {
+                load_spinor<S>(b.in, L.nb[(n + 1) * kSB + lane], pb);
+                dir(n, pa, acc);
+                if (n + 2 < 8) load_spinor<S>(b.in, L.nb[(n + 2) * kSB + lane], pa);
+                dir(n + 1, pb, acc);
+            }
+        } else {
+#pragma nounroll
+            for (int n = 0; n < 8; ++n) {
+                C<T> psi[12];
+                load_spinor<S>(b.in, L.nb[n * kSB + lane], psi);
+                dir(n, psi, acc);
+            }
         }
         hop_finish<S, MODE, true, true>(b, (uint32_t)ii, acc, &L);
     }
@@ -499,7 +515,7 @@ __global__ __launch_bounds__(64 * TT) void k_hop_tp(HopArgs<S> a, int nwg) {
 }
 
 struct HopShape {
-    int bs, xcd, tt, pers, slab, npi, nt, mr, rb;
+    int bs, xcd, tt, pers, slab, npi, nt, mr, rb, pf;
 };
 // Shape 0 is the default (used when tuning is off, and inside a graph capture before the key
 // was tuned): the persistent sweep, one 256-wide work-group per compute unit, two neighbours per
@@ -507,16 +523,17 @@ struct HopShape {
 // persistent grid of pers work-groups per compute unit (xcd: each XCD sweeps its own eighth);
 // slab: the XCD slab sweep; npi: neighbours per loop iteration; nt: streaming hints; mr: right-hand
 // sides per work-item (the links and clover block read once for all of them); rb: the right-hand-
-// side blocked kernel with rb wavefronts per work-group (links and clover block staged in LDS).
+// side blocked kernel with rb wavefronts per work-group (link work and clover block in LDS), pf:
+// its next-direction prefetch.
 const HopShape kShapes[] = {
     {256, 0, 0, 1, 0, 2, 1, 1}, {256, 0, 0, 1, 0, 1, 1, 1}, {256, 0, 0, 2, 0, 1, 1, 1}, {256, 0, 0, 1, 0, 1, 0, 1},
     {256, 0, 0, 1, 0, 2, 0, 1}, {256, 1, 0, 0, 0, 1, 0, 1}, {256, 0, 0, 0, 0, 1, 0, 1}, {128, 1, 0, 0, 0, 1, 0, 1},
     {64, 1, 0, 0, 0, 1, 0, 1},  {256, 1, 4, 0, 0, 1, 0, 1}, {512, 1, 8, 0, 0, 1, 0, 1}, {512, 0, 0, 1, 0, 1, 0, 1},
     {256, 0, 0, 2, 0, 1, 0, 1}, {256, 1, 0, 1, 0, 1, 0, 1}, {256, 0, 4, 1, 0, 1, 0, 1}, {512, 0, 8, 1, 0, 1, 0, 1},
     {256, 0, 0, 1, 1, 1, 0, 1}, {256, 0, 0, 2, 1, 1, 0, 1}, {128, 0, 0, 2, 1, 1, 0, 1}, {256, 0, 0, 2, 0, 2, 0, 1},
-    {256, 0, 0, 1, 0, 1, 1, 2}, {256, 0, 0, 1, 0, 1, 1, 4}, {256, 0, 0, 2, 0, 1, 1, 2}, {256, 0, 0, 0, 0, 1, 1, 1, 4},
-    {512, 0, 0, 0, 0, 1, 1, 1, 8}, {768, 0, 0, 0, 0, 1, 1, 1, 12}, {256, 1, 0, 0, 0, 1, 1, 1, 4},
-    {512, 1, 0, 0, 0, 1, 1, 1, 8}};
+    {256, 0, 0, 1, 0, 1, 1, 2}, {256, 0, 0, 1, 0, 1, 1, 4}, {256, 0, 0, 2, 0, 1, 1, 2},
+    {256, 0, 0, 0, 0, 1, 1, 1, 4, 0}, {512, 0, 0, 0, 0, 1, 1, 1, 8, 0}, {256, 0, 0, 0, 0, 1, 1, 1, 4, 1},
+    {512, 0, 0, 0, 0, 1, 1, 1, 8, 1}, {768, 0, 0, 0, 0, 1, 1, 1, 12, 1}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 template <typename S> constexpr int num_shapes() { return kNumShapes; }
 
@@ -597,20 +614,19 @@ void launch_tiled(HopArgs<S> a, hipStream_t s) {
 }
 
 template <typename S, int DAG, int MODE, int NW>
-void launch_rb_nw(HopArgs<S> a, int xcd, hipStream_t s) {
-    const int nblk = (a.g.vh + kSB - 1) / kSB;
-    a.xcd = xcd;
-    a.nb8 = xcd ? (nblk + 7) & ~7 : nblk;
-    if (xcd) k_hop_rb<S, DAG, MODE, NW, true><<<a.nb8, 64 * NW, 0, s>>>(a);
+void launch_rb_nw(HopArgs<S> a, bool pf, hipStream_t s) {
+    a.xcd = 0;
+    a.nb8 = (a.g.vh + kSB - 1) / kSB;
+    if (pf) k_hop_rb<S, DAG, MODE, NW, true><<<a.nb8, 64 * NW, 0, s>>>(a);
     else k_hop_rb<S, DAG, MODE, NW, false><<<a.nb8, 64 * NW, 0, s>>>(a);
 }
 
 template <typename S, int DAG, int MODE>
-void launch_rb(const HopArgs<S> &a, int nw, int xcd, hipStream_t s) {
+void launch_rb(const HopArgs<S> &a, int nw, bool pf, hipStream_t s) {
     // FP64 needs about 176 registers per lane: at most two wavefronts per SIMD, 8 per work-group
-    if (nw == 4) launch_rb_nw<S, DAG, MODE, 4>(a, xcd, s);
-    else if (nw == 8 || std::is_same<S, double>::value) launch_rb_nw<S, DAG, MODE, 8>(a, xcd, s);
-    else if constexpr (!std::is_same<S, double>::value) launch_rb_nw<S, DAG, MODE, 12>(a, 0, s);
+    if (nw == 4) launch_rb_nw<S, DAG, MODE, 4>(a, pf, s);
+    else if (nw == 8 || std::is_same<S, double>::value) launch_rb_nw<S, DAG, MODE, 8>(a, pf, s);
+    else if constexpr (!std::is_same<S, double>::value) launch_rb_nw<S, DAG, MODE, 12>(a, pf, s);
 }
 
 template <typename S, int DAG, int MODE>
@@ -618,7 +634,7 @@ void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
     HopShape h = kShapes[shape];
     if ((h.tt && !tiled_ok(a.g, h.tt)) || (h.slab && !slab_ok(a.g, h.bs))) h = kShapes[0];  // does not fit
     if (h.rb) {
-        launch_rb<S, DAG, MODE>(a, h.rb, h.xcd, s);
+        launch_rb<S, DAG, MODE>(a, h.rb, h.pf != 0, s);
     } else if (h.mr > 1) {
         // two right-hand sides per work-item in FP64 (four would not fit the registers)
         if constexpr (std::is_same<S, double>::value) {

@@ -61,8 +61,6 @@ DEV void load_link(const HopArgs<S> &a, int dir, uint32_t i, C<typename St<S>::a
 //   e_0 = -1: (0, -1, -1)   e_1 = -i sigma_1: (1, -i, -i)
 //   e_2 = -i sigma_2: (1, -1, +1)   e_3 = -i sigma_3: (0, -i, +i)
 // so (e l)_k = c_k l_{p_k} and (e^dag w)_{p_k} = conj(c_k) w_k.
-template <typename T>
-DEV C<T> cmul_unit(T cr, T ci, C<T> z) { return mk(cr * z.r - ci * z.i, cr * z.i + ci * z.r); }
 
 // Index of the neighbour of site (x, row) in direction n = 2 mu + back, in the other parity.
 template <typename S>
@@ -79,36 +77,66 @@ DEV uint32_t neighbour(const HopArgs<S> &a, const int x[4], int row, int n) {
 
 // acc += the direction-n term for the neighbour spinor psi and the link (u, co, si): project to
 // a half-spinor, multiply by the link (or its adjoint), reconstruct.
-// r2: the link's third row, third_row(u), computed by the caller (once for several right-hand
-// sides); the sums are those of accumulate_dir below, which forms it itself.
-template <typename T, int DAG>
-DEV void accumulate_dir_r2(int n, const C<T> psi[12], const C<T> u[6], const C<T> r2[3], T co, T si, C<T> acc[12]) {
-    const int mu = n >> 1, back = n & 1;
-    // projector sign: forward (1 + SF gamma), backward (1 - SF gamma); SF = -1 for D, +1 for D^dag
-    const T sg = (DAG ? T(1) : T(-1)) * (back ? T(-1) : T(1));
-    const int sw = (mu == 1 || mu == 2);
-    const T c0r = (mu == 0 || mu == 2) ? T(-1) : T(0), c0i = (mu == 1 || mu == 3) ? T(-1) : T(0);
-    const T c1r = mu == 0 ? T(-1) : mu == 2 ? T(1) : T(0), c1i = mu == 1 ? T(-1) : mu == 3 ? T(1) : T(0);
+// z times a unit c = CR + i CI, c in {+-1, +-i}, as sign changes and swaps (exact).
+template <int CR, int CI, typename T>
+DEV C<T> unit_mul(C<T> z) {
+    if constexpr (CR == 1) return z;
+    else if constexpr (CR == -1) return mk(-z.r, -z.i);
+    else if constexpr (CI == 1) return mk(-z.i, z.r);
+    else return mk(z.i, -z.r);
+}
+// a + SG b with SG = +-1
+template <int SG, typename T>
+DEV C<T> add_signed(C<T> a, C<T> b) {
+    if constexpr (SG > 0) return a + b;
+    else return a - b;
+}
+
+// Direction N = 2 mu + back with its spin structure fixed at compile time: the projector sign
+// (forward 1 + SF gamma, backward 1 - SF gamma; SF = -1 for D, +1 for D^dag), the spin swap and
+// the units c_0, c_1 of e_mu become sign changes, swaps and additions.  r2: the link's third row,
+// third_row(u), computed by the caller (once for several right-hand sides).
+template <typename T, int DAG, int N>
+DEV void accumulate_dir_n(const C<T> psi[12], const C<T> u[6], const C<T> r2[3], T co, T si, C<T> acc[12]) {
+    constexpr int mu = N >> 1, back = N & 1;
+    constexpr int SG = (DAG ? 1 : -1) * (back ? -1 : 1);
+    constexpr bool SW = (mu == 1 || mu == 2);
+    constexpr int C0R = (mu == 0 || mu == 2) ? -1 : 0, C0I = (mu == 1 || mu == 3) ? -1 : 0;
+    constexpr int C1R = mu == 0 ? -1 : mu == 2 ? 1 : 0, C1I = mu == 1 ? -1 : mu == 3 ? 1 : 0;
     C<T> h[6], w[6];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const C<T> l0 = psi[6 + c], l1 = psi[9 + c];
-        const C<T> e0 = cmul_unit(c0r, c0i, sw ? l1 : l0);
-        const C<T> e1 = cmul_unit(c1r, c1i, sw ? l0 : l1);
-        h[c] = mk(fma(sg, e0.r, psi[c].r), fma(sg, e0.i, psi[c].i));
-        h[3 + c] = mk(fma(sg, e1.r, psi[3 + c].r), fma(sg, e1.i, psi[3 + c].i));
+        const C<T> e0 = unit_mul<C0R, C0I>(SW ? psi[9 + c] : psi[6 + c]);
+        const C<T> e1 = unit_mul<C1R, C1I>(SW ? psi[6 + c] : psi[9 + c]);
+        h[c] = add_signed<SG>(psi[c], e0);
+        h[3 + c] = add_signed<SG>(psi[3 + c], e1);
     }
-    if (back) link_adj_mul_r2(u, r2, co, si, h, w);
+    if constexpr (back) link_adj_mul_r2(u, r2, co, si, h, w);
     else link_mul_r2(u, r2, co, si, h, w);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         acc[c] = acc[c] + w[c];
         acc[3 + c] = acc[3 + c] + w[3 + c];
-        const C<T> t0 = cmul_unit(c0r, -c0i, w[c]);      // conj(c_0) w_0 -> lower spin p_0
-        const C<T> t1 = cmul_unit(c1r, -c1i, w[3 + c]);  // conj(c_1) w_1 -> lower spin p_1
-        const C<T> l0 = sw ? t1 : t0, l1 = sw ? t0 : t1;
-        acc[6 + c] = mk(fma(sg, l0.r, acc[6 + c].r), fma(sg, l0.i, acc[6 + c].i));
-        acc[9 + c] = mk(fma(sg, l1.r, acc[9 + c].r), fma(sg, l1.i, acc[9 + c].i));
+        const C<T> t0 = unit_mul<C0R, -C0I>(w[c]);      // conj(c_0) w_0 -> lower spin p_0
+        const C<T> t1 = unit_mul<C1R, -C1I>(w[3 + c]);  // conj(c_1) w_1 -> lower spin p_1
+        acc[6 + c] = add_signed<SG>(acc[6 + c], SW ? t1 : t0);
+        acc[9 + c] = add_signed<SG>(acc[9 + c], SW ? t0 : t1);
+    }
+}
+
+// acc += the direction-n term (n a run-time value, uniform over the wavefront): one of the eight
+// specialised bodies above.
+template <typename T, int DAG>
+DEV void accumulate_dir_r2(int n, const C<T> psi[12], const C<T> u[6], const C<T> r2[3], T co, T si, C<T> acc[12]) {
+    switch (n) {
+        case 0: accumulate_dir_n<T, DAG, 0>(psi, u, r2, co, si, acc); break;
+        case 1: accumulate_dir_n<T, DAG, 1>(psi, u, r2, co, si, acc); break;
+        case 2: accumulate_dir_n<T, DAG, 2>(psi, u, r2, co, si, acc); break;
+        case 3: accumulate_dir_n<T, DAG, 3>(psi, u, r2, co, si, acc); break;
+        case 4: accumulate_dir_n<T, DAG, 4>(psi, u, r2, co, si, acc); break;
+        case 5: accumulate_dir_n<T, DAG, 5>(psi, u, r2, co, si, acc); break;
+        case 6: accumulate_dir_n<T, DAG, 6>(psi, u, r2, co, si, acc); break;
+        default: accumulate_dir_n<T, DAG, 7>(psi, u, r2, co, si, acc); break;
     }
 }
 

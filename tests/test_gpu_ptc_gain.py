@@ -1,5 +1,5 @@
-"""What the trained network gains: a (1, 8, 8, 1) network trained briefly with the library's own
-kernels on pairs from two 16^3 x 32 fields (eps = 0.5, kappa = 0.1245, c_sw = 1.6, c_sw^QED = 1.0,
+"""What the trained network gains: a (1, 8, 8, 1) and a (1, 4, 1) network, each trained briefly with
+the library's own kernels on pairs from two 16^3 x 32 fields (eps = 0.5, kappa = 0.1245, c_sw = 1.6, c_sw^QED = 1.0,
 qhat = -1), then used as the preconditioner of flexible GCR on the Schur system of a third,
 held-out field, against plain even-odd GCR (the method without it) on the same field and source,
 both to 1e-10; the held-out loss falls during training."""
@@ -18,7 +18,8 @@ from paper_2502_02490_amd import ptc_train as T
 pytestmark = pytest.mark.gpu
 
 
-def test_trained_network_cuts_iterations_on_a_held_out_field():
+@pytest.mark.parametrize("channels", [(1, 8, 8, 1), (1, 4, 1)])
+def test_trained_network_cuts_iterations_on_a_held_out_field(channels):
     need_gpu()
     dims = (32, 16, 16, 16)
     train = []
@@ -33,9 +34,9 @@ def test_trained_network_cuts_iterations_on_a_held_out_field():
         held = Case(dims, kappa=0.1245, seed=503)
         hr, he = T.generate_pairs(held.D, 6, seed=10503)
         har, hae = T.generate_apply_pairs(held.D, 6, seed=10603)
-        net = P.PTC((1, 8, 8, 1))
+        net = P.PTC(channels)
         try:
-            net.set_weights(T.init_weights((1, 8, 8, 1), seed=7))
+            net.set_weights(T.init_weights(channels, seed=7))
             loss0 = T.evaluate([(held.D, hr + har, he + hae)], net)
             T.train([(c.D, rs, es) for c, rs, es in train], net, epochs=6, batch=16, lr=2e-3, seed=11, lr_decay=0.8)
             loss1 = T.evaluate([(held.D, hr + har, he + hae)], net)
@@ -51,7 +52,7 @@ def test_trained_network_cuts_iterations_on_a_held_out_field():
                   f"{res['fgcr_ptc']['iters']} it {res['fgcr_ptc']['seconds'] * 1e3:.1f} ms")
             assert not res["fgcr_ptc_eo"]["fell_back"]
             assert res["fgcr_ptc_eo"]["true_rel_res"] < 1e-10
-            assert res["fgcr_ptc_eo"]["iters"] < 0.8 * res["eo_gcr"]["iters"]
+            assert res["fgcr_ptc_eo"]["iters"] < (0.8 if len(channels) > 3 else 0.9) * res["eo_gcr"]["iters"]
             # the solution the network-preconditioned solve returns satisfies the oracle's operator
             x = torch.zeros_like(b)
             held.D.solve(x, b, method=P.FGCR_PTC_EO, ptc=net, tol=1e-10)
