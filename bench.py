@@ -177,9 +177,17 @@ def cpu_baseline(reps: int = 20):
             "single_thread_GBps": round(one, 4), "nproc": ncpu, "cpu_model": _cpu_model()}
 
 
+# restart of the inner GCR of the mixed solves, per inner precision: the inner solves stop at 1e-5
+# (FP32) or 1e-3 (FP16), where a short restart takes the same iterations for fewer orthogonalisation
+# bytes (32^3x64: FP32 0.045 s with GCR(8) against 0.057 s with GCR(32)); the BF16 inner solves stop
+# at 1e-2 within a few iterations, where the restart makes no difference
+MIXED_INNER_RESTART = {"f32": 8, "f16": 8, "bf16": 32}
+
+
 def solve_suite(D, b, inner_precs):
     """Time to |b - D x| / |b| < 1e-10: plain FP64 even-odd GCR(32), then FP64 defect correction
-    around FP32 / FP16 / BF16 inner GCR(32); each mixed solution is compared with the FP64 one."""
+    around FP32 / FP16 / BF16 inner GCR (restart MIXED_INNER_RESTART); each mixed solution is
+    compared with the FP64 one."""
     import torch
 
     import paper_2502_02490_amd as P
@@ -187,8 +195,9 @@ def solve_suite(D, b, inner_precs):
     res = {}
     # untimed loose solves first: the launch-shape tuner times its candidates on the first call
     # of each kernel at a new lattice size and precision, which must not land in the timings
-    for kw in (dict(method=P.GCR),) + tuple(dict(method=P.MIXED_GCR, inner_prec=pr) for pr in inner_precs):
-        D.solve(torch.zeros_like(b), b, tol=1e-4, restart=32, max_iter=100000, **kw)
+    for kw in (dict(method=P.GCR, restart=32),) + tuple(dict(method=P.MIXED_GCR, inner_prec=pr,
+                                                             restart=MIXED_INNER_RESTART[pr]) for pr in inner_precs):
+        D.solve(torch.zeros_like(b), b, tol=1e-4, max_iter=100000, **kw)
     x64 = torch.zeros_like(b)
     info = D.solve(x64, b, method=P.GCR, tol=1e-10, restart=32, max_iter=100000)
     res["fp64_gcr"] = {"seconds": round(info.seconds, 4), "iters": info.iters, "restarts": info.restarts,
@@ -196,8 +205,10 @@ def solve_suite(D, b, inner_precs):
     nx = torch.linalg.vector_norm(x64).item()
     for pr in inner_precs:
         x = torch.zeros_like(b)
-        info = D.solve(x, b, method=P.MIXED_GCR, inner_prec=pr, tol=1e-10, restart=32, max_iter=100000)
-        res[f"mixed_{pr}"] = {"seconds": round(info.seconds, 4), "inner_iters": info.iters, "outer": info.outer,
+        info = D.solve(x, b, method=P.MIXED_GCR, inner_prec=pr, tol=1e-10, restart=MIXED_INNER_RESTART[pr],
+                       max_iter=100000)
+        res[f"mixed_{pr}"] = {"seconds": round(info.seconds, 4), "inner_restart": MIXED_INNER_RESTART[pr],
+                              "inner_iters": info.iters, "outer": info.outer,
                               "fell_back": info.fell_back, "true_rel_res": info.true_rel_res,
                               "rel_err_vs_fp64": torch.linalg.vector_norm(x - x64).item() / nx,
                               "speedup_vs_fp64": round(res["fp64_gcr"]["seconds"] / info.seconds, 3)}
@@ -269,13 +280,16 @@ def sap_kernels(reps: int):
 
 
 BATCH_DIMS = [(8, 8, 8, 8), (12, 12, 12, 12)] + [(32, 16, 16, 16)] * 3 + [(48, 24, 24, 24)] * 3
+# restart of the batched inner FP32 GCR: the inner solves stop at 1e-5, where GCR(8) takes about the
+# iterations GCR(32) does at a quarter of the orthogonalisation bytes (measured 0.39 s against 0.54 s)
+BATCH_INNER_RESTART = 8
 
 
 def batched_suite():
     """12 spin-colour point sources (at the origin) on each of 8 lattices of uneven size, kappa_j =
     0.120 + 0.005 j / 7, eps = 0.5, c_sw = 1.6, c_sw^QED = 1.0, qhat = -1, seeds 401 + j; FP64
-    defect correction around batched FP32 GCR(32), to 1e-10; compared with the 96 plain FP64
-    even-odd GCR(32) solves done one after another on the same GPU."""
+    defect correction around batched FP32 GCR(8), to 1e-10; compared with the 96 plain FP64
+    even-odd GCR(32) solves and the 96 same mixed solves done one after another on the same GPU."""
     import numpy as np
     import torch
 
@@ -295,11 +309,13 @@ def batched_suite():
                 b[3 * s_ + a, 0, s_, a] = 1.0
         bs.append(b)
     xs = [torch.zeros_like(b) for b in bs]
-    P.solve_batched(ops, xs, bs, 12, method=P.MIXED_GCR, inner_prec="f32", tol=1e-10)  # tuning, graphs
+    P.solve_batched(ops, xs, bs, 12, method=P.MIXED_GCR, inner_prec="f32", tol=1e-10,
+                    restart=BATCH_INNER_RESTART)  # tuning, graphs
     xs = [torch.zeros_like(b) for b in bs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = P.solve_batched(ops, xs, bs, 12, method=P.MIXED_GCR, inner_prec="f32", tol=1e-10)
+    infos = P.solve_batched(ops, xs, bs, 12, method=P.MIXED_GCR, inner_prec="f32", tol=1e-10,
+                            restart=BATCH_INNER_RESTART)
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     t1 = time.perf_counter()
@@ -317,13 +333,13 @@ def batched_suite():
     for D, b in zip(ops, bs):
         for r in range(12):
             y = torch.zeros_like(b[r])
-            D.solve(y, b[r].contiguous(), method=P.MIXED_GCR, inner_prec="f32", tol=1e-10, restart=32)
+            D.solve(y, b[r].contiguous(), method=P.MIXED_GCR, inner_prec="f32", tol=1e-10, restart=BATCH_INNER_RESTART)
     torch.cuda.synchronize()
     t_seq_mixed = time.perf_counter() - t2
     worst = max(i.true_rel_res for row in infos for i in row)
     for D in ops:
         D.close()
-    return {"lattices": ["x".join(map(str, d)) for d in BATCH_DIMS], "nrhs": 12,
+    return {"lattices": ["x".join(map(str, d)) for d in BATCH_DIMS], "nrhs": 12, "inner_restart": BATCH_INNER_RESTART,
             "batched_mixed_f32_seconds": round(t_batched, 4), "sequential_fp64_gcr_seconds": round(t_seq, 4),
             "speedup_vs_sequential_fp64": round(t_seq / t_batched, 3),
             "sequential_mixed_f32_seconds": round(t_seq_mixed, 4),
@@ -388,6 +404,19 @@ def gcr_solves(n: int):
         out.append({"iters": info.iters, "seconds": round(info.seconds, 4), "true_rel_res": info.true_rel_res})
     D.close()
     return {"lattice": "x".join(map(str, DIMS)), "solves": out}
+
+
+def copy_calibration(n: int = 5):
+    """n plain device copies of exactly 768 MiB (read and written): a kernel of known size that
+    scales the FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    import torch
+
+    src = torch.ones(768 * 2**20 // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(n):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def apply_kernels(reps: int):
@@ -601,6 +630,9 @@ def main():
     ap.add_argument("--apply-kernels", action="store_true",
                     help="only time the Schur applies on 32^3x64 in FP64 / FP32 / FP16 / BF16 and the FP32 12-RHS apply "
                          "(one JSON line), for kernel traces and counter runs")
+    ap.add_argument("--batched-solves", action="store_true",
+                    help="only run the 8-lattice x 12 point-source batched solve suite (one JSON line), for a "
+                         "kernel trace of the batched iteration")
     ap.add_argument("--gcr-solves", action="store_true",
                     help="only run three plain FP64 even-odd GCR(32) solves on 32^3x64 (one JSON line), for a "
                          "kernel trace of the Krylov BLAS")
@@ -634,7 +666,16 @@ def main():
         import torch
 
         torch.cuda.set_device(0)
-        print(json.dumps({"apply_kernels": apply_kernels(max(1, args.steps))}), flush=True)
+        out = apply_kernels(max(1, args.steps))
+        if args.copy_calibration:
+            copy_calibration()
+        print(json.dumps({"apply_kernels": out}), flush=True)
+        return
+    if args.batched_solves:
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"batched_solves": batched_suite()}), flush=True)
         return
     if args.gcr_solves:
         import torch

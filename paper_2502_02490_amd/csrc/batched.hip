@@ -31,6 +31,8 @@ struct BWork {
     unsigned long long id = g_bwork_ids++;  // identifies this work space in graph keys
     hipStream_t s = nullptr;                // the lattice's stream (set-up and per-lattice steps)
     DevBuf P, Q, r, e, b, act, cyc, cnt;
+    DevBuf stage;                   // device staging of per-system values (contiguous)
+    unsigned char *pin = nullptr;   // pinned host staging (kPinBytes): every host <-> device value copy
     DevBuf h64[4];  // FP64 half vectors x nrhs: eta-hat, x_e, r, tmp
     DevBuf f64[3];  // FP64 full vectors x nrhs: b, x, r
     // batch-level state, used when this lattice leads a batch (is its first lattice)
@@ -61,7 +63,8 @@ struct BWork {
         if (fork) (void)hipEventDestroy(fork);
         for (auto e : ev) (void)hipEventDestroy(e);
         if (host_nact) (void)hipHostFree(host_nact);
-        for (DevBuf *d : {&P, &Q, &r, &e, &b, &act, &cyc, &cnt, &table, &nact}) d->release();
+        if (pin) (void)hipHostFree(pin);
+        for (DevBuf *d : {&P, &Q, &r, &e, &b, &act, &cyc, &cnt, &table, &nact, &stage}) d->release();
         for (auto &d : h64) d.release();
         for (auto &d : f64) d.release();
     }
@@ -157,6 +160,16 @@ __global__ void k_bat_backsub(int R, const int *cyc, const int *cnt, double *sca
     }
 }
 
+// dst[r] = src[r * stride] and back: per-system scalars to and from a contiguous staging array.
+__global__ void k_sys_gather(int n, const double *src, int stride, double *dst) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) dst[r] = src[(size_t)r * stride];
+}
+__global__ void k_sys_scatter(int n, const double *src, double *dst, int stride) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) dst[(size_t)r * stride] = src[r];
+}
+
 // out[l] = *src[l]: the active counts of all lattices into one array.
 __global__ void k_gather_counts(int n, const int *const *src, int *out) {
     const int l = threadIdx.x;
@@ -175,21 +188,42 @@ struct Lat {
     int *cnt() { return (int *)w->cnt.p; }
 };
 
+// Host <-> device values of a lattice go through its pinned staging memory: per-system scalars
+// (strided by kSysScal on the device) are gathered into / scattered from a contiguous device array
+// by a small kernel, so every copy is a plain 1-D copy between device and pinned memory.
+// Pinned layout: ints at [0, kPinInts), doubles after them.
+constexpr int kPinInts = 512, kPinDoubles = 256;
+constexpr size_t kPinBytes = kPinInts * sizeof(int) + kPinDoubles * sizeof(double);
+int *pin_ints(Lat &L) { return (int *)L.w->pin; }
+double *pin_doubles(Lat &L) { return (double *)(L.w->pin + kPinInts * sizeof(int)); }
+
+// queue: device per-system slot -> pinned doubles (no wait)
+void gather_sys(Lat &L, int slot, hipStream_t s) {
+    k_sys_gather<<<1, 64, 0, s>>>(L.nrhs, L.sp(slot), kSysScal, (double *)L.w->stage.p);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipMemcpyAsync(pin_doubles(L), L.w->stage.p, L.nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+}
+// queue: pinned doubles -> device per-system slot (the pinned values must stay until s has run it)
+void scatter_sys(Lat &L, int slot, hipStream_t s) {
+    HIP_CHECK(hipMemcpyAsync(L.w->stage.p, pin_doubles(L), L.nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+    k_sys_scatter<<<1, 64, 0, s>>>(L.nrhs, (const double *)L.w->stage.p, L.sp(slot), kSysScal);
+    HIP_CHECK(hipGetLastError());
+}
 // strided per-system scalars <-> host (on the lattice's stream, blocking)
 void read_sys(Lat &L, int slot, std::vector<double> &h, hipStream_t s) {
-    h.resize(L.nrhs);
-    HIP_CHECK(hipMemcpy2DAsync(h.data(), sizeof(double), L.sp(slot), kSysScal * sizeof(double), sizeof(double),
-                               L.nrhs, hipMemcpyDeviceToHost, s));
+    gather_sys(L, slot, s);
     HIP_CHECK(hipStreamSynchronize(s));
+    h.assign(pin_doubles(L), pin_doubles(L) + L.nrhs);
 }
 void write_sys(Lat &L, int slot, const std::vector<double> &h, hipStream_t s) {
-    HIP_CHECK(hipMemcpy2DAsync(L.sp(slot), kSysScal * sizeof(double), h.data(), sizeof(double), sizeof(double),
-                               L.nrhs, hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipStreamSynchronize(s));  // h may be a temporary
+    std::copy(h.begin(), h.begin() + L.nrhs, pin_doubles(L));
+    scatter_sys(L, slot, s);
+    HIP_CHECK(hipStreamSynchronize(s));  // the pinned values are reused by the next call
 }
-void upload_mask(const std::vector<int> &m, int *d, hipStream_t s) {
-    HIP_CHECK(hipMemcpyAsync(d, m.data(), m.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipStreamSynchronize(s));  // m may change right after
+void upload_mask(Lat &L, const std::vector<int> &m, int *d, hipStream_t s) {
+    std::copy(m.begin(), m.begin() + L.nrhs, pin_ints(L));
+    HIP_CHECK(hipMemcpyAsync(d, pin_ints(L), L.nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));  // idem
 }
 
 struct BOut {
@@ -203,6 +237,7 @@ struct Batch {
     std::vector<Lat> lats;
     BWork *lead = nullptr;
     long syncs = 0;  // host waits on the device during the solve
+    bool concurrent = true;  // lattices as concurrent graph branches (else one after another)
     hipStream_t ms() const { return lead->ms; }
     // the batch stream waits for everything queued on the lattice streams, or the reverse
     void lattices_to_batch() {
@@ -219,7 +254,7 @@ struct Batch {
     // branches forked from and joined back into the batch stream; otherwise one after another.
     template <typename F>
     void branches(bool capture, F &&body) {
-        if (!capture) {
+        if (!capture || !concurrent) {
             for (size_t l = 0; l < lats.size(); ++l) body((int)l, ms());
             return;
         }
@@ -287,10 +322,11 @@ std::vector<BOut> gcr_batched(Batch &B, const std::vector<dirac_prec> &pr, const
         dirac_ctx *c = L.c;
         const int R = L.nrhs;
         c->f[pr[l]].tmp_half.alloc((size_t)R * 24 * real_size(pr[l]) * c->g.vhp);
-        HIP_CHECK(hipMemcpyAsync(L.act(), start[l].data(), R * sizeof(int), hipMemcpyHostToDevice, ms));
+        std::copy(start[l].begin(), start[l].begin() + R, pin_ints(L));
+        std::copy(target[l].begin(), target[l].begin() + R, pin_doubles(L));
+        HIP_CHECK(hipMemcpyAsync(L.act(), pin_ints(L), R * sizeof(int), hipMemcpyHostToDevice, ms));
         HIP_CHECK(hipMemsetAsync(L.cnt(), 0, (4 * R + 1) * sizeof(int), ms));
-        HIP_CHECK(hipMemcpy2DAsync(L.sp(S_TGT), kSysScal * sizeof(double), target[l].data(), sizeof(double),
-                                   sizeof(double), R, hipMemcpyHostToDevice, ms));
+        scatter_sys(L, S_TGT, ms);
         for (const unsigned long long v :
              {L.w->id, (unsigned long long)pr[l], (unsigned long long)R, (unsigned long long)(uintptr_t)x[l],
               (unsigned long long)(uintptr_t)b[l], (unsigned long long)(uintptr_t)c->work->blas.part.p,
@@ -323,7 +359,7 @@ std::vector<BOut> gcr_batched(Batch &B, const std::vector<dirac_prec> &pr, const
         HIP_CHECK(hipGetLastError());
     }
     B.gather(ms);
-    int active = B.poll();  // also completes the uploads above, whose host arrays are the caller's
+    int active = B.poll();  // also completes the uploads above from the pinned staging
     // the launch-shape tuner cannot time candidates inside a capture: one eager operator
     // application per lattice (on the residual, into basis slot 0, which iteration 0 overwrites)
     // lets it choose before the graphs are recorded
@@ -395,14 +431,12 @@ std::vector<BOut> gcr_batched(Batch &B, const std::vector<dirac_prec> &pr, const
     // per-system counters of every lattice
     std::vector<BOut> out(nl);
     std::vector<std::vector<int>> hc(nl);
-    for (int l = 0; l < nl; ++l) {
-        const int R = B.lats[l].nrhs;
-        hc[l].resize(4 * R + 1);
-        HIP_CHECK(hipMemcpyAsync(hc[l].data(), B.lats[l].cnt(), hc[l].size() * sizeof(int), hipMemcpyDeviceToHost,
-                                 ms));
-    }
+    for (int l = 0; l < nl; ++l)
+        HIP_CHECK(hipMemcpyAsync(pin_ints(B.lats[l]), B.lats[l].cnt(), (4 * B.lats[l].nrhs + 1) * sizeof(int),
+                                 hipMemcpyDeviceToHost, ms));
     HIP_CHECK(hipStreamSynchronize(ms));
     ++B.syncs;
+    for (int l = 0; l < nl; ++l) hc[l].assign(pin_ints(B.lats[l]), pin_ints(B.lats[l]) + 4 * B.lats[l].nrhs + 1);
     for (int l = 0; l < nl; ++l) {
         const int R = B.lats[l].nrhs;
         BOut &o = out[l];
@@ -433,6 +467,8 @@ void ensure_bwork(dirac_ctx *c, int m, int nrhs) {
     w.act.alloc(nrhs * sizeof(int));
     w.cyc.alloc(nrhs * sizeof(int));
     w.cnt.alloc((4 * nrhs + 1) * sizeof(int));
+    w.stage.alloc(kPinDoubles * sizeof(double));
+    if (!w.pin) HIP_CHECK(hipHostMalloc((void **)&w.pin, kPinBytes, hipHostMallocDefault));
     for (auto &d : w.h64) d.alloc(hb);
     for (auto &d : w.f64) d.alloc(2 * hb);
 }
@@ -455,10 +491,10 @@ void ensure_lead(BWork &w, const std::vector<Lat> &lats) {
     }
     w.table.alloc(64 * sizeof(int *));
     w.nact.alloc(64 * sizeof(int));
-    std::vector<const int *> src(nl);
+    const int **src = (const int **)w.pin;  // the leader's pinned staging (64 pointers fit)
     for (int l = 0; l < nl; ++l) src[l] = (const int *)lats[l].w->cnt.p + 4 * lats[l].nrhs;
-    HIP_CHECK(hipMemcpyAsync(w.table.p, src.data(), nl * sizeof(int *), hipMemcpyHostToDevice, w.ms));
-    HIP_CHECK(hipStreamSynchronize(w.ms));  // src is a temporary
+    HIP_CHECK(hipMemcpyAsync(w.table.p, src, nl * sizeof(int *), hipMemcpyHostToDevice, w.ms));
+    HIP_CHECK(hipStreamSynchronize(w.ms));  // the staging is reused
 }
 
 // All lattices: solve D x_r = b_r for nrhs NATIVE FP64 full vectors each (in w.f64[0] -> w.f64[1]).
@@ -493,7 +529,7 @@ void solve_all(Batch &B, const dirac_solver_params *p, std::vector<dirac_solve_i
         const int R = L.nrhs;
         require(c->f[DIRAC_F64].inv_ready[1], "odd-site clover inverse not available");
         all[l].assign(R, 1);
-        upload_mask(all[l], L.act(), s);
+        upload_mask(L, all[l], L.act(), s);
         // |b_r|
         Bl.mdot(DIRAC_F64, 2, L.w->f64[0].p, 1, L.w->f64[0].p, L.sp(S_MISC), scale(l), s, L.spec(L.act()));
         // eta-hat_e = b_e - D_eo A_oo^-1 b_o (all systems): even halves into eta, odd into r64
@@ -581,7 +617,7 @@ void solve_all(Batch &B, const dirac_solver_params *p, std::vector<dirac_solve_i
                     std::vector<double> inv(L.nrhs);
                     for (int q = 0; q < L.nrhs; ++q) inv[q] = outer[l][q] ? 1.0 / rn[l][q] : 0.0;
                     write_sys(L, S_ALPHA, inv, s);
-                    upload_mask(outer[l], L.act(), s);
+                    upload_mask(L, outer[l], L.act(), s);
                     L.c->work->blas.lincomb(cur[l], DIRAC_F64, DIRAC_F64, 1, L.w->b.p, nullptr, 1.0, L.w->h64[2].p,
                                             0.0, nullptr, nullptr, 1.0, s, L.spec(L.act()), L.sp(S_ALPHA));
                     tg[l] = itarget[l];
@@ -611,7 +647,7 @@ void solve_all(Batch &B, const dirac_solver_params *p, std::vector<dirac_solve_i
                 write_sys(L, S_XS, cur[l] == DIRAC_F64 ? std::vector<double>(R, 1.0) : rn[l], s);
                 write_sys(L, S_ONE, std::vector<double>(R, 1.0), s);
                 write_sys(L, S_ONE + 1, std::vector<double>(R, 0.0), s);
-                upload_mask(outer[l], L.act(), s);
+                upload_mask(L, outer[l], L.act(), s);
                 Bl.axpy_multi(DIRAC_F64, cur[l], 1, xe[l], ee[l], 1, L.sp(S_ONE), 1.0, s, L.spec(L.act()), L.sp(S_XS));
                 if (cur[l] == DIRAC_F64) continue;  // finished: nothing more for this lattice
                 done = false;
@@ -656,7 +692,7 @@ void solve_all(Batch &B, const dirac_solver_params *p, std::vector<dirac_solve_i
         const size_t full64 = 2 * half64(l);
         halves(l, bf, nullptr, r64, true);  // r64 <- b_o
         hop_apply(c, t64, xe[l], nullptr, 1, HOP_PLAIN, -0.5, 0, DIRAC_F64, s, R);
-        upload_mask(all[l], L.act(), s);
+        upload_mask(L, all[l], L.act(), s);
         Bl.lincomb(DIRAC_F64, DIRAC_F64, DIRAC_F64, 1, r64, nullptr, 1.0, r64, -1.0, t64, nullptr, 1.0, s,
                    L.spec(L.act()));
         clover_apply(c, t64, r64, 1, 1, DIRAC_F64, s, R);
@@ -696,6 +732,7 @@ dirac_status solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x, cons
         B.lats.push_back(Lat{ctx[l], ctx[l]->bwork, nrhs});
     }
     B.lead = ctx[0]->bwork;
+    if (const char *e = getenv("DIRAC_BATCH_CONCURRENT")) B.concurrent = atoi(e) != 0;
     ensure_lead(*B.lead, B.lats);
     hipEvent_t ready;
     HIP_CHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
@@ -717,13 +754,13 @@ dirac_status solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x, cons
         inf[l] = info + (size_t)l * nrhs;
         for (int q = 0; q < nrhs; ++q) inf[l][q] = dirac_solve_info{};
     }
-    (void)hipEventDestroy(ready);
     try {
         solve_all(B, p, inf);
     } catch (...) {
         // leave no work of this call queued behind the caller's back
         for (auto &L : B.lats) (void)hipStreamSynchronize(L.w->s);
         (void)hipStreamSynchronize(B.ms());
+        (void)hipEventDestroy(ready);
         throw;
     }
     for (int l = 0; l < nlat; ++l) {
@@ -741,6 +778,9 @@ dirac_status solve_batched(dirac_ctx *const *ctx, int nlat, void *const *x, cons
     }
     for (auto &L : B.lats) HIP_CHECK(hipStreamSynchronize(L.w->s));
     ++B.syncs;
+    // destroyed only now: the lattice streams' waits on it have run (a wait on an event destroyed
+    // before the wait executes need not order anything)
+    (void)hipEventDestroy(ready);
     const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     dirac_status st = DIRAC_OK;
     for (int l = 0; l < nlat; ++l)
