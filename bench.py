@@ -46,7 +46,9 @@ HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persis
               "k_hop_rb 4 waves (right-hand sides blocked, link work and clover in LDS)",
               "k_hop_rb 8 waves (right-hand sides blocked, link work and clover in LDS)",
               "k_hop_rb 4 waves, next-direction prefetch", "k_hop_rb 8 waves, next-direction prefetch",
-              "k_hop_rb 12 waves, next-direction prefetch"]
+              "k_hop_rb 12 waves, next-direction prefetch",
+              "k_hop_p bs256 1/CU 4 neighbours/iteration streaming hints (persistent)",
+              "k_hop_p bs256 2/CU 4 neighbours/iteration streaming hints (persistent)"]
 
 # The FP64 hop + A chi kernel of each launch shape, as rocprofv3 names it, and its grid in
 # work-items on 32^3 x 64 (V/2 = 1,048,576 output sites, 256 compute units): the key of its row in
@@ -59,6 +61,7 @@ HOP_CLOV_KERNEL_32C64 = {
     14: ("k_hop_tp<double, 0, 2, 4>", 65536), 15: ("k_hop_tp<double, 0, 2, 8>", 131072),
     16: ("k_hop_ps<double, 0, 2, 256>", 65536), 17: ("k_hop_ps<double, 0, 2, 256>", 131072),
     18: ("k_hop_ps<double, 0, 2, 128>", 65536), 19: ("k_hop_p<double, 0, 2, 256, 0, 2, false>", 131072),
+    28: ("k_hop_p<double, 0, 2, 256, 0, 4, true>", 65536), 29: ("k_hop_p<double, 0, 2, 256, 0, 4, true>", 131072),
 }
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hop_fp64_32c64_hbm_traffic.txt")
 # the sources the hop kernels are compiled from: the counter summary records their hash, and a

@@ -51,8 +51,10 @@ DEV void hop_dir(const HopArgs<S> &a, const int x[4], int row, uint32_t i, int n
 // uniform run-time value: straight-line code lets the compiler issue the loads of all eight
 // neighbours up front, which needs more registers than a lane has (spills, one wave per SIMD).
 // NPI = 1 keeps one neighbour's data live at a time; NPI = 2 takes the forward and backward
-// neighbour of one mu per iteration, so each wave has twice the loads in flight.  The sums are
-// accumulated in the same order either way.
+// neighbour of one mu per iteration, so each wave has twice the loads in flight; NPI = 4 takes
+// two mu per iteration (four times the loads in flight, for the persistent shapes with one
+// wavefront per SIMD, whose register file allows it).  The sums are accumulated in the same
+// order either way.
 template <typename S, int DAG, int NPI, bool NT>
 DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<S>::acc> acc[12],
                  const typename St<S>::vec *tile = nullptr, int tslot = 0) {
@@ -60,6 +62,14 @@ DEV void hop_all(const HopArgs<S> &a, const int x[4], uint32_t i, C<typename St<
     if constexpr (NPI == 1) {
 #pragma nounroll
         for (int n = 0; n < 8; ++n) hop_dir<S, DAG, NT>(a, x, row, i, n, acc, tile, tslot);
+    } else if constexpr (NPI == 4) {
+#pragma nounroll
+        for (int mu = 0; mu < 4; mu += 2) {
+            hop_dir<S, DAG, NT>(a, x, row, i, 2 * mu, acc, tile, tslot);
+            hop_dir<S, DAG, NT>(a, x, row, i, 2 * mu + 1, acc, tile, tslot);
+            hop_dir<S, DAG, NT>(a, x, row, i, 2 * mu + 2, acc, tile, tslot);
+            hop_dir<S, DAG, NT>(a, x, row, i, 2 * mu + 3, acc, tile, tslot);
+        }
     } else {
 #pragma nounroll
         for (int mu = 0; mu < 4; ++mu) {
@@ -533,7 +543,8 @@ const HopShape kShapes[] = {
     {256, 0, 0, 1, 1, 1, 0, 1}, {256, 0, 0, 2, 1, 1, 0, 1}, {128, 0, 0, 2, 1, 1, 0, 1}, {256, 0, 0, 2, 0, 2, 0, 1},
     {256, 0, 0, 1, 0, 1, 1, 2}, {256, 0, 0, 1, 0, 1, 1, 4}, {256, 0, 0, 2, 0, 1, 1, 2},
     {256, 0, 0, 0, 0, 1, 1, 1, 4, 0}, {512, 0, 0, 0, 0, 1, 1, 1, 8, 0}, {256, 0, 0, 0, 0, 1, 1, 1, 4, 1},
-    {512, 0, 0, 0, 0, 1, 1, 1, 8, 1}, {768, 0, 0, 0, 0, 1, 1, 1, 12, 1}};
+    {512, 0, 0, 0, 0, 1, 1, 1, 8, 1}, {768, 0, 0, 0, 0, 1, 1, 1, 12, 1}, {256, 0, 0, 1, 0, 4, 1, 1, 0, 0},
+    {256, 0, 0, 2, 0, 4, 1, 1, 0, 0}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 template <typename S> constexpr int num_shapes() { return kNumShapes; }
 
@@ -656,6 +667,7 @@ void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
         else launch_slab<S, DAG, MODE, 128>(a, h.pers, s);
     } else if (h.pers) {
         if (h.bs == 512) launch_persistent<S, DAG, MODE, 512>(a, h.pers, h.xcd, s);
+        else if (h.nt && h.npi == 4) launch_persistent<S, DAG, MODE, 256, 4, true>(a, h.pers, 0, s);
         else if (h.nt && h.npi == 2) launch_persistent<S, DAG, MODE, 256, 2, true>(a, h.pers, 0, s);
         else if (h.nt) launch_persistent<S, DAG, MODE, 256, 1, true>(a, h.pers, 0, s);
         else if (h.npi == 2) launch_persistent<S, DAG, MODE, 256, 2>(a, h.pers, 0, s);

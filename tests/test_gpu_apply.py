@@ -184,7 +184,7 @@ def test_hop_launch_shapes_bitwise_identical(monkeypatch):
         for prec in ("f64", "f32", "f16", "bf16"):
             nat = c.D.to_native(to_dev(psi_e.astype(np.complex64) if prec == "f32" else psi_e), prec, "eo", sites=1)
             ref = None
-            for shape in range(28):
+            for shape in range(30):
                 monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
                 out = c.D.native_empty(prec, 1)
                 c.D.apply_eo(out, nat, prec, "native")
