@@ -19,9 +19,11 @@ Modules
   ptc       parallel-transport convolution network (forward, gradients, Adam)
 
 Parity status: every function is pinned by a `-m "not gpu"` test against a
-closed form, an invariant, a brute-force dense computation or a LAPACK routine,
-except the clover values of a generic random field, which are pinned only by
-invariants and by closed forms for abelian fields ("parity unpinned" beyond
-those; the paper prints no worked example).
+closed form, an invariant, a brute-force dense computation or a LAPACK routine.
+The clover term of a random field, for which the paper prints no worked
+example, is pinned by its parts: a closed form for a position-dependent abelian
+flux (where each leaf sits), one for constant non-commuting SU(2) links (the
+order and adjoints of the link products, which an abelian field cannot see),
+and gauge covariance on random fields.
 """
 from . import geometry, dirac, solvers  # noqa: F401

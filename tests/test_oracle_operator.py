@@ -1,6 +1,8 @@
 """Pins of the oracle operator: closed forms, invariants and brute force, none of which reuses
 the oracle's own formula.  A dropped term, a wrong sign, a transposed link, a wrong gamma matrix
 or a misplaced boundary phase each fail at least one test here."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -161,6 +163,60 @@ def test_clover_constant_abelian_flux_closed_form():
     c12 = np.diag(csw * np.sin(Ba) + cq * qhat * np.sin(B))
     c03 = np.diag(csw * np.sin(Bpa) + cq * qhat * np.sin(Bp))
     expect = np.eye(12) / (2 * kappa) + 0.5 * (np.kron(S12, c12) - np.kron(S03, c03))
+    assert np.abs(f.clover() - expect[None]).max() < 1e-14
+
+
+def _su2_mul(p, q):
+    """(s, v) pairs for the SU(2) element s + i v.sigma: (s1 s2 - v1.v2, s1 v2 + s2 v1 - v1 x v2)."""
+    return p[0] * q[0] - np.dot(p[1], q[1]), p[0] * q[1] + q[0] * p[1] - np.cross(p[1], q[1])
+
+
+def _su2_dag(p):
+    return p[0], -p[1]
+
+
+def _su2_in_su3(p):
+    """s + i v.sigma on colours 0, 1 and 1 on colour 2."""
+    s, (v1, v2, v3) = p
+    return np.array([[s + 1j * v3, 1j * v1 + v2, 0], [1j * v1 - v2, s - 1j * v3, 0], [0, 0, 1]], dtype=complex)
+
+
+def test_clover_non_abelian_constant_links_closed_form():
+    """Constant links g = exp(i a m.sigma) in direction 0 and h = exp(i b n.sigma) in direction 1 (unit
+    vectors m, n in general position), in the SU(2) of colours 0 and 1, unit links elsewhere and
+    theta = 0.  Every leaf of the (0, 1)
+    plane is then a group commutator (g h g^-1 h^-1, h g^-1 h^-1 g, g^-1 h^-1 g h, h^-1 g h g^-1),
+    computed here with the SU(2) product rule.  With s + i w.tau the sum of the four leaves
+    (tau the Pauli matrices on colours 0, 1), F_01 = (Q - Q^dag)/8 = (i/4) w.tau, and the two
+    terms (0, 1) and (1, 0) of the clover sum are equal, so
+    A = (4 + m0) 1 + c_sw (i/2) sigma_01 (x) F_01 = 1/(2 kappa) - (c_sw / 8) diag(s1, -s1) (x) w.tau
+    (sigma_01 = diag(sigma_1, -sigma_1) in the chiral basis).  The commutators point along m x n,
+    which has all three components here, so the clover block mixes colours 0 and 1: the SU(3) term
+    on a field whose plaquettes do not commute with the links."""
+    L = (4, 4, 2, 2)
+    a, b = 0.37, -0.61
+    kappa, csw = 0.124, 1.7
+    m = np.array([np.cos(0.8), np.sin(0.8), 0.0])
+    n = np.array([0.0, np.cos(0.3), np.sin(0.3)])
+    g = (np.cos(a), np.sin(a) * m)
+    h = (np.cos(b), np.sin(b) * n)
+    gd, hd = _su2_dag(g), _su2_dag(h)
+    prod = lambda *ps: functools.reduce(_su2_mul, ps)  # noqa: E731
+    leaves = [prod(g, h, gd, hd), prod(h, gd, hd, g), prod(gd, hd, g, h), prod(hd, g, h, gd)]
+    w = sum(l[1] for l in leaves)
+    assert np.min(np.abs(w)) > 1e-3  # genuinely non-abelian: every colour Pauli component present
+    V = int(np.prod(L))
+    U = gen.unit_links(L)
+    U[:, 0] = _su2_in_su3(g)
+    U[:, 1] = _su2_in_su3(h)
+    f = dirac.Fields(U, np.zeros((V, 4)), dirac.Params(L, kappa, csw, 0.9, -1))
+    pauli = [np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]])]
+    wt = np.zeros((3, 3), dtype=complex)
+    wt[:2, :2] = sum(wk * pk for wk, pk in zip(w, pauli))
+    s01 = np.zeros((4, 4), dtype=complex)
+    s01[:2, :2] = pauli[0]
+    s01[2:, 2:] = -pauli[0]
+    expect = np.eye(12) / (2 * kappa) - (csw / 8) * np.kron(s01, wt)
     assert np.abs(f.clover() - expect[None]).max() < 1e-14
 
 
