@@ -48,7 +48,18 @@ HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persis
               "k_hop_rb 4 waves, next-direction prefetch", "k_hop_rb 8 waves, next-direction prefetch",
               "k_hop_rb 12 waves, next-direction prefetch",
               "k_hop_p bs256 1/CU 4 neighbours/iteration streaming hints (persistent)",
-              "k_hop_p bs256 2/CU 4 neighbours/iteration streaming hints (persistent)"]
+              "k_hop_p bs256 2/CU 4 neighbours/iteration streaming hints (persistent)",
+              "k_hop_px bs256 1/CU 2 neighbours/iteration streaming hints (x1-split sweep)",
+              "k_hop_px bs256 2/CU 2 neighbours/iteration streaming hints (x1-split sweep)",
+              "k_hop_px bs128 2/CU 2 neighbours/iteration streaming hints (x1-split sweep)",
+              "k_hop_px bs256 1/CU 4 neighbours/iteration streaming hints (x1-split sweep)",
+              "k_hop_ps bs256 1/CU 2 neighbours/iteration streaming hints (XCD slab sweep)",
+              "k_hop_ps bs128 2/CU 2 neighbours/iteration streaming hints (XCD slab sweep)",
+              "k_hop_px bs256 2/CU 4 neighbours/iteration streaming hints (x1-split sweep)",
+              "k_hop_px bs256 4/CU 2 neighbours/iteration streaming hints (x1-split sweep)",
+              "k_hop_rb 4 waves, next-direction prefetch, x1-split block order",
+              "k_hop_rb 8 waves, next-direction prefetch, x1-split block order",
+              "k_hop_px bs256 3/CU 4 neighbours/iteration streaming hints (x1-split sweep)"]
 
 # The FP64 hop + A chi kernel of each launch shape, as rocprofv3 names it, and its grid in
 # work-items on 32^3 x 64 (V/2 = 1,048,576 output sites, 256 compute units): the key of its row in
@@ -59,9 +70,14 @@ HOP_CLOV_KERNEL_32C64 = {
     4: ("k_hop_p<double, 0, 2, 256, 0, 2, false>", 65536), 11: ("k_hop_p<double, 0, 2, 512, 0, 1, false>", 131072),
     12: ("k_hop_p<double, 0, 2, 256, 0, 1, false>", 131072), 13: ("k_hop_p<double, 0, 2, 256, 1, 1, false>", 65536),
     14: ("k_hop_tp<double, 0, 2, 4>", 65536), 15: ("k_hop_tp<double, 0, 2, 8>", 131072),
-    16: ("k_hop_ps<double, 0, 2, 256>", 65536), 17: ("k_hop_ps<double, 0, 2, 256>", 131072),
-    18: ("k_hop_ps<double, 0, 2, 128>", 65536), 19: ("k_hop_p<double, 0, 2, 256, 0, 2, false>", 131072),
+    16: ("k_hop_ps<double, 0, 2, 256, 1, false>", 65536), 17: ("k_hop_ps<double, 0, 2, 256, 1, false>", 131072),
+    18: ("k_hop_ps<double, 0, 2, 128, 1, false>", 65536), 19: ("k_hop_p<double, 0, 2, 256, 0, 2, false>", 131072),
     28: ("k_hop_p<double, 0, 2, 256, 0, 4, true>", 65536), 29: ("k_hop_p<double, 0, 2, 256, 0, 4, true>", 131072),
+    30: ("k_hop_px<double, 0, 2, 256, 2, true>", 65536), 31: ("k_hop_px<double, 0, 2, 256, 2, true>", 131072),
+    32: ("k_hop_px<double, 0, 2, 128, 2, true>", 65536), 33: ("k_hop_px<double, 0, 2, 256, 4, true>", 65536),
+    34: ("k_hop_ps<double, 0, 2, 256, 2, true>", 65536), 35: ("k_hop_ps<double, 0, 2, 128, 2, true>", 65536),
+    36: ("k_hop_px<double, 0, 2, 256, 4, true>", 131072), 37: ("k_hop_px<double, 0, 2, 256, 2, true>", 262144),
+    40: ("k_hop_px<double, 0, 2, 256, 4, true>", 196608),
 }
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hop_fp64_32c64_hbm_traffic.txt")
 # the sources the hop kernels are compiled from: the counter summary records their hash, and a

@@ -333,11 +333,13 @@ __global__ __launch_bounds__(BS) void k_hop_mr(HopArgs<S> a, int nlog) {
 // computed once instead of once per right-hand side.  The rebuilt rows and phases are the values
 // the one-RHS kernel computes with the same code, and each site's sums run in the same order, so
 // the results equal the one-RHS kernel's bit for bit.  Work-group b takes block b (dispatch
-// order: blocks 8 and 256 apart, the x1 and time neighbours at 32^3 x 64, run on the same XCD).
+// order: blocks 8 and 256 apart, the x1 and time neighbours at 32^3 x 64, run on the same XCD),
+// or with X1S the blocks in the x1-split order of k_hop_px (XCD b % 8 walks the time slices of its
+// eighth of the x1 range, so the x2 neighbours are on the same XCD too).
 // PF: the loop over the 8 directions is unrolled by two with the next direction's spinor loads
 // issued before the current direction's arithmetic.  The stores of the output and the loads of
 // chi carry a streaming hint.
-template <typename S, int DAG, int MODE, int NW, bool PF>
+template <typename S, int DAG, int MODE, int NW, bool PF, bool X1S>
 __global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
     using T = typename St<S>::acc;
     using V = typename St<S>::vec;
@@ -346,7 +348,12 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
     __shared__ T s_lk[8 * NL * kSB];
     __shared__ uint32_t s_nb[8 * kSB];
     __shared__ V s_cl[MODE != HOP_PLAIN ? CP * kSB : 1];
-    const int blk = (int)blockIdx.x;
+    int blk = (int)blockIdx.x;
+    if constexpr (X1S) {
+        const int bps = a.g.vh / (a.g.L[0] * 8 * kSB);  // blocks in an XCD's part of a time slice
+        const int j = blk >> 3;
+        blk = ((j / bps) * 8 + (blk & 7)) * bps + j % bps;
+    }
     const int t = (int)threadIdx.x;
     for (int k = t; k < 8 * kSB; k += 64 * NW) {
         const int n = k / kSB, ln = k - n * kSB;
@@ -428,7 +435,7 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rb(HopArgs<S> a) {
 // few (t, x1) planes of all its time slices, so the neighbours in every direction but across the
 // slab's time boundaries are read by the same XCD within a short window and hit in its L2.
 // Needs L0 % 8 == 0 and the sites of one parity in a (t, x1) plane a multiple of BS.
-template <typename S, int DAG, int MODE, int BS>
+template <typename S, int DAG, int MODE, int BS, int NPI = 1, bool NT = false>
 __global__ __launch_bounds__(BS) void k_hop_ps(HopArgs<S> a, int nper) {
     const int xcd = (int)(blockIdx.x & 7);
     const int T8 = a.g.L[0] >> 3;
@@ -448,7 +455,37 @@ __global__ __launch_bounds__(BS) void k_hop_ps(HopArgs<S> a, int nper) {
             b.out += rhs * a.vs;
             if (b.chi) b.chi += rhs * a.vs;
         }
-        hop_site<S, DAG, MODE>(b, (t * a.g.L[1] + x1) * plane + h * BS + (int)threadIdx.x, nullptr, 0);
+        hop_site<S, DAG, MODE, NPI, NT>(b, (t * a.g.L[1] + x1) * plane + h * BS + (int)threadIdx.x, nullptr, 0);
+    }
+}
+
+// x1-split sweep: XCD k (work-groups b with b % 8 == k) owns the x1 range [k L1 / 8, (k + 1) L1 / 8)
+// of every time slice, and its work-groups walk the time slices in order.  The sites of one
+// parity in that part of a slice are contiguous in the half index, and the work-groups of one
+// XCD in flight together cover a few consecutive slices of it: every neighbour but the x1
+// neighbours across the XCD's range boundaries is read by the same XCD within a short window
+// (a time slice earlier at most) and hits in its L2, while the once-touched streams carry the
+// streaming hint.  Needs L1 % 8 == 0; the part of a slice is cut into chunks of BS sites, the last
+// one partial when BS does not divide it.
+template <typename S, int DAG, int MODE, int BS, int NPI, bool NT>
+__global__ __launch_bounds__(BS) void k_hop_px(HopArgs<S> a, int nper) {
+    const int xcd = (int)(blockIdx.x & 7);
+    const int sub = a.g.vh / (a.g.L[0] * 8);  // sites of one parity in an XCD's part of a time slice
+    const int cps = (sub + BS - 1) / BS;
+#pragma nounroll
+    for (int j = (int)(blockIdx.x >> 3); j < nper; j += (int)(gridDim.x >> 3)) {
+        const int rhs = j % a.nrhs;
+        const int r = j / a.nrhs;
+        const int c = r % cps, t = r / cps;
+        if (a.active && !a.active[rhs]) continue;
+        if (c * BS + (int)threadIdx.x >= sub) continue;  // no barrier follows
+        HopArgs<S> b = a;
+        if (rhs) {
+            b.in += rhs * a.vs;
+            b.out += rhs * a.vs;
+            if (b.chi) b.chi += rhs * a.vs;
+        }
+        hop_site<S, DAG, MODE, NPI, NT>(b, (t * 8 + xcd) * sub + c * BS + (int)threadIdx.x, nullptr, 0);
     }
 }
 
@@ -525,7 +562,7 @@ __global__ __launch_bounds__(64 * TT) void k_hop_tp(HopArgs<S> a, int nwg) {
 }
 
 struct HopShape {
-    int bs, xcd, tt, pers, slab, npi, nt, mr, rb, pf;
+    int bs, xcd, tt, pers, slab, npi, nt, mr, rb, pf, x1s;
 };
 // Shape 0 is the default (used when tuning is off, and inside a graph capture before the key
 // was tuned): the persistent sweep, one 256-wide work-group per compute unit, two neighbours per
@@ -534,7 +571,7 @@ struct HopShape {
 // slab: the XCD slab sweep; npi: neighbours per loop iteration; nt: streaming hints; mr: right-hand
 // sides per work-item (the links and clover block read once for all of them); rb: the right-hand-
 // side blocked kernel with rb wavefronts per work-group (link work and clover block in LDS), pf:
-// its next-direction prefetch.
+// its next-direction prefetch; x1s: the x1-split sweep.
 const HopShape kShapes[] = {
     {256, 0, 0, 1, 0, 2, 1, 1}, {256, 0, 0, 1, 0, 1, 1, 1}, {256, 0, 0, 2, 0, 1, 1, 1}, {256, 0, 0, 1, 0, 1, 0, 1},
     {256, 0, 0, 1, 0, 2, 0, 1}, {256, 1, 0, 0, 0, 1, 0, 1}, {256, 0, 0, 0, 0, 1, 0, 1}, {128, 1, 0, 0, 0, 1, 0, 1},
@@ -544,7 +581,10 @@ const HopShape kShapes[] = {
     {256, 0, 0, 1, 0, 1, 1, 2}, {256, 0, 0, 1, 0, 1, 1, 4}, {256, 0, 0, 2, 0, 1, 1, 2},
     {256, 0, 0, 0, 0, 1, 1, 1, 4, 0}, {512, 0, 0, 0, 0, 1, 1, 1, 8, 0}, {256, 0, 0, 0, 0, 1, 1, 1, 4, 1},
     {512, 0, 0, 0, 0, 1, 1, 1, 8, 1}, {768, 0, 0, 0, 0, 1, 1, 1, 12, 1}, {256, 0, 0, 1, 0, 4, 1, 1, 0, 0},
-    {256, 0, 0, 2, 0, 4, 1, 1, 0, 0}};
+    {256, 0, 0, 2, 0, 4, 1, 1, 0, 0}, {256, 0, 0, 1, 0, 2, 1, 1, 0, 0, 1}, {256, 0, 0, 2, 0, 2, 1, 1, 0, 0, 1},
+    {128, 0, 0, 2, 0, 2, 1, 1, 0, 0, 1}, {256, 0, 0, 1, 0, 4, 1, 1, 0, 0, 1}, {256, 0, 0, 1, 1, 2, 1, 1, 0, 0, 0},
+    {128, 0, 0, 2, 1, 2, 1, 1, 0, 0, 0}, {256, 0, 0, 2, 0, 4, 1, 1, 0, 0, 1}, {256, 0, 0, 4, 0, 2, 1, 1, 0, 0, 1},
+    {256, 0, 0, 0, 0, 1, 1, 1, 4, 1, 1}, {512, 0, 0, 0, 0, 1, 1, 1, 8, 1, 1}, {256, 0, 0, 3, 0, 4, 1, 1, 0, 0, 1}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 template <typename S> constexpr int num_shapes() { return kNumShapes; }
 
@@ -562,6 +602,12 @@ bool slab_ok(const Geom &g, int bs) {
     if (g.L[0] % 8) return false;
     const int plane = g.vh / (g.L[0] * g.L[1]);
     return plane % bs == 0;
+}
+// The x1-split order fits when L1 % 8 == 0; the right-hand-side blocked kernel takes whole site
+// blocks, so its XCD's part of a time slice must be whole blocks.
+bool x1split_ok(const Geom &g, bool whole_blocks) {
+    if (g.L[1] % 8) return false;
+    return !whole_blocks || (g.vh / (g.L[0] * 8)) % kSB == 0;
 }
 bool tiled_ok(const Geom &g, int tt) {
     const int ns = g.vh / g.L[0];
@@ -587,14 +633,24 @@ void launch_persistent(HopArgs<S> a, int per_cu, int xcd, hipStream_t s) {
     else k_hop_p<S, DAG, MODE, BS, 0, NPI, NT><<<grid, BS, 0, s>>>(a, nlog);
 }
 
-template <typename S, int DAG, int MODE, int BS>
+template <typename S, int DAG, int MODE, int BS, int NPI = 1, bool NT = false>
 void launch_slab(HopArgs<S> a, int per_cu, hipStream_t s) {
     const int plane = a.g.vh / (a.g.L[0] * a.g.L[1]);
     const int nper = (a.g.L[0] / 8) * a.g.L[1] * (plane / BS) * a.nrhs;
     const int grid = 8 * std::max(1, std::min(nper, per_cu * compute_units() / 8));
     a.xcd = 0;
     a.nb8 = grid;
-    k_hop_ps<S, DAG, MODE, BS><<<grid, BS, 0, s>>>(a, nper);
+    k_hop_ps<S, DAG, MODE, BS, NPI, NT><<<grid, BS, 0, s>>>(a, nper);
+}
+
+template <typename S, int DAG, int MODE, int BS, int NPI>
+void launch_x1split(HopArgs<S> a, int per_cu, hipStream_t s) {
+    const int sub = a.g.vh / (a.g.L[0] * 8);
+    const int nper = a.g.L[0] * ((sub + BS - 1) / BS) * a.nrhs;
+    const int grid = 8 * std::max(1, std::min(nper, per_cu * compute_units() / 8));
+    a.xcd = 0;
+    a.nb8 = grid;
+    k_hop_px<S, DAG, MODE, BS, NPI, true><<<grid, BS, 0, s>>>(a, nper);
 }
 
 template <typename S, int DAG, int MODE, int NR>
@@ -625,27 +681,29 @@ void launch_tiled(HopArgs<S> a, hipStream_t s) {
 }
 
 template <typename S, int DAG, int MODE, int NW>
-void launch_rb_nw(HopArgs<S> a, bool pf, hipStream_t s) {
+void launch_rb_nw(HopArgs<S> a, bool pf, bool x1s, hipStream_t s) {
     a.xcd = 0;
     a.nb8 = (a.g.vh + kSB - 1) / kSB;
-    if (pf) k_hop_rb<S, DAG, MODE, NW, true><<<a.nb8, 64 * NW, 0, s>>>(a);
-    else k_hop_rb<S, DAG, MODE, NW, false><<<a.nb8, 64 * NW, 0, s>>>(a);
+    if (x1s) k_hop_rb<S, DAG, MODE, NW, true, true><<<a.nb8, 64 * NW, 0, s>>>(a);  // pf with x1s only
+    else if (pf) k_hop_rb<S, DAG, MODE, NW, true, false><<<a.nb8, 64 * NW, 0, s>>>(a);
+    else k_hop_rb<S, DAG, MODE, NW, false, false><<<a.nb8, 64 * NW, 0, s>>>(a);
 }
 
 template <typename S, int DAG, int MODE>
-void launch_rb(const HopArgs<S> &a, int nw, bool pf, hipStream_t s) {
+void launch_rb(const HopArgs<S> &a, int nw, bool pf, bool x1s, hipStream_t s) {
     // FP64 needs about 176 registers per lane: at most two wavefronts per SIMD, 8 per work-group
-    if (nw == 4) launch_rb_nw<S, DAG, MODE, 4>(a, pf, s);
-    else if (nw == 8 || std::is_same<S, double>::value) launch_rb_nw<S, DAG, MODE, 8>(a, pf, s);
-    else if constexpr (!std::is_same<S, double>::value) launch_rb_nw<S, DAG, MODE, 12>(a, pf, s);
+    if (nw == 4) launch_rb_nw<S, DAG, MODE, 4>(a, pf, x1s, s);
+    else if (nw == 8 || std::is_same<S, double>::value) launch_rb_nw<S, DAG, MODE, 8>(a, pf, x1s, s);
+    else if constexpr (!std::is_same<S, double>::value) launch_rb_nw<S, DAG, MODE, 12>(a, pf, false, s);
 }
 
 template <typename S, int DAG, int MODE>
 void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
     HopShape h = kShapes[shape];
-    if ((h.tt && !tiled_ok(a.g, h.tt)) || (h.slab && !slab_ok(a.g, h.bs))) h = kShapes[0];  // does not fit
+    if ((h.tt && !tiled_ok(a.g, h.tt)) || (h.slab && !slab_ok(a.g, h.bs)) || (h.x1s && !x1split_ok(a.g, h.rb != 0)))
+        h = kShapes[0];  // does not fit
     if (h.rb) {
-        launch_rb<S, DAG, MODE>(a, h.rb, h.pf != 0, s);
+        launch_rb<S, DAG, MODE>(a, h.rb, h.pf != 0, h.x1s != 0, s);
     } else if (h.mr > 1) {
         // two right-hand sides per work-item in FP64 (four would not fit the registers)
         if constexpr (std::is_same<S, double>::value) {
@@ -662,8 +720,14 @@ void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
             if (h.tt == 4) launch_tiled<S, DAG, MODE, 4>(a, s);
             else launch_tiled<S, DAG, MODE, 8>(a, s);
         }
+    } else if (h.x1s) {
+        if (h.npi == 4) launch_x1split<S, DAG, MODE, 256, 4>(a, h.pers, s);
+        else if (h.bs == 256) launch_x1split<S, DAG, MODE, 256, 2>(a, h.pers, s);
+        else launch_x1split<S, DAG, MODE, 128, 2>(a, h.pers, s);
     } else if (h.slab) {
-        if (h.bs == 256) launch_slab<S, DAG, MODE, 256>(a, h.pers, s);
+        if (h.nt && h.bs == 256) launch_slab<S, DAG, MODE, 256, 2, true>(a, h.pers, s);
+        else if (h.nt) launch_slab<S, DAG, MODE, 128, 2, true>(a, h.pers, s);
+        else if (h.bs == 256) launch_slab<S, DAG, MODE, 256>(a, h.pers, s);
         else launch_slab<S, DAG, MODE, 128>(a, h.pers, s);
     } else if (h.pers) {
         if (h.bs == 512) launch_persistent<S, DAG, MODE, 512>(a, h.pers, h.xcd, s);

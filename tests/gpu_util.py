@@ -12,6 +12,11 @@ from oracle import dirac as odirac
 from oracle import geometry as geo
 
 
+# number of launch shapes in the hop kernel's shape table (csrc/hop.hip), which DIRAC_HOP_SHAPE
+# indexes; test_abi checks it against the table and bench.py's names
+N_HOP_SHAPES = 41
+
+
 def need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

@@ -55,3 +55,20 @@ def _load_missing(tmp_path):
         _lib.load(str(tmp_path / "missing.so"))
     finally:
         _lib._lib = saved
+
+
+def test_hop_shape_count_matches_table_and_bench_names():
+    """DIRAC_HOP_SHAPE indexes the hop kernel's shape table: the GPU tests that run every shape,
+    and bench.py's shape names, have as many entries as the table."""
+    import ast
+    import sys
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_util import N_HOP_SHAPES
+
+    src = open(os.path.join(ROOT, "paper_2502_02490_amd", "csrc", "hop.hip")).read()
+    table = re.search(r"const HopShape kShapes\[\] = \{(.*?)\};", src, flags=re.S).group(1)
+    assert len(re.findall(r"\{[^{}]*\}", table)) == N_HOP_SHAPES
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    names = [n for n in tree.body if isinstance(n, ast.Assign) and getattr(n.targets[0], "id", "") == "HOP_SHAPES"]
+    assert len(names) == 1 and len(names[0].value.elts) == N_HOP_SHAPES

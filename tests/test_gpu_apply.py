@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import Case, flush, need_gpu, rel, to_dev
+from gpu_util import N_HOP_SHAPES, Case, flush, need_gpu, rel, to_dev
 from storage_envelope import U_BF16, U_FP16, schur_envelope
 from oracle import dirac as odirac
 from oracle import geometry as geo
@@ -171,20 +171,23 @@ def test_schur_32c64_sampled_sites(qhat):
         c.D.close()
 
 
-def test_hop_launch_shapes_bitwise_identical(monkeypatch):
+# (8, 8, 16, 32): L0 % 8 == 0, (L1 L2 L3 / 2) % 64 == 0, (L2 L3 / 2) % 256 == 0, L1 % 8 == 0 and
+# (L1 / 8) (L2 L3 / 2) % 256 == 0: the time tiles, the slab and the x1-split sweeps fit, so every
+# shape runs its own kernel.  (4, 8, 12, 48): an XCD's part of a time slice is 288 sites, so the
+# x1-split sweeps end each slice with a partial chunk (32 of 256 or 128 sites).
+@pytest.mark.parametrize("dims", [(8, 8, 16, 32), (4, 8, 12, 48)], ids=lambda d: "x".join(map(str, d)))
+def test_hop_launch_shapes_bitwise_identical(monkeypatch, dims):
     """Every launch shape the tuner may pick (work-group size, occupancy hint, work-group order,
     time-tiled LDS staging, persistent sweeps) gives bitwise the same Schur output, in every
     precision."""
     need_gpu()
-    # L0 % 8 == 0, (L1 L2 L3 / 2) % 64 == 0 and (L2 L3 / 2) % 256 == 0: the time tiles and the
-    # slab sweeps fit, so every shape runs its own kernel
-    c = Case((8, 2, 16, 32), seed=55, qhat=2)
+    c = Case(dims, seed=55, qhat=2)
     try:
         psi_e = c.spinor(3)[c.even]
         for prec in ("f64", "f32", "f16", "bf16"):
             nat = c.D.to_native(to_dev(psi_e.astype(np.complex64) if prec == "f32" else psi_e), prec, "eo", sites=1)
             ref = None
-            for shape in range(30):
+            for shape in range(N_HOP_SHAPES):
                 monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
                 out = c.D.native_empty(prec, 1)
                 c.D.apply_eo(out, nat, prec, "native")
@@ -221,7 +224,7 @@ def test_multi_rhs_schur_equals_single(case, prec, monkeypatch):
         singles.append(one)
     one_dag = torch.zeros_like(nats[nr - 1])
     D.apply_eo(one_dag, nats[nr - 1], prec, "native", dagger=True)
-    for shape in (None, 20, 21, 22, 23, 24, 25, 26, 27):
+    for shape in (None, 20, 21, 22, 23, 24, 25, 26, 27, 38, 39):
         if shape is not None:
             monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
         out = torch.zeros_like(inp)
@@ -231,3 +234,32 @@ def test_multi_rhs_schur_equals_single(case, prec, monkeypatch):
         dag = torch.zeros_like(inp)
         D.apply_eo_multi(dag, inp, nr, prec, dagger=True)
         assert torch.equal(dag[(nr - 1) * n:], one_dag), shape
+
+
+def test_multi_rhs_shapes_on_x1split_lattice(monkeypatch):
+    """On a lattice where the x1-split block order fits (L1 % 8 == 0), every multi-right-hand-side
+    shape, the x1-split ones included, equals single applies bit for bit, in FP64 and FP32."""
+    need_gpu()
+    c = Case((8, 8, 16, 32), seed=58, qhat=-1)
+    try:
+        nr = 3
+        for prec in ("f64", "f32"):
+            vecs = [c.spinor(60 + r)[c.even] for r in range(nr)]
+            nats = [c.D.to_native(to_dev(v.astype(np.complex64) if prec == "f32" else v), prec, "eo", sites=1)
+                    for v in vecs]
+            singles = []
+            monkeypatch.setenv("DIRAC_HOP_SHAPE", "0")
+            for r in range(nr):
+                one = torch.zeros_like(nats[r])
+                c.D.apply_eo(one, nats[r], prec, "native")
+                singles.append(one)
+            inp = torch.cat(nats)
+            n = nats[0].numel()
+            for shape in range(N_HOP_SHAPES):
+                monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
+                out = torch.zeros_like(inp)
+                c.D.apply_eo_multi(out, inp, nr, prec)
+                for r in range(nr):
+                    assert torch.equal(out[r * n:(r + 1) * n], singles[r]), (prec, shape, r)
+    finally:
+        c.D.close()

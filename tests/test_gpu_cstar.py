@@ -10,7 +10,7 @@ import torch
 
 import gen
 import paper_2502_02490_amd as P
-from gpu_util import Case, flush, need_gpu, rel, rel_norm, to_dev
+from gpu_util import N_HOP_SHAPES, Case, flush, need_gpu, rel, rel_norm, to_dev
 from ptc_envelope import envelope
 from oracle import dirac as odirac
 from oracle import openqxd as oq
@@ -99,12 +99,12 @@ def test_openqxd_storage_with_cstar(case):
 def test_hop_launch_shapes_with_cstar(monkeypatch):
     """Every hop launch shape applies the shifted boundaries (bitwise equal outputs)."""
     need_gpu()
-    c = Case((8, 4, 16, 32), seed=57, qhat=-1, cstar=3)
+    c = Case((8, 8, 16, 32), seed=57, qhat=-1, cstar=3)  # the slab and x1-split sweeps fit
     try:
         psi_e = c.spinor(3)[c.even]
         nat = c.D.to_native(to_dev(psi_e), "f64", "eo", sites=1)
         ref = None
-        for shape in range(23):
+        for shape in range(N_HOP_SHAPES):
             monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
             out = c.D.native_empty("f64", 1)
             c.D.apply_eo(out, nat, "f64", "native")
