@@ -59,7 +59,10 @@ HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persis
               "k_hop_px bs256 4/CU 2 neighbours/iteration streaming hints (x1-split sweep)",
               "k_hop_rb 4 waves, next-direction prefetch, x1-split block order",
               "k_hop_rb 8 waves, next-direction prefetch, x1-split block order",
-              "k_hop_px bs256 3/CU 4 neighbours/iteration streaming hints (x1-split sweep)"]
+              "k_hop_px bs256 3/CU 4 neighbours/iteration streaming hints (x1-split sweep)",
+              "k_hop_rbc 12 waves x 1 RHS, column walk, x1-split", "k_hop_rbc 8 waves x 2 RHS, column walk, x1-split",
+              "k_hop_rbc 4 waves x 3 RHS, 2/CU, column walk, x1-split", "k_hop_rbc 6 waves x 2 RHS, column walk, x1-split",
+              "k_hop_rbc 12 waves x 1 RHS, column walk"]
 
 # The FP64 hop + A chi kernel of each launch shape, as rocprofv3 names it, and its grid in
 # work-items on 32^3 x 64 (V/2 = 1,048,576 output sites, 256 compute units): the key of its row in
@@ -82,7 +85,7 @@ HOP_CLOV_KERNEL_32C64 = {
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hop_fp64_32c64_hbm_traffic.txt")
 # the sources the hop kernels are compiled from: the counter summary records their hash, and a
 # summary taken from other sources is not used
-HOP_SOURCES = ["hop.hip", "hop_core.h", "dirac_ops.h", "common.h"]
+HOP_SOURCES = ["hop.hip", "hop_kernels.h", "hop_core.h", "dirac_ops.h", "common.h"]
 
 
 def hop_source_hash() -> str:

@@ -62,6 +62,7 @@ struct SolverWork {
     Blas blas;
     DevBuf P, Q, r, e, b;   // Krylov vectors, inner solution / right-hand side (solve precision)
     DevBuf h64[4];          // FP64 half vectors: eta-hat, x_e, r, tmp
+    DevBuf ctl;             // device-side iteration control of a GCR cycle (solver.hip)
     DevBuf f64[3];          // FP64 full vectors: b, x, r
     int m = 0;
     dirac_prec pr = DIRAC_F64;

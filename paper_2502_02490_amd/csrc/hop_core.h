@@ -1,4 +1,4 @@
-// Device pieces of the hopping term shared by the hop kernels (hop.hip) and the Schwarz block
+// Device pieces of the hopping term shared by the hop kernels (hop_kernels.h) and the Schwarz block
 // solver (sap.hip): kernel arguments, spinor and link loads, the neighbour index and the
 // projected accumulation of one direction.
 #pragma once
@@ -96,14 +96,16 @@ DEV C<T> add_signed(C<T> a, C<T> b) {
 // (forward 1 + SF gamma, backward 1 - SF gamma; SF = -1 for D, +1 for D^dag), the spin swap and
 // the units c_0, c_1 of e_mu become sign changes, swaps and additions.  r2: the link's third row,
 // third_row(u), computed by the caller (once for several right-hand sides).
+// project_dir_n: the half-spinor h of the neighbour spinor psi; apply_dir_n: the link product
+// of h and the reconstruction into acc.  accumulate_dir_n is the two in sequence, so a
+// half-spinor projected early and kept gives the same bits as the whole.
 template <typename T, int DAG, int N>
-DEV void accumulate_dir_n(const C<T> psi[12], const C<T> u[6], const C<T> r2[3], T co, T si, C<T> acc[12]) {
+DEV void project_dir_n(const C<T> psi[12], C<T> h[6]) {
     constexpr int mu = N >> 1, back = N & 1;
     constexpr int SG = (DAG ? 1 : -1) * (back ? -1 : 1);
     constexpr bool SW = (mu == 1 || mu == 2);
     constexpr int C0R = (mu == 0 || mu == 2) ? -1 : 0, C0I = (mu == 1 || mu == 3) ? -1 : 0;
     constexpr int C1R = mu == 0 ? -1 : mu == 2 ? 1 : 0, C1I = mu == 1 ? -1 : mu == 3 ? 1 : 0;
-    C<T> h[6], w[6];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const C<T> e0 = unit_mul<C0R, C0I>(SW ? psi[9 + c] : psi[6 + c]);
@@ -111,6 +113,16 @@ DEV void accumulate_dir_n(const C<T> psi[12], const C<T> u[6], const C<T> r2[3],
         h[c] = add_signed<SG>(psi[c], e0);
         h[3 + c] = add_signed<SG>(psi[3 + c], e1);
     }
+}
+
+template <typename T, int DAG, int N>
+DEV void apply_dir_n(const C<T> h[6], const C<T> u[6], const C<T> r2[3], T co, T si, C<T> acc[12]) {
+    constexpr int mu = N >> 1, back = N & 1;
+    constexpr int SG = (DAG ? 1 : -1) * (back ? -1 : 1);
+    constexpr bool SW = (mu == 1 || mu == 2);
+    constexpr int C0R = (mu == 0 || mu == 2) ? -1 : 0, C0I = (mu == 1 || mu == 3) ? -1 : 0;
+    constexpr int C1R = mu == 0 ? -1 : mu == 2 ? 1 : 0, C1I = mu == 1 ? -1 : mu == 3 ? 1 : 0;
+    C<T> w[6];
     if constexpr (back) link_adj_mul_r2(u, r2, co, si, h, w);
     else link_mul_r2(u, r2, co, si, h, w);
 #pragma unroll
@@ -122,6 +134,13 @@ DEV void accumulate_dir_n(const C<T> psi[12], const C<T> u[6], const C<T> r2[3],
         acc[6 + c] = add_signed<SG>(acc[6 + c], SW ? t1 : t0);
         acc[9 + c] = add_signed<SG>(acc[9 + c], SW ? t0 : t1);
     }
+}
+
+template <typename T, int DAG, int N>
+DEV void accumulate_dir_n(const C<T> psi[12], const C<T> u[6], const C<T> r2[3], T co, T si, C<T> acc[12]) {
+    C<T> h[6];
+    project_dir_n<T, DAG, N>(psi, h);
+    apply_dir_n<T, DAG, N>(h, u, r2, co, si, acc);
 }
 
 // acc += the direction-n term (n a run-time value, uniform over the wavefront): one of the eight

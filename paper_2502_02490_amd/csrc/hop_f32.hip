@@ -1,0 +1,11 @@
+// The hop kernels of hop_kernels.h instantiated for float storage.
+#include "hop_kernels.h"
+
+namespace dl {
+
+void hop_prec_f32(dirac_ctx *c, void *out, const void *in, const void *chi, int p, HopMode mode, double coef,
+                  int dagger, hipStream_t s, int nrhs, const int *active, bool no_tune) {
+    hop_t<float>(c, out, in, chi, p, mode, coef, dagger, DIRAC_F32, s, nrhs, active, no_tune);
+}
+
+}  // namespace dl

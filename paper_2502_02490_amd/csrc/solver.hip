@@ -11,6 +11,7 @@
 //           by less than 2x raises the inner precision (16-bit -> FP32 -> plain FP64 GCR).
 // Inner products inside GCR are normalised by the vector length (mean instead of sum), so that
 // unit-norm Krylov vectors have O(1) components in every storage precision.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -38,6 +39,33 @@ struct GcrOut {
 using Precond = std::function<void(void *p, const void *r)>;
 
 double *sc_ptr(SolverWork &w, int slot) { return (double *)w.blas.scal.p + slot; }
+
+// Device-side iteration control of one GCR cycle without a preconditioner: ctl[0] = 1 while the
+// system is active, ctl[1] = iterations done in the cycle, ctl[2] = 1 after a non-finite residual.
+// After each iteration k_gcr_poll compares the updated residual norm with the target and clears
+// ctl[0]; every kernel of a later iteration of the cycle takes ctl as its active mask and does
+// nothing, so the host only reads ctl every kPoll iterations and at the end of the cycle.
+constexpr int kPoll = 4;
+
+__global__ void k_gcr_ctl_start(int *ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl[0] = 1;
+        ctl[1] = 0;
+        ctl[2] = 0;
+    }
+}
+
+__global__ void k_gcr_poll(const double *rn2p, double target, int *ctl) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || !ctl[0]) return;
+    ++ctl[1];
+    const double rn2 = *rn2p;
+    if (!isfinite(rn2)) {
+        ctl[2] = 1;
+        ctl[0] = 0;
+    } else if (sqrt(rn2) <= target) {
+        ctl[0] = 0;
+    }
+}
 
 double read_scalar(SolverWork &w, int slot, hipStream_t s) {
     double h = 0.0;
@@ -77,6 +105,7 @@ void ensure_work(dirac_ctx *c, int m, dirac_prec inner, int nh) {
     w.b.alloc(hb);
     w.m = m;
     w.pr = inner;
+    w.ctl.alloc(4 * sizeof(int));
 }
 
 namespace {
@@ -121,25 +150,57 @@ GcrOut gcr(dirac_ctx *c, SolverWork &w, dirac_prec pr, void *x, const void *b, b
         if (M) (*M)(P, r);
         else B.lincomb(pr, pr, pr, nh, P, nullptr, 1.0, r, 0.0, nullptr, nullptr, 1.0, s);
         int n = 0;
-        for (int k = 0; k < m; ++k) {
-            char *qk = Q + k * hb;
-            apply(qk, P + k * hb);
-            double *bcol = sc_ptr(w, S_BETA + 2 * kMaxRestart * k);
-            if (k > 0) B.mdot(pr, nh, Q, k, qk, bcol, scale, s);
-            B.maxpy_dot(pr, nh, Q, k, bcol, qk, r, sc_ptr(w, S_RED), scale, s);
-            B.gcr_scalars(sc_ptr(w, S_RED), sc_ptr(w, S_SC), sc_ptr(w, S_GAM), sc_ptr(w, S_ALP), k, s);
-            // the next direction is r itself (copied by the update) or M(r)
-            B.gcr_update(pr, nh, sc_ptr(w, S_SC), qk, r, M ? nullptr : P + (k + 1) * hb, sc_ptr(w, S_RED + 4),
-                         scale, s);
-            rn2 = read_scalar(w, S_RED + 4, s);
-            ++out.iters;
-            n = k + 1;
-            if (!std::isfinite(rn2)) {
+        if (!M && !full) {
+            // iterations decided on the device: the host queues up to kPoll iterations ahead
+            int *ctl = (int *)w.ctl.p;
+            const BatchSpec bs{1, ctl, 0};
+            k_gcr_ctl_start<<<1, 64, 0, s>>>(ctl);
+            const int kmax = std::min(m, max_iter - out.iters);
+            int h[3] = {1, 0, 0};
+            for (int k = 0; k < kmax; ++k) {
+                char *qk = Q + k * hb;
+                schur_apply(c, qk, P + k * hb, 0, pr, s, 1, ctl);
+                double *bcol = sc_ptr(w, S_BETA + 2 * kMaxRestart * k);
+                if (k > 0) B.mdot(pr, nh, Q, k, qk, bcol, scale, s, bs);
+                B.maxpy_dot(pr, nh, Q, k, bcol, qk, r, sc_ptr(w, S_RED), scale, s, bs);
+                B.gcr_scalars(sc_ptr(w, S_RED), sc_ptr(w, S_SC), sc_ptr(w, S_GAM), sc_ptr(w, S_ALP), k, s, bs);
+                B.gcr_update(pr, nh, sc_ptr(w, S_SC), qk, r, P + (k + 1) * hb, sc_ptr(w, S_RED + 4), scale, s, bs);
+                k_gcr_poll<<<1, 64, 0, s>>>(sc_ptr(w, S_RED + 4), target, ctl);
+                HIP_CHECK(hipGetLastError());
+                if ((k + 1) % kPoll == 0 || k + 1 == kmax) {
+                    HIP_CHECK(hipMemcpyAsync(h, ctl, sizeof h, hipMemcpyDeviceToHost, s));
+                    HIP_CHECK(hipStreamSynchronize(s));
+                    ++w.syncs;
+                    if (!h[0]) break;
+                }
+            }
+            n = h[1];
+            out.iters += n;
+            if (h[2]) {
                 out.nonfinite = true;
                 return out;
             }
-            if (std::sqrt(rn2) <= target || out.iters >= max_iter || k + 1 == m) break;
-            if (M) (*M)(P + (k + 1) * hb, r);
+        } else {
+            for (int k = 0; k < m; ++k) {
+                char *qk = Q + k * hb;
+                apply(qk, P + k * hb);
+                double *bcol = sc_ptr(w, S_BETA + 2 * kMaxRestart * k);
+                if (k > 0) B.mdot(pr, nh, Q, k, qk, bcol, scale, s);
+                B.maxpy_dot(pr, nh, Q, k, bcol, qk, r, sc_ptr(w, S_RED), scale, s);
+                B.gcr_scalars(sc_ptr(w, S_RED), sc_ptr(w, S_SC), sc_ptr(w, S_GAM), sc_ptr(w, S_ALP), k, s);
+                // the next direction is r itself (copied by the update) or M(r)
+                B.gcr_update(pr, nh, sc_ptr(w, S_SC), qk, r, M ? nullptr : P + (k + 1) * hb, sc_ptr(w, S_RED + 4),
+                             scale, s);
+                rn2 = read_scalar(w, S_RED + 4, s);
+                ++out.iters;
+                n = k + 1;
+                if (!std::isfinite(rn2)) {
+                    out.nonfinite = true;
+                    return out;
+                }
+                if (std::sqrt(rn2) <= target || out.iters >= max_iter || k + 1 == m) break;
+                if (M) (*M)(P + (k + 1) * hb, r);
+            }
         }
         // back-substitution: alpha_j = c_j gamma_j + sum_{k > j} c_k beta_jk
         HIP_CHECK(hipMemcpyAsync(gam.data(), sc_ptr(w, S_GAM), n * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -12,9 +12,9 @@ from oracle import dirac as odirac
 from oracle import geometry as geo
 
 
-# number of launch shapes in the hop kernel's shape table (csrc/hop.hip), which DIRAC_HOP_SHAPE
+# number of launch shapes in the hop kernel's shape table (csrc/hop_kernels.h), which DIRAC_HOP_SHAPE
 # indexes; test_abi checks it against the table and bench.py's names
-N_HOP_SHAPES = 41
+N_HOP_SHAPES = 46
 
 
 def need_gpu():

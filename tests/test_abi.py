@@ -66,7 +66,7 @@ def test_hop_shape_count_matches_table_and_bench_names():
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from gpu_util import N_HOP_SHAPES
 
-    src = open(os.path.join(ROOT, "paper_2502_02490_amd", "csrc", "hop.hip")).read()
+    src = open(os.path.join(ROOT, "paper_2502_02490_amd", "csrc", "hop_kernels.h")).read()
     table = re.search(r"const HopShape kShapes\[\] = \{(.*?)\};", src, flags=re.S).group(1)
     assert len(re.findall(r"\{[^{}]*\}", table)) == N_HOP_SHAPES
     tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())

@@ -224,7 +224,7 @@ def test_multi_rhs_schur_equals_single(case, prec, monkeypatch):
         singles.append(one)
     one_dag = torch.zeros_like(nats[nr - 1])
     D.apply_eo(one_dag, nats[nr - 1], prec, "native", dagger=True)
-    for shape in (None, 20, 21, 22, 23, 24, 25, 26, 27, 38, 39):
+    for shape in (None, 20, 21, 22, 23, 24, 25, 26, 27, 38, 39, 41, 42, 43, 44, 45):
         if shape is not None:
             monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
         out = torch.zeros_like(inp)
@@ -234,6 +234,51 @@ def test_multi_rhs_schur_equals_single(case, prec, monkeypatch):
         dag = torch.zeros_like(inp)
         D.apply_eo_multi(dag, inp, nr, prec, dagger=True)
         assert torch.equal(dag[(nr - 1) * n:], one_dag), shape
+
+
+# shapes of the right-hand-side blocked column walk (k_hop_rbc in csrc/hop_kernels.h)
+COLUMN_SHAPES = (41, 42, 43, 44, 45)
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 16, 32), (4, 8, 12, 48)], ids=lambda d: "x".join(map(str, d)))
+def test_column_walk_equals_single_applies(monkeypatch, dims):
+    """The column walk keeps each -t half-spinor in registers for two time slices instead of
+    loading it again: with 12 and 7 right-hand sides (all waves busy, and some idle) its Schur
+    output and that of its dagger equal single applies bit for bit in FP32, FP16 and BF16.
+    (8, 8, 16, 32): 32 spatial blocks per slice (the x1-split order applies) in two chunks of four
+    slices, so the kept half-spinors cross no chunk boundary; (4, 8, 12, 48): 36 blocks (plain
+    order), one chunk of four slices."""
+    need_gpu()
+    c = Case(dims, seed=61, qhat=2)
+    try:
+        for prec in ("f32", "f16", "bf16"):
+            for nr in (12, 7):
+                flush(f"[gpu] column walk {dims} {prec} nrhs={nr}")
+                vecs = [c.spinor(70 + r)[c.even] for r in range(nr)]
+                nats = [c.D.to_native(to_dev(v.astype(np.complex64) if prec == "f32" else v), prec, "eo", sites=1)
+                        for v in vecs]
+                monkeypatch.setenv("DIRAC_HOP_SHAPE", "0")
+                singles, sdag = [], []
+                for r in range(nr):
+                    one = torch.zeros_like(nats[r])
+                    c.D.apply_eo(one, nats[r], prec, "native")
+                    singles.append(one)
+                    d = torch.zeros_like(nats[r])
+                    c.D.apply_eo(d, nats[r], prec, "native", dagger=True)
+                    sdag.append(d)
+                inp = torch.cat(nats)
+                n = nats[0].numel()
+                for shape in COLUMN_SHAPES:
+                    monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
+                    out = torch.zeros_like(inp)
+                    c.D.apply_eo_multi(out, inp, nr, prec)
+                    dag = torch.zeros_like(inp)
+                    c.D.apply_eo_multi(dag, inp, nr, prec, dagger=True)
+                    for r in range(nr):
+                        assert torch.equal(out[r * n:(r + 1) * n], singles[r]), (prec, nr, shape, r)
+                        assert torch.equal(dag[r * n:(r + 1) * n], sdag[r]), (prec, nr, shape, r, "dagger")
+    finally:
+        c.D.close()
 
 
 def test_multi_rhs_shapes_on_x1split_lattice(monkeypatch):
