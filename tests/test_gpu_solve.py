@@ -56,6 +56,28 @@ def test_eo_gcr_f64_tight(cfg1, layout):
     assert osolvers.rel_residual(c.f, xs, eta) < 2e-12
 
 
+def test_gcr_polls_convergence_every_four_iterations():
+    """Plain GCR decides convergence on the device and the host reads it every 4 iterations: a
+    solve with restarts waits on the device at most iters / 4 + 4 times per cycle (the cycle's
+    last poll, the back-substitution and the true-residual reads) + 4 (set-up and final checks),
+    and its solution is the oracle's.  Restarts of 5 (not a multiple of 4) make the last poll of a
+    cycle fall on its last iteration."""
+    need_gpu()
+    c = Case((8, 8, 8, 8), eps=0.4, kappa=0.124, seed=111)
+    try:
+        eta = c.spinor(111)
+        for restart in (32, 5):
+            x = torch.zeros_like(to_dev(eta))
+            info = c.D.solve(x, to_dev(eta), method=P.GCR, tol=1e-11, restart=restart, layout="lex")
+            cycles = info.restarts + 1
+            flush(f"[gpu] GCR({restart}) 8^4: {info.iters} iterations, {cycles} cycles, {info.host_syncs} host waits")
+            assert info.true_rel_res < 1e-11
+            assert info.host_syncs <= info.iters // 4 + 4 * cycles + 4, (restart, info.iters, info.host_syncs)
+            assert osolvers.rel_residual(c.f, x.cpu().numpy(), eta) < 2e-11
+    finally:
+        c.D.close()
+
+
 @pytest.mark.parametrize("inner,itol", [("f32", None), ("f16", None), ("bf16", None)])
 def test_mixed_precision_config1(cfg1, inner, itol):
     c, eta, exact = cfg1
