@@ -62,7 +62,9 @@ HOP_SHAPES = ["k_hop_p bs256 1/CU 2 neighbours/iteration streaming hints (persis
               "k_hop_px bs256 3/CU 4 neighbours/iteration streaming hints (x1-split sweep)",
               "k_hop_rbc 12 waves x 1 RHS, column walk, x1-split", "k_hop_rbc 8 waves x 2 RHS, column walk, x1-split",
               "k_hop_rbc 4 waves x 3 RHS, 2/CU, column walk, x1-split", "k_hop_rbc 6 waves x 2 RHS, column walk, x1-split",
-              "k_hop_rbc 12 waves x 1 RHS, column walk"]
+              "k_hop_rbc 12 waves x 1 RHS, column walk",
+              "k_hop_rbc 12 waves x 1 RHS, column walk, x1-split, double-buffered LDS",
+              "k_hop_rbc 8 waves x 2 RHS, column walk, x1-split, double-buffered LDS"]
 
 # The FP64 hop + A chi kernel of each launch shape, as rocprofv3 names it, and its grid in
 # work-items on 32^3 x 64 (V/2 = 1,048,576 output sites, 256 compute units): the key of its row in
@@ -359,6 +361,19 @@ def batched_suite():
     torch.cuda.synchronize()
     t_seq_mixed = time.perf_counter() - t2
     worst = max(i.true_rel_res for row in infos for i in row)
+    # the same batch with BF16 inner solves (GCR(16) inside), which the mixed scheme also offers
+    xb = [torch.zeros_like(b) for b in bs]
+    P.solve_batched(ops, xb, bs, 12, method=P.MIXED_GCR, inner_prec="bf16", tol=1e-10, restart=16)
+    xb = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    infb = P.solve_batched(ops, xb, bs, 12, method=P.MIXED_GCR, inner_prec="bf16", tol=1e-10, restart=16)
+    torch.cuda.synchronize()
+    t_bf16 = time.perf_counter() - t3
+    worst_bf16 = max(i.true_rel_res for row in infb for i in row)
+    diff_bf16 = max((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
+                    for xa, xf in zip(xb, xs) for a, b in zip(xa, xf))
+    del xb
     for D in ops:
         D.close()
     return {"lattices": ["x".join(map(str, d)) for d in BATCH_DIMS], "nrhs": 12, "inner_restart": BATCH_INNER_RESTART,
@@ -367,6 +382,9 @@ def batched_suite():
             "sequential_mixed_f32_seconds": round(t_seq_mixed, 4),
             "speedup_vs_sequential_mixed_f32": round(t_seq_mixed / t_batched, 3), "worst_true_rel_res": worst,
             "max_rel_diff_vs_fp64": err, "fp64_total_iters": iters,
+            "batched_mixed_bf16_seconds": round(t_bf16, 4), "batched_mixed_bf16_worst_true_rel_res": worst_bf16,
+            "batched_mixed_bf16_max_rel_diff_vs_f32": diff_bf16,
+            "batched_mixed_bf16_speedup_vs_sequential_fp64": round(t_seq / t_bf16, 3),
             "inner_iters_per_lattice": [max(i.iters for i in row) for row in infos],
             "host_syncs": infos[0][0].host_syncs}
 

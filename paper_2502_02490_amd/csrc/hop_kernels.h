@@ -469,7 +469,9 @@ DEV void dir_lds(const T *lk, int lane, const C<T> psi[12], C<T> acc[12]) {
     apply_lds<T, DAG, N>(lk, lane, h, acc);
 }
 
-template <typename S, int DAG, int MODE, int NW, int R, bool X1S>
+// DB: the staging data is double-buffered in LDS, so a slice's data is written while the previous
+// slice is still being computed from the other buffer (one barrier per slice instead of two).
+template <typename S, int DAG, int MODE, int NW, int R, bool X1S, bool DB>
 __global__ __launch_bounds__(64 * NW) void k_hop_rbc(HopArgs<S> a, int tc) {
     using T = typename St<S>::acc;
     using V = typename St<S>::vec;
@@ -481,9 +483,10 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rbc(HopArgs<S> a, int tc) {
     constexpr int NTH = 64 * NW;
     constexpr int LI = (8 * kSB + NTH - 1) / NTH;                               // link items per thread
     constexpr int CI = MODE != HOP_PLAIN ? (CP * kSB + NTH - 1) / NTH : 1;     // clover vectors per thread
-    __shared__ T s_lk[8 * NL * kSB];
-    __shared__ uint32_t s_nb[8 * kSB];
-    __shared__ V s_cl[MODE != HOP_PLAIN ? CP * kSB : 1];
+    constexpr int NB = DB ? 2 : 1;  // LDS buffers
+    __shared__ T s_lk[NB][8 * NL * kSB];
+    __shared__ uint32_t s_nb[NB][8 * kSB];
+    __shared__ V s_cl[NB][MODE != HOP_PLAIN ? CP * kSB : 1];
     const int nsb = a.g.vh / (a.g.L[0] * kSB);  // spatial blocks per time slice
     int sb, ch;
     if constexpr (X1S) {
@@ -523,8 +526,8 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rbc(HopArgs<S> a, int tc) {
             }
         }
     };
-    // rebuild slice t's staging data and write it to LDS
-    auto commit = [&](int t) {
+    // rebuild slice t's staging data and write it to LDS buffer bf
+    auto commit = [&](int t, int bf) {
         const int blk = t * nsb + sb;
 #pragma unroll
         for (int k = 0; k < LI; ++k) {
@@ -535,7 +538,7 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rbc(HopArgs<S> a, int tc) {
                 int x[4];
                 site_coords(a.g, ii, a.p, x);
                 const int row = (x[0] * a.g.L[1] + x[1]) * a.g.L[2] + x[2];
-                s_nb[item] = neighbour(a, x, row, n);
+                s_nb[bf][item] = neighbour(a, x, row, n);
                 T r[12];
 #pragma unroll
                 for (int q = 0; q < 12 / LW; ++q) Lk<S>::unpack(lraw[k][q], r + q * LW);
@@ -546,7 +549,7 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rbc(HopArgs<S> a, int tc) {
                 if constexpr (Lk<S>::phase_pair) Lk<S>::phase(oraw[k], co, si);
                 else sc((T)oraw[k], si, co);
                 third_row(u, r2);
-                T *d = s_lk + (size_t)n * NL * kSB + ln;
+                T *d = s_lk[bf] + (size_t)n * NL * kSB + ln;
 #pragma unroll
                 for (int q = 0; q < 6; ++q) {
                     d[(2 * q) * kSB] = u[q].r;
@@ -565,20 +568,23 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rbc(HopArgs<S> a, int tc) {
 #pragma unroll
             for (int k = 0; k < CI; ++k) {
                 const int item = tid + k * NTH;
-                if (item < CP * kSB) s_cl[item] = craw[k];
+                if (item < CP * kSB) s_cl[bf][item] = craw[k];
             }
         }
     };
-    const LdsBlock<S> L{s_lk, s_nb, s_cl};
     C<T> carry[R][2][6];  // [slot][k & 1]: -t half-spinor of the slice loaded as +t neighbour at step k
     // one time slice (step k of the chunk) with the carry slot SL = k & 1 fixed at compile time
     auto step = [&](int k, auto slot) {
         constexpr int SL = decltype(slot)::value;
         const int t = t0 + k;
-        __syncthreads();  // the previous slice's LDS data has been read
-        commit(t);
-        __syncthreads();
-        if (k + 1 < tc) fetch(t + 1);  // in flight during this slice's arithmetic
+        const int bf = DB ? SL : 0;  // buffer of slice t: k & 1 (= SL) with double buffering
+        if constexpr (!DB) {
+            __syncthreads();  // the previous slice's LDS data has been read
+            commit(t, 0);
+            __syncthreads();
+            if (k + 1 < tc) fetch(t + 1);  // in flight during this slice's arithmetic
+        }
+        const LdsBlock<S> L{s_lk[bf], s_nb[bf], s_cl[bf]};
         const uint32_t ii = (uint32_t)((t * nsb + sb) * kSB + lane);
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -621,8 +627,22 @@ __global__ __launch_bounds__(64 * NW) void k_hop_rbc(HopArgs<S> a, int tc) {
             dir_lds<T, DAG, 7>(L.lk, lane, pb, acc);
             hop_finish<S, MODE, true, true>(b, ii, acc, &L);
         }
+        if constexpr (DB) {
+            // the next slice into the other buffer (last read in the previous slice, before the
+            // barrier that ended it), then the loads of the one after it
+            if (k + 1 < tc) {
+                commit(t + 1, SL ^ 1);
+                if (k + 2 < tc) fetch(t + 2);
+            }
+            __syncthreads();
+        }
     };
     fetch(t0);
+    if constexpr (DB) {
+        commit(t0, 0);
+        if (tc > 1) fetch(t0 + 1);
+        __syncthreads();
+    }
 #pragma nounroll
     for (int k = 0; k < tc; k += 2) {
         step(k, std::integral_constant<int, 0>());
@@ -762,7 +782,7 @@ __global__ __launch_bounds__(64 * TT) void k_hop_tp(HopArgs<S> a, int nwg) {
 }
 
 struct HopShape {
-    int bs, xcd, tt, pers, slab, npi, nt, mr, rb, pf, x1s, cw, cr;
+    int bs, xcd, tt, pers, slab, npi, nt, mr, rb, pf, x1s, cw, cr, db;
 };
 // Shape 0 is the default (used when tuning is off, and inside a graph capture before the key
 // was tuned): the persistent sweep, one 256-wide work-group per compute unit, two neighbours per
@@ -773,7 +793,8 @@ struct HopShape {
 // side blocked kernel with rb wavefronts per work-group (link work and clover block in LDS), pf:
 // its next-direction prefetch; x1s: the x1-split sweep (or block order); cw: the right-hand-side
 // blocked column walk with cw wavefronts per work-group and at most cr right-hand sides each,
-// pers work-groups per compute unit wanted (16-bit and FP32 storage only).
+// pers work-groups per compute unit wanted (16-bit and FP32 storage only), db: its LDS staging
+// double-buffered.
 const HopShape kShapes[] = {
     {256, 0, 0, 1, 0, 2, 1, 1}, {256, 0, 0, 1, 0, 1, 1, 1}, {256, 0, 0, 2, 0, 1, 1, 1}, {256, 0, 0, 1, 0, 1, 0, 1},
     {256, 0, 0, 1, 0, 2, 0, 1}, {256, 1, 0, 0, 0, 1, 0, 1}, {256, 0, 0, 0, 0, 1, 0, 1}, {128, 1, 0, 0, 0, 1, 0, 1},
@@ -789,7 +810,8 @@ const HopShape kShapes[] = {
     {256, 0, 0, 0, 0, 1, 1, 1, 4, 1, 1}, {512, 0, 0, 0, 0, 1, 1, 1, 8, 1, 1}, {256, 0, 0, 3, 0, 4, 1, 1, 0, 0, 1},
     {768, 0, 0, 1, 0, 1, 1, 1, 0, 0, 1, 12, 1}, {512, 0, 0, 1, 0, 1, 1, 1, 0, 0, 1, 8, 2},
     {256, 0, 0, 2, 0, 1, 1, 1, 0, 0, 1, 4, 3}, {384, 0, 0, 1, 0, 1, 1, 1, 0, 0, 1, 6, 2},
-    {768, 0, 0, 1, 0, 1, 1, 1, 0, 0, 0, 12, 1}};
+    {768, 0, 0, 1, 0, 1, 1, 1, 0, 0, 0, 12, 1}, {768, 0, 0, 1, 0, 1, 1, 1, 0, 0, 1, 12, 1, 1},
+    {512, 0, 0, 1, 0, 1, 1, 1, 0, 0, 1, 8, 2, 1}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 template <typename S> constexpr int num_shapes() { return kNumShapes; }
 
@@ -889,7 +911,7 @@ void launch_tiled(HopArgs<S> a, hipStream_t s) {
 
 // Column walk: chunks of tc time slices, tc the largest divisor of L0 of at least 4 slices (or
 // L0 itself) that still gives per_cu work-groups per compute unit where the lattice allows.
-template <typename S, int DAG, int MODE, int NW, int R>
+template <typename S, int DAG, int MODE, int NW, int R, bool DB = false>
 void launch_rbc(HopArgs<S> a, int per_cu, bool x1s, hipStream_t s) {
     const int L0 = a.g.L[0];
     const int nsb = a.g.vh / (L0 * kSB);
@@ -905,8 +927,8 @@ void launch_rbc(HopArgs<S> a, int per_cu, bool x1s, hipStream_t s) {
     const int grid = nsb * nch;
     a.xcd = 0;
     a.nb8 = grid;
-    if (x1s && nsb % 8 == 0) k_hop_rbc<S, DAG, MODE, NW, R, true><<<grid, 64 * NW, 0, s>>>(a, tc);
-    else k_hop_rbc<S, DAG, MODE, NW, R, false><<<grid, 64 * NW, 0, s>>>(a, tc);
+    if (x1s && nsb % 8 == 0) k_hop_rbc<S, DAG, MODE, NW, R, true, DB><<<grid, 64 * NW, 0, s>>>(a, tc);
+    else k_hop_rbc<S, DAG, MODE, NW, R, false, DB><<<grid, 64 * NW, 0, s>>>(a, tc);
 }
 
 template <typename S, int DAG, int MODE, int NW>
@@ -935,7 +957,9 @@ void launch_hop(const HopArgs<S> &a, int shape, hipStream_t s) {
         h = kShapes[0];  // does not fit
     if (h.cw) {
         if constexpr (!std::is_same<S, double>::value) {
-            if (h.cw == 12) launch_rbc<S, DAG, MODE, 12, 1>(a, h.pers, h.x1s != 0, s);
+            if (h.cw == 12 && h.db) launch_rbc<S, DAG, MODE, 12, 1, true>(a, h.pers, h.x1s != 0, s);
+            else if (h.cw == 8 && h.db) launch_rbc<S, DAG, MODE, 8, 2, true>(a, h.pers, h.x1s != 0, s);
+            else if (h.cw == 12) launch_rbc<S, DAG, MODE, 12, 1>(a, h.pers, h.x1s != 0, s);
             else if (h.cw == 8) launch_rbc<S, DAG, MODE, 8, 2>(a, h.pers, h.x1s != 0, s);
             else if (h.cw == 6) launch_rbc<S, DAG, MODE, 6, 2>(a, h.pers, h.x1s != 0, s);
             else launch_rbc<S, DAG, MODE, 4, 3>(a, h.pers, h.x1s != 0, s);

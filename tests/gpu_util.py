@@ -14,7 +14,7 @@ from oracle import geometry as geo
 
 # number of launch shapes in the hop kernel's shape table (csrc/hop_kernels.h), which DIRAC_HOP_SHAPE
 # indexes; test_abi checks it against the table and bench.py's names
-N_HOP_SHAPES = 46
+N_HOP_SHAPES = 48
 
 
 def need_gpu():

@@ -224,7 +224,7 @@ def test_multi_rhs_schur_equals_single(case, prec, monkeypatch):
         singles.append(one)
     one_dag = torch.zeros_like(nats[nr - 1])
     D.apply_eo(one_dag, nats[nr - 1], prec, "native", dagger=True)
-    for shape in (None, 20, 21, 22, 23, 24, 25, 26, 27, 38, 39, 41, 42, 43, 44, 45):
+    for shape in (None, 20, 21, 22, 23, 24, 25, 26, 27, 38, 39, 41, 42, 43, 44, 45, 46, 47):
         if shape is not None:
             monkeypatch.setenv("DIRAC_HOP_SHAPE", str(shape))
         out = torch.zeros_like(inp)
@@ -237,7 +237,7 @@ def test_multi_rhs_schur_equals_single(case, prec, monkeypatch):
 
 
 # shapes of the right-hand-side blocked column walk (k_hop_rbc in csrc/hop_kernels.h)
-COLUMN_SHAPES = (41, 42, 43, 44, 45)
+COLUMN_SHAPES = (41, 42, 43, 44, 45, 46, 47)
 
 
 @pytest.mark.parametrize("dims", [(8, 8, 16, 32), (4, 8, 12, 48)], ids=lambda d: "x".join(map(str, d)))

@@ -77,11 +77,13 @@ def test_config3_48c96_solves_sampled_residual():
         D.close()
 
 
-def test_config4_lattices_batched_point_sources():
+@pytest.mark.parametrize("inner", ["f32", "bf16"])
+def test_config4_lattices_batched_point_sources(inner):
     """The batched workload's 16^3 x 32 lattice (kappa_2 = 0.120 + 0.005 * 2 / 7, seed 403) and 8^4
     lattice (kappa_0 = 0.120, seed 401) with 12 spin-colour point sources at the origin each,
-    FP64 defect correction around batched FP32 GCR: every solution's residual recomputed by the
-    oracle at the source's neighbourhood and at random sites."""
+    FP64 defect correction around batched FP32 GCR (the configuration) and around batched BF16
+    GCR(16): every solution's residual recomputed by the oracle at the source's neighbourhood and
+    at random sites."""
     need_gpu()
     lat = [((32, 16, 16, 16), 0.120 + 0.005 * 2 / 7, 403), ((8, 8, 8, 8), 0.120, 401)]
     cases = []
@@ -98,7 +100,7 @@ def test_config4_lattices_batched_point_sources():
             bs.append(bb)
         xs = [torch.zeros((12, c.V, 4, 3), dtype=torch.complex128, device="cuda") for c in cases]
         infos = P.solve_batched([c.D for c in cases], xs, [to_dev(bb) for bb in bs], 12, method=P.MIXED_GCR,
-                                inner_prec="f32", tol=1e-10)
+                                inner_prec=inner, tol=1e-10, restart=8 if inner == "f32" else 16)
         for c, bb, x, row in zip(cases, bs, xs, infos):
             nbh = np.unique(np.concatenate([[0]] + [geo.shift(np.array([0]), c.dims, mu, s, 0)
                                                     for mu in range(4) for s in (1, -1)]))
@@ -108,7 +110,7 @@ def test_config4_lattices_batched_point_sources():
             for r in range(12):
                 assert row[r].true_rel_res < 1e-10
                 worst = max(worst, sampled_residual(c.f, xh[r], bb[r], sites))
-            flush(f"[gpu] batched {c.dims}: worst oracle residual over {len(sites)} sites {worst:.2e}")
+            flush(f"[gpu] batched {inner} {c.dims}: worst oracle residual over {len(sites)} sites {worst:.2e}")
             assert worst <= 1e-10
     finally:
         for c in cases:
