@@ -42,7 +42,7 @@ def sampled_residual(f, x, b, sites):
     return float(np.linalg.norm(r) / np.linalg.norm(b))
 
 
-def test_config3_48c96_solves_sampled_residual():
+def test_48c96_solves_sampled_residual():
     need_gpu()
     dims = (96, 48, 48, 48)
     flush("[gpu] 48^3x96: generating fields")
@@ -78,7 +78,7 @@ def test_config3_48c96_solves_sampled_residual():
 
 
 @pytest.mark.parametrize("inner", ["f32", "bf16"])
-def test_config4_lattices_batched_point_sources(inner):
+def test_batched_point_sources_16c32_and_8c4(inner):
     """The batched workload's 16^3 x 32 lattice (kappa_2 = 0.120 + 0.005 * 2 / 7, seed 403) and 8^4
     lattice (kappa_0 = 0.120, seed 401) with 12 spin-colour point sources at the origin each,
     FP64 defect correction around batched FP32 GCR (the configuration) and around batched BF16

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def case4():
     """4^4, eps = 0.3, kappa = 0.12, c_sw = c_sw^QED = 1, qhat = -1 (the plain-method small case)."""
     need_gpu()
     flush("[gpu] solve case 4^4")
@@ -29,8 +29,8 @@ def cfg1():
     c.D.close()
 
 
-def test_cgls_config1(cfg1):
-    c, eta, exact = cfg1
+def test_cgls_4c4(case4):
+    c, eta, exact = case4
     x = torch.zeros_like(to_dev(eta))
     info = c.D.solve(x, to_dev(eta), method=P.CGLS, tol=1e-10, max_iter=5000)
     xs = x.cpu().numpy()
@@ -41,8 +41,8 @@ def test_cgls_config1(cfg1):
 
 
 @pytest.mark.parametrize("layout", ["lex", "eo"])
-def test_eo_gcr_f64_tight(cfg1, layout):
-    c, eta, exact = cfg1
+def test_eo_gcr_f64_tight(case4, layout):
+    c, eta, exact = case4
     from oracle import geometry as geo
 
     perm = geo.lex_to_eo_perm(c.dims) if layout == "eo" else np.arange(c.V)
@@ -79,8 +79,8 @@ def test_gcr_polls_convergence_every_four_iterations():
 
 
 @pytest.mark.parametrize("inner,itol", [("f32", None), ("f16", None), ("bf16", None)])
-def test_mixed_precision_config1(cfg1, inner, itol):
-    c, eta, exact = cfg1
+def test_mixed_precision_4c4(case4, inner, itol):
+    c, eta, exact = case4
     x = torch.zeros_like(to_dev(eta))
     info = c.D.solve(x, to_dev(eta), method=P.MIXED_GCR, tol=1e-10, inner_prec=inner, max_iter=4000)
     xs = x.cpu().numpy()
@@ -111,16 +111,16 @@ def test_gcr_ragged_mixed_extents():
         c.D.close()
 
 
-def test_warm_start_returns_immediately(cfg1):
-    c, eta, exact = cfg1
+def test_warm_start_returns_immediately(case4):
+    c, eta, exact = case4
     x = to_dev(exact.copy())
     info = c.D.solve(x, to_dev(eta), method=P.GCR, tol=1e-10, x0_given=True)
     assert info.iters == 0 and info.true_rel_res < 1e-10
 
 
 # ---------------------------------------------------------------- failure handling
-def test_max_iter_gives_noconv(cfg1):
-    c, eta, _ = cfg1
+def test_max_iter_gives_noconv(case4):
+    c, eta, _ = case4
     x = torch.zeros_like(to_dev(eta))
     with pytest.raises(P.DiracError) as e:
         c.D.solve(x, to_dev(eta), method=P.GCR, tol=1e-10, max_iter=1)
@@ -129,8 +129,8 @@ def test_max_iter_gives_noconv(cfg1):
     assert info.iters == 1 and info.true_rel_res < 1.0  # best iterate returned
 
 
-def test_nan_rhs_is_reported(cfg1):
-    c, eta, _ = cfg1
+def test_nan_rhs_is_reported(case4):
+    c, eta, _ = case4
     bad = eta.copy()
     bad[7, 1, 2] = np.nan
     x = torch.zeros_like(to_dev(bad))
@@ -140,8 +140,8 @@ def test_nan_rhs_is_reported(cfg1):
         assert e.value.status == P._lib.ENONFINITE
 
 
-def test_argument_errors(cfg1):
-    c, eta, _ = cfg1
+def test_argument_errors(case4):
+    c, eta, _ = case4
     b = to_dev(eta)
     with pytest.raises(P.DiracError) as e:
         c.D.apply(b, b)  # output aliases input
@@ -187,7 +187,7 @@ def test_singular_clover_block_is_reported():
         c.D.close()
 
 
-def test_loaded_clover_is_used(cfg1):
+def test_loaded_clover_is_used(case4):
     """Uploading the clover field the oracle computes (Sec. 4.1.3 path) gives the same operator."""
     need_gpu()
     c = Case((4, 2, 2, 4), seed=9)

@@ -76,7 +76,7 @@ def test_full_residual_equals_schur_residual(small):
     assert np.abs(r[ev] - (eta_hat - dirac.apply_schur(f, psi_e))).max() < 1e-13
 
 
-def test_config1_cgls_and_eo_gcr_agree():
+def test_4c4_cgls_and_eo_gcr_agree():
     """4^4 at the plain-method parameters: CGLS to 1e-10 and even-odd GCR to 1e-12 agree within the
     error bound cond(D) * 1e-10 (cond(D) is about 10 here) and both pass the a-posteriori check."""
     f = cfg1_fields()
