@@ -560,7 +560,7 @@ def ptc_suite(pairs_per_field: int, epochs: int, checkpoint: str | None):
     """Learned preconditioner: PTC networks (the configured (1, 8, 8, 1) and the thin (1, 4, 1) and
     (1, 2, 2, 2, 1)) trained on the same pairs from four 16^3 x 32 fields (seeds 501..504,
     eps = 0.5, kappa = 0.1245, c_sw = 1.6, c_sw^QED = 1.0, qhat = -1), then each deployed in
-    flexible GCR on a 32^3 x 64 field (seed 505) against plain FP64 even-odd GCR(32), all to 1e-10.
+    flexible GCR(8) on a 32^3 x 64 field (seed 505) against plain FP64 even-odd GCR(32), all to 1e-10.
     Pair generation and training time are reported apart from the solves; the network with the
     shortest measured solve is the selected one."""
     import torch

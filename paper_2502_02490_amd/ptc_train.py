@@ -166,19 +166,23 @@ def load_checkpoint(path: str):
     return net, header
 
 
-def compare_solvers(D: Dirac, net: PTC, b: torch.Tensor, tol: float = 1e-10, restart: int = 32, reps: int = 1):
-    """Solve D x = b with plain even-odd FP64 GCR, flexible GCR on D with the network, and
-    flexible GCR on D-hat with the network's even block; returns a dict of iterations, seconds
-    (best of reps) and residuals for each."""
+def compare_solvers(D: Dirac, net: PTC, b: torch.Tensor, tol: float = 1e-10, restart: int = 32, reps: int = 1,
+                    flex_restart: int = 8):
+    """Solve D x = b with plain even-odd FP64 GCR(restart), flexible GCR(flex_restart) on D with
+    the network, and flexible GCR(flex_restart) on D-hat with the network's even block; returns a
+    dict of iterations, restart lengths, seconds (best of reps) and residuals for each.  The
+    flexible forms take the same iterations at restart 8 as at 32 on the 32^3 x 64 field of the
+    measurements, for a quarter of the orthogonalisation work."""
     out = {}
-    for name, kw in (("eo_gcr", dict(method=GCR)), ("fgcr_ptc", dict(method=FGCR_PTC, ptc=net)),
-                     ("fgcr_ptc_eo", dict(method=FGCR_PTC_EO, ptc=net))):
+    for name, kw in (("eo_gcr", dict(method=GCR, restart=restart)),
+                     ("fgcr_ptc", dict(method=FGCR_PTC, ptc=net, restart=flex_restart)),
+                     ("fgcr_ptc_eo", dict(method=FGCR_PTC_EO, ptc=net, restart=flex_restart))):
         best = None
         for _ in range(reps):
             x = torch.zeros_like(b)
-            info = D.solve(x, b, tol=tol, restart=restart, max_iter=20000, **kw)
+            info = D.solve(x, b, tol=tol, max_iter=20000, **kw)
             if best is None or info.seconds < best.seconds:
                 best = info
-        out[name] = {"iters": best.iters, "restarts": best.restarts, "seconds": best.seconds,
+        out[name] = {"iters": best.iters, "restart": kw["restart"], "restarts": best.restarts, "seconds": best.seconds,
                      "true_rel_res": best.true_rel_res, "fell_back": bool(best.fell_back)}
     return out
