@@ -92,3 +92,31 @@ def test_batched_gaussian_rhs_and_f16(lattices):
         exact, _ = osolvers.solve_eo(c.f, b[r], 1e-13)
         assert rel(x[r].cpu().numpy(), exact) < 1e-8
     assert all(i.true_rel_res < 1e-10 for i in infos[0])
+
+
+@pytest.mark.parametrize("shape", [41, 46])
+def test_batched_column_walk_with_frozen_systems(monkeypatch, shape):
+    """The batched mixed solve on a lattice where the column walk fits (8 x 8 x 16 x 32, 12 point
+    sources at two sites, so the systems converge after different iterations and the active mask
+    freezes some while the others go on), with its inner FP32 operator forced to a column-walk
+    shape (single- or double-buffered), gives bitwise the solutions of the default shape, and the
+    oracle's residual of one solution is below the tolerance."""
+    need_gpu()
+    c = Case((8, 8, 16, 32), kappa=0.124, seed=404)
+    try:
+        b = point_sources(c.dims)
+        b[6:] = point_sources(c.dims, site=c.V // 2 + 37)[6:]
+        sols = {}
+        for sh in (None, shape):
+            if sh is not None:
+                monkeypatch.setenv("DIRAC_HOP_SHAPE", str(sh))
+            x = torch.zeros_like(to_dev(b))
+            infos = P.solve_batched([c.D], [x], [to_dev(b)], 12, method=P.MIXED_GCR, inner_prec="f32", tol=1e-10,
+                                    restart=8)
+            its = [i.iters for i in infos[0]]
+            flush(f"[gpu] batched column walk shape {sh}: iterations {its}")
+            sols[sh] = x.cpu().numpy()
+        assert np.array_equal(sols[None], sols[shape])
+        assert osolvers.rel_residual(c.f, sols[shape][9], b[9]) < 1e-10
+    finally:
+        c.D.close()
