@@ -106,35 +106,77 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
     load_sp(a.rho + spinor_at(k, t), r);
     if (a.update) {
         // rho += 1/2 H delta over the faces of the block: the previous step's corrections live on
-        // the neighbouring blocks (the other colour)
+        // the neighbouring blocks (the other colour).  The 8 faces of 64 sites are taken face by
+        // face, wavefront w the faces of directions w (first pass) and w + 4 (second pass), so no
+        // lane idles; each face term, formed from zero, goes through LDS (the residual tile, free
+        // until the minimal-residual steps) to its site, which adds its terms in direction order.
+        float *fb = reinterpret_cast<float *>(&rs[0][0]);  // [4 directions][24 reals][64 face sites]
         C<float> acc[12];
 #pragma unroll
         for (int q = 0; q < 12; ++q) acc[q] = mk(0.f, 0.f);
-        int x[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) x[m] = kSapB * n[m] + b[m];
-#pragma nounroll
-        for (int d = 0; d < 8; ++d) {
-            const int mu = d >> 1, back = d & 1;
-            const int bm = mu == 0 ? b[0] : mu == 1 ? b[1] : mu == 2 ? b[2] : b[3];
-            if (back ? bm != 0 : bm != kSapB - 1) continue;  // the neighbour is inside the block
-            // the neighbour across the face, with the lattice wrap and the C* mirror shift
-            int y[4] = {x[0], x[1], x[2], x[3]};
-            const int Lm = a.g.L[mu];
-            const int ym = mu == 0 ? y[0] : mu == 1 ? y[1] : mu == 2 ? y[2] : y[3];
-            const bool cross = back ? ym == 0 : ym == Lm - 1;
-            const int yn = back ? (ym == 0 ? Lm - 1 : ym - 1) : (ym == Lm - 1 ? 0 : ym + 1);
-            if (mu == 0) y[0] = yn; else if (mu == 1) y[1] = yn; else if (mu == 2) y[2] = yn; else y[3] = yn;
-            y[1] = cstar_x1(a.g, mu, cross, y[1]);
-            int nn[4];
+        for (int pass = 0; pass < 2; ++pass) {
+            {
+                // face site `lane` of direction d: b_mu on the face, the other coordinates from lane
+                const int d = 4 * pass + wave, mu = d >> 1, back = d & 1;
+                int bf[4], o = 0;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) nn[m] = y[m] / kSapB;
-            const int tn = ((y[0] % kSapB) * kSapB + (y[1] % kSapB)) * kSapB * kSapB + (y[2] % kSapB) * kSapB + (y[3] % kSapB);
-            C<float> nb[12], u[6];
-            float co, si;
-            load_sp(a.dlt + spinor_at(block_of(a, nn), tn), nb);
-            load_blink(a, k, d, t, u, co, si);
-            accumulate_dir<float, 0>(d, nb, u, co, si, acc);
+                for (int m = 3; m >= 0; --m) {
+                    if (m == mu) {
+                        bf[m] = back ? 0 : kSapB - 1;
+                    } else {
+                        bf[m] = (lane >> (2 * o)) & 3;
+                        ++o;
+                    }
+                }
+                const int tf = ((bf[0] * kSapB + bf[1]) * kSapB + bf[2]) * kSapB + bf[3];
+                int y[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) y[m] = kSapB * n[m] + bf[m];
+                // the neighbour across the face, with the lattice wrap and the C* mirror shift
+                const int Lm = a.g.L[mu];
+                const int ym = y[mu];
+                const bool cross = back ? ym == 0 : ym == Lm - 1;
+                const int yn = back ? (ym == 0 ? Lm - 1 : ym - 1) : (ym == Lm - 1 ? 0 : ym + 1);
+                if (mu == 0) y[0] = yn; else if (mu == 1) y[1] = yn; else if (mu == 2) y[2] = yn; else y[3] = yn;
+                y[1] = cstar_x1(a.g, mu, cross, y[1]);
+                int nn[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) nn[m] = y[m] / kSapB;
+                const int tn = ((y[0] % kSapB) * kSapB + (y[1] % kSapB)) * kSapB * kSapB + (y[2] % kSapB) * kSapB + (y[3] % kSapB);
+                C<float> nb[12], u[6], v[12];
+                float co, si;
+                load_sp(a.dlt + spinor_at(block_of(a, nn), tn), nb);
+                load_blink(a, k, d, tf, u, co, si);
+#pragma unroll
+                for (int q = 0; q < 12; ++q) v[q] = mk(0.f, 0.f);
+                accumulate_dir<float, 0>(d, nb, u, co, si, v);
+                float *dst = fb + (size_t)wave * 24 * 64 + lane;
+#pragma unroll
+                for (int q = 0; q < 12; ++q) {
+                    dst[(2 * q) * 64] = v[q].r;
+                    dst[(2 * q + 1) * 64] = v[q].i;
+                }
+            }
+            __syncthreads();
+            // this site's terms of the pass's four directions, in direction order
+#pragma unroll
+            for (int dd = 0; dd < 4; ++dd) {
+                const int d = 4 * pass + dd, mu = d >> 1, back = d & 1;
+                const int bm = mu == 0 ? b[0] : mu == 1 ? b[1] : mu == 2 ? b[2] : b[3];
+                if (back ? bm != 0 : bm != kSapB - 1) continue;  // not on this face
+                int f = 0, o = 0;
+#pragma unroll
+                for (int m = 3; m >= 0; --m) {
+                    if (m == mu) continue;
+                    f |= b[m] << (2 * o);
+                    ++o;
+                }
+                const float *src = fb + (size_t)dd * 24 * 64 + f;
+#pragma unroll
+                for (int q = 0; q < 12; ++q) acc[q] = mk(acc[q].r + src[(2 * q) * 64], acc[q].i + src[(2 * q + 1) * 64]);
+            }
+            __syncthreads();  // the pass's terms are read before the next pass (or the residual tile) overwrites them
         }
 #pragma unroll
         for (int q = 0; q < 12; ++q) r[q] = mk(fmaf(0.5f, acc[q].r, r[q].r), fmaf(0.5f, acc[q].i, r[q].i));
