@@ -51,6 +51,27 @@ def test_sap_matches_oracle(case):
     assert torch.equal(out, o2)
 
 
+def test_sap_four_blocks_in_time():
+    """A lattice four blocks long in time (antiperiodic, with phases in space): the face update of
+    the second colour step takes the corrections of the blocks on both sides in time, which are
+    different blocks here (with two blocks in a direction the block ahead and the block behind
+    are the same block)."""
+    need_gpu()
+    flush("[gpu] sap case (16, 8, 8, 8)")
+    c = Case((16, 8, 8, 8), seed=34, bc_phase=(math.pi, 0.3, 0.0, -0.2))
+    try:
+        r = c.spinor(1).astype(np.complex64).astype(np.complex128)
+        exp = osap.sap(c.f, r, (4, 4, 4, 4), ncy=1, nmr=2)
+        inp = c.D.to_native(to_dev(r.astype(np.complex64)), "f32", "lex")
+        out = torch.empty_like(inp)
+        c.D.sap(out, inp, ncy=1, nmr=2)
+        err = rel(c.D.from_native(out, "f32", "lex").cpu().numpy().astype(np.complex128), exp)
+        flush(f"[gpu] SAP 16x8x8x8 vs oracle {err:.2e}")
+        assert err < 1e-5
+    finally:
+        c.D.close()
+
+
 def test_fgcr_sap_solve(case):
     b = case.spinor(2)
     x = torch.zeros_like(to_dev(b))
