@@ -246,7 +246,10 @@ def solve_suite(D, b, inner_precs):
 # once per block solve (held in registers and LDS over its minimal-residual steps, whatever their
 # number); a site takes one step per cycle
 def sap_bytes_per_site(ncy, nmr):
-    return ncy * (5 * 96 + 2 * (96 + 52) + 288 + 3 * 52)
+    # per cycle (each site in one colour step): residual read and written, solution read and
+    # written, correction written, the face neighbours' corrections and links, clover block and
+    # in-block links; the first cycle reads no solution (it starts at zero)
+    return ncy * (5 * 96 + 2 * (96 + 52) + 288 + 3 * 52) - 96
 
 
 SAP_SETTINGS = ((2, 4), (4, 4), (4, 6))

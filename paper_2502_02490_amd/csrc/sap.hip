@@ -29,14 +29,19 @@ constexpr int kSapInner = kSapSites / kSapB * (kSapB - 1);  // 192 sites of a bl
 // block, so that a work-group reads one contiguous chunk and every wavefront load is 1 KB of
 // consecutive 16-byte vectors:  spinor [k][6][256], clover [k][18][256], links [k][8][4][256].
 // (The sites of a 4^4 block lie in 2-site pieces of the x3-fastest NATIVE order: read from there,
-// every wavefront load touches 32 cache lines for 32 bytes each.)
+// every wavefront load touches 32 cache lines for 32 bytes each.  The first cycle reads the
+// residual from there all the same, which costs less than a separate reordering pass; the
+// solution goes back through one, as scattered 32-byte writes of partial cache lines from the
+// last cycle's steps cost more than the pass.)
 struct SapArgs {
     Geom g;
     const float4 *links;  // block order
     const float4 *clov;   // block order
     float4 *rho, *psi, *dlt;  // block order, all blocks
+    const float4 *rin;    // NATIVE input residual, read instead of rho when set (the first cycle)
     int nb[4];            // blocks per direction
     int colour, nmr, update;
+    int first;            // the first cycle: psi is zero, so psi = delta
 };
 
 DEV int block_of(const SapArgs &a, const int n[4]) { return ((n[0] * a.nb[1] + n[1]) * a.nb[2] + n[2]) * a.nb[3] + n[3]; }
@@ -102,8 +107,25 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
     sap_block(a, blockIdx.x, n);
     const int k = block_of(a, n);
 
+    // the site's position in the NATIVE full vectors (parity-major, 6 planes per site)
+    int xs[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) xs[m] = kSapB * n[m] + b[m];
+    const int par = (xs[0] + xs[1] + xs[2] + xs[3]) & 1;
+    const int hi = half_index(a.g, xs);
+    const size_t nat = (size_t)par * 6 * a.g.vhp + (size_t)(hi >> 6) * 6 * kSB + (hi & (kSB - 1));
+
     C<float> r[12];
-    load_sp(a.rho + spinor_at(k, t), r);
+    if (a.rin) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const float4 v = a.rin[nat + q * kSB];
+            r[2 * q] = mk(v.x, v.y);
+            r[2 * q + 1] = mk(v.z, v.w);
+        }
+    } else {
+        load_sp(a.rho + spinor_at(k, t), r);
+    }
     if (a.update) {
         // rho += 1/2 H delta over the faces of the block: the previous step's corrections live on
         // the neighbouring blocks (the other colour).  The 8 faces of 64 sites are taken face by
@@ -280,9 +302,14 @@ __global__ __launch_bounds__(kSapSites) void k_sap_step(SapArgs a) {
     // psi += delta, rho = the block residual, delta kept for the next step's face update
     float4 *ps = a.psi + spinor_at(k, t);
     C<float> o[12];
-    load_sp(ps, o);
+    if (a.first) {
 #pragma unroll
-    for (int q = 0; q < 12; ++q) o[q] = mk(o[q].r + dl_[q].r, o[q].i + dl_[q].i);
+        for (int q = 0; q < 12; ++q) o[q] = dl_[q];
+    } else {
+        load_sp(ps, o);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) o[q] = mk(o[q].r + dl_[q].r, o[q].i + dl_[q].i);
+    }
     store_sp(ps, o);
     store_sp(a.rho + spinor_at(k, t), r);
     store_sp(a.dlt + spinor_at(k, t), dl_);
@@ -326,8 +353,8 @@ __global__ void k_sap_fields(Geom g, int p, int4 nb4, const float4 *__restrict__
     for (int q = 0; q < 18; ++q) cd[q * kSapSites] = cs[q * kSB];
 }
 
-// NATIVE F32 full vector <-> block order (to_block = 1: NATIVE -> block)
-__global__ void k_sap_order(Geom g, int p, int4 nb4, int to_block, float4 *__restrict__ nat, float4 *__restrict__ blk) {
+// Block order -> NATIVE F32 full vector, parity p (the solution at the end of an application)
+__global__ void k_sap_unorder(Geom g, int p, int4 nb4, float4 *__restrict__ nat, const float4 *__restrict__ blk) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.vh) return;
     const int nb[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
@@ -335,12 +362,9 @@ __global__ void k_sap_order(Geom g, int p, int4 nb4, int to_block, float4 *__res
     site_coords(g, i, p, x);
     block_pos(g, nb, x, k, t);
     float4 *q = site_ptr(nat + (size_t)p * 6 * g.vhp, (uint32_t)i, 6);
-    float4 *bq = blk + spinor_at(k, t);
+    const float4 *bq = blk + spinor_at(k, t);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        if (to_block) bq[j * kSapSites] = q[j * kSB];
-        else q[j * kSB] = bq[j * kSapSites];
-    }
+    for (int j = 0; j < 6; ++j) q[j * kSB] = bq[j * kSapSites];
 }
 
 }  // namespace
@@ -383,10 +407,8 @@ void sap_apply(dirac_ctx *c, void *psi, const void *r, int ncy, int nmr, hipStre
     const size_t vbytes = (size_t)nblk * 6 * kSapSites * sizeof(float4);
     c->sap_rho.alloc(3 * vbytes);  // rho, psi, delta in block order
     float4 *rho = (float4 *)c->sap_rho.p, *pb = rho + vbytes / sizeof(float4), *dlt = pb + vbytes / sizeof(float4);
-    for (int p = 0; p < 2; ++p)
-        k_sap_order<<<grid_for(vh), kBlock, 0, s>>>(c->g, p, nb4, 1, (float4 *)const_cast<void *>(r), rho);
-    HIP_CHECK(hipGetLastError());
-    zero_fill(pb, vbytes, s);
+    // the first cycle reads the residual from the NATIVE input (no reordering pass in), and psi
+    // starts as the first cycle's corrections (no zero fill)
     SapArgs a{};
     a.g = c->g;
     a.links = (const float4 *)c->sap_links.p;
@@ -400,11 +422,12 @@ void sap_apply(dirac_ctx *c, void *psi, const void *r, int ncy, int nmr, hipStre
         for (int col = 0; col < 2; ++col) {
             a.colour = col;
             a.update = !(cy == 0 && col == 0);
+            a.first = cy == 0;
+            a.rin = cy == 0 ? (const float4 *)r : nullptr;
             k_sap_step<<<nblk / 2, kSapSites, 0, s>>>(a);
             HIP_CHECK(hipGetLastError());
         }
-    for (int p = 0; p < 2; ++p)
-        k_sap_order<<<grid_for(vh), kBlock, 0, s>>>(c->g, p, nb4, 0, (float4 *)psi, pb);
+    for (int p = 0; p < 2; ++p) k_sap_unorder<<<grid_for(vh), kBlock, 0, s>>>(c->g, p, nb4, (float4 *)psi, pb);
     HIP_CHECK(hipGetLastError());
 }
 
